@@ -1,0 +1,167 @@
+/*
+ * fpsz.h -- C ABI of the MI355X (gfx950) fixed-PSNR SZ-style compressor.
+ *
+ * Method: D. Tao, S. Di, X. Liang, Z. Chen, F. Cappello, "Fixed-PSNR Lossy
+ * Compression for Scientific Data", arXiv:1805.07384.  The user fixes the
+ * PSNR of a field; the value-range-relative error bound follows from Eq. 7,
+ * eb_rel = sqrt(3) * 10^(-PSNR/20), and an SZ-style prediction + uniform
+ * quantization + Huffman compressor runs with eb_abs = eb_rel * vr (Sec. IV,
+ * the three-step fixed-PSNR workflow after Eq. 7).  The achieved PSNR is the
+ * one measured after decompression (Sec. V, Eq. 4).
+ *
+ * Conventions for every entry point:
+ *  - Device pointers are plain HIP device addresses (e.g. torch tensor
+ *    data_ptr()); host pointers are ordinary process memory.  The caller owns
+ *    every buffer; the library never frees caller memory and allocates
+ *    nothing per call (only the small context in fpsz_create).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is stream-ordered.  Entry points that return host values
+ *    (sizes, fpsz_info, fpsz_stats) synchronize that stream before returning.
+ *  - Fields are C-ordered with dims given slowest-first (NumPy order);
+ *    ndim is 1, 2 or 3 and the element count must be below 2^31.
+ *  - Errors are status codes; no exception crosses the ABI.  On an error the
+ *    contents of output buffers are undefined.  fpsz_last_error() gives a
+ *    message for the last failing call on a context.
+ *  - Calls on one context must not overlap in time (one host thread per
+ *    context at a time).  Separate contexts are independent.
+ */
+#ifndef FPSZ_H
+#define FPSZ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { FPSZ_F32 = 0, FPSZ_F64 = 1 } fpsz_dtype;
+
+/* Lorenzo prediction domain.  GLOBAL: the predictor reads zero only outside
+ * the field (the prefix-sum inverse spans the whole field).  TILE: it reads
+ * zero outside each 8192-point tile.  Both reconstruct the same values
+ * (Theorem 1 and Theorem 3: the error is that of the quantizer alone); only
+ * the bitstream differs. */
+typedef enum { FPSZ_DOMAIN_GLOBAL = 0, FPSZ_DOMAIN_TILE = 1 } fpsz_domain;
+
+typedef enum {
+  FPSZ_OK = 0,
+  FPSZ_E_INVALID_ARG = 1, /* bad dims/ndim/dtype/target/sizes/pointers */
+  FPSZ_E_NONFINITE = 2,   /* the field holds NaN or Inf */
+  FPSZ_E_RANGE = 3,       /* target needs more than 2^23 (f32) / 2^27 (f64) bins */
+  FPSZ_E_CORRUPT = 4,     /* blob fails its checks (magic, sizes, checksum, code) */
+  FPSZ_E_CAPACITY = 5,    /* a caller buffer is too small; see the entry point */
+  FPSZ_E_NOMEM = 6,       /* context allocation failed */
+  FPSZ_E_DEVICE = 7,      /* a HIP runtime call failed */
+  FPSZ_E_UNSUPPORTED = 8  /* no gfx950 device / feature not built */
+} fpsz_status;
+
+typedef struct fpsz_ctx fpsz_ctx;
+
+/* Per-call report of fpsz_compress. */
+typedef struct {
+  double target_psnr; /* as requested */
+  double eb_rel;      /* Eq. 7 */
+  double vr;          /* value range max - min of the input (definition under Eq. 4) */
+  double eb;          /* eb_abs = eb_rel * vr (remark after Eq. 6) */
+  double min, max;
+  uint64_t n;            /* element count */
+  uint64_t n_outliers;   /* residuals |d| >= 2^15 kept in the exception list */
+  uint64_t n_patches;    /* points stored exactly (float rounding past eb) */
+  uint64_t n_exceptions; /* 8-byte exception records in the blob */
+  uint64_t blob_bytes;
+  double bits_per_value; /* 8 * blob_bytes / n */
+  uint32_t is_const;     /* vr == 0: the blob only records the value */
+  uint32_t domain;       /* fpsz_domain used */
+} fpsz_info;
+
+/* Eq. 4: SSE, MSE = SSE / n, PSNR = -20 log10(sqrt(MSE) / vr), max |x - x'|,
+ * and the number of points with |x - x'| > eb.  All in float64. */
+typedef struct {
+  double sse, mse, psnr, max_abs_err;
+  uint64_t n_over_eb;
+} fpsz_stats;
+
+/* Create a context bound to HIP device `hip_device` (must be gfx950).
+ * Allocates a few KiB of device memory for status words.  *out receives the
+ * context or NULL on error. */
+fpsz_status fpsz_create(int hip_device, fpsz_ctx **out);
+void fpsz_destroy(fpsz_ctx *ctx);
+const char *fpsz_status_str(fpsz_status s);
+const char *fpsz_last_error(const fpsz_ctx *ctx);
+/* Library version string (format version + build). */
+const char *fpsz_version(void);
+
+/* Eq. 7 on the host: eb_rel = sqrt(3) * 10^(-psnr/20).  INVALID_ARG for a
+ * non-finite psnr. */
+fpsz_status fpsz_eb_rel(double target_psnr, double *eb_rel);
+
+/* Device workspace needed by fpsz_compress / fpsz_decompress / fpsz_verify
+ * for a field of this shape and dtype (bytes, 256-aligned).  The workspace is
+ * scratch: its contents need not be initialised and are clobbered. */
+fpsz_status fpsz_compress_workspace_bytes(int ndim, const uint64_t *dims, fpsz_dtype dtype,
+                                          uint64_t *bytes);
+fpsz_status fpsz_decompress_workspace_bytes(int ndim, const uint64_t *dims, fpsz_dtype dtype,
+                                            uint64_t *bytes);
+fpsz_status fpsz_verify_workspace_bytes(uint64_t n, uint64_t *bytes);
+
+/* A blob capacity that fits every field of this shape: header, tables, and
+ * per point 32 code bits plus its largest possible exception records (an
+ * outlier record and a patch of 1 (f32) or 2 (f64) records).  Typical blobs
+ * are far smaller; fpsz_compress reports the exact size on FPSZ_E_CAPACITY. */
+fpsz_status fpsz_compress_bound(int ndim, const uint64_t *dims, fpsz_dtype dtype,
+                                uint64_t *bytes);
+
+/* Compress one field at a target PSNR (the three-step fixed-PSNR workflow
+ * after Eq. 7: target -> eb_rel -> SZ-style compression with eb_rel * vr).
+ *   field_dev      device, ndim/dims/dtype as described; read only
+ *   workspace_dev  device scratch of >= fpsz_compress_workspace_bytes
+ *   blob_dev       device output of blob_capacity bytes
+ *   blob_bytes     host out: size written; on FPSZ_E_CAPACITY the size needed
+ *   info           host out, may be NULL
+ * Synchronizes `stream`.  Status: INVALID_ARG, NONFINITE, RANGE, CAPACITY,
+ * DEVICE.  A constant field (vr == 0) yields a 256-byte blob. */
+fpsz_status fpsz_compress(fpsz_ctx *ctx, const void *field_dev, int ndim, const uint64_t *dims,
+                          fpsz_dtype dtype, double target_psnr, fpsz_domain domain,
+                          void *workspace_dev, uint64_t workspace_bytes, void *blob_dev,
+                          uint64_t blob_capacity, uint64_t *blob_bytes, fpsz_info *info,
+                          void *stream);
+
+/* Parse a blob header held in HOST memory (the first 256 bytes suffice).
+ * dims receives 3 entries (unused ones = 1).  CORRUPT on a bad magic or
+ * version, INVALID_ARG on NULL pointers or bytes < 256. */
+fpsz_status fpsz_blob_header(const void *blob_host, uint64_t bytes, int *ndim, uint64_t *dims,
+                             fpsz_dtype *dtype, fpsz_info *info);
+
+/* Decompress a blob produced by fpsz_compress (Sec. III: decode, repeat the
+ * prediction by inclusive prefix sums, reconstruct bin midpoints q * 2 eb).
+ *   blob_dev       device, blob_bytes long; read only
+ *   workspace_dev  device scratch of >= fpsz_decompress_workspace_bytes for
+ *                  the blob's shape
+ *   field_out_dev  device output, out_bytes >= n * element size
+ * Synchronizes `stream`.  Status: INVALID_ARG, CORRUPT (header, sizes,
+ * checksum, Huffman code or exception list inconsistent), CAPACITY
+ * (out_bytes or workspace too small), DEVICE. */
+fpsz_status fpsz_decompress(fpsz_ctx *ctx, const void *blob_dev, uint64_t blob_bytes,
+                            void *workspace_dev, uint64_t workspace_bytes, void *field_out_dev,
+                            uint64_t out_bytes, void *stream);
+
+/* Eq. 4 check of a reconstruction against the original (both device, n
+ * elements of dtype).  vr and eb as reported by fpsz_compress.  The float64
+ * reduction order is fixed, so repeated calls return identical bits.
+ * Synchronizes `stream`. */
+fpsz_status fpsz_verify(fpsz_ctx *ctx, const void *orig_dev, const void *recon_dev, uint64_t n,
+                        fpsz_dtype dtype, double vr, double eb, void *workspace_dev,
+                        uint64_t workspace_bytes, fpsz_stats *out, void *stream);
+
+/* Offsets (bytes) of intermediates inside a compress workspace, for tests
+ * and diagnostics: which = 0 parameter block, 1 histogram (u32[1036]),
+ * 2 code lengths (u8[1036]), 3 codewords (u32[1036]), 4 residual codes in
+ * stream order (i16[n]: the residual, or -32768 for an outlier). */
+fpsz_status fpsz_compress_workspace_offset(int ndim, const uint64_t *dims, fpsz_dtype dtype,
+                                           int which, uint64_t *offset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FPSZ_H */

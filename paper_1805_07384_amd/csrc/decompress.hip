@@ -1,0 +1,619 @@
+// decompress.hip -- gfx950 kernels of decompression and the Eq. 4 check.
+//
+// Decompression repeats the prediction of the compressor (Sec. III, Eq. 1):
+// the Lorenzo residual is undone by inclusive prefix sums along x, y and z,
+// and bin indexes become bin midpoints q * 2eb (Sec. IV, Eq. 5-6).
+//
+// GLOBAL domain (prefix sums over the whole field), three passes:
+//   A  decode each tile into LDS and write its three projections
+//      (sums of the residual along z, y and x) into full-resolution face
+//      arrays Fz[gz][ny][nx], Fy[nz][gy][nx], Fx[nz][ny][gx];
+//   B  inclusive prefix sums of each face array along its three axes.  Then
+//      Fz[a][y][x] is the reconstructed q on the last plane of tile slab a,
+//      and likewise Fy / Fx for the last row / column of each tile band;
+//   C  decode again, local 3D prefix sum L, and add the halo terms:
+//      q = L + (qz[y][x] - qz[y0-1][x] - qz[y][x0-1] + qz[y0-1][x0-1])
+//            + (qy[z][x] - qy[z][x0-1]) + qx[z][y]
+//      (inclusion-exclusion over the regions before the tile), then scale.
+// Sums are taken modulo 2^32; the true bin indexes fit in 32 bits, so the
+// result is exact.  TILE domain: pass C alone with zero halo.
+#include <math.h>
+
+#include "fpsz_internal.h"
+
+namespace fpsz {
+
+template <int NDIM> struct DGeo;
+template <> struct DGeo<1> { static constexpr int TZ = 1, TY = 1, TX = 8192; };
+template <> struct DGeo<2> { static constexpr int TZ = 1, TY = 64, TX = 128; };
+template <> struct DGeo<3> { static constexpr int TZ = 16, TY = 16, TX = 32; };
+
+__device__ __host__ constexpr int dphys(int L) { return L + (L >> 5); }
+
+struct DecodeArgs {
+  uint64_t off_words, n_words, n_exc;
+  double e2;
+  float e2_f;
+  const uint32_t *lut;
+  const uint32_t *ltab;
+  const uint16_t *sorted;
+  uint32_t *fz, *fy, *fx;
+};
+
+// ---------------------------------------------------------------------------
+// decoder tables from the code lengths in the blob (one workgroup)
+__global__ __launch_bounds__(1024) void k_dec_tables(Plan P, const uint8_t *__restrict__ blob,
+                                                     DevParams *__restrict__ dp,
+                                                     uint32_t *__restrict__ lut,
+                                                     uint32_t *__restrict__ ltab,
+                                                     uint16_t *__restrict__ sorted) {
+  __shared__ uint8_t lens[kNSym];
+  __shared__ uint32_t code[kNSym];
+  __shared__ uint32_t lcount[kLMax + 2], lfirst[kLMax + 2], lbase[kLMax + 2];
+  __shared__ unsigned long long kraft;
+  __shared__ uint32_t bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) { kraft = 0; bad = 0; }
+  __syncthreads();
+  for (int s = tid; s < kNSym; s += blockDim.x) {
+    const uint8_t l = blob[P.off_len + s];
+    lens[s] = l;
+    if (l > kLMax) atomicOr(&bad, 1u);
+    else if (l) atomicAdd(&kraft, 1ull << (kLMax - l));
+  }
+  __syncthreads();
+  if (bad || kraft > (1ull << kLMax) || kraft == 0) {
+    if (tid == 0) atomicOr(&dp->corrupt, 1u);
+    return;
+  }
+  canonical_from_lengths(lens, code, lcount, lfirst, lbase, sorted);
+  for (int i = tid; i < (1 << kLutBits); i += blockDim.x) lut[i] = 0;
+  __syncthreads();
+  for (int s = tid; s < kNSym; s += blockDim.x) {
+    const int l = lens[s];
+    if (l == 0 || l > kLutBits) continue;
+    const uint32_t lo = code[s] << (kLutBits - l), hi = (code[s] + 1) << (kLutBits - l);
+    for (uint32_t i = lo; i < hi; i++) lut[i] = ((uint32_t)s << 5) | (uint32_t)l;
+  }
+  if (tid <= kLMax) {
+    ltab[tid] = lfirst[tid];
+    ltab[32 + tid] = lcount[tid];
+    ltab[64 + tid] = lbase[tid];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One tile per workgroup.  PASS 0 = projections (A), 1 = reconstruction (C).
+template <typename T, int NDIM, int PASS, bool GLOBAL>
+__global__ __launch_bounds__(kBlock) void k_decode(Plan P, const uint8_t *__restrict__ blob,
+                                                   DecodeArgs A, DevParams *__restrict__ dp,
+                                                   T *__restrict__ out) {
+  using G = DGeo<NDIM>;
+  constexpr int TZ = G::TZ, TY = G::TY, TX = G::TX;
+  constexpr int LDS = dphys(kTilePts - 1) + 1;
+  __shared__ int32_t dl[LDS];
+  __shared__ uint32_t lut[1 << kLutBits];
+  __shared__ uint32_t lfirst[kLMax + 1], lcnt[kLMax + 1], lbase[kLMax + 1];
+  __shared__ uint16_t sorted[kNSym];
+  __shared__ uint32_t omask[kTilePts / 32], pmask[kTilePts / 32];
+  __shared__ uint32_t hA[TY * TX > 1 && NDIM == 3 ? TY * TX : 1];
+  __shared__ uint32_t hB[NDIM >= 2 ? TZ * TX : 1];
+  __shared__ uint32_t hC[TZ * TY];
+  __shared__ uint32_t s_bad;
+  __shared__ uint32_t scr[8];
+
+  if (dp->corrupt) return;
+  const int tid = threadIdx.x;
+  const uint64_t t = blockIdx.x;
+  const TileGeo g = tile_geo(P, t);
+  const int ez = (int)g.ez, ey = (int)g.ey, ex = (int)g.ex, nt = (int)g.nt;
+  const bool full = ez == TZ && ey == TY && ex == TX;
+
+  for (int i = tid; i < (1 << kLutBits); i += kBlock) lut[i] = A.lut[i];
+  for (int i = tid; i < kNSym; i += kBlock) sorted[i] = A.sorted[i];
+  if (tid <= kLMax) {
+    lfirst[tid] = A.ltab[tid];
+    lcnt[tid] = A.ltab[32 + tid];
+    lbase[tid] = A.ltab[64 + tid];
+  }
+  omask[tid] = 0;
+  pmask[tid] = 0;
+  if (tid == 0) s_bad = 0;
+  const uint64_t *two = reinterpret_cast<const uint64_t *>(blob + P.off_two);
+  const uint64_t *teo = reinterpret_cast<const uint64_t *>(blob + P.off_teo);
+  const uint64_t w0 = two[t], w1 = two[t + 1];
+  const uint64_t e0 = teo[t], e1 = teo[t + 1];
+  __syncthreads();
+  if (w0 > w1 || w1 > A.n_words || e0 > e1 || e1 > A.n_exc) {
+    if (tid == 0) atomicOr(&dp->corrupt, 1u);
+    return;
+  }
+
+  // ---- decode: lane k of wave 0 decodes chunk k of the tile
+  if (tid < 64) {
+    const int lane = tid;
+    const uint16_t *cbits = reinterpret_cast<const uint16_t *>(blob + P.off_cb);
+    const uint32_t cb = lane < (int)g.nck ? cbits[g.chunk_base + lane] : 0u;
+    const uint32_t incl = wave_incl_scan_u32(cb);
+    const uint32_t total = __shfl(incl, 63, 64);
+    if ((uint64_t)total > (w1 - w0) * 32) {
+      if (lane == 0) atomicOr(&s_bad, 1u);
+    } else if (lane < (int)g.nck) {
+      const uint32_t *words = reinterpret_cast<const uint32_t *>(blob + A.off_words);
+      uint64_t bitpos = w0 * 32 + (incl - cb);
+      uint64_t widx = bitpos >> 5;
+      const uint32_t sh = (uint32_t)(bitpos & 31);
+      uint64_t buf = (uint64_t)(widx < w1 ? words[widx] : 0u) << 32;
+      widx++;
+      buf <<= sh;
+      int nb = 32 - (int)sh;
+      const int k0 = lane * kChunk;
+      const int k1 = k0 + kChunk < nt ? k0 + kChunk : nt;
+      int z = k0 / (ey * ex);
+      const int rem = k0 - z * ey * ex;
+      int y = rem / ex, xx = rem - (rem / ex) * ex;
+      uint32_t used = 0;
+      bool ok = true;
+      for (int k = k0; k < k1; k++) {
+        if (nb < 32) {
+          buf |= (uint64_t)(widx < w1 ? words[widx] : 0u) << (32 - nb);
+          widx++;
+          nb += 32;
+        }
+        const uint32_t e = lut[(uint32_t)(buf >> (64 - kLutBits))];
+        int L = (int)(e & 31u);
+        int s = (int)(e >> 5);
+        if (L == 0) {
+          const uint32_t v = (uint32_t)(buf >> (64 - kLMax));
+          s = -1;
+          for (int l = kLutBits + 1; l <= kLMax; l++) {
+            const uint32_t c = v >> (kLMax - l);
+            if (c - lfirst[l] < lcnt[l]) { s = sorted[lbase[l] + (c - lfirst[l])]; L = l; break; }
+          }
+          if (s < 0) { ok = false; break; }
+        }
+        buf <<= L;
+        nb -= L;
+        int32_t dv;
+        if (s >= 1024) {
+          const int kk = (s - 1024) / 2 + 9;
+          const uint32_t ev = (uint32_t)(buf >> (64 - kk));
+          buf <<= kk;
+          nb -= kk;
+          L += kk;
+          const int32_t mag = (1 << kk) + (int32_t)ev;
+          dv = (s & 1) ? -mag : mag;
+        } else if (s == 0) {
+          const int si = k;
+          atomicOr(&omask[si >> 5], 1u << (si & 31));
+          dv = 0;
+        } else {
+          dv = s - 512;
+        }
+        used += (uint32_t)L;
+        dl[dphys((z * TY + y) * TX + xx)] = dv;
+        if (++xx == ex) { xx = 0; if (++y == ey) { y = 0; z++; } }
+      }
+      if (!ok || used != cb) atomicOr(&s_bad, 1u);
+    }
+  }
+  __syncthreads();
+
+  // ---- exception list of this tile: outlier residuals, patch marks
+  for (uint64_t e = e0 + tid; e < e1; e += kBlock) {
+    const uint32_t *rec = reinterpret_cast<const uint32_t *>(blob + P.off_exc + 8 * e);
+    const uint32_t key = rec[0];
+    const uint64_t pos = key & ~kTagPatch;
+    if (pos < g.start || pos >= g.start + (uint64_t)nt) { atomicOr(&s_bad, 1u); continue; }
+    const int si = (int)(pos - g.start);
+    if (key & kTagPatch) {
+      atomicOr(&pmask[si >> 5], 1u << (si & 31));
+    } else {
+      const uint32_t old = atomicAnd(&omask[si >> 5], ~(1u << (si & 31)));
+      if (!((old >> (si & 31)) & 1u)) { atomicOr(&s_bad, 1u); continue; }
+      const int z = si / (ey * ex), rem = si - z * ey * ex, y = rem / ex, xx = rem - y * ex;
+      dl[dphys((z * TY + y) * TX + xx)] = (int32_t)rec[1];
+    }
+  }
+  __syncthreads();
+  if (omask[tid]) atomicOr(&s_bad, 1u);
+  __syncthreads();
+  if (s_bad) {
+    if (tid == 0) atomicOr(&dp->corrupt, 1u);
+    return;
+  }
+
+  if (PASS == 0) {
+    // ---- projections into the face arrays
+    if (NDIM == 3 && P.gz > 1) {
+      for (int i = tid; i < ey * ex; i += kBlock) {
+        const int y = i / ex, xx = i - (i / ex) * ex;
+        uint32_t s = 0;
+        for (int z = 0; z < ez; z++) s += (uint32_t)dl[dphys((z * TY + y) * TX + xx)];
+        A.fz[((uint64_t)g.a * P.ny + g.y0 + y) * P.nx + g.x0 + xx] = s;
+      }
+    }
+    if (NDIM >= 2 && P.gy > 1) {
+      for (int i = tid; i < ez * ex; i += kBlock) {
+        const int z = i / ex, xx = i - (i / ex) * ex;
+        uint32_t s = 0;
+        for (int y = 0; y < ey; y++) s += (uint32_t)dl[dphys((z * TY + y) * TX + xx)];
+        A.fy[((g.z0 + z) * P.gy + g.b) * P.nx + g.x0 + xx] = s;
+      }
+    }
+    if (P.gx > 1) {
+      if (NDIM == 1) {
+        uint32_t s = 0;
+        for (int i = tid; i < nt; i += kBlock) s += (uint32_t)dl[dphys(i)];
+        s = wave_sum_u32(s);
+        if ((tid & 63) == 0) scr[tid >> 6] = s;
+        __syncthreads();
+        if (tid == 0) A.fx[g.c] = scr[0] + scr[1] + scr[2] + scr[3];
+      } else {
+        for (int i = tid; i < ez * ey; i += kBlock) {
+          const int z = i / ey, y = i - (i / ey) * ey;
+          uint32_t s = 0;
+          for (int xx = 0; xx < ex; xx++) s += (uint32_t)dl[dphys((z * TY + y) * TX + xx)];
+          A.fx[((g.z0 + z) * P.ny + g.y0 + y) * P.gx + g.c] = s;
+        }
+      }
+    }
+    return;
+  }
+
+  // ---- PASS C: local inclusive prefix sums (modulo 2^32) along x, y, z
+  if (NDIM == 1) {
+    const int i0 = 32 * tid;
+    uint32_t run = 0;
+    for (int j = 0; j < 32; j++)
+      if (i0 + j < nt) { run += (uint32_t)dl[dphys(i0 + j)]; dl[dphys(i0 + j)] = (int32_t)run; }
+    uint32_t tot;
+    const uint32_t ex0 = block_excl_scan_u32(run, scr, &tot);
+    for (int j = 0; j < 32; j++)
+      if (i0 + j < nt) dl[dphys(i0 + j)] = (int32_t)((uint32_t)dl[dphys(i0 + j)] + ex0);
+  } else {
+    for (int r = tid; r < ez * ey; r += kBlock) {
+      const int z = r / ey, y = r - (r / ey) * ey;
+      uint32_t run = 0;
+      for (int xx = 0; xx < ex; xx++) {
+        const int o = dphys((z * TY + y) * TX + xx);
+        run += (uint32_t)dl[o];
+        dl[o] = (int32_t)run;
+      }
+    }
+    __syncthreads();
+    for (int c = tid; c < ez * ex; c += kBlock) {
+      const int z = c / ex, xx = c - (c / ex) * ex;
+      uint32_t run = 0;
+      for (int y = 0; y < ey; y++) {
+        const int o = dphys((z * TY + y) * TX + xx);
+        run += (uint32_t)dl[o];
+        dl[o] = (int32_t)run;
+      }
+    }
+    if (NDIM == 3) {
+      __syncthreads();
+      for (int c = tid; c < ey * ex; c += kBlock) {
+        const int y = c / ex, xx = c - (c / ex) * ex;
+        uint32_t run = 0;
+        for (int z = 0; z < ez; z++) {
+          const int o = dphys((z * TY + y) * TX + xx);
+          run += (uint32_t)dl[o];
+          dl[o] = (int32_t)run;
+        }
+      }
+    }
+  }
+
+  // ---- halo terms from the scanned face arrays
+  if (GLOBAL) {
+    if (NDIM == 3) {
+      for (int i = tid; i < ey * ex; i += kBlock) {
+        const int y = i / ex, xx = i - (i / ex) * ex;
+        uint32_t v = 0;
+        if (g.a > 0) {
+          const uint32_t *F = A.fz + (uint64_t)(g.a - 1) * P.ny * P.nx;
+          const int64_t yy = (int64_t)g.y0 + y, xg = (int64_t)g.x0 + xx;
+          const int64_t yp = (int64_t)g.y0 - 1, xp = (int64_t)g.x0 - 1;
+          v = F[yy * P.nx + xg];
+          if (yp >= 0) v -= F[yp * P.nx + xg];
+          if (xp >= 0) v -= F[yy * P.nx + xp];
+          if (yp >= 0 && xp >= 0) v += F[yp * P.nx + xp];
+        }
+        hA[y * TX + xx] = v;
+      }
+    }
+    if (NDIM >= 2) {
+      for (int i = tid; i < ez * ex; i += kBlock) {
+        const int z = i / ex, xx = i - (i / ex) * ex;
+        uint32_t v = 0;
+        if (g.b > 0) {
+          const uint32_t *F = A.fy + ((g.z0 + z) * P.gy + (g.b - 1)) * P.nx;
+          v = F[g.x0 + xx];
+          if (g.x0 > 0) v -= F[g.x0 - 1];
+        }
+        hB[z * TX + xx] = v;
+      }
+    }
+    for (int i = tid; i < ez * ey; i += kBlock) {
+      const int z = i / ey, y = i - (i / ey) * ey;
+      uint32_t v = 0;
+      if (g.c > 0) v = A.fx[((g.z0 + z) * P.ny + g.y0 + y) * P.gx + (g.c - 1)];
+      hC[z * TY + y] = v;
+    }
+  }
+  __syncthreads();
+
+  // ---- bin midpoints q * 2eb, patched points exact, coalesced store
+  const uint32_t *exc = reinterpret_cast<const uint32_t *>(blob + P.off_exc);
+  for (int i = tid; i < nt; i += kBlock) {
+    int z, y, xx;
+    if (full) { z = i / (TY * TX); y = (i / TX) % TY; xx = i % TX; }
+    else { z = i / (ey * ex); const int rem = i - z * ey * ex; y = rem / ex; xx = rem - y * ex; }
+    uint32_t q = (uint32_t)dl[dphys((z * TY + y) * TX + xx)];
+    if (GLOBAL) {
+      if (NDIM == 3) q += hA[y * TX + xx];
+      if (NDIM >= 2) q += hB[z * TX + xx];
+      q += hC[z * TY + y];
+    }
+    T v;
+    if (sizeof(T) == 4) v = (T)((float)(int32_t)q * A.e2_f);
+    else v = (T)((double)(int32_t)q * A.e2);
+    if ((pmask[i >> 5] >> (i & 31)) & 1u) {
+      // exact value from the exception list (records sorted by position)
+      const uint32_t want = (uint32_t)(g.start + (uint64_t)i) | kTagPatch;
+      uint64_t lo = e0, hi = e1;
+      while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        const uint32_t k = exc[2 * mid];
+        if ((k & ~kTagPatch) < (want & ~kTagPatch) ||
+            ((k & ~kTagPatch) == (want & ~kTagPatch) && k < want))
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      if (lo < e1 && exc[2 * lo] == want) {
+        if (sizeof(T) == 4) {
+          const uint32_t b = exc[2 * lo + 1];
+          __builtin_memcpy(&v, &b, 4);
+        } else if (lo + 1 < e1 && exc[2 * lo + 2] == want) {
+          const uint64_t b = (uint64_t)exc[2 * lo + 1] | ((uint64_t)exc[2 * lo + 3] << 32);
+          __builtin_memcpy(&v, &b, 8);
+        } else {
+          atomicOr(&dp->corrupt, 1u);
+        }
+      } else {
+        atomicOr(&dp->corrupt, 1u);
+      }
+    }
+    out[((g.z0 + z) * P.ny + g.y0 + y) * P.nx + g.x0 + xx] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass B: inclusive scans of a row-major u32 array along one axis
+// contiguous axis: one workgroup per line
+__global__ __launch_bounds__(kBlock) void k_scan_inner(uint32_t *__restrict__ a, uint64_t lines,
+                                                       uint32_t len) {
+  __shared__ uint32_t scr[8];
+  for (uint64_t line = blockIdx.x; line < lines; line += gridDim.x) {
+    uint32_t *p = a + line * len;
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < len; base += 4 * kBlock) {
+      const uint32_t i0 = base + 4 * threadIdx.x;
+      uint32_t v[4];
+#pragma unroll
+      for (int k = 0; k < 4; k++) v[k] = i0 + k < len ? p[i0 + k] : 0u;
+      v[1] += v[0];
+      v[2] += v[1];
+      v[3] += v[2];
+      uint32_t tot;
+      const uint32_t ex0 = block_excl_scan_u32(v[3], scr, &tot);
+#pragma unroll
+      for (int k = 0; k < 4; k++)
+        if (i0 + k < len) p[i0 + k] = v[k] + ex0 + carry;
+      carry += tot;
+    }
+  }
+}
+
+// strided axis: element (o, k, i) at (o * len + k) * inner + i; one thread
+// per (o, i), sequential along k
+__global__ __launch_bounds__(kBlock) void k_scan_outer(uint32_t *__restrict__ a, uint64_t outer,
+                                                       uint64_t len, uint64_t inner) {
+  const uint64_t total = outer * inner;
+  for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < total;
+       j += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t o = j / inner, i = j - o * inner;
+    uint32_t *p = a + o * len * inner + i;
+    uint32_t run = 0;
+    for (uint64_t k = 0; k < len; k++) {
+      run += p[k * inner];
+      p[k * inner] = run;
+    }
+  }
+}
+
+static void scan3(uint32_t *a, uint64_t d0, uint64_t d1, uint64_t d2, hipStream_t s) {
+  if (d2 > 1) {
+    const uint64_t lines = d0 * d1;
+    const uint32_t grid = (uint32_t)(lines < 65536 ? lines : 65536);
+    hipLaunchKernelGGL(k_scan_inner, dim3(grid), dim3(kBlock), 0, s, a, lines, (uint32_t)d2);
+  }
+  if (d1 > 1) {
+    const uint64_t th = d0 * d2;
+    const uint64_t b = th / kBlock + 1;
+    hipLaunchKernelGGL(k_scan_outer, dim3((uint32_t)(b < 65536 ? b : 65536)), dim3(kBlock), 0, s, a,
+                       d0, d1, d2);
+  }
+  if (d0 > 1) {
+    const uint64_t th = d1 * d2;
+    const uint64_t b = th / kBlock + 1;
+    hipLaunchKernelGGL(k_scan_outer, dim3((uint32_t)(b < 65536 ? b : 65536)), dim3(kBlock), 0, s, a,
+                       (uint64_t)1, d0, d1 * d2);
+  }
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_csum_check(const uint8_t *__restrict__ blob, DevParams *__restrict__ dp) {
+  const uint64_t stored = *reinterpret_cast<const uint64_t *>(blob + H_CSUM);
+  if (stored != dp->checksum) dp->corrupt = 1;
+}
+
+template <typename T, int NDIM>
+static void launch_dec_t(const Plan &P, const uint8_t *blob, const DecodeArgs &A, DevParams *dp,
+                         T *out, hipStream_t s) {
+  const dim3 grid((uint32_t)P.n_tiles), blk(kBlock);
+  if (P.domain == FPSZ_DOMAIN_GLOBAL) {
+    hipLaunchKernelGGL((k_decode<T, NDIM, 0, true>), grid, blk, 0, s, P, blob, A, dp, out);
+    if (NDIM == 3 && P.gz > 1) scan3(A.fz, P.gz, P.ny, P.nx, s);
+    if (NDIM >= 2 && P.gy > 1) scan3(A.fy, P.nz, P.gy, P.nx, s);
+    if (P.gx > 1) scan3(A.fx, P.nz, P.ny, P.gx, s);
+    hipLaunchKernelGGL((k_decode<T, NDIM, 1, true>), grid, blk, 0, s, P, blob, A, dp, out);
+  } else {
+    hipLaunchKernelGGL((k_decode<T, NDIM, 1, false>), grid, blk, 0, s, P, blob, A, dp, out);
+  }
+}
+
+hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const DecompressWs &W,
+                                  uint64_t off_words, uint64_t n_words, uint64_t n_exc, double e2,
+                                  float e2_f, void *out, hipStream_t s) {
+  hipError_t e = launch_fill_zero(W.P, W.zero_bytes, s);
+  if (e != hipSuccess) return e;
+  e = launch_checksum(blob, P.capacity, W.P, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_csum_check, dim3(1), dim3(1), 0, s, blob, W.P);
+  hipLaunchKernelGGL(k_dec_tables, dim3(1), dim3(1024), 0, s, P, blob, W.P, W.lut, W.ltab,
+                     W.sorted);
+  DecodeArgs A;
+  A.off_words = off_words;
+  A.n_words = n_words;
+  A.n_exc = n_exc;
+  A.e2 = e2;
+  A.e2_f = e2_f;
+  A.lut = W.lut;
+  A.ltab = W.ltab;
+  A.sorted = W.sorted;
+  A.fz = W.fz;
+  A.fy = W.fy;
+  A.fx = W.fx;
+  if (P.dtype == FPSZ_F32) {
+    if (P.ndim == 1) launch_dec_t<float, 1>(P, blob, A, W.P, (float *)out, s);
+    else if (P.ndim == 2) launch_dec_t<float, 2>(P, blob, A, W.P, (float *)out, s);
+    else launch_dec_t<float, 3>(P, blob, A, W.P, (float *)out, s);
+  } else {
+    if (P.ndim == 1) launch_dec_t<double, 1>(P, blob, A, W.P, (double *)out, s);
+    else if (P.ndim == 2) launch_dec_t<double, 2>(P, blob, A, W.P, (double *)out, s);
+    else launch_dec_t<double, 3>(P, blob, A, W.P, (double *)out, s);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_const_fill(T *__restrict__ out, uint64_t n, uint64_t bits) {
+  T v;
+  if (sizeof(T) == 4) { const uint32_t b = (uint32_t)bits; __builtin_memcpy(&v, &b, 4); }
+  else __builtin_memcpy(&v, &bits, 8);
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = v;
+}
+
+hipError_t launch_const_fill_bits(const Plan &P, uint64_t bits, void *out, hipStream_t s) {
+  const uint64_t b = P.n / kBlock + 1;
+  const uint32_t grid = (uint32_t)(b < 2048 ? b : 2048);
+  if (P.dtype == FPSZ_F32)
+    hipLaunchKernelGGL(k_const_fill<float>, dim3(grid), dim3(kBlock), 0, s, (float *)out, P.n, bits);
+  else
+    hipLaunchKernelGGL(k_const_fill<double>, dim3(grid), dim3(kBlock), 0, s, (double *)out, P.n,
+                       bits);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// a12: SSE, max |e| and #(|e| > eb) in float64 with a fixed reduction tree:
+// block b owns a fixed contiguous span; partials are combined in block order.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_verify(const T *__restrict__ x, const T *__restrict__ y,
+                                                   uint64_t n, double eb, double *__restrict__ part) {
+  const uint64_t span = (n + gridDim.x - 1) / gridDim.x;
+  const uint64_t b0 = blockIdx.x * span;
+  const uint64_t b1 = b0 + span < n ? b0 + span : n;
+  double sse = 0.0, mx = 0.0;
+  uint64_t over = 0;
+  for (uint64_t i = b0 + threadIdx.x; i < b1; i += kBlock) {
+    const double e = (double)x[i] - (double)y[i];
+    sse += e * e;
+    const double ae = fabs(e);
+    mx = ae > mx ? ae : mx;
+    over += ae > eb ? 1 : 0;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    sse += __shfl_xor(sse, o, 64);
+    const double m2 = __shfl_xor(mx, o, 64);
+    mx = m2 > mx ? m2 : mx;
+    over += __shfl_xor(over, o, 64);
+  }
+  __shared__ double s_sse[4], s_mx[4];
+  __shared__ uint64_t s_over[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) { s_sse[wv] = sse; s_mx[wv] = mx; s_over[wv] = over; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = ((s_sse[0] + s_sse[1]) + (s_sse[2] + s_sse[3]));
+    double m = s_mx[0];
+    for (int w = 1; w < 4; w++) m = s_mx[w] > m ? s_mx[w] : m;
+    const uint64_t ov = s_over[0] + s_over[1] + s_over[2] + s_over[3];
+    part[3 * blockIdx.x + 0] = a;
+    part[3 * blockIdx.x + 1] = m;
+    part[3 * blockIdx.x + 2] = __longlong_as_double((long long)ov);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_verify_final(const double *__restrict__ part, int nb,
+                                                         DevParams *__restrict__ dp) {
+  double sse = 0.0, mx = 0.0;
+  uint64_t over = 0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) {
+    sse += part[3 * b];
+    mx = part[3 * b + 1] > mx ? part[3 * b + 1] : mx;
+    over += (uint64_t)__double_as_longlong(part[3 * b + 2]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    sse += __shfl_xor(sse, o, 64);
+    const double m2 = __shfl_xor(mx, o, 64);
+    mx = m2 > mx ? m2 : mx;
+    over += __shfl_xor(over, o, 64);
+  }
+  __shared__ double s_sse[4], s_mx[4];
+  __shared__ uint64_t s_over[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) { s_sse[wv] = sse; s_mx[wv] = mx; s_over[wv] = over; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    dp->v_sse = (s_sse[0] + s_sse[1]) + (s_sse[2] + s_sse[3]);
+    double m = s_mx[0];
+    for (int w = 1; w < 4; w++) m = s_mx[w] > m ? s_mx[w] : m;
+    dp->v_max = m;
+    dp->v_over = s_over[0] + s_over[1] + s_over[2] + s_over[3];
+  }
+}
+
+hipError_t launch_verify(const void *x, const void *y, uint64_t n, int dtype, double eb,
+                         DevParams *P, void *part, hipStream_t s) {
+  const uint64_t want = n / (kBlock * 8) + 1;
+  const int nb = (int)(want < (uint64_t)kVerifyBlocks ? want : kVerifyBlocks);
+  if (dtype == FPSZ_F32)
+    hipLaunchKernelGGL(k_verify<float>, dim3(nb), dim3(kBlock), 0, s, (const float *)x,
+                       (const float *)y, n, eb, (double *)part);
+  else
+    hipLaunchKernelGGL(k_verify<double>, dim3(nb), dim3(kBlock), 0, s, (const double *)x,
+                       (const double *)y, n, eb, (double *)part);
+  hipLaunchKernelGGL(k_verify_final, dim3(1), dim3(kBlock), 0, s, (const double *)part, nb, P);
+  return hipGetLastError();
+}
+
+}  // namespace fpsz

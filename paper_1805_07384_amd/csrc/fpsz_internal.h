@@ -1,0 +1,318 @@
+// fpsz_internal.h -- shared definitions of the gfx950 library (format
+// constants, the per-call plan, device parameter block, wave primitives).
+//
+// Format (little-endian, 8-byte aligned sections):
+//   header (256 B) | code_len u8[1036] | tile_word_offset u64[T+1] |
+//   tile_exc_offset u64[T+1] | chunk_bits u16[C] | exceptions {u32 key, u32 val}[E] |
+//   words u32[W]
+// Stream order: tiles row-major over the tile grid, points row-major inside
+// the edge-clipped tile.  Tiles: 1D 8192, 2D 64x128, 3D 16x16x32 points.
+// Each tile's bits form one MSB-first stream cut into chunks of 128 symbols
+// (chunk_bits records each chunk's length) and padded to a 32-bit word.
+// Symbol of a Lorenzo residual d: |d| <= 511 -> d + 512; 512 <= |d| < 2^15 ->
+// 1024 + 2(k - 9) + (d < 0) followed by k raw bits of |d| - 2^k, k = floor
+// log2 |d|; |d| >= 2^15 -> symbol 0 with d in the exception list.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fpsz.h"
+
+namespace fpsz {
+
+constexpr uint32_t kMagic = 0x5A535046u;  // "FPSZ"
+constexpr uint16_t kVersion = 1;
+constexpr uint64_t kHdr = 256;
+constexpr int kNSym = 1036;
+constexpr int kLMax = 18;
+constexpr int kChunk = 128;
+constexpr int kTilePts = 8192;
+constexpr int kLutBits = 11;
+constexpr uint32_t kTagPatch = 0x80000000u;
+constexpr uint16_t kFlagConst = 1, kFlagTile = 2;
+constexpr int kBlock = 256;
+constexpr int kRangeBlocks = 1024;
+constexpr int kVerifyBlocks = 1024;
+
+// header byte offsets
+enum : uint32_t {
+  H_MAGIC = 0, H_VERSION = 4, H_FLAGS = 6, H_DTYPE = 8, H_NDIM = 9, H_LOG2D = 10,
+  H_LOG2R = 11, H_LMAX = 12, H_DIMS = 16, H_TILE = 40, H_CHUNK = 52, H_PSNR = 56,
+  H_EBREL = 64, H_VR = 72, H_EB = 80, H_E2 = 88, H_R = 96, H_E2T = 104, H_RT = 112,
+  H_MIN = 120, H_MAX = 128, H_N = 136, H_NTILES = 144, H_NCHUNKS = 152, H_NWORDS = 160,
+  H_NEXC = 168, H_NOUT = 176, H_NPATCH = 184, H_BYTES = 192, H_CSUM = 200, H_CONST = 208
+};
+
+__host__ __device__ inline uint64_t align8(uint64_t v) { return (v + 7) & ~uint64_t(7); }
+__host__ __device__ inline uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
+
+// Per-call geometry, computed on the host and passed by value.
+struct Plan {
+  int32_t ndim, dtype, domain, pad_;
+  uint64_t dims[3];             // as given (slowest-first), unused = 1
+  uint64_t nz, ny, nx, n;       // normalized to 3D
+  uint32_t tz, ty, tx, pad2_;   // tile extents
+  uint32_t gz, gy, gx, pad3_;   // tile grid
+  uint64_t n_tiles, n_chunks;
+  // blob sections with sizes known before compression
+  uint64_t off_len, off_two, off_teo, off_cb, off_exc;
+  uint64_t capacity;            // blob capacity (compress) or blob bytes (decompress)
+  double target_psnr, eb_rel;
+};
+
+// Geometry of one tile.
+struct TileGeo {
+  uint32_t a, b, c;       // tile grid coordinates (z, y, x)
+  uint32_t ez, ey, ex;    // clipped extents
+  uint64_t z0, y0, x0;    // origin in the field
+  uint32_t nt;            // points in the tile
+  uint32_t nck;           // chunks in the tile
+  uint64_t start;         // stream position of the first point
+  uint64_t chunk_base;    // index of the first chunk
+};
+
+__host__ __device__ inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+__host__ __device__ inline uint64_t chunks_of(uint64_t ez, uint64_t ey, uint64_t ex) {
+  return ceil_div(ez * ey * ex, kChunk);
+}
+
+// Closed forms: only the last tile along each axis is clipped, so every tile
+// before (a, b, c) in row-major order has full extents along the axes where
+// it precedes.
+__host__ __device__ inline TileGeo tile_geo(const Plan &P, uint64_t t) {
+  TileGeo g;
+  g.c = (uint32_t)(t % P.gx);
+  g.b = (uint32_t)((t / P.gx) % P.gy);
+  g.a = (uint32_t)(t / ((uint64_t)P.gx * P.gy));
+  g.z0 = (uint64_t)g.a * P.tz;
+  g.y0 = (uint64_t)g.b * P.ty;
+  g.x0 = (uint64_t)g.c * P.tx;
+  g.ez = (uint32_t)(g.z0 + P.tz <= P.nz ? P.tz : P.nz - g.z0);
+  g.ey = (uint32_t)(g.y0 + P.ty <= P.ny ? P.ty : P.ny - g.y0);
+  g.ex = (uint32_t)(g.x0 + P.tx <= P.nx ? P.tx : P.nx - g.x0);
+  g.nt = g.ez * g.ey * g.ex;
+  g.nck = (uint32_t)ceil_div(g.nt, kChunk);
+  g.start = g.z0 * P.ny * P.nx + (uint64_t)g.b * g.ez * P.ty * P.nx +
+            (uint64_t)g.c * g.ez * g.ey * P.tx;
+  const uint64_t ex_last = P.nx - (uint64_t)(P.gx - 1) * P.tx;
+  const uint64_t ey_last = P.ny - (uint64_t)(P.gy - 1) * P.ty;
+  auto row = [&](uint64_t ez, uint64_t ey) {
+    return (uint64_t)(P.gx - 1) * chunks_of(ez, ey, P.tx) + chunks_of(ez, ey, ex_last);
+  };
+  auto slab = [&](uint64_t ez) { return (uint64_t)(P.gy - 1) * row(ez, P.ty) + row(ez, ey_last); };
+  g.chunk_base = (uint64_t)g.a * slab(P.tz) + (uint64_t)g.b * row(g.ez, P.ty) +
+                 (uint64_t)g.c * chunks_of(g.ez, g.ey, P.tx);
+  return g;
+}
+
+// Device parameter / status block, first bytes of every workspace.
+struct DevParams {
+  uint32_t status;      // fpsz_status of the device-side pipeline
+  uint32_t is_const;
+  uint32_t range_done;  // last-block counter of the range reduction
+  uint32_t spin_fail;   // a bounded wait gave up (reported as FPSZ_E_DEVICE)
+  uint32_t overflow;    // a blob write fell beyond the capacity
+  uint32_t corrupt;     // decompress: inconsistency found
+  uint32_t ticket_q, ticket_e;
+  double mn, mx, vr, eb_rel, eb, e2, r, maxabs;
+  float e2_f, r_f;
+  uint64_t nonfinite;
+  uint64_t n_out, n_pat, n_exc, off_words, n_words, blob_bytes;
+  uint64_t checksum;
+  uint64_t verify_done;
+  double v_sse, v_max;
+  uint64_t v_over;
+  uint64_t pad_[8];
+};
+
+// ---- wave primitives (wave64) ----------------------------------------------
+__device__ inline uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+// inclusive scan over the 64 lanes
+__device__ inline uint32_t wave_incl_scan_u32(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t u = __shfl_up(v, o, 64);
+    if (lane >= o) v += u;
+  }
+  return v;
+}
+__device__ inline uint64_t wave_incl_scan_u64(uint64_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint64_t u = __shfl_up(v, o, 64);
+    if (lane >= o) v += u;
+  }
+  return v;
+}
+
+// Block-wide exclusive scan of one u32 per thread (blockDim.x == 256).
+// `scratch` holds >= 4 u32.  Returns the exclusive prefix; *total the sum.
+__device__ inline uint32_t block_excl_scan_u32(uint32_t v, uint32_t *scratch, uint32_t *total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t inc = wave_incl_scan_u32(v);
+  if (lane == 63) scratch[wv] = inc;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; w++) {
+    uint32_t s = scratch[w];
+    if (w < wv) base += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + inc - v;
+}
+
+// Agent-scope atomics for cross-workgroup flags (coherent across XCDs).
+__device__ inline uint64_t ld_agent(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_agent(uint64_t *p, uint64_t v) {
+  __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Decoupled look-back over per-tile counts in ticket order.  state[t] holds
+// (flag << 62) | value; flag 1 = this tile's count, 2 = inclusive prefix.
+// Called by all 64 lanes of one wave; returns the exclusive prefix of tile t.
+// The wait is bounded: after `max_spins` rounds it flags *fail and returns 0
+// so that every wave exits.
+constexpr uint64_t kLbAgg = 1ull << 62, kLbInc = 2ull << 62, kLbMask = kLbAgg - 1;
+__device__ inline uint64_t lookback_excl(uint64_t *state, uint64_t t, uint64_t agg,
+                                         uint32_t *fail) {
+  const int lane = threadIdx.x & 63;
+  if (t == 0) {
+    if (lane == 0) st_agent(&state[0], kLbInc | agg);
+    return 0;
+  }
+  if (lane == 0) st_agent(&state[t], kLbAgg | agg);
+  uint64_t excl = 0;
+  int64_t base = (int64_t)t - 1;
+  uint32_t spins = 0;
+  while (true) {
+    const int64_t j = base - lane;
+    const uint64_t v = j >= 0 ? ld_agent(&state[j]) : kLbInc;
+    const uint64_t flag = v >> 62;
+    const uint64_t empty = __ballot(flag == 0);
+    const uint64_t incl = __ballot(flag == 2);
+    const int first_incl = incl ? __ffsll((long long)incl) - 1 : 64;
+    const uint64_t upto = first_incl >= 63 ? ~0ull : ((2ull << first_incl) - 1);
+    if (empty & upto) {
+      if (++spins > (1u << 24)) {
+        if (lane == 0) atomicOr(fail, 1u);
+        return 0;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    const uint64_t val = (lane <= first_incl && j >= 0) ? (v & kLbMask) : 0;
+    excl += wave_sum_u64(val);
+    if (first_incl < 64) break;
+    base -= 64;
+  }
+  if (lane == 0) st_agent(&state[t], kLbInc | (excl + agg));
+  return excl;
+}
+
+// Symbol of a residual code (i16 stream value): returns the symbol; *ne and
+// *ev receive the raw-bit count and value of an escape class.
+__device__ inline int sym_of_code(int32_t d, int *ne, uint32_t *ev) {
+  if (d == -32768) { *ne = 0; *ev = 0; return 0; }
+  const int32_t a = d < 0 ? -d : d;
+  if (a <= 511) { *ne = 0; *ev = 0; return d + 512; }
+  const int k = 31 - __clz(a);
+  *ne = k;
+  *ev = (uint32_t)(a - (1 << k));
+  return 1024 + 2 * (k - 9) + (d < 0 ? 1 : 0);
+}
+
+__device__ inline uint64_t mix64(uint32_t w, uint64_t j) {
+  uint64_t h = (uint64_t)w * 0x9E3779B97F4A7C15ull + j * 0xC2B2AE3D27D4EB4Full;
+  h ^= h >> 31;
+  h *= 0xBF58476D1CE4E5B9ull;
+  h ^= h >> 29;
+  return h;
+}
+
+// Canonical codes from lengths (shared with the decoder-table kernel):
+// codes of each length are consecutive in symbol order, and the first code
+// of length l is (first(l-1) + count(l-1)) << 1.
+__device__ inline void canonical_from_lengths(const uint8_t *lens, uint32_t *code_out, uint32_t *lcount,
+                                       uint32_t *lfirst, uint32_t *lbase, uint16_t *sorted) {
+  const int tid = threadIdx.x;
+  if (tid <= kLMax + 1) lcount[tid] = 0;
+  __syncthreads();
+  for (int s = tid; s < kNSym; s += blockDim.x)
+    if (lens[s]) atomicAdd(&lcount[lens[s]], 1u);
+  __syncthreads();
+  if (tid == 0) {
+    // lcount[0] stays 0: unused symbols are not counted
+    uint32_t c = 0, base = 0;
+    lfirst[0] = 0;
+    lbase[0] = 0;
+    for (int l = 1; l <= kLMax; l++) {
+      c = (c + lcount[l - 1]) << 1;
+      lfirst[l] = c;
+      lbase[l] = base;
+      base += lcount[l];
+    }
+  }
+  __syncthreads();
+  for (int s = tid; s < kNSym; s += blockDim.x) {
+    const int l = lens[s];
+    if (!l) { if (code_out) code_out[s] = 0; continue; }
+    uint32_t rank = 0;
+    for (int k = 0; k < s; k++) rank += (lens[k] == l);
+    if (code_out) code_out[s] = lfirst[l] + rank;
+    if (sorted) sorted[lbase[l] + rank] = (uint16_t)s;
+  }
+  __syncthreads();
+}
+
+// ---- launchers (defined in the .hip files) ---------------------------------
+struct CompressWs {
+  DevParams *P;
+  void *range_part;
+  uint32_t *hist;
+  uint8_t *code_len;
+  uint32_t *code;
+  uint64_t *exc_state;
+  uint64_t *word_state;
+  int16_t *codes;
+  uint64_t zero_bytes;  // bytes from P to clear before a call
+};
+
+struct DecompressWs {
+  DevParams *P;
+  uint32_t *lut;       // 2048 entries: (symbol << 5) | length, 0 = long/invalid
+  uint32_t *ltab;      // first[19], count[19], base[19]
+  uint16_t *sorted;    // symbols in canonical order
+  uint32_t *fz, *fy, *fx;  // tile-face projection arrays (GLOBAL domain)
+  uint64_t zero_bytes;
+};
+
+hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t s);
+hipError_t launch_compress(const Plan &P, const void *x, const CompressWs &W, uint8_t *blob,
+                           hipStream_t s);
+hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const DecompressWs &W,
+                                  uint64_t off_words, uint64_t n_words, uint64_t n_exc, double e2,
+                                  float e2_f, void *out, hipStream_t s);
+hipError_t launch_const_fill_bits(const Plan &P, uint64_t bits, void *out, hipStream_t s);
+hipError_t launch_checksum(const uint8_t *blob, uint64_t bytes, DevParams *dp, hipStream_t s);
+hipError_t launch_verify(const void *x, const void *y, uint64_t n, int dtype, double eb,
+                         DevParams *P, void *part, hipStream_t s);
+
+}  // namespace fpsz

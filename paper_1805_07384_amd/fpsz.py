@@ -1,0 +1,300 @@
+"""Python binding of the gfx950 library ``libfpsz.so`` (C ABI in include/fpsz.h).
+
+Argument marshalling only: every step of compression, decompression and the
+PSNR check runs in the library's HIP kernels.  torch provides device memory
+and streams.  There is no fallback: if the library is missing or the device
+is not gfx950 the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfpsz.so")
+
+OK, E_INVALID_ARG, E_NONFINITE, E_RANGE, E_CORRUPT, E_CAPACITY, E_NOMEM, E_DEVICE, E_UNSUPPORTED = range(9)
+F32, F64 = 0, 1
+GLOBAL, TILE = 0, 1
+HDR_BYTES = 256
+
+
+class FpszError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("fpsz status %d: %s" % (status, msg))
+        self.status = status
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("target_psnr", ctypes.c_double), ("eb_rel", ctypes.c_double), ("vr", ctypes.c_double),
+        ("eb", ctypes.c_double), ("min", ctypes.c_double), ("max", ctypes.c_double),
+        ("n", ctypes.c_uint64), ("n_outliers", ctypes.c_uint64), ("n_patches", ctypes.c_uint64),
+        ("n_exceptions", ctypes.c_uint64), ("blob_bytes", ctypes.c_uint64),
+        ("bits_per_value", ctypes.c_double), ("is_const", ctypes.c_uint32),
+        ("domain", ctypes.c_uint32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("sse", ctypes.c_double), ("mse", ctypes.c_double), ("psnr", ctypes.c_double),
+                ("max_abs_err", ctypes.c_double), ("n_over_eb", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_vp = ctypes.c_void_p
+
+# name -> (restype, argtypes); every symbol declared in include/fpsz.h
+SIGNATURES = {
+    "fpsz_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp)]),
+    "fpsz_destroy": (None, [_vp]),
+    "fpsz_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "fpsz_last_error": (ctypes.c_char_p, [_vp]),
+    "fpsz_version": (ctypes.c_char_p, []),
+    "fpsz_eb_rel": (ctypes.c_int, [ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
+    "fpsz_compress_workspace_bytes": (ctypes.c_int, [ctypes.c_int, _u64p, ctypes.c_int, _u64p]),
+    "fpsz_decompress_workspace_bytes": (ctypes.c_int, [ctypes.c_int, _u64p, ctypes.c_int, _u64p]),
+    "fpsz_verify_workspace_bytes": (ctypes.c_int, [ctypes.c_uint64, _u64p]),
+    "fpsz_compress_bound": (ctypes.c_int, [ctypes.c_int, _u64p, ctypes.c_int, _u64p]),
+    "fpsz_compress": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _u64p, ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_int, _vp, ctypes.c_uint64, _vp, ctypes.c_uint64,
+                                     _u64p, ctypes.POINTER(Info), _vp]),
+    "fpsz_blob_header": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), _u64p,
+                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(Info)]),
+    "fpsz_decompress": (ctypes.c_int, [_vp, _vp, ctypes.c_uint64, _vp, ctypes.c_uint64, _vp,
+                                       ctypes.c_uint64, _vp]),
+    "fpsz_verify": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_uint64, ctypes.c_int, ctypes.c_double,
+                                   ctypes.c_double, _vp, ctypes.c_uint64, ctypes.POINTER(Stats), _vp]),
+    "fpsz_compress_workspace_offset": (ctypes.c_int, [ctypes.c_int, _u64p, ctypes.c_int, ctypes.c_int,
+                                                      _u64p]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libfpsz.so and bind every exported entry point.  Raises if the
+    library was not built (run ``__graft_entry__.build()``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise FpszError(E_UNSUPPORTED, "libfpsz.so is not built: %s" % path)
+        L = ctypes.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _dims(shape):
+    d = [int(s) for s in shape] + [1] * max(0, 3 - len(shape))
+    return (ctypes.c_uint64 * len(d))(*d)
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError("fpsz compresses float32 or float64 fields")
+
+
+def eb_rel(psnr: float) -> float:
+    """Eq. 7 (host): eb_rel = sqrt(3) * 10^(-PSNR/20)."""
+    out = ctypes.c_double()
+    st = load_library().fpsz_eb_rel(float(psnr), ctypes.byref(out))
+    if st != OK:
+        raise FpszError(st, "eb_rel")
+    return out.value
+
+
+def _ws_bytes(fn, ndim, shape, dt) -> int:
+    out = ctypes.c_uint64()
+    st = fn(ndim, _dims(shape), dt, ctypes.byref(out))
+    if st != OK:
+        raise FpszError(st, "workspace size for shape %s" % (tuple(shape),))
+    return out.value
+
+
+def compress_workspace_bytes(shape, dtype=torch.float32) -> int:
+    dt = F32 if dtype == torch.float32 else F64
+    return _ws_bytes(load_library().fpsz_compress_workspace_bytes, len(shape), shape, dt)
+
+
+def decompress_workspace_bytes(shape, dtype=torch.float32) -> int:
+    dt = F32 if dtype == torch.float32 else F64
+    return _ws_bytes(load_library().fpsz_decompress_workspace_bytes, len(shape), shape, dt)
+
+
+def compress_bound(shape, dtype=torch.float32) -> int:
+    dt = F32 if dtype == torch.float32 else F64
+    return _ws_bytes(load_library().fpsz_compress_bound, len(shape), shape, dt)
+
+
+def workspace_offset(shape, dtype, which: int) -> int:
+    dt = F32 if dtype == torch.float32 else F64
+    out = ctypes.c_uint64()
+    st = load_library().fpsz_compress_workspace_offset(len(shape), _dims(shape), dt, which,
+                                                       ctypes.byref(out))
+    if st != OK:
+        raise FpszError(st, "workspace offset")
+    return out.value
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+@dataclass
+class Header:
+    ndim: int
+    shape: tuple
+    dtype: torch.dtype
+    info: dict
+
+
+def parse_header(blob_host: bytes) -> Header:
+    b = bytes(blob_host[:HDR_BYTES])
+    buf = ctypes.create_string_buffer(b, len(b))
+    nd = ctypes.c_int()
+    dims = (ctypes.c_uint64 * 3)()
+    dt = ctypes.c_int()
+    info = Info()
+    st = load_library().fpsz_blob_header(buf, len(b), ctypes.byref(nd), dims, ctypes.byref(dt),
+                                         ctypes.byref(info))
+    if st != OK:
+        raise FpszError(st, "blob header")
+    return Header(nd.value, tuple(int(dims[i]) for i in range(nd.value)),
+                  torch.float32 if dt.value == F32 else torch.float64, info.as_dict())
+
+
+class Context:
+    """One library context on one HIP device."""
+
+    def __init__(self, device: int | None = None):
+        self.lib = load_library()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        h = _vp()
+        st = self.lib.fpsz_create(self.device, ctypes.byref(h))
+        if st != OK:
+            raise FpszError(st, "fpsz_create(%d): %s" % (self.device,
+                                                         self.lib.fpsz_status_str(st).decode()))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.fpsz_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self, st, what):
+        msg = self.lib.fpsz_last_error(self.handle)
+        return FpszError(st, "%s: %s" % (what, msg.decode() if msg else ""))
+
+    # -- raw entry points on preallocated buffers ---------------------------
+    def compress_into(self, x: torch.Tensor, psnr: float, workspace: torch.Tensor,
+                      blob: torch.Tensor, domain: int = GLOBAL, stream=None):
+        """Compress x into the device buffer ``blob``; returns (status,
+        blob_bytes, Info).  Status CAPACITY reports the size needed."""
+        assert x.is_contiguous() and x.is_cuda
+        nb = ctypes.c_uint64()
+        info = Info()
+        st = self.lib.fpsz_compress(self.handle, x.data_ptr(), x.dim(), _dims(x.shape),
+                                    _dtype_code(x), float(psnr), int(domain), workspace.data_ptr(),
+                                    workspace.numel() * workspace.element_size(), blob.data_ptr(),
+                                    blob.numel(), ctypes.byref(nb), ctypes.byref(info),
+                                    _stream(stream))
+        return st, nb.value, info
+
+    def decompress_into(self, blob: torch.Tensor, nbytes: int, workspace: torch.Tensor,
+                        out: torch.Tensor, stream=None) -> int:
+        return self.lib.fpsz_decompress(self.handle, blob.data_ptr(), int(nbytes), workspace.data_ptr(),
+                                         workspace.numel() * workspace.element_size(), out.data_ptr(),
+                                         out.numel() * out.element_size(), _stream(stream))
+
+    def verify_into(self, x: torch.Tensor, y: torch.Tensor, vr: float, eb: float,
+                    workspace: torch.Tensor, stream=None):
+        stats = Stats()
+        st = self.lib.fpsz_verify(self.handle, x.data_ptr(), y.data_ptr(), x.numel(),
+                                  _dtype_code(x), float(vr), float(eb), workspace.data_ptr(),
+                                  workspace.numel() * workspace.element_size(),
+                                  ctypes.byref(stats), _stream(stream))
+        return st, stats
+
+    # -- convenience API ------------------------------------------------------
+    def compress(self, x: torch.Tensor, psnr: float, domain: int = GLOBAL, stream=None):
+        """Returns (blob: uint8 device tensor of exactly the blob's size, info dict)."""
+        x = x.contiguous()
+        ws = torch.empty(compress_workspace_bytes(x.shape, x.dtype), dtype=torch.uint8,
+                         device=x.device)
+        cap = x.numel() * x.element_size() + (1 << 20) + x.numel() // 8
+        blob = torch.empty(cap, dtype=torch.uint8, device=x.device)
+        st, nb, info = self.compress_into(x, psnr, ws, blob, domain, stream)
+        if st == E_CAPACITY and nb > cap:
+            blob = torch.empty(nb, dtype=torch.uint8, device=x.device)
+            st, nb, info = self.compress_into(x, psnr, ws, blob, domain, stream)
+        if st != OK:
+            raise self._err(st, "fpsz_compress")
+        return blob[:nb], info.as_dict()
+
+    def decompress(self, blob: torch.Tensor, stream=None) -> torch.Tensor:
+        hdr = parse_header(blob[:HDR_BYTES].cpu().numpy().tobytes())
+        out = torch.empty(hdr.shape, dtype=hdr.dtype, device=blob.device)
+        ws = torch.empty(decompress_workspace_bytes(hdr.shape, hdr.dtype), dtype=torch.uint8,
+                         device=blob.device)
+        st = self.decompress_into(blob, blob.numel(), ws, out, stream)
+        if st != OK:
+            raise self._err(st, "fpsz_decompress")
+        return out
+
+    def verify(self, x: torch.Tensor, y: torch.Tensor, vr: float, eb: float, stream=None) -> dict:
+        ws_n = ctypes.c_uint64()
+        self.lib.fpsz_verify_workspace_bytes(x.numel(), ctypes.byref(ws_n))
+        ws = torch.empty(ws_n.value, dtype=torch.uint8, device=x.device)
+        st, stats = self.verify_into(x.contiguous(), y.contiguous(), vr, eb, ws, stream)
+        if st != OK:
+            raise self._err(st, "fpsz_verify")
+        return stats.as_dict()
+
+
+_default = {}
+
+
+def default_context(device: int | None = None) -> Context:
+    if device is None:
+        device = torch.cuda.current_device()
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def compress(x: torch.Tensor, psnr: float, domain: int = GLOBAL):
+    return default_context(x.device.index).compress(x, psnr, domain)
+
+
+def decompress(blob: torch.Tensor) -> torch.Tensor:
+    return default_context(blob.device.index).decompress(blob)
+
+
+def verify(x: torch.Tensor, y: torch.Tensor, vr: float, eb: float) -> dict:
+    return default_context(x.device.index).verify(x, y, vr, eb)

@@ -1,0 +1,205 @@
+"""GPU (gfx950) library vs the CPU oracle, through the C ABI.
+
+Bar: the blob (header, code lengths, tile/chunk tables, exception list,
+bitstream) and the decompressed field are bit-exact; the float64 Eq. 4
+statistics agree to 1e-9 relative.  Every case prints its name first so a
+failing run names it.
+"""
+import numpy as np
+import pytest
+
+from paper_1805_07384_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1805_07384_amd import fpsz
+    return fpsz.Context(0)
+
+
+def _bits(a: np.ndarray) -> np.ndarray:
+    return a.view(np.uint32 if a.dtype == np.float32 else np.uint64)
+
+
+def _gpu_compress(ctx, x: np.ndarray, psnr: float, domain: int):
+    from paper_1805_07384_amd import fpsz
+    xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    ws = torch.empty(fpsz.compress_workspace_bytes(x.shape, xt.dtype), dtype=torch.uint8,
+                     device="cuda")
+    ws.fill_(0xA5)  # garbage: the library must not rely on a clean workspace
+    cap = fpsz.compress_bound(x.shape, xt.dtype)
+    blob = torch.full((cap,), 0x5A, dtype=torch.uint8, device="cuda")
+    st, nb, info = ctx.compress_into(xt, psnr, ws, blob, domain)
+    torch.cuda.synchronize()
+    return st, blob[:nb], info.as_dict(), ws, xt
+
+
+def _diagnose(ctx, orc, x, psnr, domain, ws, gblob: bytes, oblob: bytes):
+    """Localise a blob mismatch through the workspace intermediates."""
+    from paper_1805_07384_amd import fpsz
+    _, t = orc.compress(x, psnr, domain=domain, trace=True)
+    msgs = []
+    hg, ho = orc.header(gblob) if len(gblob) >= 256 else {}, orc.header(oblob)
+    for k in ho:
+        if hg.get(k) != ho[k]:
+            msgs.append("header %s: gpu %r oracle %r" % (k, hg.get(k), ho[k]))
+    wsn = ws.cpu().numpy()
+    o = fpsz.workspace_offset(x.shape, torch.float32 if x.dtype == np.float32 else torch.float64, 1)
+    hist = wsn[o:o + 4 * 1036].view(np.uint32)
+    if not np.array_equal(hist, t["hist"]):
+        d = np.nonzero(hist != t["hist"])[0]
+        msgs.append("histogram differs at %d bins, first %s" % (len(d), d[:5]))
+    o = fpsz.workspace_offset(x.shape, torch.float32 if x.dtype == np.float32 else torch.float64, 2)
+    ln = wsn[o:o + 1036]
+    if not np.array_equal(ln, t["code_len"]):
+        msgs.append("code lengths differ")
+    o = fpsz.workspace_offset(x.shape, torch.float32 if x.dtype == np.float32 else torch.float64, 4)
+    c16 = wsn[o:o + 2 * x.size].view(np.int16)
+    if not np.array_equal(c16, t["code16"]):
+        d = np.nonzero(c16 != t["code16"])[0]
+        msgs.append("residual codes differ at %d positions, first %s gpu %s oracle %s"
+                    % (len(d), d[:5], c16[d[:5]], t["code16"][d[:5]]))
+    n = min(len(gblob), len(oblob))
+    gb = np.frombuffer(gblob[:n], np.uint8)
+    ob = np.frombuffer(oblob[:n], np.uint8)
+    d = np.nonzero(gb != ob)[0]
+    if len(d):
+        msgs.append("first differing byte %d (of %d / %d)" % (d[0], len(gblob), len(oblob)))
+    return "; ".join(msgs)
+
+
+def _parity(ctx, orc, x, psnr, domain=0, check_stats=True):
+    print("case shape=%s dtype=%s psnr=%s domain=%d" % (x.shape, x.dtype, psnr, domain), flush=True)
+    ob, ot = orc.compress(x, psnr, domain=domain, trace=True)
+    st, blob, info, ws, xt = _gpu_compress(ctx, x, psnr, domain)
+    assert st == 0, "gpu compress status %d" % st
+    gb = blob.cpu().numpy().tobytes()
+    if gb != ob:
+        pytest.fail("blob mismatch: " + _diagnose(ctx, orc, x, psnr, domain, ws, gb, ob))
+    assert info["blob_bytes"] == len(ob)
+    assert info["n_patches"] == ot["n_patches"] and info["n_outliers"] == ot["n_outliers"]
+    assert info["eb"] == ot["eb"] and info["vr"] == ot["vr"]
+    y = ctx.decompress(blob)
+    oy = orc.decompress(ob)
+    yn = y.cpu().numpy()
+    assert yn.shape == x.shape
+    assert np.array_equal(_bits(yn), _bits(oy)), "decompressed field differs"
+    if check_stats:
+        gs = ctx.verify(xt, y, info["vr"], info["eb"])
+        os_ = orc.stats(x, oy, ot["vr"], ot["eb"])
+        assert gs["n_over_eb"] == 0 == os_["n_over_eb"]
+        assert gs["max_abs_err"] == os_["max_abs_err"]
+        if os_["sse"] > 0:
+            assert abs(gs["sse"] - os_["sse"]) <= 1e-9 * os_["sse"]
+            assert abs(gs["psnr"] - os_["psnr"]) <= 1e-9 * abs(os_["psnr"])
+    return info, y
+
+
+SHAPES = [(20000,), (8192,), (8193,), (3, 5), (150, 300), (64, 128), (65, 129), (129, 257),
+          (16, 16, 32), (17, 17, 33), (40, 37, 70), (1, 5, 8200), (2, 3, 4), (33, 17, 65)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_parity_shapes(ctx, orc, shape, dt):
+    x = (synth.grf_numpy(shape, -3.0, 5) * 7.0 + 2.0).astype(dt)
+    for domain in (0, 1):
+        _parity(ctx, orc, x, 80.0, domain)
+
+
+@pytest.mark.parametrize("psnr", [20.0, 40.0, 60.0, 100.0, 120.0])
+def test_parity_psnr_sweep(ctx, orc, psnr):
+    x = synth.field_3d_lognormal(shape=(48, 40, 70), seed=2)
+    _parity(ctx, orc, x, psnr, 0)
+    _parity(ctx, orc, x.astype(np.float64), psnr, 0)
+
+
+def test_parity_outliers_and_patches(ctx, orc):
+    x = synth.field_3d_spiky_f64(shape=(40, 64, 64), seed=5)
+    info, _ = _parity(ctx, orc, x, 100.0, 0)
+    assert info["n_outliers"] > 0
+    info, _ = _parity(ctx, orc, x, 100.0, 1)
+    xf = synth.field_2d_grf(300, 200, seed=3)
+    info, _ = _parity(ctx, orc, xf, 120.0, 0)
+    assert info["n_patches"] > 0
+    # float64 at 150 dB: deep escapes and 2-record patches
+    _parity(ctx, orc, xf.astype(np.float64) * 1.0001, 150.0, 0)
+
+
+def test_parity_config1_full_size(ctx, orc):
+    # 2D float32 512 x 512, spectrum k^-3, range [-50, 50], 80 dB
+    x = synth.field_2d_grf(512, 512, seed=1)
+    info, _ = _parity(ctx, orc, x, 80.0, 0)
+    assert abs(info["eb"] - 100 * orc.eb_rel(80.0)) < 1e-12
+
+
+def test_constant_and_tiny(ctx, orc):
+    from paper_1805_07384_amd import fpsz
+    for shape in [(1,), (7,), (3, 3), (2, 2, 2)]:
+        x = np.full(shape, 3.25, dtype=np.float32)
+        print("case const", shape, flush=True)
+        ob, _ = orc.compress(x, 80.0)
+        st, blob, info, ws, xt = _gpu_compress(ctx, x, 80.0, 0)
+        assert st == 0 and info["is_const"] == 1
+        assert blob.cpu().numpy().tobytes() == ob
+        y = ctx.decompress(blob)
+        assert np.array_equal(y.cpu().numpy(), x)
+    _parity(ctx, orc, np.array([1.0, 2.0], dtype=np.float32), 60.0, 0)
+    _parity(ctx, orc, np.array([[0.0], [-1.0]], dtype=np.float64), 60.0, 0)
+
+
+def test_error_statuses(ctx):
+    from paper_1805_07384_amd import fpsz
+    print("case errors", flush=True)
+    x = np.linspace(0, 1, 5000, dtype=np.float32)
+    x[1234] = np.nan
+    st, *_ = _gpu_compress(ctx, x, 80.0, 0)
+    assert st == fpsz.E_NONFINITE
+    x[1234] = np.inf
+    st, *_ = _gpu_compress(ctx, x, 80.0, 0)
+    assert st == fpsz.E_NONFINITE
+    st, *_ = _gpu_compress(ctx, np.linspace(0, 1, 5000, dtype=np.float32), 200.0, 0)
+    assert st == fpsz.E_RANGE
+    # capacity: the exact size is reported
+    xs = synth.field_2d_grf(100, 100, seed=8)
+    xt = torch.from_numpy(xs).cuda()
+    ws = torch.empty(fpsz.compress_workspace_bytes(xs.shape), dtype=torch.uint8, device="cuda")
+    big = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    st, need, _ = ctx.compress_into(xt, 80.0, ws, big, 0)
+    assert st == 0
+    small = torch.empty(need - 8, dtype=torch.uint8, device="cuda")
+    st, need2, _ = ctx.compress_into(xt, 80.0, ws, small, 0)
+    assert st == fpsz.E_CAPACITY and need2 == need
+
+
+def test_corrupt_blob_detected(ctx, orc):
+    from paper_1805_07384_amd import fpsz
+    print("case corrupt", flush=True)
+    x = synth.field_2d_grf(200, 300, seed=4)
+    blob, info = ctx.compress(torch.from_numpy(x).cuda(), 60.0)
+    good = blob.cpu().numpy()
+    rng = np.random.default_rng(7)
+    for _ in range(16):
+        bad = good.copy()
+        i = int(rng.integers(256, len(bad)))
+        bad[i] ^= np.uint8(1 << int(rng.integers(0, 8)))
+        with pytest.raises(fpsz.FpszError) as e:
+            ctx.decompress(torch.from_numpy(bad).cuda())
+        assert e.value.status == fpsz.E_CORRUPT
+    with pytest.raises(fpsz.FpszError):
+        ctx.decompress(torch.from_numpy(good[:-8].copy()).cuda())
+
+
+def test_deterministic_repeat(ctx):
+    print("case determinism", flush=True)
+    x = torch.from_numpy(synth.field_3d_lognormal(shape=(64, 64, 64), seed=3)).cuda()
+    a, _ = ctx.compress(x, 100.0)
+    for _ in range(3):
+        b, _ = ctx.compress(x, 100.0)
+        assert torch.equal(a, b)
