@@ -153,6 +153,18 @@ fpsz_status fpsz_verify(fpsz_ctx *ctx, const void *orig_dev, const void *recon_d
                         fpsz_dtype dtype, double vr, double eb, void *workspace_dev,
                         uint64_t workspace_bytes, fpsz_stats *out, void *stream);
 
+/* Per-stage timing.  When enabled, each call records HIP events on its
+ * stream between its kernels (a small cost); after the call returns,
+ * fpsz_last_stage_times copies up to `max` (stage name, milliseconds) pairs of
+ * that call and sets *count to the number recorded.  Enabling creates the
+ * events once (DEVICE on failure). */
+typedef struct {
+  char name[24];
+  double ms;
+} fpsz_stage_time;
+fpsz_status fpsz_set_profiling(fpsz_ctx *ctx, int enable);
+fpsz_status fpsz_last_stage_times(const fpsz_ctx *ctx, fpsz_stage_time *out, int max, int *count);
+
 /* Offsets (bytes) of intermediates inside a compress workspace, for tests
  * and diagnostics: which = 0 parameter block, 1 histogram (u32[1036]),
  * 2 code lengths (u8[1036]), 3 codewords (u32[1036]), 4 residual codes in

@@ -16,6 +16,11 @@ struct fpsz_ctx {
   int device;
   char err[512];
   DevParams *host;  // pinned read-back buffer
+  bool profiling;
+  bool events_made;
+  Timer timer;
+  int n_stages;
+  fpsz_stage_time stages[Timer::kMax];
 };
 
 namespace {
@@ -156,6 +161,28 @@ fpsz_status hip_fail(fpsz_ctx *c, hipError_t e, const char *what) {
   return fail(c, FPSZ_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+Timer *timer_begin(fpsz_ctx *c) {
+  c->timer.n = 0;
+  c->timer.on = c->profiling && c->events_made;
+  c->n_stages = 0;
+  return &c->timer;
+}
+
+// after the stream has been synchronized: stage i spans marks i-1 .. i
+void timer_collect(fpsz_ctx *c) {
+  Timer &t = c->timer;
+  c->n_stages = 0;
+  for (int i = 1; i < t.n; i++) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.ev[i - 1], t.ev[i]) != hipSuccess) ms = -1.f;
+    fpsz_stage_time &st = c->stages[c->n_stages++];
+    memset(st.name, 0, sizeof(st.name));
+    strncpy(st.name, t.names[i], sizeof(st.name) - 1);
+    st.ms = ms;
+  }
+  t.on = false;
+}
+
 }  // namespace
 
 extern "C" {
@@ -204,7 +231,32 @@ fpsz_status fpsz_create(int hip_device, fpsz_ctx **out) {
 void fpsz_destroy(fpsz_ctx *ctx) {
   if (!ctx) return;
   if (ctx->host) (void)hipHostFree(ctx->host);
+  if (ctx->events_made)
+    for (int i = 0; i < Timer::kMax; i++) (void)hipEventDestroy(ctx->timer.ev[i]);
   delete ctx;
+}
+
+fpsz_status fpsz_set_profiling(fpsz_ctx *ctx, int enable) {
+  if (!ctx) return FPSZ_E_INVALID_ARG;
+  if (enable && !ctx->events_made) {
+    DeviceGuard g(ctx->device);
+    for (int i = 0; i < Timer::kMax; i++)
+      if (hipEventCreate(&ctx->timer.ev[i]) != hipSuccess) {
+        for (int j = 0; j < i; j++) (void)hipEventDestroy(ctx->timer.ev[j]);
+        return fail(ctx, FPSZ_E_DEVICE, "hipEventCreate failed");
+      }
+    ctx->events_made = true;
+  }
+  ctx->profiling = enable != 0;
+  return FPSZ_OK;
+}
+
+fpsz_status fpsz_last_stage_times(const fpsz_ctx *ctx, fpsz_stage_time *out, int max, int *count) {
+  if (!ctx || !count || (max > 0 && !out)) return FPSZ_E_INVALID_ARG;
+  const int n = ctx->n_stages < max ? ctx->n_stages : max;
+  for (int i = 0; i < n; i++) out[i] = ctx->stages[i];
+  *count = ctx->n_stages;
+  return FPSZ_OK;
 }
 
 fpsz_status fpsz_eb_rel(double target_psnr, double *eb_rel) {
@@ -314,12 +366,14 @@ fpsz_status fpsz_compress(fpsz_ctx *ctx, const void *field_dev, int ndim, const 
   W.codes = (int16_t *)(ws + L.off_codes);
   W.zero_bytes = L.zero;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = launch_compress(P, field_dev, W, (uint8_t *)blob_dev, s);
+  Timer *tm = timer_begin(ctx);
+  hipError_t e = launch_compress(P, field_dev, W, (uint8_t *)blob_dev, s, tm);
   if (e != hipSuccess) return hip_fail(ctx, e, "compress launch");
   e = hipMemcpyAsync(ctx->host, W.P, sizeof(DevParams), hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "read-back");
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(ctx, e, "compress");
+  timer_collect(ctx);
   const DevParams &D = *ctx->host;
   if (info) {
     memset(info, 0, sizeof(*info));
@@ -466,12 +520,14 @@ fpsz_status fpsz_decompress(fpsz_ctx *ctx, const void *blob_dev, uint64_t blob_b
   W.fy = (uint32_t *)(ws + L.off_fy);
   W.fx = (uint32_t *)(ws + L.off_fx);
   W.zero_bytes = align256(sizeof(DevParams));
+  Timer *tm = timer_begin(ctx);
   e = launch_decompress_args(P, (const uint8_t *)blob_dev, W, off_words, n_words, n_exc, e2, e2_f,
-                             field_out_dev, s);
+                             field_out_dev, s, tm);
   if (e != hipSuccess) return hip_fail(ctx, e, "decompress launch");
   e = hipMemcpyAsync(ctx->host, W.P, sizeof(DevParams), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(ctx, e, "decompress");
+  timer_collect(ctx);
   if (ctx->host->corrupt) return fail(ctx, FPSZ_E_CORRUPT, "blob failed a consistency check");
   return FPSZ_OK;
 }
@@ -492,10 +548,12 @@ fpsz_status fpsz_verify(fpsz_ctx *ctx, const void *orig_dev, const void *recon_d
   hipStream_t s = (hipStream_t)stream;
   DevParams *dp = (DevParams *)workspace_dev;
   void *part = (uint8_t *)workspace_dev + align256(sizeof(DevParams));
-  hipError_t e = launch_verify(orig_dev, recon_dev, n, dtype, eb, dp, part, s);
+  Timer *tm = timer_begin(ctx);
+  hipError_t e = launch_verify(orig_dev, recon_dev, n, dtype, eb, dp, part, s, tm);
   if (e == hipSuccess) e = hipMemcpyAsync(ctx->host, dp, sizeof(DevParams), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(ctx, e, "verify");
+  timer_collect(ctx);
   const DevParams &D = *ctx->host;
   out->sse = D.v_sse;
   out->mse = D.v_sse / (double)n;

@@ -843,32 +843,39 @@ static void launch_quant(const Plan &P, const T *x, const CompressWs &W, uint8_t
 
 template <typename T>
 static void launch_compress_t(const Plan &P, const T *x, const CompressWs &W, uint8_t *blob,
-                              hipStream_t s) {
+                              hipStream_t s, Timer *tm) {
   const uint64_t want = P.n / (kBlock * 16) + 1;
   const uint32_t rgrid = (uint32_t)(want < (uint64_t)kRangeBlocks ? want : kRangeBlocks);
   hipLaunchKernelGGL(k_range<T>, dim3(rgrid), dim3(kBlock), 0, s, x, P, W.P,
                      (uint64_t *)W.range_part);
+  tm->mark(s, "range");
   if (P.ndim == 1) launch_quant<T, 1>(P, x, W, blob, s);
   else if (P.ndim == 2) launch_quant<T, 2>(P, x, W, blob, s);
   else launch_quant<T, 3>(P, x, W, blob, s);
+  tm->mark(s, "quant");
   hipLaunchKernelGGL(k_codebook, dim3(1), dim3(kCbThreads), 0, s, P, W.P, W.hist, W.code_len,
                      W.code, W.exc_state, blob);
+  tm->mark(s, "codebook");
   const uint32_t egrid = (uint32_t)(P.n_tiles < 2048 ? P.n_tiles : 2048);
   hipLaunchKernelGGL(k_encode, dim3(egrid), dim3(kBlock), 0, s, P, W.P, W.codes, W.code_len,
                      W.code, W.word_state, blob);
+  tm->mark(s, "encode");
   hipLaunchKernelGGL(k_header, dim3(1), dim3(kBlock), 0, s, P, W.P, blob);
   const uint64_t cw = P.capacity / 4 / kBlock + 1;
   const uint32_t cgrid = (uint32_t)(cw < 1024 ? cw : 1024);
   hipLaunchKernelGGL(k_checksum, dim3(cgrid), dim3(kBlock), 0, s, blob, (uint64_t)0, W.P, 1);
   hipLaunchKernelGGL(k_checksum_store, dim3(1), dim3(1), 0, s, W.P, blob);
+  tm->mark(s, "header+checksum");
 }
 
 hipError_t launch_compress(const Plan &P, const void *x, const CompressWs &W, uint8_t *blob,
-                           hipStream_t s) {
+                           hipStream_t s, Timer *tm) {
+  tm->mark(s, "begin");
   hipError_t e = launch_fill_zero(W.P, W.zero_bytes, s);
   if (e != hipSuccess) return e;
-  if (P.dtype == FPSZ_F32) launch_compress_t<float>(P, (const float *)x, W, blob, s);
-  else launch_compress_t<double>(P, (const double *)x, W, blob, s);
+  tm->mark(s, "init");
+  if (P.dtype == FPSZ_F32) launch_compress_t<float>(P, (const float *)x, W, blob, s, tm);
+  else launch_compress_t<double>(P, (const double *)x, W, blob, s, tm);
   return hipGetLastError();
 }
 

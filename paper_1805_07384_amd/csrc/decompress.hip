@@ -462,29 +462,36 @@ __global__ void k_csum_check(const uint8_t *__restrict__ blob, DevParams *__rest
 
 template <typename T, int NDIM>
 static void launch_dec_t(const Plan &P, const uint8_t *blob, const DecodeArgs &A, DevParams *dp,
-                         T *out, hipStream_t s) {
+                         T *out, hipStream_t s, Timer *tm) {
   const dim3 grid((uint32_t)P.n_tiles), blk(kBlock);
   if (P.domain == FPSZ_DOMAIN_GLOBAL) {
     hipLaunchKernelGGL((k_decode<T, NDIM, 0, true>), grid, blk, 0, s, P, blob, A, dp, out);
+    tm->mark(s, "decode_a");
     if (NDIM == 3 && P.gz > 1) scan3(A.fz, P.gz, P.ny, P.nx, s);
     if (NDIM >= 2 && P.gy > 1) scan3(A.fy, P.nz, P.gy, P.nx, s);
     if (P.gx > 1) scan3(A.fx, P.nz, P.ny, P.gx, s);
+    tm->mark(s, "face_scan");
     hipLaunchKernelGGL((k_decode<T, NDIM, 1, true>), grid, blk, 0, s, P, blob, A, dp, out);
+    tm->mark(s, "decode_c");
   } else {
     hipLaunchKernelGGL((k_decode<T, NDIM, 1, false>), grid, blk, 0, s, P, blob, A, dp, out);
+    tm->mark(s, "decode_c");
   }
 }
 
 hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const DecompressWs &W,
                                   uint64_t off_words, uint64_t n_words, uint64_t n_exc, double e2,
-                                  float e2_f, void *out, hipStream_t s) {
+                                  float e2_f, void *out, hipStream_t s, Timer *tm) {
+  tm->mark(s, "begin");
   hipError_t e = launch_fill_zero(W.P, W.zero_bytes, s);
   if (e != hipSuccess) return e;
   e = launch_checksum(blob, P.capacity, W.P, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_csum_check, dim3(1), dim3(1), 0, s, blob, W.P);
+  tm->mark(s, "checksum");
   hipLaunchKernelGGL(k_dec_tables, dim3(1), dim3(1024), 0, s, P, blob, W.P, W.lut, W.ltab,
                      W.sorted);
+  tm->mark(s, "tables");
   DecodeArgs A;
   A.off_words = off_words;
   A.n_words = n_words;
@@ -498,13 +505,13 @@ hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const Deco
   A.fy = W.fy;
   A.fx = W.fx;
   if (P.dtype == FPSZ_F32) {
-    if (P.ndim == 1) launch_dec_t<float, 1>(P, blob, A, W.P, (float *)out, s);
-    else if (P.ndim == 2) launch_dec_t<float, 2>(P, blob, A, W.P, (float *)out, s);
-    else launch_dec_t<float, 3>(P, blob, A, W.P, (float *)out, s);
+    if (P.ndim == 1) launch_dec_t<float, 1>(P, blob, A, W.P, (float *)out, s, tm);
+    else if (P.ndim == 2) launch_dec_t<float, 2>(P, blob, A, W.P, (float *)out, s, tm);
+    else launch_dec_t<float, 3>(P, blob, A, W.P, (float *)out, s, tm);
   } else {
-    if (P.ndim == 1) launch_dec_t<double, 1>(P, blob, A, W.P, (double *)out, s);
-    else if (P.ndim == 2) launch_dec_t<double, 2>(P, blob, A, W.P, (double *)out, s);
-    else launch_dec_t<double, 3>(P, blob, A, W.P, (double *)out, s);
+    if (P.ndim == 1) launch_dec_t<double, 1>(P, blob, A, W.P, (double *)out, s, tm);
+    else if (P.ndim == 2) launch_dec_t<double, 2>(P, blob, A, W.P, (double *)out, s, tm);
+    else launch_dec_t<double, 3>(P, blob, A, W.P, (double *)out, s, tm);
   }
   return hipGetLastError();
 }
@@ -603,7 +610,8 @@ __global__ __launch_bounds__(kBlock) void k_verify_final(const double *__restric
 }
 
 hipError_t launch_verify(const void *x, const void *y, uint64_t n, int dtype, double eb,
-                         DevParams *P, void *part, hipStream_t s) {
+                         DevParams *P, void *part, hipStream_t s, Timer *tm) {
+  tm->mark(s, "begin");
   const uint64_t want = n / (kBlock * 8) + 1;
   const int nb = (int)(want < (uint64_t)kVerifyBlocks ? want : kVerifyBlocks);
   if (dtype == FPSZ_F32)
@@ -612,7 +620,9 @@ hipError_t launch_verify(const void *x, const void *y, uint64_t n, int dtype, do
   else
     hipLaunchKernelGGL(k_verify<double>, dim3(nb), dim3(kBlock), 0, s, (const double *)x,
                        (const double *)y, n, eb, (double *)part);
+  tm->mark(s, "verify");
   hipLaunchKernelGGL(k_verify_final, dim3(1), dim3(kBlock), 0, s, (const double *)part, nb, P);
+  tm->mark(s, "verify_final");
   return hipGetLastError();
 }
 

@@ -282,6 +282,22 @@ __device__ inline void canonical_from_lengths(const uint8_t *lens, uint32_t *cod
   __syncthreads();
 }
 
+// Optional per-stage timing with HIP events recorded on the launch stream.
+struct Timer {
+  static constexpr int kMax = 48;
+  bool on = false;
+  int n = 0;
+  hipEvent_t ev[kMax];
+  const char *names[kMax];
+  void mark(hipStream_t s, const char *name) {
+    if (on && n < kMax) {
+      names[n] = name;
+      (void)hipEventRecord(ev[n], s);
+      n++;
+    }
+  }
+};
+
 // ---- launchers (defined in the .hip files) ---------------------------------
 struct CompressWs {
   DevParams *P;
@@ -306,13 +322,13 @@ struct DecompressWs {
 
 hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t s);
 hipError_t launch_compress(const Plan &P, const void *x, const CompressWs &W, uint8_t *blob,
-                           hipStream_t s);
+                           hipStream_t s, Timer *tm);
 hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const DecompressWs &W,
                                   uint64_t off_words, uint64_t n_words, uint64_t n_exc, double e2,
-                                  float e2_f, void *out, hipStream_t s);
+                                  float e2_f, void *out, hipStream_t s, Timer *tm);
 hipError_t launch_const_fill_bits(const Plan &P, uint64_t bits, void *out, hipStream_t s);
 hipError_t launch_checksum(const uint8_t *blob, uint64_t bytes, DevParams *dp, hipStream_t s);
 hipError_t launch_verify(const void *x, const void *y, uint64_t n, int dtype, double eb,
-                         DevParams *P, void *part, hipStream_t s);
+                         DevParams *P, void *part, hipStream_t s, Timer *tm);
 
 }  // namespace fpsz

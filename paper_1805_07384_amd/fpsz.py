@@ -50,6 +50,10 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class StageTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("ms", ctypes.c_double)]
+
+
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _vp = ctypes.c_void_p
 
@@ -76,6 +80,9 @@ SIGNATURES = {
                                    ctypes.c_double, _vp, ctypes.c_uint64, ctypes.POINTER(Stats), _vp]),
     "fpsz_compress_workspace_offset": (ctypes.c_int, [ctypes.c_int, _u64p, ctypes.c_int, ctypes.c_int,
                                                       _u64p]),
+    "fpsz_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "fpsz_last_stage_times": (ctypes.c_int, [_vp, ctypes.POINTER(StageTime), ctypes.c_int,
+                                             ctypes.POINTER(ctypes.c_int)]),
 }
 
 _lib = None
@@ -210,6 +217,20 @@ class Context:
     def _err(self, st, what):
         msg = self.lib.fpsz_last_error(self.handle)
         return FpszError(st, "%s: %s" % (what, msg.decode() if msg else ""))
+
+    def set_profiling(self, on: bool = True):
+        st = self.lib.fpsz_set_profiling(self.handle, 1 if on else 0)
+        if st != OK:
+            raise self._err(st, "fpsz_set_profiling")
+
+    def stage_times(self):
+        """[(stage, ms)] of the last call (profiling must be on)."""
+        buf = (StageTime * 48)()
+        n = ctypes.c_int()
+        st = self.lib.fpsz_last_stage_times(self.handle, buf, 48, ctypes.byref(n))
+        if st != OK:
+            raise self._err(st, "fpsz_last_stage_times")
+        return [(buf[i].name.decode(), buf[i].ms) for i in range(min(n.value, 48))]
 
     # -- raw entry points on preallocated buffers ---------------------------
     def compress_into(self, x: torch.Tensor, psnr: float, workspace: torch.Tensor,
