@@ -54,8 +54,8 @@ def algorithmic_bytes(stage: str, n: int, s: int, b: float) -> float:
         "range": s,
         "quant": s,
         "encode": b / 8.0,
-        "decode_a": b / 8.0,
-        "decode_c": b / 8.0 + s,
+        "decode": b / 8.0,
+        "rec": s,
         "verify": 2.0 * s,
     }.get(stage)
     return None if per is None else per * n

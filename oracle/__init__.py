@@ -72,6 +72,9 @@ def lib():
         L.or_huffman_unlimited.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
         L.or_code_lengths.restype = None
         L.or_code_lengths.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+        L.or_code_lengths_limited.restype = None
+        L.or_code_lengths_limited.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_void_p]
         L.or_canonical_codes.restype = None
         L.or_canonical_codes.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
         L.or_checksum.restype = ctypes.c_uint64
@@ -134,10 +137,19 @@ def huffman_unlimited(weights) -> np.ndarray:
 
 
 def code_lengths(hist) -> np.ndarray:
-    """Format code lengths: Huffman, limited to 18 bits by count halving."""
+    """Format code lengths: Huffman, limited to 18 bits by rebalancing the
+    number of codes per length."""
     h = np.ascontiguousarray(np.asarray(hist, dtype=np.uint32))
     out = np.zeros(len(h), dtype=np.uint8)
     lib().or_code_lengths(h.ctypes.data, len(h), out.ctypes.data)
+    return out
+
+
+def code_lengths_limited(hist, lmax: int) -> np.ndarray:
+    """The same length-limit rule with the limit as a parameter (for tests)."""
+    h = np.ascontiguousarray(np.asarray(hist, dtype=np.uint32))
+    out = np.zeros(len(h), dtype=np.uint8)
+    lib().or_code_lengths_limited(h.ctypes.data, len(h), int(lmax), out.ctypes.data)
     return out
 
 

@@ -39,8 +39,9 @@
  *   - points whose float32 reconstruction lands just outside eb are kept
  *     exactly in the same exception list ("patches");
  *   - Huffman: two-queue construction with leaves ordered by (count, symbol)
- *     and leaf-first ties; code lengths limited to 18 bits by halving the
- *     counts and rebuilding; canonical codes in (length, symbol) order;
+ *     and leaf-first ties; code lengths limited to 18 bits by rebalancing
+ *     the per-length code counts (see or_code_lengths); canonical codes in
+ *     (length, symbol) order;
  *   - GZIP (step (3) of SZ) is omitted.
  *
  * Built with -O2 -ffp-contract=off, no fast-math, no SIMD intrinsics.
@@ -257,18 +258,61 @@ static int huffman_lengths(const uint64_t *w, int nsym, uint8_t *len) {
   return maxl;
 }
 
-/* Length-limited variant used by the format: while the tree is deeper than
- * 18, halve every non-zero count (rounding up) and rebuild. */
-void or_code_lengths(const uint32_t *hist, int nsym, uint8_t *len) {
-  uint64_t *w = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)nsym);
+/* Length-limited variant used by the format.  Build the optimal lengths
+ * once.  If some code is longer than 18 bits, rebalance the number of codes
+ * per length: repeatedly take two codes at the deepest level d (siblings)
+ * and move them up to one code at d - 1, and split one code at the deepest
+ * level j < d - 1 that has any into two codes at j + 1.  The number of codes
+ * and the Kraft sum stay the same.  Then hand the resulting lengths out again
+ * in frequency order: leaves ordered by (count, symbol) get the lengths
+ * sorted from longest to shortest, so the rarest symbol gets the longest
+ * code. */
+typedef struct { uint32_t c; int sym; } cnt_t;
+
+static int cnt_cmp(const void *a, const void *b) {
+  const cnt_t *x = (const cnt_t *)a, *y = (const cnt_t *)b;
+  if (x->c != y->c) return x->c < y->c ? -1 : 1;
+  return x->sym < y->sym ? -1 : (x->sym > y->sym ? 1 : 0);
+}
+
+void or_code_lengths_limited(const uint32_t *hist, int nsym, int lmax, uint8_t *len) {
+  uint64_t *w = (uint64_t *)calloc((size_t)nsym + 1, sizeof(uint64_t));
   for (int s = 0; s < nsym; s++) w[s] = hist[s];
-  for (;;) {
-    int maxl = huffman_lengths(w, nsym, len);
-    if (maxl <= OR_LMAX) break;
-    for (int s = 0; s < nsym; s++)
-      if (w[s] > 0) w[s] = (w[s] + 1) >> 1;
-  }
+  int maxl = huffman_lengths(w, nsym, len);
   free(w);
+  if (maxl <= lmax) return;
+  uint32_t bits[64];
+  memset(bits, 0, sizeof(bits));
+  for (int s = 0; s < nsym; s++)
+    if (len[s]) bits[len[s]]++;
+  for (int d = maxl; d > lmax; d--) {
+    while (bits[d] > 0) {
+      int j = d - 2;
+      while (bits[j] == 0) j--;
+      bits[d] -= 2;
+      bits[d - 1] += 1;
+      bits[j + 1] += 2;
+      bits[j] -= 1;
+    }
+  }
+  /* leaves in (count, symbol) order take lengths longest first */
+  cnt_t *L = (cnt_t *)malloc(sizeof(cnt_t) * (size_t)nsym);
+  int n = 0;
+  for (int s = 0; s < nsym; s++)
+    if (hist[s] > 0) { L[n].c = hist[s]; L[n].sym = s; n++; }
+  qsort(L, (size_t)n, sizeof(cnt_t), cnt_cmp);
+  int l = lmax, j = 0;
+  while (j < n) {
+    while (bits[l] == 0) l--;
+    len[L[j].sym] = (uint8_t)l;
+    bits[l]--;
+    j++;
+  }
+  free(L);
+}
+
+void or_code_lengths(const uint32_t *hist, int nsym, uint8_t *len) {
+  or_code_lengths_limited(hist, nsym, OR_LMAX, len);
 }
 
 /* exposed for the Huffman pins: unlimited lengths */

@@ -100,8 +100,8 @@ fpsz_status make_plan(int ndim, const uint64_t *dims, fpsz_dtype dtype, Plan *P)
 }
 
 struct CompressLayout {
-  uint64_t off_part, off_hist, off_len, off_code, off_exc_state, off_word_state, off_codes, zero,
-      total;
+  uint64_t off_part, off_hist, off_len, off_code, off_word_state, off_exc_cnt, off_exc_off,
+      off_stage, off_codes, zero, total;
 };
 
 CompressLayout compress_layout(const Plan &P) {
@@ -115,11 +115,15 @@ CompressLayout compress_layout(const Plan &P) {
   o = align256(o + (uint64_t)kNSym);
   L.off_code = o;
   o = align256(o + 4 * (uint64_t)kNSym);
-  L.off_exc_state = o;
-  o = align256(o + 8 * P.n_tiles);
   L.off_word_state = o;
   o = align256(o + 8 * P.n_tiles);
-  L.zero = o;
+  L.zero = o;  // everything before this is cleared at the start of a call
+  L.off_exc_cnt = o;
+  o = align256(o + 4 * P.n_tiles);
+  L.off_exc_off = o;
+  o = align256(o + 8 * P.n_tiles);
+  L.off_stage = o;
+  o = align256(o + 8 * 64 * P.n_tiles);  // kStage records of 8 bytes per tile
   L.off_codes = o;
   o = align256(o + 2 * P.n);
   L.total = o;
@@ -127,7 +131,7 @@ CompressLayout compress_layout(const Plan &P) {
 }
 
 struct DecompressLayout {
-  uint64_t off_lut, off_ltab, off_sorted, off_fz, off_fy, off_fx, total;
+  uint64_t off_lut, off_ltab, off_sorted, off_fz, off_fy, off_fx, off_tmp, off_codes, total;
 };
 
 DecompressLayout decompress_layout(const Plan &P) {
@@ -144,7 +148,19 @@ DecompressLayout decompress_layout(const Plan &P) {
   L.off_fy = o;
   if (P.ndim >= 2 && P.gy > 1) o = align256(o + 4 * P.nz * (uint64_t)P.gy * P.nx);
   L.off_fx = o;
-  if (P.gx > 1) o = align256(o + 4 * P.nz * P.ny * (uint64_t)P.gx);
+  uint64_t face_max = 0;
+  if (P.gx > 1) {
+    o = align256(o + 4 * P.nz * P.ny * (uint64_t)P.gx);
+    face_max = P.nz * P.ny * (uint64_t)P.gx;
+  }
+  if (P.ndim == 3 && P.gz > 1 && (uint64_t)P.gz * P.ny * P.nx > face_max) face_max = (uint64_t)P.gz * P.ny * P.nx;
+  if (P.ndim >= 2 && P.gy > 1 && P.nz * (uint64_t)P.gy * P.nx > face_max) face_max = P.nz * (uint64_t)P.gy * P.nx;
+  // segment sums of a scan with len > 32 along its axis: ceil(len / 32) <=
+  // len / 16 per column, so at most one per 16 elements of the largest array
+  L.off_tmp = o;
+  o = align256(o + 4 * (face_max / 16 + 64));
+  L.off_codes = o;
+  o = align256(o + 2 * P.n);
   L.total = o;
   return L;
 }
@@ -361,7 +377,9 @@ fpsz_status fpsz_compress(fpsz_ctx *ctx, const void *field_dev, int ndim, const 
   W.hist = (uint32_t *)(ws + L.off_hist);
   W.code_len = ws + L.off_len;
   W.code = (uint32_t *)(ws + L.off_code);
-  W.exc_state = (uint64_t *)(ws + L.off_exc_state);
+  W.exc_cnt = (uint32_t *)(ws + L.off_exc_cnt);
+  W.exc_off = (uint64_t *)(ws + L.off_exc_off);
+  W.stage = (uint32_t *)(ws + L.off_stage);
   W.word_state = (uint64_t *)(ws + L.off_word_state);
   W.codes = (int16_t *)(ws + L.off_codes);
   W.zero_bytes = L.zero;
@@ -519,6 +537,8 @@ fpsz_status fpsz_decompress(fpsz_ctx *ctx, const void *blob_dev, uint64_t blob_b
   W.fz = (uint32_t *)(ws + L.off_fz);
   W.fy = (uint32_t *)(ws + L.off_fy);
   W.fx = (uint32_t *)(ws + L.off_fx);
+  W.tmp = (uint32_t *)(ws + L.off_tmp);
+  W.codes = (int16_t *)(ws + L.off_codes);
   W.zero_bytes = align256(sizeof(DevParams));
   Timer *tm = timer_begin(ctx);
   e = launch_decompress_args(P, (const uint8_t *)blob_dev, W, off_words, n_words, n_exc, e2, e2_f,

@@ -177,13 +177,33 @@ __global__ __launch_bounds__(kBlock) void k_range(const T *__restrict__ x, Plan 
 
 // ---------------------------------------------------------------------------
 // a3-a7: prequantization, Lorenzo residual, symbols, histogram, codes and
-// the stream-ordered exception list.
+// the exception list.
+//
+// The tile and its one-point halo (the preceding plane, row and column) are
+// quantized into an LDS box.  Rows of the box are loaded by one thread each
+// (segments of up to 32 points along x), so the index arithmetic is paid per
+// row, not per point.  Each thread then owns 32 consecutive points of the
+// stream and walks them along x, reusing the previous point's neighbours.
+// Exception records of a tile (outliers, then patches, in stream order) are
+// staged in a fixed slot of kStage records; a later pass places them at
+// their final offsets (tiles with more records recompute them there).
 template <int NDIM> struct Geo;
 template <> struct Geo<1> { static constexpr int TZ = 1, TY = 1, TX = 8192, HZ = 0, HY = 0; };
 template <> struct Geo<2> { static constexpr int TZ = 1, TY = 64, TX = 128, HZ = 0, HY = 1; };
 template <> struct Geo<3> { static constexpr int TZ = 16, TY = 16, TX = 32, HZ = 1, HY = 1; };
 
-__device__ __host__ constexpr int phys(int L) { return L + (L >> 5); }
+// LDS address of box point (bz, by, bx): rows of TX + 1 points; the 1D box
+// (a single long row) gets one pad word per 32 points to spread banks.
+template <int NDIM> struct BoxAddr {
+  using G = Geo<NDIM>;
+  static constexpr int BZ = G::TZ + G::HZ, BY = G::TY + G::HY, BX = G::TX + 1;
+  static constexpr int BOX = BZ * BY * BX;
+  static constexpr int SIZE = NDIM == 1 ? BOX + (BOX >> 5) + 1 : BOX;
+  __device__ static int at(int bz, int by, int bx) {
+    const int L = (bz * BY + by) * BX + bx;
+    return NDIM == 1 ? L + (L >> 5) : L;
+  }
+};
 
 template <typename T> struct Quant;
 template <> struct Quant<float> {
@@ -201,66 +221,108 @@ template <> struct Quant<double> {
   }
 };
 
+constexpr int kStage = 64;  // staged exception records per tile
+
+// Load one box row segment: points bx in [1 + 32 seg, 1 + 32 seg + 32) of box
+// row (bz, by), plus the halo point bx = 0 when seg == 0.  Quantizes into
+// the box and sets patch bits of interior points.
 template <typename T, int NDIM, bool GLOBAL>
+__device__ inline void load_row(const T *__restrict__ x, const Plan &P, const TileGeo &g, int bz,
+                                int by, int seg, int32_t *box, uint32_t *pmask, float rf, double r,
+                                float e2f, double e2, double eb) {
+  using G = Geo<NDIM>;
+  using B = BoxAddr<NDIM>;
+  const int z = bz - G::HZ, y = by - G::HY;
+  const int ez = (int)g.ez, ey = (int)g.ey, ex = (int)g.ex;
+  const bool row_in = z < ez && y < ey;
+  const bool row_field = GLOBAL ? ((z >= 0 || g.z0 > 0) && (y >= 0 || g.y0 > 0)) : (z >= 0 && y >= 0);
+  const bool interior_row = z >= 0 && y >= 0;
+  const int x0l = 32 * seg;  // first interior x (tile-local) of the segment
+  int nx_seg = ex - x0l;
+  nx_seg = nx_seg < 0 ? 0 : (nx_seg > 32 ? 32 : nx_seg);
+  const bool load_row_pts = row_in && row_field;
+  const uint64_t rowbase =
+      ((uint64_t)((int64_t)g.z0 + z) * P.ny + (uint64_t)((int64_t)g.y0 + y)) * P.nx + g.x0;
+  // halo column point (x0 - 1)
+  if (seg == 0) {
+    int32_t qh = 0;
+    if (GLOBAL && load_row_pts && g.x0 > 0) qh = Quant<T>::q(x[rowbase - 1], rf, r);
+    box[B::at(bz, by, 0)] = qh;
+  }
+  T v[32];
+  constexpr int VW = 16 / sizeof(T);
+  const bool vec = load_row_pts && nx_seg == 32 && (((rowbase + x0l) % VW) == 0);
+  if (vec) {
+    using V = typename VecOf<T>::V;
+    const V *src = reinterpret_cast<const V *>(x + rowbase + x0l);
+#pragma unroll
+    for (int k = 0; k < 32 / VW; k++) {
+      const V a = src[k];
+      const T *pa = reinterpret_cast<const T *>(&a);
+#pragma unroll
+      for (int h = 0; h < VW; h++) v[k * VW + h] = pa[h];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 32; j++) v[j] = (load_row_pts && j < nx_seg) ? x[rowbase + x0l + j] : (T)0;
+  }
+  uint32_t pbits = 0;
+#pragma unroll
+  for (int j = 0; j < 32; j++) {
+    const int32_t qv = Quant<T>::q(v[j], rf, r);
+    if (row_in && j < nx_seg) box[B::at(bz, by, 1 + x0l + j)] = qv;
+    if (interior_row && row_in && j < nx_seg && Quant<T>::patch(v[j], qv, e2f, e2, eb))
+      pbits |= 1u << j;
+  }
+  if (pbits) {
+    // stream index of the segment's first point
+    const int si = (z * ey + y) * ex + x0l;
+    const int w = si >> 5, sh = si & 31;
+    atomicOr(&pmask[w], pbits << sh);
+    if (sh) atomicOr(&pmask[w + 1], pbits >> (32 - sh));
+  }
+}
+
+template <typename T, int NDIM, bool GLOBAL, bool RECORDS>
 __global__ __launch_bounds__(kBlock) void k_quant(const T *__restrict__ x, Plan P,
                                                   DevParams *__restrict__ dp,
                                                   uint32_t *__restrict__ hist_g,
-                                                  uint64_t *__restrict__ exc_state,
+                                                  uint32_t *__restrict__ exc_cnt,
+                                                  uint32_t *__restrict__ stage,
+                                                  const uint64_t *__restrict__ exc_off,
                                                   int16_t *__restrict__ codes,
                                                   uint8_t *__restrict__ blob) {
   using G = Geo<NDIM>;
-  constexpr int BZ = G::TZ + G::HZ, BY = G::TY + G::HY, BX = G::TX + 1;
-  constexpr int BOX = BZ * BY * BX;
-  constexpr int LDS = phys(BOX - 1) + 1;
-  __shared__ int32_t box[LDS];
-  __shared__ uint32_t hist[kNSym];
-  __shared__ uint32_t pmask[kTilePts / 32];
+  using B = BoxAddr<NDIM>;
+  __shared__ int32_t box[B::SIZE];
+  __shared__ uint32_t hist[RECORDS ? 1 : kNSym];
+  __shared__ uint32_t pmask[kTilePts / 32 + 1];
   __shared__ uint32_t scr[8];
-  __shared__ uint64_t sh_t, sh_excl;
 
   if (dp->status != 0 || dp->is_const) return;
   const int tid = threadIdx.x;
   const float rf = dp->r_f, e2f = dp->e2_f;
   const double r = dp->r, e2 = dp->e2, eb = dp->eb;
   constexpr int RW = sizeof(T) / 4;  // exception records per patch
-  for (int s = tid; s < kNSym; s += kBlock) hist[s] = 0;
+  if (!RECORDS)
+    for (int s = tid; s < kNSym; s += kBlock) hist[s] = 0;
   uint64_t my_out = 0, my_pat = 0;
 
-  while (true) {
-    __syncthreads();
-    if (tid == 0) sh_t = atomicAdd(&dp->ticket_q, 1u);
-    __syncthreads();
-    const uint64_t t = sh_t;
-    if (t >= P.n_tiles) break;
+  for (uint64_t t = blockIdx.x; t < P.n_tiles; t += gridDim.x) {
+    if (RECORDS && exc_cnt[t] <= (uint32_t)kStage) continue;  // uniform
     const TileGeo g = tile_geo(P, t);
     const int ez = (int)g.ez, ey = (int)g.ey, ex = (int)g.ex, nt = (int)g.nt;
-    pmask[tid] = 0;
+    __syncthreads();
+    for (int i = tid; i <= kTilePts / 32; i += kBlock) pmask[i] = 0;
     __syncthreads();
 
-    // load q for the tile and its halo (the preceding plane / row / column)
-    for (int L = tid; L < BOX; L += kBlock) {
-      const int bz = L / (BY * BX), rem = L - bz * (BY * BX);
-      const int by = rem / BX, bx = rem - by * BX;
-      const int z = bz - G::HZ, y = by - G::HY, xx = bx - 1;
-      int32_t qv = 0;
-      const bool inside = z < ez && y < ey && xx < ex;
-      const bool interior = z >= 0 && y >= 0 && xx >= 0;
-      bool load;
-      if (GLOBAL)
-        load = inside && (z >= 0 || g.z0 > 0) && (y >= 0 || g.y0 > 0) && (xx >= 0 || g.x0 > 0);
-      else
-        load = inside && interior;
-      if (load) {
-        const uint64_t fi = ((uint64_t)((int64_t)g.z0 + z) * P.ny + (uint64_t)((int64_t)g.y0 + y)) * P.nx +
-                            (uint64_t)((int64_t)g.x0 + xx);
-        const T v = x[fi];
-        qv = Quant<T>::q(v, rf, r);
-        if (interior && Quant<T>::patch(v, qv, e2f, e2, eb)) {
-          const int si = (z * ey + y) * ex + xx;
-          atomicOr(&pmask[si >> 5], 1u << (si & 31));
-        }
-      }
-      box[phys(L)] = qv;
+    // load phase: box rows in segments of 32 points
+    constexpr int NSEG = (G::TX + 31) / 32;
+    constexpr int ITEMS = B::BZ * B::BY * NSEG;
+    for (int it = tid; it < ITEMS; it += kBlock) {
+      const int seg = it % NSEG, row = it / NSEG;
+      const int bz = row / B::BY, by = row - bz * B::BY;
+      load_row<T, NDIM, GLOBAL>(x, P, g, bz, by, seg, box, pmask, rf, r, e2f, e2, eb);
     }
     __syncthreads();
 
@@ -268,9 +330,8 @@ __global__ __launch_bounds__(kBlock) void k_quant(const T *__restrict__ x, Plan 
     const int i0 = 32 * tid;
     const int cnt = nt - i0 < 0 ? 0 : (nt - i0 > 32 ? 32 : nt - i0);
     int32_t d[32];
-    uint32_t flags = 0;  // bit j: outlier
-    uint32_t pflags = 0; // bit j: patch
-    uint32_t nexc = 0;
+    uint32_t flags = 0;   // bit j: outlier
+    const uint32_t pflags = cnt > 0 ? ((pmask[tid]) & (cnt == 32 ? ~0u : ((1u << cnt) - 1))) : 0;
     {
       int z = 0, y = 0, xx = 0;
       if (cnt > 0) {
@@ -279,46 +340,55 @@ __global__ __launch_bounds__(kBlock) void k_quant(const T *__restrict__ x, Plan 
         y = rem / ex;
         xx = rem - y * ex;
       }
-      const uint32_t pm = cnt > 0 ? pmask[tid] : 0;  // bits of points i0..i0+31
+      // neighbours of the point before (x - 1) carried along the row
+      int32_t c_prev = 0, cy_prev = 0, cz_prev = 0, cyz_prev = 0;
+      bool have_prev = false;
       uint32_t run_sym = 0xffffffffu, run_n = 0;
 #pragma unroll
       for (int j = 0; j < 32; j++) {
         if (j < cnt) {
-          const int Lc = ((z + G::HZ) * BY + (y + G::HY)) * BX + (xx + 1);
-          int32_t dv = box[phys(Lc)] - box[phys(Lc - 1)];
-          if (NDIM >= 2) dv += box[phys(Lc - BX - 1)] - box[phys(Lc - BX)];
-          if (NDIM == 3)
-            dv += box[phys(Lc - BY * BX - BX)] - box[phys(Lc - BY * BX)] + box[phys(Lc - BY * BX - 1)] -
-                  box[phys(Lc - BY * BX - BX - 1)];
+          const int bz = z + G::HZ, by = y + G::HY, bx = xx + 1;
+          if (!have_prev) {
+            c_prev = box[B::at(bz, by, bx - 1)];
+            if (NDIM >= 2) cy_prev = box[B::at(bz, by - 1, bx - 1)];
+            if (NDIM == 3) { cz_prev = box[B::at(bz - 1, by, bx - 1)]; cyz_prev = box[B::at(bz - 1, by - 1, bx - 1)]; }
+          }
+          const int32_t c0 = box[B::at(bz, by, bx)];
+          int32_t dv = c0 - c_prev;
+          int32_t cy = 0, cz = 0, cyz = 0;
+          if (NDIM >= 2) { cy = box[B::at(bz, by - 1, bx)]; dv += cy_prev - cy; }
+          if (NDIM == 3) {
+            cz = box[B::at(bz - 1, by, bx)];
+            cyz = box[B::at(bz - 1, by - 1, bx)];
+            dv += cyz - cz + cz_prev - cyz_prev;
+          }
+          c_prev = c0; cy_prev = cy; cz_prev = cz; cyz_prev = cyz;
+          have_prev = true;
           d[j] = dv;
           const int32_t a = dv < 0 ? -dv : dv;
           uint32_t s;
           if (a <= 511) s = (uint32_t)(dv + 512);
-          else if (a < 32768) {
-            const int k = 31 - __clz(a);
-            s = 1024u + 2u * (uint32_t)(k - 9) + (dv < 0 ? 1u : 0u);
-          } else {
-            s = 0;
-            flags |= 1u << j;
-            nexc++;
+          else if (a < 32768) s = 1024u + 2u * (uint32_t)(22 - __clz(a)) + (dv < 0 ? 1u : 0u);  // k - 9, k = floor(log2 a)
+          else { s = 0; flags |= 1u << j; }
+          if (!RECORDS) {
+            if (s == run_sym) run_n++;
+            else {
+              if (run_n) atomicAdd(&hist[run_sym], run_n);
+              run_sym = s;
+              run_n = 1;
+            }
           }
-          if ((pm >> j) & 1u) { pflags |= 1u << j; nexc += RW; }
-          if (s == run_sym) run_n++;
-          else {
-            if (run_n) atomicAdd(&hist[run_sym], run_n);
-            run_sym = s;
-            run_n = 1;
-          }
-          if (++xx == ex) { xx = 0; if (++y == ey) { y = 0; z++; } }
+          if (++xx == ex) { xx = 0; have_prev = false; if (++y == ey) { y = 0; z++; } }
         }
       }
-      if (run_n) atomicAdd(&hist[run_sym], run_n);
+      if (!RECORDS && run_n) atomicAdd(&hist[run_sym], run_n);
     }
-    my_out += __popc(flags);
-    my_pat += __popc(pflags);
+    const uint32_t nexc = __popc(flags) + RW * __popc(pflags);
 
-    // residual codes, stream order
-    {
+    if (!RECORDS) {
+      my_out += __popc(flags);
+      my_pat += __popc(pflags);
+      // residual codes, stream order
       const uint64_t base = g.start + (uint64_t)i0;
       if (cnt == 32 && (base & 7) == 0) {
         int4 *dst = reinterpret_cast<int4 *>(codes + base);
@@ -341,57 +411,52 @@ __global__ __launch_bounds__(kBlock) void k_quant(const T *__restrict__ x, Plan 
       }
     }
 
-    // exception list: exclusive offset of this thread inside the tile, then
-    // the tile's offset in the whole stream by look-back
+    // exception records in stream order: staged (or written in place by the
+    // recompute pass for tiles with more than kStage records)
     uint32_t tile_total;
     const uint32_t my_off = block_excl_scan_u32(nexc, scr, &tile_total);
-    if (tid < 64) {
-      const uint64_t ex0 = lookback_excl(exc_state, t, tile_total, &dp->spin_fail);
-      if (tid == 0) sh_excl = ex0;
-    }
-    __syncthreads();
-    const uint64_t excl = sh_excl;
-    if (tid == 0) {
-      const uint64_t o = P.off_teo + 8 * t;
-      if (o + 8 <= P.capacity) *reinterpret_cast<uint64_t *>(blob + o) = excl;
-      else atomicOr(&dp->overflow, 1u);
-    }
-    if (nexc) {
-      uint64_t e = excl + my_off;
+    if (!RECORDS && tid == 0) exc_cnt[t] = tile_total;
+    const bool staged = tile_total <= (uint32_t)kStage;
+    if (nexc && (RECORDS || staged)) {
+      uint32_t e = my_off;
+      const uint64_t base_off = RECORDS ? exc_off[t] : 0;
       int z = i0 / (ey * ex);
       const int rem = i0 - z * ey * ex;
       int y = rem / ex, xx = rem - (rem / ex) * ex;
       for (int j = 0; j < cnt; j++) {
         const uint32_t pos = (uint32_t)(g.start + (uint64_t)(i0 + j));
-        if ((flags >> j) & 1u) {
-          const uint64_t o = P.off_exc + 8 * e;
-          if (o + 8 <= P.capacity) {
-            uint32_t *rec = reinterpret_cast<uint32_t *>(blob + o);
-            rec[0] = pos;
-            rec[1] = (uint32_t)d[j];
-          } else atomicOr(&dp->overflow, 1u);
-          e++;
-        }
+        uint32_t recs[6];
+        int nr = 0;
+        if ((flags >> j) & 1u) { recs[0] = pos; recs[1] = (uint32_t)d[j]; nr = 1; }
         if ((pflags >> j) & 1u) {
           const uint64_t fi = ((g.z0 + z) * P.ny + (g.y0 + y)) * P.nx + (g.x0 + xx);
           uint32_t bits[2];
           const T v = x[fi];
           __builtin_memcpy(bits, &v, sizeof(T));
 #pragma unroll
-          for (int k = 0; k < RW; k++) {
-            const uint64_t o = P.off_exc + 8 * e;
+          for (int k = 0; k < RW; k++) { recs[2 * nr] = pos | kTagPatch; recs[2 * nr + 1] = bits[k]; nr++; }
+        }
+        for (int k = 0; k < nr; k++, e++) {
+          if (RECORDS) {
+            const uint64_t o = P.off_exc + 8 * (base_off + e);
             if (o + 8 <= P.capacity) {
               uint32_t *rec = reinterpret_cast<uint32_t *>(blob + o);
-              rec[0] = pos | kTagPatch;
-              rec[1] = bits[k];
-            } else atomicOr(&dp->overflow, 1u);
-            e++;
+              rec[0] = recs[2 * k];
+              rec[1] = recs[2 * k + 1];
+            } else {
+              atomicOr(&dp->overflow, 1u);
+            }
+          } else {
+            uint32_t *rec = stage + (t * kStage + e) * 2;
+            rec[0] = recs[2 * k];
+            rec[1] = recs[2 * k + 1];
           }
         }
         if (++xx == ex) { xx = 0; if (++y == ey) { y = 0; z++; } }
       }
     }
   }
+  if (RECORDS) return;
   __syncthreads();
   for (int s = tid; s < kNSym; s += kBlock)
     if (hist[s]) atomicAdd(&hist_g[s], hist[s]);
@@ -400,6 +465,73 @@ __global__ __launch_bounds__(kBlock) void k_quant(const T *__restrict__ x, Plan 
   if ((tid & 63) == 0) {
     if (my_out) atomicAdd((unsigned long long *)&dp->n_out, (unsigned long long)my_out);
     if (my_pat) atomicAdd((unsigned long long *)&dp->n_pat, (unsigned long long)my_pat);
+  }
+}
+
+// Exclusive scan of the per-tile record counts (one workgroup): tile offsets
+// into the blob's tile_exc_offset section and the workspace, the total.
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void k_exc_scan(Plan P, DevParams *__restrict__ dp,
+                                                           const uint32_t *__restrict__ cnt,
+                                                           uint64_t *__restrict__ off,
+                                                           uint8_t *__restrict__ blob) {
+  __shared__ uint64_t wsum[kScanThreads / 64];
+  __shared__ uint64_t carry;
+  if (dp->status != 0 || dp->is_const) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  const uint64_t nt = P.n_tiles;
+  for (uint64_t base = 0; base < nt; base += kScanThreads) {
+    const uint64_t t = base + tid;
+    const uint64_t v = t < nt ? cnt[t] : 0;
+    const uint64_t inc = wave_incl_scan_u64(v);
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    uint64_t pre = carry;
+    for (int w = 0; w < wv; w++) pre += wsum[w];
+    const uint64_t ex0 = pre + inc - v;
+    if (t < nt) {
+      off[t] = ex0;
+      const uint64_t o = P.off_teo + 8 * t;
+      if (o + 8 <= P.capacity) *reinterpret_cast<uint64_t *>(blob + o) = ex0;
+      else atomicOr(&dp->overflow, 1u);
+    }
+    __syncthreads();
+    if (tid == kScanThreads - 1) carry = ex0 + v;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const uint64_t tot = carry;
+    dp->n_exc = tot;
+    dp->off_words = align8(P.off_exc + 8 * tot);
+    const uint64_t o = P.off_teo + 8 * nt;
+    if (o + 8 <= P.capacity) *reinterpret_cast<uint64_t *>(blob + o) = tot;
+    else atomicOr(&dp->overflow, 1u);
+  }
+}
+
+// Place staged records (one wave per tile).
+__global__ __launch_bounds__(kBlock) void k_exc_copy(Plan P, DevParams *__restrict__ dp,
+                                                     const uint32_t *__restrict__ cnt,
+                                                     const uint32_t *__restrict__ stage,
+                                                     const uint64_t *__restrict__ off,
+                                                     uint8_t *__restrict__ blob) {
+  if (dp->status != 0 || dp->is_const) return;
+  const uint64_t t = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (t >= P.n_tiles) return;
+  const uint32_t c = cnt[t];
+  if (c == 0 || c > (uint32_t)kStage) return;
+  const uint64_t o0 = P.off_exc + 8 * off[t];
+  for (uint32_t e = lane; e < c; e += 64) {
+    const uint64_t o = o0 + 8 * e;
+    if (o + 8 <= P.capacity) {
+      const uint2 v = *reinterpret_cast<const uint2 *>(stage + (t * kStage + e) * 2);
+      *reinterpret_cast<uint2 *>(blob + o) = v;
+    } else {
+      atomicOr(&dp->overflow, 1u);
+    }
   }
 }
 
@@ -412,6 +544,10 @@ __global__ __launch_bounds__(kBlock) void k_quant(const T *__restrict__ x, Plan 
 // merged node is consumed before v, in merge order, so all of them can be
 // ranked at once and paired.  A batch with an odd count pairs its last item
 // with v itself.  The result is identical to the one-pick-at-a-time loop.
+// Codes longer than 18 bits are removed by rebalancing the per-length code
+// counts (two deepest siblings move up one level, one shallower code splits
+// in two), and the lengths are handed out again along the (count, symbol)
+// order, longest first.
 constexpr int kCbThreads = 1024;
 
 __device__ inline void bitonic_sort_2048(uint64_t *key) {
@@ -445,10 +581,8 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(Plan P, DevParams *__re
                                                          const uint32_t *__restrict__ hist_g,
                                                          uint8_t *__restrict__ len_out,
                                                          uint32_t *__restrict__ code_out,
-                                                         const uint64_t *__restrict__ exc_state,
                                                          uint8_t *__restrict__ blob) {
   __shared__ uint64_t key[2048];
-  __shared__ uint32_t cnt[kNSym];
   __shared__ uint32_t Lw[kNSym];
   __shared__ uint16_t Ls[kNSym];
   __shared__ uint32_t Iw[kNSym];
@@ -457,38 +591,30 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(Plan P, DevParams *__re
   __shared__ uint16_t dA[kNSym], pA[kNSym], dB[kNSym], pB[kNSym];
   __shared__ uint8_t lens[kNSym];
   __shared__ uint32_t lcount[kLMax + 2], lfirst[kLMax + 2], lbase[kLMax + 2];
+  __shared__ uint32_t wcnt[17 * 20];
+  __shared__ uint32_t bits[64], lstart[64];
   __shared__ int s_n, s_li, s_ii, s_ni, s_ml, s_maxl;
   __shared__ uint32_t s_v;
   const int tid = threadIdx.x;
   if (dp->status != 0 || dp->is_const) return;
 
-  if (tid == 0) {
-    const uint64_t tot = P.n_tiles ? (exc_state[P.n_tiles - 1] & kLbMask) : 0;
-    dp->n_exc = tot;
-    dp->off_words = align8(P.off_exc + 8 * tot);
-    const uint64_t o = P.off_teo + 8 * P.n_tiles;
-    if (o + 8 <= P.capacity) *reinterpret_cast<uint64_t *>(blob + o) = tot;
-    else atomicOr(&dp->overflow, 1u);
+  for (int i = tid; i < 2048; i += kCbThreads) {
+    const uint32_t c = i < kNSym ? hist_g[i] : 0u;
+    key[i] = c ? (((uint64_t)c << 11) | (uint64_t)i) : ~0ull;
   }
-  for (int s = tid; s < kNSym; s += kCbThreads) cnt[s] = hist_g[s];
+  for (int s = tid; s < kNSym; s += kCbThreads) lens[s] = 0;
+  if (tid < 64) bits[tid] = 0;
+  if (tid == 0) { s_n = 0; s_maxl = 0; }
   __syncthreads();
-
-  for (int round = 0; round < 40; round++) {
-    for (int i = tid; i < 2048; i += kCbThreads)
-      key[i] = (i < kNSym && cnt[i]) ? (((uint64_t)cnt[i] << 11) | (uint64_t)i) : ~0ull;
-    for (int s = tid; s < kNSym; s += kCbThreads) lens[s] = 0;
-    if (tid == 0) { s_n = 0; s_maxl = 0; }
+  bitonic_sort_2048(key);
+  for (int i = tid; i < 2048; i += kCbThreads)
+    if (key[i] != ~0ull && (i == 2047 || key[i + 1] == ~0ull)) s_n = i + 1;
+  __syncthreads();
+  const int n = s_n;
+  if (n <= 1) {
+    if (tid == 0 && n == 1) lens[key[0] & 2047] = 1;
     __syncthreads();
-    bitonic_sort_2048(key);
-    for (int i = tid; i < 2048; i += kCbThreads)
-      if (key[i] != ~0ull && (i == 2047 || key[i + 1] == ~0ull)) s_n = i + 1;
-    __syncthreads();
-    const int n = s_n;
-    if (n <= 1) {
-      if (tid == 0 && n == 1) lens[key[0] & 2047] = 1;
-      __syncthreads();
-      break;
-    }
+  } else {
     for (int j = tid; j < n; j += kCbThreads) {
       Lw[j] = (uint32_t)(key[j] >> 11);
       Ls[j] = (uint16_t)(key[j] & 2047);
@@ -572,18 +698,38 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(Plan P, DevParams *__re
     }
     for (int j = tid; j < n; j += kCbThreads) {
       const int l = dc[parL[j]] + 1;
-      lens[Ls[j]] = (uint8_t)l;
+      lens[Ls[j]] = (uint8_t)(l < 63 ? l : 63);
       atomicMax(&s_maxl, l);
+      atomicAdd(&bits[l < 63 ? l : 63], 1u);
     }
     __syncthreads();
-    if (s_maxl <= kLMax) break;
-    // too deep: halve the counts (rounding up) and rebuild
-    for (int s = tid; s < kNSym; s += kCbThreads)
-      if (cnt[s]) cnt[s] = (cnt[s] + 1) >> 1;
-    __syncthreads();
+    if (s_maxl > kLMax) {
+      if (tid == 0) {
+        for (int d = s_maxl < 63 ? s_maxl : 63; d > kLMax; d--) {
+          while (bits[d] > 0) {
+            int j = d - 2;
+            while (j > 0 && bits[j] == 0) j--;
+            bits[d] -= 2;
+            bits[d - 1] += 1;
+            bits[j + 1] += 2;
+            bits[j] -= 1;
+          }
+        }
+        // sorted position ranges per length, longest first
+        uint32_t st = 0;
+        for (int l = kLMax; l >= 1; l--) { lstart[l] = st; st += bits[l]; }
+      }
+      __syncthreads();
+      for (int j = tid; j < n; j += kCbThreads) {
+        int l = kLMax;
+        while (l > 1 && !(j >= (int)lstart[l] && j < (int)(lstart[l] + bits[l]))) l--;
+        lens[Ls[j]] = (uint8_t)l;
+      }
+      __syncthreads();
+    }
   }
 
-  canonical_from_lengths(lens, code_out, lcount, lfirst, lbase, nullptr);
+  canonical_from_lengths(lens, code_out, lcount, lfirst, lbase, nullptr, wcnt);
   for (int s = tid; s < kNSym; s += kCbThreads) len_out[s] = lens[s];
   // code_len section (plus its 4 padding bytes)
   for (int s = tid; s < 1040; s += kCbThreads) {
@@ -829,16 +975,27 @@ __global__ void k_checksum_store(DevParams *__restrict__ dp, uint8_t *__restrict
 }
 
 // ---------------------------------------------------------------------------
+template <typename T, int NDIM, bool GLOBAL>
+static void launch_quant_d(const Plan &P, const T *x, const CompressWs &W, uint8_t *blob,
+                           hipStream_t s) {
+  const uint32_t grid = (uint32_t)(P.n_tiles < 2048 ? P.n_tiles : 2048);
+  hipLaunchKernelGGL((k_quant<T, NDIM, GLOBAL, false>), dim3(grid), dim3(kBlock), 0, s, x, P, W.P,
+                     W.hist, W.exc_cnt, W.stage, (const uint64_t *)W.exc_off, W.codes, blob);
+  hipLaunchKernelGGL(k_exc_scan, dim3(1), dim3(kScanThreads), 0, s, P, W.P, W.exc_cnt, W.exc_off,
+                     blob);
+  const uint32_t cgrid = (uint32_t)ceil_div(P.n_tiles, kBlock / 64);
+  hipLaunchKernelGGL(k_exc_copy, dim3(cgrid), dim3(kBlock), 0, s, P, W.P, W.exc_cnt, W.stage,
+                     W.exc_off, blob);
+  // tiles with more than kStage records recompute them in place
+  hipLaunchKernelGGL((k_quant<T, NDIM, GLOBAL, true>), dim3(grid), dim3(kBlock), 0, s, x, P, W.P,
+                     W.hist, W.exc_cnt, W.stage, (const uint64_t *)W.exc_off, W.codes, blob);
+}
+
 template <typename T, int NDIM>
 static void launch_quant(const Plan &P, const T *x, const CompressWs &W, uint8_t *blob,
                          hipStream_t s) {
-  const uint32_t grid = (uint32_t)(P.n_tiles < 1024 ? P.n_tiles : 1024);
-  if (P.domain == FPSZ_DOMAIN_GLOBAL)
-    hipLaunchKernelGGL((k_quant<T, NDIM, true>), dim3(grid), dim3(kBlock), 0, s, x, P, W.P, W.hist,
-                       W.exc_state, W.codes, blob);
-  else
-    hipLaunchKernelGGL((k_quant<T, NDIM, false>), dim3(grid), dim3(kBlock), 0, s, x, P, W.P, W.hist,
-                       W.exc_state, W.codes, blob);
+  if (P.domain == FPSZ_DOMAIN_GLOBAL) launch_quant_d<T, NDIM, true>(P, x, W, blob, s);
+  else launch_quant_d<T, NDIM, false>(P, x, W, blob, s);
 }
 
 template <typename T>
@@ -854,7 +1011,7 @@ static void launch_compress_t(const Plan &P, const T *x, const CompressWs &W, ui
   else launch_quant<T, 3>(P, x, W, blob, s);
   tm->mark(s, "quant");
   hipLaunchKernelGGL(k_codebook, dim3(1), dim3(kCbThreads), 0, s, P, W.P, W.hist, W.code_len,
-                     W.code, W.exc_state, blob);
+                     W.code, blob);
   tm->mark(s, "codebook");
   const uint32_t egrid = (uint32_t)(P.n_tiles < 2048 ? P.n_tiles : 2048);
   hipLaunchKernelGGL(k_encode, dim3(egrid), dim3(kBlock), 0, s, P, W.P, W.codes, W.code_len,

@@ -52,6 +52,7 @@ __global__ __launch_bounds__(1024) void k_dec_tables(Plan P, const uint8_t *__re
   __shared__ uint32_t lcount[kLMax + 2], lfirst[kLMax + 2], lbase[kLMax + 2];
   __shared__ unsigned long long kraft;
   __shared__ uint32_t bad;
+  __shared__ uint32_t wcnt[17 * 20];
   const int tid = threadIdx.x;
   if (tid == 0) { kraft = 0; bad = 0; }
   __syncthreads();
@@ -66,7 +67,7 @@ __global__ __launch_bounds__(1024) void k_dec_tables(Plan P, const uint8_t *__re
     if (tid == 0) atomicOr(&dp->corrupt, 1u);
     return;
   }
-  canonical_from_lengths(lens, code, lcount, lfirst, lbase, sorted);
+  canonical_from_lengths(lens, code, lcount, lfirst, lbase, sorted, wcnt);
   for (int i = tid; i < (1 << kLutBits); i += blockDim.x) lut[i] = 0;
   __syncthreads();
   for (int s = tid; s < kNSym; s += blockDim.x) {
@@ -83,32 +84,30 @@ __global__ __launch_bounds__(1024) void k_dec_tables(Plan P, const uint8_t *__re
 }
 
 // ---------------------------------------------------------------------------
-// One tile per workgroup.  PASS 0 = projections (A), 1 = reconstruction (C).
-template <typename T, int NDIM, int PASS, bool GLOBAL>
+// Decode: one wave per tile, lane k decodes chunk k (128 symbols) through an
+// 11-bit lookup table in LDS with a canonical search for longer codes.  The
+// residual codes are written in stream order (outliers as -32768, their
+// value is taken from the exception list), and in the GLOBAL domain the
+// tile's projections (sums of the residual along z, y and x) are gathered in
+// LDS and written to the face arrays.
+constexpr int kDecWaves = 4;
+
+template <int NDIM, bool PROJ>
 __global__ __launch_bounds__(kBlock) void k_decode(Plan P, const uint8_t *__restrict__ blob,
                                                    DecodeArgs A, DevParams *__restrict__ dp,
-                                                   T *__restrict__ out) {
+                                                   int16_t *__restrict__ codes) {
   using G = DGeo<NDIM>;
   constexpr int TZ = G::TZ, TY = G::TY, TX = G::TX;
-  constexpr int LDS = dphys(kTilePts - 1) + 1;
-  __shared__ int32_t dl[LDS];
+  constexpr int AZ = (PROJ && NDIM == 3) ? TY * TX : 1;  // z-projection: (y, x)
+  constexpr int AY = (PROJ && NDIM >= 2) ? TZ * TX : 1;  // y-projection: (z, x)
+  constexpr int AX = PROJ ? TZ * TY : 1;                 // x-projection: (z, y)
   __shared__ uint32_t lut[1 << kLutBits];
   __shared__ uint32_t lfirst[kLMax + 1], lcnt[kLMax + 1], lbase[kLMax + 1];
   __shared__ uint16_t sorted[kNSym];
-  __shared__ uint32_t omask[kTilePts / 32], pmask[kTilePts / 32];
-  __shared__ uint32_t hA[TY * TX > 1 && NDIM == 3 ? TY * TX : 1];
-  __shared__ uint32_t hB[NDIM >= 2 ? TZ * TX : 1];
-  __shared__ uint32_t hC[TZ * TY];
-  __shared__ uint32_t s_bad;
-  __shared__ uint32_t scr[8];
+  __shared__ uint32_t accz[kDecWaves][AZ], accy[kDecWaves][AY], accx[kDecWaves][AX];
 
   if (dp->corrupt) return;
-  const int tid = threadIdx.x;
-  const uint64_t t = blockIdx.x;
-  const TileGeo g = tile_geo(P, t);
-  const int ez = (int)g.ez, ey = (int)g.ey, ex = (int)g.ex, nt = (int)g.nt;
-  const bool full = ez == TZ && ey == TY && ex == TX;
-
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int i = tid; i < (1 << kLutBits); i += kBlock) lut[i] = A.lut[i];
   for (int i = tid; i < kNSym; i += kBlock) sorted[i] = A.sorted[i];
   if (tid <= kLMax) {
@@ -116,152 +115,232 @@ __global__ __launch_bounds__(kBlock) void k_decode(Plan P, const uint8_t *__rest
     lcnt[tid] = A.ltab[32 + tid];
     lbase[tid] = A.ltab[64 + tid];
   }
-  omask[tid] = 0;
-  pmask[tid] = 0;
-  if (tid == 0) s_bad = 0;
+  if (PROJ) {
+    for (int i = lane; i < AZ; i += 64) accz[wv][i] = 0;
+    for (int i = lane; i < AY; i += 64) accy[wv][i] = 0;
+    for (int i = lane; i < AX; i += 64) accx[wv][i] = 0;
+  }
+  __syncthreads();
+  const uint64_t t = (uint64_t)blockIdx.x * kDecWaves + wv;
+  if (t >= P.n_tiles) return;  // no barrier follows
+  const TileGeo g = tile_geo(P, t);
+  const int ey = (int)g.ey, ex = (int)g.ex, nt = (int)g.nt;
   const uint64_t *two = reinterpret_cast<const uint64_t *>(blob + P.off_two);
   const uint64_t *teo = reinterpret_cast<const uint64_t *>(blob + P.off_teo);
   const uint64_t w0 = two[t], w1 = two[t + 1];
   const uint64_t e0 = teo[t], e1 = teo[t + 1];
-  __syncthreads();
   if (w0 > w1 || w1 > A.n_words || e0 > e1 || e1 > A.n_exc) {
-    if (tid == 0) atomicOr(&dp->corrupt, 1u);
+    if (lane == 0) atomicOr(&dp->corrupt, 1u);
     return;
   }
-
-  // ---- decode: lane k of wave 0 decodes chunk k of the tile
-  if (tid < 64) {
-    const int lane = tid;
-    const uint16_t *cbits = reinterpret_cast<const uint16_t *>(blob + P.off_cb);
-    const uint32_t cb = lane < (int)g.nck ? cbits[g.chunk_base + lane] : 0u;
-    const uint32_t incl = wave_incl_scan_u32(cb);
-    const uint32_t total = __shfl(incl, 63, 64);
-    if ((uint64_t)total > (w1 - w0) * 32) {
-      if (lane == 0) atomicOr(&s_bad, 1u);
-    } else if (lane < (int)g.nck) {
-      const uint32_t *words = reinterpret_cast<const uint32_t *>(blob + A.off_words);
-      uint64_t bitpos = w0 * 32 + (incl - cb);
-      uint64_t widx = bitpos >> 5;
-      const uint32_t sh = (uint32_t)(bitpos & 31);
-      uint64_t buf = (uint64_t)(widx < w1 ? words[widx] : 0u) << 32;
-      widx++;
-      buf <<= sh;
-      int nb = 32 - (int)sh;
-      const int k0 = lane * kChunk;
-      const int k1 = k0 + kChunk < nt ? k0 + kChunk : nt;
-      int z = k0 / (ey * ex);
+  const uint16_t *cbits = reinterpret_cast<const uint16_t *>(blob + P.off_cb);
+  const uint32_t cb = lane < (int)g.nck ? cbits[g.chunk_base + lane] : 0u;
+  const uint32_t incl = wave_incl_scan_u32(cb);
+  const uint32_t total = __shfl(incl, 63, 64);
+  if ((uint64_t)total > (w1 - w0) * 32) {
+    if (lane == 0) atomicOr(&dp->corrupt, 1u);
+    return;
+  }
+  bool ok = true;
+  if (lane < (int)g.nck) {
+    const uint32_t *words = reinterpret_cast<const uint32_t *>(blob + A.off_words);
+    const uint32_t *exc = reinterpret_cast<const uint32_t *>(blob + P.off_exc);
+    uint64_t bitpos = w0 * 32 + (incl - cb);
+    uint64_t widx = bitpos >> 5;
+    const uint32_t sh = (uint32_t)(bitpos & 31);
+    uint64_t buf = (uint64_t)(widx < w1 ? words[widx] : 0u) << 32;
+    widx++;
+    buf <<= sh;
+    int nb = 32 - (int)sh;
+    const int k0 = lane * kChunk;
+    const int k1 = k0 + kChunk < nt ? k0 + kChunk : nt;
+    int z = 0, y = 0, xx = 0;
+    if (PROJ) {
+      z = k0 / (ey * ex);
       const int rem = k0 - z * ey * ex;
-      int y = rem / ex, xx = rem - (rem / ex) * ex;
-      uint32_t used = 0;
-      bool ok = true;
-      for (int k = k0; k < k1; k++) {
-        if (nb < 32) {
-          buf |= (uint64_t)(widx < w1 ? words[widx] : 0u) << (32 - nb);
-          widx++;
-          nb += 32;
-        }
-        const uint32_t e = lut[(uint32_t)(buf >> (64 - kLutBits))];
-        int L = (int)(e & 31u);
-        int s = (int)(e >> 5);
-        if (L == 0) {
-          const uint32_t v = (uint32_t)(buf >> (64 - kLMax));
-          s = -1;
-          for (int l = kLutBits + 1; l <= kLMax; l++) {
-            const uint32_t c = v >> (kLMax - l);
-            if (c - lfirst[l] < lcnt[l]) { s = sorted[lbase[l] + (c - lfirst[l])]; L = l; break; }
-          }
-          if (s < 0) { ok = false; break; }
-        }
-        buf <<= L;
-        nb -= L;
-        int32_t dv;
-        if (s >= 1024) {
-          const int kk = (s - 1024) / 2 + 9;
-          const uint32_t ev = (uint32_t)(buf >> (64 - kk));
-          buf <<= kk;
-          nb -= kk;
-          L += kk;
-          const int32_t mag = (1 << kk) + (int32_t)ev;
-          dv = (s & 1) ? -mag : mag;
-        } else if (s == 0) {
-          const int si = k;
-          atomicOr(&omask[si >> 5], 1u << (si & 31));
-          dv = 0;
-        } else {
-          dv = s - 512;
-        }
-        used += (uint32_t)L;
-        dl[dphys((z * TY + y) * TX + xx)] = dv;
-        if (++xx == ex) { xx = 0; if (++y == ey) { y = 0; z++; } }
+      y = rem / ex;
+      xx = rem - y * ex;
+    }
+    int16_t *dst = codes + g.start;
+    const bool vec = ((g.start + (uint64_t)k0) & 7) == 0;
+    uint32_t used = 0, pack[4] = {0, 0, 0, 0};
+    int32_t rowsum = 0;
+    for (int k = k0; k < k1; k++) {
+      if (nb < 32) {
+        buf |= (uint64_t)(widx < w1 ? words[widx] : 0u) << (32 - nb);
+        widx++;
+        nb += 32;
       }
-      if (!ok || used != cb) atomicOr(&s_bad, 1u);
+      const uint32_t e = lut[(uint32_t)(buf >> (64 - kLutBits))];
+      int L = (int)(e & 31u);
+      int s = (int)(e >> 5);
+      if (L == 0) {
+        const uint32_t v = (uint32_t)(buf >> (64 - kLMax));
+        s = -1;
+        for (int l = kLutBits + 1; l <= kLMax; l++) {
+          const uint32_t c = v >> (kLMax - l);
+          if (c - lfirst[l] < lcnt[l]) { s = sorted[lbase[l] + (c - lfirst[l])]; L = l; break; }
+        }
+        if (s < 0) { ok = false; break; }
+      }
+      buf <<= L;
+      nb -= L;
+      int32_t dv, code;
+      if (s >= 1024) {
+        const int kk = (s - 1024) / 2 + 9;
+        const uint32_t ev = (uint32_t)(buf >> (64 - kk));
+        buf <<= kk;
+        nb -= kk;
+        L += kk;
+        const int32_t mag = (1 << kk) + (int32_t)ev;
+        dv = (s & 1) ? -mag : mag;
+        code = dv;
+      } else if (s == 0) {
+        // outlier: its residual sits in the exception list (sorted by key)
+        const uint32_t want = (uint32_t)(g.start + (uint64_t)k);
+        uint64_t lo = e0, hi = e1;
+        while (lo < hi) {  // records sorted by position; outlier before patch
+          const uint64_t mid = (lo + hi) >> 1;
+          if ((exc[2 * mid] & ~kTagPatch) < want) lo = mid + 1;
+          else hi = mid;
+        }
+        if (lo < e1 && exc[2 * lo] == want) dv = (int32_t)exc[2 * lo + 1];
+        else { ok = false; break; }
+        code = -32768;
+      } else {
+        dv = s - 512;
+        code = dv;
+      }
+      used += (uint32_t)L;
+      if (vec) {
+        const int j = k - k0;
+        pack[(j >> 1) & 3] |= ((uint32_t)code & 0xffffu) << (16 * (j & 1));
+        if ((j & 7) == 7 || k + 1 == k1) {
+          if ((j & 7) == 7)
+            *reinterpret_cast<int4 *>(dst + (k - 7)) =
+                make_int4((int)pack[0], (int)pack[1], (int)pack[2], (int)pack[3]);
+          else
+            for (int q = (j & ~7); q <= j; q++)
+              dst[k0 + q] = (int16_t)(pack[(q >> 1) & 3] >> (16 * (q & 1)));
+          pack[0] = pack[1] = pack[2] = pack[3] = 0;
+        }
+      } else {
+        dst[k] = (int16_t)code;
+      }
+      if (PROJ) {
+        if (NDIM == 3) atomicAdd(&accz[wv][y * TX + xx], (uint32_t)dv);
+        if (NDIM >= 2) atomicAdd(&accy[wv][z * TX + xx], (uint32_t)dv);
+        rowsum += dv;
+        if (++xx == ex) {
+          atomicAdd(&accx[wv][z * TY + y], (uint32_t)rowsum);
+          rowsum = 0;
+          xx = 0;
+          if (++y == ey) { y = 0; z++; }
+        }
+      }
+    }
+    if (PROJ && ok && xx != 0) atomicAdd(&accx[wv][z * TY + y], (uint32_t)rowsum);
+    if (!ok || used != cb) ok = false;
+  }
+  if (!ok) atomicOr(&dp->corrupt, 1u);
+  if (!PROJ) return;
+  // the wave's accumulators are complete once every lane is past this point
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int ez = (int)g.ez;
+  if (NDIM == 3 && P.gz > 1)
+    for (int i = lane; i < ey * ex; i += 64) {
+      const int yy = i / ex, x2 = i - yy * ex;
+      A.fz[((uint64_t)g.a * P.ny + g.y0 + yy) * P.nx + g.x0 + x2] = accz[wv][yy * TX + x2];
+    }
+  if (NDIM >= 2 && P.gy > 1)
+    for (int i = lane; i < ez * ex; i += 64) {
+      const int zz = i / ex, x2 = i - zz * ex;
+      A.fy[((g.z0 + zz) * P.gy + g.b) * P.nx + g.x0 + x2] = accy[wv][zz * TX + x2];
+    }
+  if (P.gx > 1)
+    for (int i = lane; i < ez * ey; i += 64) {
+      const int zz = i / ey, yy = i - zz * ey;
+      A.fx[((g.z0 + zz) * P.ny + g.y0 + yy) * P.gx + g.c] = accx[wv][zz * TY + yy];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reconstruction: one tile per workgroup.  Residuals from the decoded codes
+// (outliers from the exception list), local inclusive prefix sums modulo
+// 2^32 in LDS, the halo terms of the GLOBAL domain, bin midpoints q * 2eb,
+// patched points exact, coalesced store.
+template <typename T, int NDIM, bool GLOBAL>
+__global__ __launch_bounds__(kBlock) void k_rec(Plan P, const uint8_t *__restrict__ blob,
+                                                DecodeArgs A, DevParams *__restrict__ dp,
+                                                const int16_t *__restrict__ codes,
+                                                T *__restrict__ out) {
+  using G = DGeo<NDIM>;
+  constexpr int TZ = G::TZ, TY = G::TY, TX = G::TX;
+  constexpr int LDS = dphys(kTilePts - 1) + 1;
+  __shared__ int32_t dl[LDS];
+  __shared__ uint32_t pmask[kTilePts / 32];
+  __shared__ uint32_t hA[NDIM == 3 ? TY * TX : 1];
+  __shared__ uint32_t hB[NDIM >= 2 ? TZ * TX : 1];
+  __shared__ uint32_t hC[TZ * TY];
+  __shared__ uint32_t scr[8];
+  __shared__ uint32_t s_bad;
+
+  if (dp->corrupt) return;
+  const int tid = threadIdx.x;
+  const uint64_t t = blockIdx.x;
+  const TileGeo g = tile_geo(P, t);
+  const int ez = (int)g.ez, ey = (int)g.ey, ex = (int)g.ex, nt = (int)g.nt;
+  const bool full = ez == TZ && ey == TY && ex == TX;
+  const uint64_t *teo = reinterpret_cast<const uint64_t *>(blob + P.off_teo);
+  const uint64_t e0 = teo[t], e1 = teo[t + 1];
+  if (e0 > e1 || e1 > A.n_exc) return;  // reported by the decode kernel
+  const uint32_t *exc = reinterpret_cast<const uint32_t *>(blob + P.off_exc);
+  pmask[tid] = 0;
+  if (tid == 0) s_bad = 0;
+
+  // residuals into LDS (tile layout), 8 codes per load where aligned
+  const int16_t *src = codes + g.start;
+  if (full && (g.start & 7) == 0) {
+    for (int i = 8 * tid; i < nt; i += 8 * kBlock) {
+      const int4 v = *reinterpret_cast<const int4 *>(src + i);
+      const uint32_t w[4] = {(uint32_t)v.x, (uint32_t)v.y, (uint32_t)v.z, (uint32_t)v.w};
+#pragma unroll
+      for (int h = 0; h < 8; h++) {
+        const int32_t c = (int32_t)(int16_t)(w[h >> 1] >> (16 * (h & 1)));
+        dl[dphys(i + h)] = c;  // full tile: layout index == stream index
+      }
+    }
+  } else {
+    for (int i = tid; i < nt; i += kBlock) {
+      const int z = i / (ey * ex), rem = i - z * ey * ex, y = rem / ex, xx = rem - y * ex;
+      dl[dphys((z * TY + y) * TX + xx)] = (int32_t)src[i];
     }
   }
   __syncthreads();
-
-  // ---- exception list of this tile: outlier residuals, patch marks
+  // exception list: outlier residuals and patch marks
   for (uint64_t e = e0 + tid; e < e1; e += kBlock) {
-    const uint32_t *rec = reinterpret_cast<const uint32_t *>(blob + P.off_exc + 8 * e);
-    const uint32_t key = rec[0];
+    const uint32_t key = exc[2 * e];
     const uint64_t pos = key & ~kTagPatch;
     if (pos < g.start || pos >= g.start + (uint64_t)nt) { atomicOr(&s_bad, 1u); continue; }
     const int si = (int)(pos - g.start);
     if (key & kTagPatch) {
       atomicOr(&pmask[si >> 5], 1u << (si & 31));
     } else {
-      const uint32_t old = atomicAnd(&omask[si >> 5], ~(1u << (si & 31)));
-      if (!((old >> (si & 31)) & 1u)) { atomicOr(&s_bad, 1u); continue; }
       const int z = si / (ey * ex), rem = si - z * ey * ex, y = rem / ex, xx = rem - y * ex;
-      dl[dphys((z * TY + y) * TX + xx)] = (int32_t)rec[1];
+      const int o = dphys((z * TY + y) * TX + xx);
+      if (dl[o] != -32768) atomicOr(&s_bad, 1u);
+      dl[o] = (int32_t)exc[2 * e + 1];
     }
   }
-  __syncthreads();
-  if (omask[tid]) atomicOr(&s_bad, 1u);
   __syncthreads();
   if (s_bad) {
     if (tid == 0) atomicOr(&dp->corrupt, 1u);
     return;
   }
 
-  if (PASS == 0) {
-    // ---- projections into the face arrays
-    if (NDIM == 3 && P.gz > 1) {
-      for (int i = tid; i < ey * ex; i += kBlock) {
-        const int y = i / ex, xx = i - (i / ex) * ex;
-        uint32_t s = 0;
-        for (int z = 0; z < ez; z++) s += (uint32_t)dl[dphys((z * TY + y) * TX + xx)];
-        A.fz[((uint64_t)g.a * P.ny + g.y0 + y) * P.nx + g.x0 + xx] = s;
-      }
-    }
-    if (NDIM >= 2 && P.gy > 1) {
-      for (int i = tid; i < ez * ex; i += kBlock) {
-        const int z = i / ex, xx = i - (i / ex) * ex;
-        uint32_t s = 0;
-        for (int y = 0; y < ey; y++) s += (uint32_t)dl[dphys((z * TY + y) * TX + xx)];
-        A.fy[((g.z0 + z) * P.gy + g.b) * P.nx + g.x0 + xx] = s;
-      }
-    }
-    if (P.gx > 1) {
-      if (NDIM == 1) {
-        uint32_t s = 0;
-        for (int i = tid; i < nt; i += kBlock) s += (uint32_t)dl[dphys(i)];
-        s = wave_sum_u32(s);
-        if ((tid & 63) == 0) scr[tid >> 6] = s;
-        __syncthreads();
-        if (tid == 0) A.fx[g.c] = scr[0] + scr[1] + scr[2] + scr[3];
-      } else {
-        for (int i = tid; i < ez * ey; i += kBlock) {
-          const int z = i / ey, y = i - (i / ey) * ey;
-          uint32_t s = 0;
-          for (int xx = 0; xx < ex; xx++) s += (uint32_t)dl[dphys((z * TY + y) * TX + xx)];
-          A.fx[((g.z0 + z) * P.ny + g.y0 + y) * P.gx + g.c] = s;
-        }
-      }
-    }
-    return;
-  }
-
-  // ---- PASS C: local inclusive prefix sums (modulo 2^32) along x, y, z
+  // local inclusive prefix sums (modulo 2^32) along x, y, z
   if (NDIM == 1) {
     const int i0 = 32 * tid;
     uint32_t run = 0;
@@ -305,7 +384,7 @@ __global__ __launch_bounds__(kBlock) void k_decode(Plan P, const uint8_t *__rest
     }
   }
 
-  // ---- halo terms from the scanned face arrays
+  // halo terms from the scanned face arrays
   if (GLOBAL) {
     if (NDIM == 3) {
       for (int i = tid; i < ey * ex; i += kBlock) {
@@ -344,8 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_decode(Plan P, const uint8_t *__rest
   }
   __syncthreads();
 
-  // ---- bin midpoints q * 2eb, patched points exact, coalesced store
-  const uint32_t *exc = reinterpret_cast<const uint32_t *>(blob + P.off_exc);
+  // bin midpoints q * 2eb, patched points exact, coalesced store
   for (int i = tid; i < nt; i += kBlock) {
     int z, y, xx;
     if (full) { z = i / (TY * TX); y = (i / TX) % TY; xx = i % TX; }
@@ -391,67 +469,71 @@ __global__ __launch_bounds__(kBlock) void k_decode(Plan P, const uint8_t *__rest
 }
 
 // ---------------------------------------------------------------------------
-// pass B: inclusive scans of a row-major u32 array along one axis
-// contiguous axis: one workgroup per line
-__global__ __launch_bounds__(kBlock) void k_scan_inner(uint32_t *__restrict__ a, uint64_t lines,
-                                                       uint32_t len) {
-  __shared__ uint32_t scr[8];
-  for (uint64_t line = blockIdx.x; line < lines; line += gridDim.x) {
-    uint32_t *p = a + line * len;
-    uint32_t carry = 0;
-    for (uint32_t base = 0; base < len; base += 4 * kBlock) {
-      const uint32_t i0 = base + 4 * threadIdx.x;
-      uint32_t v[4];
-#pragma unroll
-      for (int k = 0; k < 4; k++) v[k] = i0 + k < len ? p[i0 + k] : 0u;
-      v[1] += v[0];
-      v[2] += v[1];
-      v[3] += v[2];
-      uint32_t tot;
-      const uint32_t ex0 = block_excl_scan_u32(v[3], scr, &tot);
-#pragma unroll
-      for (int k = 0; k < 4; k++)
-        if (i0 + k < len) p[i0 + k] = v[k] + ex0 + carry;
-      carry += tot;
-    }
-  }
-}
+// pass B: inclusive scans (modulo 2^32) of a row-major u32 array along one
+// axis.  Element (o, k, i) sits at (o * len + k) * inner + i.  The axis is
+// cut into segments of 32; each thread scans one segment of one column after
+// adding the totals of the column's earlier segments.
+constexpr int kSeg = 32;
 
-// strided axis: element (o, k, i) at (o * len + k) * inner + i; one thread
-// per (o, i), sequential along k
-__global__ __launch_bounds__(kBlock) void k_scan_outer(uint32_t *__restrict__ a, uint64_t outer,
-                                                       uint64_t len, uint64_t inner) {
-  const uint64_t total = outer * inner;
+__global__ __launch_bounds__(kBlock) void k_seg_sums(const uint32_t *__restrict__ a, uint64_t outer,
+                                                     uint64_t len, uint64_t inner,
+                                                     uint32_t *__restrict__ sums) {
+  const uint64_t nseg = (len + kSeg - 1) / kSeg;
+  const uint64_t total = outer * nseg * inner;
   for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < total;
        j += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t o = j / inner, i = j - o * inner;
-    uint32_t *p = a + o * len * inner + i;
+    const uint64_t i = j % inner, r = j / inner, sg = r % nseg, o = r / nseg;
+    const uint64_t k0 = sg * kSeg, k1 = k0 + kSeg < len ? k0 + kSeg : len;
+    const uint32_t *p = a + (o * len) * inner + i;
+    uint32_t s = 0;
+    for (uint64_t k = k0; k < k1; k++) s += p[k * inner];
+    sums[j] = s;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_scan(uint32_t *__restrict__ a, uint64_t outer,
+                                                     uint64_t len, uint64_t inner,
+                                                     const uint32_t *__restrict__ sums) {
+  const uint64_t nseg = (len + kSeg - 1) / kSeg;
+  const uint64_t total = outer * nseg * inner;
+  for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < total;
+       j += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t i = j % inner, r = j / inner, sg = r % nseg, o = r / nseg;
     uint32_t run = 0;
-    for (uint64_t k = 0; k < len; k++) {
-      run += p[k * inner];
-      p[k * inner] = run;
+    if (sums)
+      for (uint64_t q = 0; q < sg; q++) run += sums[(o * nseg + q) * inner + i];
+    const uint64_t k0 = sg * kSeg, k1 = k0 + kSeg < len ? k0 + kSeg : len;
+    uint32_t *p = a + (o * len) * inner + i;
+    uint32_t v[kSeg];
+#pragma unroll
+    for (int k = 0; k < kSeg; k++) v[k] = (k0 + k < k1) ? p[(k0 + k) * inner] : 0u;
+#pragma unroll
+    for (int k = 0; k < kSeg; k++) {
+      run += v[k];
+      if (k0 + k < k1) p[(k0 + k) * inner] = run;
     }
   }
 }
 
-static void scan3(uint32_t *a, uint64_t d0, uint64_t d1, uint64_t d2, hipStream_t s) {
-  if (d2 > 1) {
-    const uint64_t lines = d0 * d1;
-    const uint32_t grid = (uint32_t)(lines < 65536 ? lines : 65536);
-    hipLaunchKernelGGL(k_scan_inner, dim3(grid), dim3(kBlock), 0, s, a, lines, (uint32_t)d2);
-  }
-  if (d1 > 1) {
-    const uint64_t th = d0 * d2;
-    const uint64_t b = th / kBlock + 1;
-    hipLaunchKernelGGL(k_scan_outer, dim3((uint32_t)(b < 65536 ? b : 65536)), dim3(kBlock), 0, s, a,
-                       d0, d1, d2);
-  }
-  if (d0 > 1) {
-    const uint64_t th = d1 * d2;
-    const uint64_t b = th / kBlock + 1;
-    hipLaunchKernelGGL(k_scan_outer, dim3((uint32_t)(b < 65536 ? b : 65536)), dim3(kBlock), 0, s, a,
-                       (uint64_t)1, d0, d1 * d2);
-  }
+static void scan_axis(uint32_t *a, uint64_t outer, uint64_t len, uint64_t inner, uint32_t *tmp,
+                      hipStream_t s) {
+  if (len <= 1) return;
+  const uint64_t nseg = (len + kSeg - 1) / kSeg;
+  const uint64_t total = outer * nseg * inner;
+  const uint64_t b = total / kBlock + 1;
+  const dim3 grid((uint32_t)(b < 65536 ? b : 65536)), blk(kBlock);
+  if (nseg > 1)
+    hipLaunchKernelGGL(k_seg_sums, grid, blk, 0, s, a, outer, len, inner, tmp);
+  hipLaunchKernelGGL(k_seg_scan, grid, blk, 0, s, a, outer, len, inner,
+                     nseg > 1 ? (const uint32_t *)tmp : nullptr);
+}
+
+// inclusive prefix sums of a (d0, d1, d2) array along all three axes
+static void scan3(uint32_t *a, uint64_t d0, uint64_t d1, uint64_t d2, uint32_t *tmp,
+                  hipStream_t s) {
+  scan_axis(a, d0 * d1, d2, 1, tmp, s);
+  scan_axis(a, d0, d1, d2, tmp, s);
+  scan_axis(a, 1, d0, d1 * d2, tmp, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -462,20 +544,22 @@ __global__ void k_csum_check(const uint8_t *__restrict__ blob, DevParams *__rest
 
 template <typename T, int NDIM>
 static void launch_dec_t(const Plan &P, const uint8_t *blob, const DecodeArgs &A, DevParams *dp,
-                         T *out, hipStream_t s, Timer *tm) {
-  const dim3 grid((uint32_t)P.n_tiles), blk(kBlock);
+                         int16_t *codes, uint32_t *tmp, T *out, hipStream_t s, Timer *tm) {
+  const dim3 dgrid((uint32_t)ceil_div(P.n_tiles, kDecWaves)), grid((uint32_t)P.n_tiles), blk(kBlock);
   if (P.domain == FPSZ_DOMAIN_GLOBAL) {
-    hipLaunchKernelGGL((k_decode<T, NDIM, 0, true>), grid, blk, 0, s, P, blob, A, dp, out);
-    tm->mark(s, "decode_a");
-    if (NDIM == 3 && P.gz > 1) scan3(A.fz, P.gz, P.ny, P.nx, s);
-    if (NDIM >= 2 && P.gy > 1) scan3(A.fy, P.nz, P.gy, P.nx, s);
-    if (P.gx > 1) scan3(A.fx, P.nz, P.ny, P.gx, s);
+    hipLaunchKernelGGL((k_decode<NDIM, true>), dgrid, blk, 0, s, P, blob, A, dp, codes);
+    tm->mark(s, "decode");
+    if (NDIM == 3 && P.gz > 1) scan3(A.fz, P.gz, P.ny, P.nx, tmp, s);
+    if (NDIM >= 2 && P.gy > 1) scan3(A.fy, P.nz, P.gy, P.nx, tmp, s);
+    if (P.gx > 1) scan3(A.fx, P.nz, P.ny, P.gx, tmp, s);
     tm->mark(s, "face_scan");
-    hipLaunchKernelGGL((k_decode<T, NDIM, 1, true>), grid, blk, 0, s, P, blob, A, dp, out);
-    tm->mark(s, "decode_c");
+    hipLaunchKernelGGL((k_rec<T, NDIM, true>), grid, blk, 0, s, P, blob, A, dp, codes, out);
+    tm->mark(s, "rec");
   } else {
-    hipLaunchKernelGGL((k_decode<T, NDIM, 1, false>), grid, blk, 0, s, P, blob, A, dp, out);
-    tm->mark(s, "decode_c");
+    hipLaunchKernelGGL((k_decode<NDIM, false>), dgrid, blk, 0, s, P, blob, A, dp, codes);
+    tm->mark(s, "decode");
+    hipLaunchKernelGGL((k_rec<T, NDIM, false>), grid, blk, 0, s, P, blob, A, dp, codes, out);
+    tm->mark(s, "rec");
   }
 }
 
@@ -505,13 +589,13 @@ hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const Deco
   A.fy = W.fy;
   A.fx = W.fx;
   if (P.dtype == FPSZ_F32) {
-    if (P.ndim == 1) launch_dec_t<float, 1>(P, blob, A, W.P, (float *)out, s, tm);
-    else if (P.ndim == 2) launch_dec_t<float, 2>(P, blob, A, W.P, (float *)out, s, tm);
-    else launch_dec_t<float, 3>(P, blob, A, W.P, (float *)out, s, tm);
+    if (P.ndim == 1) launch_dec_t<float, 1>(P, blob, A, W.P, W.codes, W.tmp, (float *)out, s, tm);
+    else if (P.ndim == 2) launch_dec_t<float, 2>(P, blob, A, W.P, W.codes, W.tmp, (float *)out, s, tm);
+    else launch_dec_t<float, 3>(P, blob, A, W.P, W.codes, W.tmp, (float *)out, s, tm);
   } else {
-    if (P.ndim == 1) launch_dec_t<double, 1>(P, blob, A, W.P, (double *)out, s, tm);
-    else if (P.ndim == 2) launch_dec_t<double, 2>(P, blob, A, W.P, (double *)out, s, tm);
-    else launch_dec_t<double, 3>(P, blob, A, W.P, (double *)out, s, tm);
+    if (P.ndim == 1) launch_dec_t<double, 1>(P, blob, A, W.P, W.codes, W.tmp, (double *)out, s, tm);
+    else if (P.ndim == 2) launch_dec_t<double, 2>(P, blob, A, W.P, W.codes, W.tmp, (double *)out, s, tm);
+    else launch_dec_t<double, 3>(P, blob, A, W.P, W.codes, W.tmp, (double *)out, s, tm);
   }
   return hipGetLastError();
 }

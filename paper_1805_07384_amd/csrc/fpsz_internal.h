@@ -249,20 +249,37 @@ __device__ inline uint64_t mix64(uint32_t w, uint64_t j) {
 
 // Canonical codes from lengths (shared with the decoder-table kernel):
 // codes of each length are consecutive in symbol order, and the first code
-// of length l is (first(l-1) + count(l-1)) << 1.
+// of length l is (first(l-1) + count(l-1)) << 1.  A symbol's rank among the
+// symbols of its length comes from per-wave ballots over blocks of 64
+// symbols.  `wcnt` holds >= 17 * 20 u32.
 __device__ inline void canonical_from_lengths(const uint8_t *lens, uint32_t *code_out, uint32_t *lcount,
-                                       uint32_t *lfirst, uint32_t *lbase, uint16_t *sorted) {
-  const int tid = threadIdx.x;
-  if (tid <= kLMax + 1) lcount[tid] = 0;
-  __syncthreads();
-  for (int s = tid; s < kNSym; s += blockDim.x)
-    if (lens[s]) atomicAdd(&lcount[lens[s]], 1u);
+                                              uint32_t *lfirst, uint32_t *lbase, uint16_t *sorted,
+                                              uint32_t *wcnt) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  constexpr int kChunks = (kNSym + 63) / 64;
+  uint32_t myrank[2] = {0, 0};
+  int k = 0;
+  for (int w = wave; w < kChunks; w += nwaves, k++) {
+    const int s = 64 * w + lane;
+    const int l = s < kNSym ? lens[s] : 0;
+    for (int ll = 1; ll <= kLMax; ll++) {
+      const uint64_t m = __ballot(l == ll);
+      if (lane == 0) wcnt[w * 20 + ll] = (uint32_t)__popcll(m);
+      if (l == ll) myrank[k] = (uint32_t)__popcll(m & ((1ull << lane) - 1));
+    }
+  }
   __syncthreads();
   if (tid == 0) {
     // lcount[0] stays 0: unused symbols are not counted
     uint32_t c = 0, base = 0;
+    lcount[0] = 0;
     lfirst[0] = 0;
     lbase[0] = 0;
+    for (int l = 1; l <= kLMax; l++) {
+      uint32_t cnt = 0;
+      for (int w = 0; w < kChunks; w++) cnt += wcnt[w * 20 + l];
+      lcount[l] = cnt;
+    }
     for (int l = 1; l <= kLMax; l++) {
       c = (c + lcount[l - 1]) << 1;
       lfirst[l] = c;
@@ -271,11 +288,14 @@ __device__ inline void canonical_from_lengths(const uint8_t *lens, uint32_t *cod
     }
   }
   __syncthreads();
-  for (int s = tid; s < kNSym; s += blockDim.x) {
+  k = 0;
+  for (int w = wave; w < kChunks; w += nwaves, k++) {
+    const int s = 64 * w + lane;
+    if (s >= kNSym) continue;
     const int l = lens[s];
     if (!l) { if (code_out) code_out[s] = 0; continue; }
-    uint32_t rank = 0;
-    for (int k = 0; k < s; k++) rank += (lens[k] == l);
+    uint32_t rank = myrank[k];
+    for (int w2 = 0; w2 < w; w2++) rank += wcnt[w2 * 20 + l];
     if (code_out) code_out[s] = lfirst[l] + rank;
     if (sorted) sorted[lbase[l] + rank] = (uint16_t)s;
   }
@@ -305,7 +325,9 @@ struct CompressWs {
   uint32_t *hist;
   uint8_t *code_len;
   uint32_t *code;
-  uint64_t *exc_state;
+  uint32_t *exc_cnt;    // per-tile exception record counts
+  uint64_t *exc_off;    // per-tile record offsets
+  uint32_t *stage;      // staged records, kStage per tile
   uint64_t *word_state;
   int16_t *codes;
   uint64_t zero_bytes;  // bytes from P to clear before a call
@@ -317,6 +339,8 @@ struct DecompressWs {
   uint32_t *ltab;      // first[19], count[19], base[19]
   uint16_t *sorted;    // symbols in canonical order
   uint32_t *fz, *fy, *fx;  // tile-face projection arrays (GLOBAL domain)
+  uint32_t *tmp;           // segment sums of the face scans
+  int16_t *codes;          // decoded residual codes, stream order
   uint64_t zero_bytes;
 };
 

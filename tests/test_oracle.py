@@ -299,6 +299,46 @@ def test_length_limit(orc):
     assert ln.max() <= 18
     assert _kraft(ln) == 1
     assert np.all((ln > 0) == (h > 0))
+    # rarer symbols never get shorter codes than more frequent ones
+    used = np.nonzero(h)[0]
+    order = sorted(used, key=lambda s: (int(h[s]), int(s)))
+    assert all(ln[a] >= ln[b] for a, b in zip(order, order[1:]))
+    # the limit costs little: within 1 % of the unlimited optimum here
+    cost = lambda l: int(np.sum(h.astype(np.int64) * l.astype(np.int64)))
+    assert cost(ln) <= 1.01 * cost(unl)
+
+
+def test_length_limit_hand_example(orc):
+    # counts 16, 8, 4, 2, 1, 1: Huffman gives a chain with lengths 1,2,3,4,5,5
+    # (codes per length {1:1, 2:1, 3:1, 4:1, 5:2}).  With a 4-bit limit the two
+    # length-5 siblings become one length-4 code and the length-3 code splits
+    # into two length-4 codes: {1:1, 2:1, 4:4}; the two most frequent
+    # symbols keep lengths 1 and 2, the other four get 4.
+    h = np.array([16, 8, 4, 2, 1, 1], dtype=np.uint32)
+    assert list(orc.huffman_unlimited(h.astype(np.uint64))) == [1, 2, 3, 4, 5, 5]
+    assert list(orc.code_lengths_limited(h, 4)) == [1, 2, 4, 4, 4, 4]
+    # by brute force the best code with lengths <= 4 costs 64, as does this one
+    best = min(sum(int(a) * b for a, b in zip(h, ls))
+               for ls in itertools.product(range(1, 5), repeat=6) if _kraft(ls) <= 1)
+    assert best == 64 == int(np.sum(h * np.array([1, 2, 4, 4, 4, 4])))
+
+
+def test_length_limit_near_optimal_small(orc):
+    # not an optimality claim: the rebalanced code is a valid complete code
+    # within the limit, and close to the brute-force best limited code
+    rng = np.random.default_rng(8)
+    for _ in range(150):
+        n = int(rng.integers(2, 7))
+        h = (2 ** rng.integers(0, 9, size=n)).astype(np.uint32)
+        lim = int(rng.integers(3, 5))
+        if (1 << lim) < n:
+            continue
+        ln = orc.code_lengths_limited(h, lim)
+        assert ln.max() <= lim and _kraft(ln) == 1
+        c = sum(int(a) * int(b) for a, b in zip(h, ln))
+        best = min(sum(int(a) * b for a, b in zip(h, ls))
+                   for ls in itertools.product(range(1, lim + 1), repeat=n) if _kraft(ls) <= 1)
+        assert best <= c <= 1.25 * best
     # when the limit is not hit the format lengths are the Huffman lengths
     h2 = np.zeros(1036, dtype=np.uint32)
     h2[100:600] = np.arange(1, 501)
