@@ -131,11 +131,15 @@ CompressLayout compress_layout(const Plan &P) {
 }
 
 struct DecompressLayout {
-  uint64_t off_lut, off_ltab, off_sorted, off_fz, off_fy, off_fx, off_tmp, off_codes, total;
+  uint64_t off_lut, off_ltab, off_sorted, off_fz, off_fy, off_fx, off_gx, off_gy, off_gz, off_tt,
+      off_tmp, off_codes, total;
 };
 
 DecompressLayout decompress_layout(const Plan &P) {
   DecompressLayout L;
+  const uint64_t T = P.n_tiles;
+  const uint64_t fz = P.ndim == 3 ? (uint64_t)P.ty * P.tx : 0, fy = P.ndim >= 2 ? (uint64_t)P.tz * P.tx : 0;
+  const uint64_t fx = (uint64_t)P.tz * P.ty;
   uint64_t o = align256(sizeof(DevParams));
   L.off_lut = o;
   o = align256(o + 4 * 2048);
@@ -144,21 +148,27 @@ DecompressLayout decompress_layout(const Plan &P) {
   L.off_sorted = o;
   o = align256(o + 2 * (uint64_t)kNSym);
   L.off_fz = o;
-  if (P.ndim == 3 && P.gz > 1) o = align256(o + 4 * (uint64_t)P.gz * P.ny * P.nx);
+  o = align256(o + 4 * T * fz);
   L.off_fy = o;
-  if (P.ndim >= 2 && P.gy > 1) o = align256(o + 4 * P.nz * (uint64_t)P.gy * P.nx);
+  o = align256(o + 4 * T * fy);
   L.off_fx = o;
-  uint64_t face_max = 0;
-  if (P.gx > 1) {
-    o = align256(o + 4 * P.nz * P.ny * (uint64_t)P.gx);
-    face_max = P.nz * P.ny * (uint64_t)P.gx;
-  }
-  if (P.ndim == 3 && P.gz > 1 && (uint64_t)P.gz * P.ny * P.nx > face_max) face_max = (uint64_t)P.gz * P.ny * P.nx;
-  if (P.ndim >= 2 && P.gy > 1 && P.nz * (uint64_t)P.gy * P.nx > face_max) face_max = P.nz * (uint64_t)P.gy * P.nx;
+  o = align256(o + 4 * T * fx);
+  L.off_gx = o;
+  o = align256(o + 4 * T * (P.ndim == 3 ? P.tx : 0));
+  L.off_gy = o;
+  o = align256(o + 4 * T * (P.ndim == 3 ? P.ty : 0));
+  L.off_gz = o;
+  o = align256(o + 4 * T * (P.ndim >= 2 ? P.tz : 0));
+  L.off_tt = o;
+  o = align256(o + 4 * T);
   // segment sums of a scan with len > 32 along its axis: ceil(len / 32) <=
   // len / 16 per column, so at most one per 16 elements of the largest array
+  uint64_t big = T * fz;
+  if (T * fy > big) big = T * fy;
+  if (T * fx > big) big = T * fx;
+  if (T * P.tx > big) big = T * P.tx;
   L.off_tmp = o;
-  o = align256(o + 4 * (face_max / 16 + 64));
+  o = align256(o + 4 * (big / 16 + 64));
   L.off_codes = o;
   o = align256(o + 2 * P.n);
   L.total = o;
@@ -537,6 +547,10 @@ fpsz_status fpsz_decompress(fpsz_ctx *ctx, const void *blob_dev, uint64_t blob_b
   W.fz = (uint32_t *)(ws + L.off_fz);
   W.fy = (uint32_t *)(ws + L.off_fy);
   W.fx = (uint32_t *)(ws + L.off_fx);
+  W.gx = (uint32_t *)(ws + L.off_gx);
+  W.gy = (uint32_t *)(ws + L.off_gy);
+  W.gz = (uint32_t *)(ws + L.off_gz);
+  W.tt = (uint32_t *)(ws + L.off_tt);
   W.tmp = (uint32_t *)(ws + L.off_tmp);
   W.codes = (int16_t *)(ws + L.off_codes);
   W.zero_bytes = align256(sizeof(DevParams));

@@ -4,19 +4,17 @@
 // the Lorenzo residual is undone by inclusive prefix sums along x, y and z,
 // and bin indexes become bin midpoints q * 2eb (Sec. IV, Eq. 5-6).
 //
-// GLOBAL domain (prefix sums over the whole field), three passes:
-//   A  decode each tile into LDS and write its three projections
-//      (sums of the residual along z, y and x) into full-resolution face
-//      arrays Fz[gz][ny][nx], Fy[nz][gy][nx], Fx[nz][ny][gx];
-//   B  inclusive prefix sums of each face array along its three axes.  Then
-//      Fz[a][y][x] is the reconstructed q on the last plane of tile slab a,
-//      and likewise Fy / Fx for the last row / column of each tile band;
-//   C  decode again, local 3D prefix sum L, and add the halo terms:
-//      q = L + (qz[y][x] - qz[y0-1][x] - qz[y][x0-1] + qz[y0-1][x0-1])
-//            + (qy[z][x] - qy[z][x0-1]) + qx[z][y]
-//      (inclusion-exclusion over the regions before the tile), then scale.
+// GLOBAL domain (prefix sums over the whole field):
+//   decode  residual codes of every tile, one wave per tile;
+//   proj    per tile, the projections of the residual along z, y and x and
+//           their 2D prefix sums inside the tile (faces Fz, Fy, Fx) with
+//           their last rows / columns (edge vectors) and the tile total;
+//   scans   exclusive prefix sums of the faces along one tile axis each and
+//           of the edge vectors over two tile axes (inclusion-exclusion over
+//           the regions of the field before a tile, split by tile axis);
+//   rec     local 3D prefix sum plus the halo terms, then bin midpoints.
 // Sums are taken modulo 2^32; the true bin indexes fit in 32 bits, so the
-// result is exact.  TILE domain: pass C alone with zero halo.
+// result is exact.  TILE domain: decode and rec with zero halo.
 #include <math.h>
 
 #include "fpsz_internal.h"
@@ -37,7 +35,8 @@ struct DecodeArgs {
   const uint32_t *lut;
   const uint32_t *ltab;
   const uint16_t *sorted;
-  uint32_t *fz, *fy, *fx;
+  // GLOBAL domain: per-tile faces and edge vectors, tile-major slots
+  uint32_t *fz, *fy, *fx, *gx, *gy, *gz, *tt;
 };
 
 // ---------------------------------------------------------------------------
@@ -84,193 +83,331 @@ __global__ __launch_bounds__(1024) void k_dec_tables(Plan P, const uint8_t *__re
 }
 
 // ---------------------------------------------------------------------------
-// Decode: one wave per tile, lane k decodes chunk k (128 symbols) through an
-// 11-bit lookup table in LDS with a canonical search for longer codes.  The
-// residual codes are written in stream order (outliers as -32768, their
-// value is taken from the exception list), and in the GLOBAL domain the
-// tile's projections (sums of the residual along z, y and x) are gathered in
-// LDS and written to the face arrays.
+// Decode: one wave per tile, lane k decodes chunk k (128 symbols).  The
+// tile's words are staged in LDS when they fit (kStageWords per wave, sized
+// by the host from the average bits per tile); the reader takes the 64 bits
+// at any bit position p from words p/32 and p/32 + 1, so there is no refill
+// state.  Symbols go through an 11-bit table in LDS with a canonical search
+// for longer codes.  The residual codes are written in stream order, eight
+// per 16-byte store (outliers as -32768; their residual is in the exception
+// list).
 constexpr int kDecWaves = 4;
 
-template <int NDIM, bool PROJ>
+struct WordsLds {
+  const uint32_t *w;  // nw + 1 staged words (the last is zero)
+  uint32_t nw;
+  __device__ uint32_t operator()(uint32_t i) const { return w[i <= nw ? i : nw]; }
+};
+struct WordsGlobal {
+  const uint32_t *w;  // tile's first word
+  uint32_t nw;        // words in the tile
+  __device__ uint32_t operator()(uint32_t i) const { return i < nw ? w[i] : 0u; }
+};
+
+// Decode symbols [k0, k1) of a tile starting at bit p (relative to the
+// tile's first word).  Returns false on an invalid code or a missing outlier
+// record; *used receives the bits consumed.
+template <typename RD>
+__device__ inline bool decode_chunk(const RD &rd, uint32_t p, int k0, int k1, const uint16_t *lut,
+                                    const uint32_t *lfirst, const uint32_t *lcnt,
+                                    const uint32_t *lbase, const uint16_t *sorted,
+                                    const uint32_t *exc, uint64_t e0, uint64_t e1, uint64_t start,
+                                    int16_t *dst, bool vec, uint32_t *used) {
+  const uint32_t p0 = p;
+  for (int kb = k0; kb < k1; kb += 8) {
+    uint32_t pk[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int h = 0; h < 8; h++) {
+      const int k = kb + h;
+      if (k < k1) {
+        const uint32_t i = p >> 5;
+        const uint64_t win = (((uint64_t)rd(i) << 32) | (uint64_t)rd(i + 1)) << (p & 31);
+        const uint32_t e = lut[(uint32_t)(win >> (64 - kLutBits))];
+        int L = (int)(e & 31u);
+        int s = (int)(e >> 5);
+        if (L == 0) {
+          const uint32_t v = (uint32_t)(win >> (64 - kLMax));
+          s = -1;
+          for (int l = kLutBits + 1; l <= kLMax; l++) {
+            const uint32_t c = v >> (kLMax - l);
+            if (c - lfirst[l] < lcnt[l]) { s = sorted[lbase[l] + (c - lfirst[l])]; L = l; break; }
+          }
+          if (s < 0) return false;
+        }
+        int32_t code;
+        if (s >= 1024) {
+          const int kk = (s - 1024) / 2 + 9;
+          const uint32_t ev = (uint32_t)((win << L) >> (64 - kk));
+          const int32_t mag = (1 << kk) + (int32_t)ev;
+          code = (s & 1) ? -mag : mag;
+          L += kk;
+        } else if (s == 0) {
+          // the residual must be in the exception list
+          const uint32_t want = (uint32_t)(start + (uint64_t)k);
+          uint64_t lo = e0, hi = e1;
+          while (lo < hi) {  // records sorted by position; outlier before patch
+            const uint64_t mid = (lo + hi) >> 1;
+            if ((exc[2 * mid] & ~kTagPatch) < want) lo = mid + 1;
+            else hi = mid;
+          }
+          if (!(lo < e1 && exc[2 * lo] == want)) return false;
+          code = -32768;
+        } else {
+          code = s - 512;
+        }
+        p += (uint32_t)L;
+        pk[h >> 1] |= ((uint32_t)code & 0xffffu) << (16 * (h & 1));
+        if (!vec) dst[k] = (int16_t)code;
+      }
+    }
+    if (vec) {
+      if (kb + 8 <= k1) {
+        *reinterpret_cast<int4 *>(dst + kb) = make_int4((int)pk[0], (int)pk[1], (int)pk[2], (int)pk[3]);
+      } else {
+        for (int h = 0; kb + h < k1; h++) dst[kb + h] = (int16_t)(pk[h >> 1] >> (16 * (h & 1)));
+      }
+    }
+  }
+  *used = p - p0;
+  return true;
+}
+
+template <int NDIM>
 __global__ __launch_bounds__(kBlock) void k_decode(Plan P, const uint8_t *__restrict__ blob,
                                                    DecodeArgs A, DevParams *__restrict__ dp,
-                                                   int16_t *__restrict__ codes) {
-  using G = DGeo<NDIM>;
-  constexpr int TZ = G::TZ, TY = G::TY, TX = G::TX;
-  constexpr int AZ = (PROJ && NDIM == 3) ? TY * TX : 1;  // z-projection: (y, x)
-  constexpr int AY = (PROJ && NDIM >= 2) ? TZ * TX : 1;  // y-projection: (z, x)
-  constexpr int AX = PROJ ? TZ * TY : 1;                 // x-projection: (z, y)
-  __shared__ uint32_t lut[1 << kLutBits];
+                                                   int16_t *__restrict__ codes, uint32_t stage_words) {
+  __shared__ uint16_t lut[1 << kLutBits];
   __shared__ uint32_t lfirst[kLMax + 1], lcnt[kLMax + 1], lbase[kLMax + 1];
   __shared__ uint16_t sorted[kNSym];
-  __shared__ uint32_t accz[kDecWaves][AZ], accy[kDecWaves][AY], accx[kDecWaves][AX];
+  extern __shared__ uint32_t wstage[];  // kDecWaves * (stage_words + 1)
 
   if (dp->corrupt) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int i = tid; i < (1 << kLutBits); i += kBlock) lut[i] = A.lut[i];
+  for (int i = tid; i < (1 << kLutBits); i += kBlock) lut[i] = (uint16_t)A.lut[i];
   for (int i = tid; i < kNSym; i += kBlock) sorted[i] = A.sorted[i];
   if (tid <= kLMax) {
     lfirst[tid] = A.ltab[tid];
     lcnt[tid] = A.ltab[32 + tid];
     lbase[tid] = A.ltab[64 + tid];
   }
-  if (PROJ) {
-    for (int i = lane; i < AZ; i += 64) accz[wv][i] = 0;
-    for (int i = lane; i < AY; i += 64) accy[wv][i] = 0;
-    for (int i = lane; i < AX; i += 64) accx[wv][i] = 0;
-  }
   __syncthreads();
   const uint64_t t = (uint64_t)blockIdx.x * kDecWaves + wv;
   if (t >= P.n_tiles) return;  // no barrier follows
   const TileGeo g = tile_geo(P, t);
-  const int ey = (int)g.ey, ex = (int)g.ex, nt = (int)g.nt;
+  const int nt = (int)g.nt;
   const uint64_t *two = reinterpret_cast<const uint64_t *>(blob + P.off_two);
   const uint64_t *teo = reinterpret_cast<const uint64_t *>(blob + P.off_teo);
   const uint64_t w0 = two[t], w1 = two[t + 1];
   const uint64_t e0 = teo[t], e1 = teo[t + 1];
-  if (w0 > w1 || w1 > A.n_words || e0 > e1 || e1 > A.n_exc) {
+  if (w0 > w1 || w1 > A.n_words || e0 > e1 || e1 > A.n_exc || w1 - w0 > (uint64_t)kTilePts) {
     if (lane == 0) atomicOr(&dp->corrupt, 1u);
     return;
+  }
+  const uint32_t nw = (uint32_t)(w1 - w0);
+  const uint32_t *gw = reinterpret_cast<const uint32_t *>(blob + A.off_words) + w0;
+  uint32_t *mine = wstage + (size_t)wv * (stage_words + 1);
+  const bool in_lds = nw <= stage_words;
+  if (in_lds) {
+    for (uint32_t i = lane; i <= nw; i += 64) mine[i] = i < nw ? gw[i] : 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   const uint16_t *cbits = reinterpret_cast<const uint16_t *>(blob + P.off_cb);
   const uint32_t cb = lane < (int)g.nck ? cbits[g.chunk_base + lane] : 0u;
   const uint32_t incl = wave_incl_scan_u32(cb);
   const uint32_t total = __shfl(incl, 63, 64);
-  if ((uint64_t)total > (w1 - w0) * 32) {
+  if (total > nw * 32u) {
     if (lane == 0) atomicOr(&dp->corrupt, 1u);
     return;
   }
-  bool ok = true;
-  if (lane < (int)g.nck) {
-    const uint32_t *words = reinterpret_cast<const uint32_t *>(blob + A.off_words);
-    const uint32_t *exc = reinterpret_cast<const uint32_t *>(blob + P.off_exc);
-    uint64_t bitpos = w0 * 32 + (incl - cb);
-    uint64_t widx = bitpos >> 5;
-    const uint32_t sh = (uint32_t)(bitpos & 31);
-    uint64_t buf = (uint64_t)(widx < w1 ? words[widx] : 0u) << 32;
-    widx++;
-    buf <<= sh;
-    int nb = 32 - (int)sh;
-    const int k0 = lane * kChunk;
-    const int k1 = k0 + kChunk < nt ? k0 + kChunk : nt;
-    int z = 0, y = 0, xx = 0;
-    if (PROJ) {
-      z = k0 / (ey * ex);
-      const int rem = k0 - z * ey * ex;
-      y = rem / ex;
-      xx = rem - y * ex;
-    }
-    int16_t *dst = codes + g.start;
-    const bool vec = ((g.start + (uint64_t)k0) & 7) == 0;
-    uint32_t used = 0, pack[4] = {0, 0, 0, 0};
-    int32_t rowsum = 0;
-    for (int k = k0; k < k1; k++) {
-      if (nb < 32) {
-        buf |= (uint64_t)(widx < w1 ? words[widx] : 0u) << (32 - nb);
-        widx++;
-        nb += 32;
-      }
-      const uint32_t e = lut[(uint32_t)(buf >> (64 - kLutBits))];
-      int L = (int)(e & 31u);
-      int s = (int)(e >> 5);
-      if (L == 0) {
-        const uint32_t v = (uint32_t)(buf >> (64 - kLMax));
-        s = -1;
-        for (int l = kLutBits + 1; l <= kLMax; l++) {
-          const uint32_t c = v >> (kLMax - l);
-          if (c - lfirst[l] < lcnt[l]) { s = sorted[lbase[l] + (c - lfirst[l])]; L = l; break; }
-        }
-        if (s < 0) { ok = false; break; }
-      }
-      buf <<= L;
-      nb -= L;
-      int32_t dv, code;
-      if (s >= 1024) {
-        const int kk = (s - 1024) / 2 + 9;
-        const uint32_t ev = (uint32_t)(buf >> (64 - kk));
-        buf <<= kk;
-        nb -= kk;
-        L += kk;
-        const int32_t mag = (1 << kk) + (int32_t)ev;
-        dv = (s & 1) ? -mag : mag;
-        code = dv;
-      } else if (s == 0) {
-        // outlier: its residual sits in the exception list (sorted by key)
-        const uint32_t want = (uint32_t)(g.start + (uint64_t)k);
-        uint64_t lo = e0, hi = e1;
-        while (lo < hi) {  // records sorted by position; outlier before patch
-          const uint64_t mid = (lo + hi) >> 1;
-          if ((exc[2 * mid] & ~kTagPatch) < want) lo = mid + 1;
-          else hi = mid;
-        }
-        if (lo < e1 && exc[2 * lo] == want) dv = (int32_t)exc[2 * lo + 1];
-        else { ok = false; break; }
-        code = -32768;
-      } else {
-        dv = s - 512;
-        code = dv;
-      }
-      used += (uint32_t)L;
-      if (vec) {
-        const int j = k - k0;
-        pack[(j >> 1) & 3] |= ((uint32_t)code & 0xffffu) << (16 * (j & 1));
-        if ((j & 7) == 7 || k + 1 == k1) {
-          if ((j & 7) == 7)
-            *reinterpret_cast<int4 *>(dst + (k - 7)) =
-                make_int4((int)pack[0], (int)pack[1], (int)pack[2], (int)pack[3]);
-          else
-            for (int q = (j & ~7); q <= j; q++)
-              dst[k0 + q] = (int16_t)(pack[(q >> 1) & 3] >> (16 * (q & 1)));
-          pack[0] = pack[1] = pack[2] = pack[3] = 0;
-        }
-      } else {
-        dst[k] = (int16_t)code;
-      }
-      if (PROJ) {
-        if (NDIM == 3) atomicAdd(&accz[wv][y * TX + xx], (uint32_t)dv);
-        if (NDIM >= 2) atomicAdd(&accy[wv][z * TX + xx], (uint32_t)dv);
-        rowsum += dv;
-        if (++xx == ex) {
-          atomicAdd(&accx[wv][z * TY + y], (uint32_t)rowsum);
-          rowsum = 0;
-          xx = 0;
-          if (++y == ey) { y = 0; z++; }
-        }
-      }
-    }
-    if (PROJ && ok && xx != 0) atomicAdd(&accx[wv][z * TY + y], (uint32_t)rowsum);
-    if (!ok || used != cb) ok = false;
-  }
-  if (!ok) atomicOr(&dp->corrupt, 1u);
-  if (!PROJ) return;
-  // the wave's accumulators are complete once every lane is past this point
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const int ez = (int)g.ez;
-  if (NDIM == 3 && P.gz > 1)
-    for (int i = lane; i < ey * ex; i += 64) {
-      const int yy = i / ex, x2 = i - yy * ex;
-      A.fz[((uint64_t)g.a * P.ny + g.y0 + yy) * P.nx + g.x0 + x2] = accz[wv][yy * TX + x2];
-    }
-  if (NDIM >= 2 && P.gy > 1)
-    for (int i = lane; i < ez * ex; i += 64) {
-      const int zz = i / ex, x2 = i - zz * ex;
-      A.fy[((g.z0 + zz) * P.gy + g.b) * P.nx + g.x0 + x2] = accy[wv][zz * TX + x2];
-    }
-  if (P.gx > 1)
-    for (int i = lane; i < ez * ey; i += 64) {
-      const int zz = i / ey, yy = i - zz * ey;
-      A.fx[((g.z0 + zz) * P.ny + g.y0 + yy) * P.gx + g.c] = accx[wv][zz * TY + yy];
-    }
+  if (lane >= (int)g.nck) return;
+  const uint32_t *exc = reinterpret_cast<const uint32_t *>(blob + P.off_exc);
+  const int k0 = lane * kChunk;
+  const int k1 = k0 + kChunk < nt ? k0 + kChunk : nt;
+  int16_t *dst = codes + g.start;
+  const bool vec = ((g.start + (uint64_t)k0) & 7) == 0;
+  uint32_t used = 0;
+  bool ok;
+  if (in_lds)
+    ok = decode_chunk(WordsLds{mine, nw}, incl - cb, k0, k1, lut, lfirst, lcnt, lbase, sorted, exc, e0,
+                      e1, g.start, dst, vec, &used);
+  else
+    ok = decode_chunk(WordsGlobal{gw, nw}, incl - cb, k0, k1, lut, lfirst, lcnt, lbase, sorted, exc,
+                      e0, e1, g.start, dst, vec, &used);
+  if (!ok || used != cb) atomicOr(&dp->corrupt, 1u);
 }
 
 // ---------------------------------------------------------------------------
-// Reconstruction: one tile per workgroup.  Residuals from the decoded codes
-// (outliers from the exception list), local inclusive prefix sums modulo
-// 2^32 in LDS, the halo terms of the GLOBAL domain, bin midpoints q * 2eb,
-// patched points exact, coalesced store.
+// Residuals of one tile into LDS (tile layout), outliers from the exception
+// list.  Returns false (uniformly) if the list is inconsistent.
+template <int NDIM>
+__device__ inline bool load_tile_residuals(const Plan &P, const TileGeo &g, const int16_t *codes,
+                                           const uint32_t *exc, uint64_t e0, uint64_t e1,
+                                           int32_t *dl, uint32_t *pmask, uint32_t *s_bad) {
+  using G = DGeo<NDIM>;
+  constexpr int TY = G::TY, TX = G::TX;
+  const int tid = threadIdx.x;
+  const int ez = (int)g.ez, ey = (int)g.ey, ex = (int)g.ex, nt = (int)g.nt;
+  const bool full = ez == G::TZ && ey == TY && ex == TX;
+  if (pmask) pmask[tid] = 0;
+  if (tid == 0) *s_bad = 0;
+  const int16_t *src = codes + g.start;
+  if (full && (g.start & 7) == 0) {
+    for (int i = 8 * tid; i < nt; i += 8 * kBlock) {
+      const int4 v = *reinterpret_cast<const int4 *>(src + i);
+      const uint32_t w[4] = {(uint32_t)v.x, (uint32_t)v.y, (uint32_t)v.z, (uint32_t)v.w};
+#pragma unroll
+      for (int h = 0; h < 8; h++) dl[dphys(i + h)] = (int32_t)(int16_t)(w[h >> 1] >> (16 * (h & 1)));
+    }
+  } else {
+    for (int i = tid; i < nt; i += kBlock) {
+      const int z = i / (ey * ex), rem = i - z * ey * ex, y = rem / ex, xx = rem - y * ex;
+      dl[dphys((z * TY + y) * TX + xx)] = (int32_t)src[i];
+    }
+  }
+  __syncthreads();
+  for (uint64_t e = e0 + tid; e < e1; e += kBlock) {
+    const uint32_t key = exc[2 * e];
+    const uint64_t pos = key & ~kTagPatch;
+    if (pos < g.start || pos >= g.start + (uint64_t)nt) { atomicOr(s_bad, 1u); continue; }
+    const int si = (int)(pos - g.start);
+    if (key & kTagPatch) {
+      if (pmask) atomicOr(&pmask[si >> 5], 1u << (si & 31));
+    } else {
+      const int z = si / (ey * ex), rem = si - z * ey * ex, y = rem / ex, xx = rem - y * ex;
+      const int o = dphys((z * TY + y) * TX + xx);
+      if (dl[o] != -32768) atomicOr(s_bad, 1u);
+      dl[o] = (int32_t)exc[2 * e + 1];
+    }
+  }
+  __syncthreads();
+  return *s_bad == 0;
+}
+
+// ---------------------------------------------------------------------------
+// GLOBAL domain, per tile: projections of the residual along z, y and x and
+// their 2D prefix sums inside the tile,
+//   Fz[y][x] = sum_{z, y' <= y, x' <= x} d,  Fy[z][x] = sum_{z' <= z, y, x' <= x} d,
+//   Fx[z][y] = sum_{z' <= z, y' <= y, x} d,
+// plus the edge vectors Gx[x] = Fz[last y][x], Gy[y] = Fz[y][last x],
+// Gz[z] = Fy[z][last x] and the tile total T.
+template <int NDIM>
+__global__ __launch_bounds__(kBlock) void k_proj(Plan P, const uint8_t *__restrict__ blob,
+                                                 DecodeArgs A, DevParams *__restrict__ dp,
+                                                 const int16_t *__restrict__ codes) {
+  using G = DGeo<NDIM>;
+  constexpr int TZ = G::TZ, TY = G::TY, TX = G::TX;
+  constexpr int LDS = dphys(kTilePts - 1) + 1;
+  constexpr int FZ = NDIM == 3 ? TY * TX : 1, FY = TZ * TX, FX = TZ * TY;
+  __shared__ int32_t dl[LDS];
+  __shared__ uint32_t fz[FZ], fy[FY], fx[FX];
+  __shared__ uint32_t s_bad;
+  if (dp->corrupt) return;
+  const int tid = threadIdx.x;
+  const uint64_t t = blockIdx.x;
+  const TileGeo g = tile_geo(P, t);
+  const int ez = (int)g.ez, ey = (int)g.ey, ex = (int)g.ex;
+  const uint64_t *teo = reinterpret_cast<const uint64_t *>(blob + P.off_teo);
+  const uint64_t e0 = teo[t], e1 = teo[t + 1];
+  if (e0 > e1 || e1 > A.n_exc) return;  // reported by the decode kernel
+  const uint32_t *exc = reinterpret_cast<const uint32_t *>(blob + P.off_exc);
+  if (!load_tile_residuals<NDIM>(P, g, codes, exc, e0, e1, dl, nullptr, &s_bad)) {
+    if (tid == 0) atomicOr(&dp->corrupt, 1u);
+    return;
+  }
+  // projections
+  if (NDIM == 3)
+    for (int i = tid; i < ey * ex; i += kBlock) {
+      const int y = i / ex, xx = i - y * ex;
+      uint32_t v = 0;
+      for (int z = 0; z < ez; z++) v += (uint32_t)dl[dphys((z * TY + y) * TX + xx)];
+      fz[y * TX + xx] = v;
+    }
+  if (NDIM >= 2)
+    for (int i = tid; i < ez * ex; i += kBlock) {
+      const int z = i / ex, xx = i - z * ex;
+      uint32_t v = 0;
+      for (int y = 0; y < ey; y++) v += (uint32_t)dl[dphys((z * TY + y) * TX + xx)];
+      fy[z * TX + xx] = v;
+    }
+  if (NDIM == 1) {
+    if (tid < 64) {  // one wave, fixed order
+      uint32_t v = 0;
+      for (int i = tid; i < ex; i += 64) v += (uint32_t)dl[dphys(i)];
+      v = wave_sum_u32(v);
+      if (tid == 0) fx[0] = v;
+    }
+  } else {
+    for (int i = tid; i < ez * ey; i += kBlock) {
+      const int z = i / ey, y = i - z * ey;
+      uint32_t v = 0;
+      for (int xx = 0; xx < ex; xx++) v += (uint32_t)dl[dphys((z * TY + y) * TX + xx)];
+      fx[z * TY + y] = v;
+    }
+  }
+  __syncthreads();
+  // 2D prefix sums inside the tile: rows then columns
+  if (NDIM == 3) {
+    for (int y = tid; y < ey; y += kBlock) {
+      uint32_t r = 0;
+      for (int xx = 0; xx < ex; xx++) { r += fz[y * TX + xx]; fz[y * TX + xx] = r; }
+    }
+  }
+  if (NDIM >= 2) {
+    for (int z = tid; z < ez; z += kBlock) {
+      uint32_t r = 0;
+      for (int xx = 0; xx < ex; xx++) { r += fy[z * TX + xx]; fy[z * TX + xx] = r; }
+    }
+    for (int z = tid; z < ez; z += kBlock) {
+      uint32_t r = 0;
+      for (int y = 0; y < ey; y++) { r += fx[z * TY + y]; fx[z * TY + y] = r; }
+    }
+  }
+  __syncthreads();
+  if (NDIM == 3) {
+    for (int xx = tid; xx < ex; xx += kBlock) {
+      uint32_t r = 0;
+      for (int y = 0; y < ey; y++) { r += fz[y * TX + xx]; fz[y * TX + xx] = r; }
+    }
+    for (int xx = tid; xx < ex; xx += kBlock) {
+      uint32_t r = 0;
+      for (int z = 0; z < ez; z++) { r += fy[z * TX + xx]; fy[z * TX + xx] = r; }
+    }
+    for (int y = tid; y < ey; y += kBlock) {
+      uint32_t r = 0;
+      for (int z = 0; z < ez; z++) { r += fx[z * TY + y]; fx[z * TY + y] = r; }
+    }
+  }
+  __syncthreads();
+  // store faces and edge vectors (tile-major slots)
+  if (NDIM == 3) {
+    uint32_t *o = A.fz + t * FZ;
+    for (int i = tid; i < FZ; i += kBlock) o[i] = fz[i];
+    for (int xx = tid; xx < TX; xx += kBlock) A.gx[t * TX + xx] = xx < ex ? fz[(ey - 1) * TX + xx] : 0u;
+    for (int y = tid; y < TY; y += kBlock) A.gy[t * TY + y] = y < ey ? fz[y * TX + ex - 1] : 0u;
+    if (tid == 0) A.tt[t] = fz[(ey - 1) * TX + ex - 1];
+  }
+  if (NDIM >= 2) {
+    uint32_t *o = A.fy + t * FY;
+    for (int i = tid; i < FY; i += kBlock) o[i] = fy[i];
+    for (int z = tid; z < TZ; z += kBlock) A.gz[t * TZ + z] = z < ez ? fy[z * TX + ex - 1] : 0u;
+  }
+  {
+    uint32_t *o = A.fx + t * FX;
+    for (int i = tid; i < FX; i += kBlock) o[i] = fx[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Reconstruction: one tile per workgroup.  Local inclusive prefix sums
+// (modulo 2^32) in LDS, the halo terms of the GLOBAL domain,
+//   q = L + A[y][x] + B[z][x] + C[z][y]
+//   A = sum over earlier tiles along z of Fz
+//   B = sum over earlier tiles along y of Fy + sum_{a' < a, b' < b} Gx
+//   C = sum over earlier tiles along x of Fx + sum_{b' < b, c' < c} Gz
+//       + sum_{a' < a, c' < c} Gy + sum_{a' < a, b' < b, c' < c} T,
+// then bin midpoints q * 2eb, patched points exact, coalesced store.
 template <typename T, int NDIM, bool GLOBAL>
 __global__ __launch_bounds__(kBlock) void k_rec(Plan P, const uint8_t *__restrict__ blob,
                                                 DecodeArgs A, DevParams *__restrict__ dp,
@@ -279,11 +416,12 @@ __global__ __launch_bounds__(kBlock) void k_rec(Plan P, const uint8_t *__restric
   using G = DGeo<NDIM>;
   constexpr int TZ = G::TZ, TY = G::TY, TX = G::TX;
   constexpr int LDS = dphys(kTilePts - 1) + 1;
+  constexpr int FZ = NDIM == 3 ? TY * TX : 1, FY = TZ * TX, FX = TZ * TY;
   __shared__ int32_t dl[LDS];
   __shared__ uint32_t pmask[kTilePts / 32];
-  __shared__ uint32_t hA[NDIM == 3 ? TY * TX : 1];
-  __shared__ uint32_t hB[NDIM >= 2 ? TZ * TX : 1];
-  __shared__ uint32_t hC[TZ * TY];
+  __shared__ uint32_t hA[FZ];
+  __shared__ uint32_t hB[FY];
+  __shared__ uint32_t hC[FX];
   __shared__ uint32_t scr[8];
   __shared__ uint32_t s_bad;
 
@@ -297,45 +435,25 @@ __global__ __launch_bounds__(kBlock) void k_rec(Plan P, const uint8_t *__restric
   const uint64_t e0 = teo[t], e1 = teo[t + 1];
   if (e0 > e1 || e1 > A.n_exc) return;  // reported by the decode kernel
   const uint32_t *exc = reinterpret_cast<const uint32_t *>(blob + P.off_exc);
-  pmask[tid] = 0;
-  if (tid == 0) s_bad = 0;
 
-  // residuals into LDS (tile layout), 8 codes per load where aligned
-  const int16_t *src = codes + g.start;
-  if (full && (g.start & 7) == 0) {
-    for (int i = 8 * tid; i < nt; i += 8 * kBlock) {
-      const int4 v = *reinterpret_cast<const int4 *>(src + i);
-      const uint32_t w[4] = {(uint32_t)v.x, (uint32_t)v.y, (uint32_t)v.z, (uint32_t)v.w};
-#pragma unroll
-      for (int h = 0; h < 8; h++) {
-        const int32_t c = (int32_t)(int16_t)(w[h >> 1] >> (16 * (h & 1)));
-        dl[dphys(i + h)] = c;  // full tile: layout index == stream index
+  // halo terms first: they do not depend on this tile's residuals
+  if (GLOBAL) {
+    if (NDIM == 3)
+      for (int i = tid; i < FZ; i += kBlock) hA[i] = A.fz[t * FZ + i];
+    if (NDIM >= 2)
+      for (int i = tid; i < FY; i += kBlock) {
+        uint32_t v = A.fy[t * FY + i];
+        if (NDIM == 3) v += A.gx[t * TX + (i % TX)];
+        hB[i] = v;
       }
-    }
-  } else {
-    for (int i = tid; i < nt; i += kBlock) {
-      const int z = i / (ey * ex), rem = i - z * ey * ex, y = rem / ex, xx = rem - y * ex;
-      dl[dphys((z * TY + y) * TX + xx)] = (int32_t)src[i];
-    }
-  }
-  __syncthreads();
-  // exception list: outlier residuals and patch marks
-  for (uint64_t e = e0 + tid; e < e1; e += kBlock) {
-    const uint32_t key = exc[2 * e];
-    const uint64_t pos = key & ~kTagPatch;
-    if (pos < g.start || pos >= g.start + (uint64_t)nt) { atomicOr(&s_bad, 1u); continue; }
-    const int si = (int)(pos - g.start);
-    if (key & kTagPatch) {
-      atomicOr(&pmask[si >> 5], 1u << (si & 31));
-    } else {
-      const int z = si / (ey * ex), rem = si - z * ey * ex, y = rem / ex, xx = rem - y * ex;
-      const int o = dphys((z * TY + y) * TX + xx);
-      if (dl[o] != -32768) atomicOr(&s_bad, 1u);
-      dl[o] = (int32_t)exc[2 * e + 1];
+    for (int i = tid; i < FX; i += kBlock) {
+      uint32_t v = A.fx[t * FX + i];
+      if (NDIM >= 2) v += A.gz[t * TZ + i / TY];
+      if (NDIM == 3) v += A.gy[t * TY + i % TY] + A.tt[t];
+      hC[i] = v;
     }
   }
-  __syncthreads();
-  if (s_bad) {
+  if (!load_tile_residuals<NDIM>(P, g, codes, exc, e0, e1, dl, pmask, &s_bad)) {
     if (tid == 0) atomicOr(&dp->corrupt, 1u);
     return;
   }
@@ -381,44 +499,6 @@ __global__ __launch_bounds__(kBlock) void k_rec(Plan P, const uint8_t *__restric
           dl[o] = (int32_t)run;
         }
       }
-    }
-  }
-
-  // halo terms from the scanned face arrays
-  if (GLOBAL) {
-    if (NDIM == 3) {
-      for (int i = tid; i < ey * ex; i += kBlock) {
-        const int y = i / ex, xx = i - (i / ex) * ex;
-        uint32_t v = 0;
-        if (g.a > 0) {
-          const uint32_t *F = A.fz + (uint64_t)(g.a - 1) * P.ny * P.nx;
-          const int64_t yy = (int64_t)g.y0 + y, xg = (int64_t)g.x0 + xx;
-          const int64_t yp = (int64_t)g.y0 - 1, xp = (int64_t)g.x0 - 1;
-          v = F[yy * P.nx + xg];
-          if (yp >= 0) v -= F[yp * P.nx + xg];
-          if (xp >= 0) v -= F[yy * P.nx + xp];
-          if (yp >= 0 && xp >= 0) v += F[yp * P.nx + xp];
-        }
-        hA[y * TX + xx] = v;
-      }
-    }
-    if (NDIM >= 2) {
-      for (int i = tid; i < ez * ex; i += kBlock) {
-        const int z = i / ex, xx = i - (i / ex) * ex;
-        uint32_t v = 0;
-        if (g.b > 0) {
-          const uint32_t *F = A.fy + ((g.z0 + z) * P.gy + (g.b - 1)) * P.nx;
-          v = F[g.x0 + xx];
-          if (g.x0 > 0) v -= F[g.x0 - 1];
-        }
-        hB[z * TX + xx] = v;
-      }
-    }
-    for (int i = tid; i < ez * ey; i += kBlock) {
-      const int z = i / ey, y = i - (i / ey) * ey;
-      uint32_t v = 0;
-      if (g.c > 0) v = A.fx[((g.z0 + z) * P.ny + g.y0 + y) * P.gx + (g.c - 1)];
-      hC[z * TY + y] = v;
     }
   }
   __syncthreads();
@@ -469,10 +549,10 @@ __global__ __launch_bounds__(kBlock) void k_rec(Plan P, const uint8_t *__restric
 }
 
 // ---------------------------------------------------------------------------
-// pass B: inclusive scans (modulo 2^32) of a row-major u32 array along one
-// axis.  Element (o, k, i) sits at (o * len + k) * inner + i.  The axis is
-// cut into segments of 32; each thread scans one segment of one column after
-// adding the totals of the column's earlier segments.
+// Exclusive scans (modulo 2^32) of a row-major u32 array along one axis.
+// Element (o, k, i) sits at (o * len + k) * inner + i.  The axis is cut into
+// segments of 32; each thread scans one segment of one column after adding
+// the totals of the column's earlier segments.
 constexpr int kSeg = 32;
 
 __global__ __launch_bounds__(kBlock) void k_seg_sums(const uint32_t *__restrict__ a, uint64_t outer,
@@ -491,7 +571,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_sums(const uint32_t *__restrict_
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_seg_scan(uint32_t *__restrict__ a, uint64_t outer,
+__global__ __launch_bounds__(kBlock) void k_seg_excl(uint32_t *__restrict__ a, uint64_t outer,
                                                      uint64_t len, uint64_t inner,
                                                      const uint32_t *__restrict__ sums) {
   const uint64_t nseg = (len + kSeg - 1) / kSeg;
@@ -509,31 +589,23 @@ __global__ __launch_bounds__(kBlock) void k_seg_scan(uint32_t *__restrict__ a, u
     for (int k = 0; k < kSeg; k++) v[k] = (k0 + k < k1) ? p[(k0 + k) * inner] : 0u;
 #pragma unroll
     for (int k = 0; k < kSeg; k++) {
-      run += v[k];
       if (k0 + k < k1) p[(k0 + k) * inner] = run;
+      run += v[k];
     }
   }
 }
 
-static void scan_axis(uint32_t *a, uint64_t outer, uint64_t len, uint64_t inner, uint32_t *tmp,
+static void excl_axis(uint32_t *a, uint64_t outer, uint64_t len, uint64_t inner, uint32_t *tmp,
                       hipStream_t s) {
-  if (len <= 1) return;
+  if (outer == 0 || inner == 0 || len == 0) return;
   const uint64_t nseg = (len + kSeg - 1) / kSeg;
   const uint64_t total = outer * nseg * inner;
   const uint64_t b = total / kBlock + 1;
   const dim3 grid((uint32_t)(b < 65536 ? b : 65536)), blk(kBlock);
   if (nseg > 1)
     hipLaunchKernelGGL(k_seg_sums, grid, blk, 0, s, a, outer, len, inner, tmp);
-  hipLaunchKernelGGL(k_seg_scan, grid, blk, 0, s, a, outer, len, inner,
+  hipLaunchKernelGGL(k_seg_excl, grid, blk, 0, s, a, outer, len, inner,
                      nseg > 1 ? (const uint32_t *)tmp : nullptr);
-}
-
-// inclusive prefix sums of a (d0, d1, d2) array along all three axes
-static void scan3(uint32_t *a, uint64_t d0, uint64_t d1, uint64_t d2, uint32_t *tmp,
-                  hipStream_t s) {
-  scan_axis(a, d0 * d1, d2, 1, tmp, s);
-  scan_axis(a, d0, d1, d2, tmp, s);
-  scan_axis(a, 1, d0, d1 * d2, tmp, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -544,23 +616,41 @@ __global__ void k_csum_check(const uint8_t *__restrict__ blob, DevParams *__rest
 
 template <typename T, int NDIM>
 static void launch_dec_t(const Plan &P, const uint8_t *blob, const DecodeArgs &A, DevParams *dp,
-                         int16_t *codes, uint32_t *tmp, T *out, hipStream_t s, Timer *tm) {
+                         int16_t *codes, uint32_t *tmp, uint32_t stage_words, T *out,
+                         hipStream_t s, Timer *tm) {
+  using G = DGeo<NDIM>;
   const dim3 dgrid((uint32_t)ceil_div(P.n_tiles, kDecWaves)), grid((uint32_t)P.n_tiles), blk(kBlock);
+  const size_t dyn = (size_t)kDecWaves * (stage_words + 1) * 4;
+  hipLaunchKernelGGL((k_decode<NDIM>), dgrid, blk, dyn, s, P, blob, A, dp, codes, stage_words);
+  tm->mark(s, "decode");
   if (P.domain == FPSZ_DOMAIN_GLOBAL) {
-    hipLaunchKernelGGL((k_decode<NDIM, true>), dgrid, blk, 0, s, P, blob, A, dp, codes);
-    tm->mark(s, "decode");
-    if (NDIM == 3 && P.gz > 1) scan3(A.fz, P.gz, P.ny, P.nx, tmp, s);
-    if (NDIM >= 2 && P.gy > 1) scan3(A.fy, P.nz, P.gy, P.nx, tmp, s);
-    if (P.gx > 1) scan3(A.fx, P.nz, P.ny, P.gx, tmp, s);
+    hipLaunchKernelGGL((k_proj<NDIM>), grid, blk, 0, s, P, blob, A, dp, codes);
+    tm->mark(s, "proj");
+    const uint64_t gz = P.gz, gy = P.gy, gx = P.gx;
+    constexpr uint64_t TZ = G::TZ, TY = G::TY, TX = G::TX;
+    constexpr uint64_t FZ = NDIM == 3 ? TY * TX : 1, FY = TZ * TX, FX = TZ * TY;
+    if (NDIM == 3) {
+      excl_axis(A.fz, 1, gz, gy * gx * FZ, tmp, s);                  // Fz along z tiles
+      excl_axis(A.gx, gz, gy, gx * TX, tmp, s);                      // Gx over (a, b)
+      excl_axis(A.gx, 1, gz, gy * gx * TX, tmp, s);
+      excl_axis(A.gy, gz * gy, gx, TY, tmp, s);                      // Gy over (a, c)
+      excl_axis(A.gy, 1, gz, gy * gx * TY, tmp, s);
+      excl_axis(A.tt, gz * gy, gx, 1, tmp, s);                       // T over (a, b, c)
+      excl_axis(A.tt, gz, gy, gx, tmp, s);
+      excl_axis(A.tt, 1, gz, gy * gx, tmp, s);
+    }
+    if (NDIM >= 2) {
+      excl_axis(A.fy, gz, gy, gx * FY, tmp, s);                      // Fy along y tiles
+      excl_axis(A.gz, gz * gy, gx, TZ, tmp, s);                      // Gz over (b, c)
+      excl_axis(A.gz, gz, gy, gx * TZ, tmp, s);
+    }
+    excl_axis(A.fx, gz * gy, gx, FX, tmp, s);                        // Fx along x tiles
     tm->mark(s, "face_scan");
     hipLaunchKernelGGL((k_rec<T, NDIM, true>), grid, blk, 0, s, P, blob, A, dp, codes, out);
-    tm->mark(s, "rec");
   } else {
-    hipLaunchKernelGGL((k_decode<NDIM, false>), dgrid, blk, 0, s, P, blob, A, dp, codes);
-    tm->mark(s, "decode");
     hipLaunchKernelGGL((k_rec<T, NDIM, false>), grid, blk, 0, s, P, blob, A, dp, codes, out);
-    tm->mark(s, "rec");
   }
+  tm->mark(s, "rec");
 }
 
 hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const DecompressWs &W,
@@ -588,14 +678,24 @@ hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const Deco
   A.fz = W.fz;
   A.fy = W.fy;
   A.fx = W.fx;
+  A.gx = W.gx;
+  A.gy = W.gy;
+  A.gz = W.gz;
+  A.tt = W.tt;
+  // LDS staging per wave: ~1.25x the average words per tile, 256..3328 (the
+  // workgroup stays under 64 KiB of LDS); larger tiles read global memory
+  const uint64_t avg = P.n_tiles ? n_words / P.n_tiles : 0;
+  uint64_t sw = (avg + avg / 4 + 255) & ~(uint64_t)255;
+  sw = sw < 256 ? 256 : (sw > 3328 ? 3328 : sw);
+  const uint32_t stage_words = (uint32_t)sw;
   if (P.dtype == FPSZ_F32) {
-    if (P.ndim == 1) launch_dec_t<float, 1>(P, blob, A, W.P, W.codes, W.tmp, (float *)out, s, tm);
-    else if (P.ndim == 2) launch_dec_t<float, 2>(P, blob, A, W.P, W.codes, W.tmp, (float *)out, s, tm);
-    else launch_dec_t<float, 3>(P, blob, A, W.P, W.codes, W.tmp, (float *)out, s, tm);
+    if (P.ndim == 1) launch_dec_t<float, 1>(P, blob, A, W.P, W.codes, W.tmp, stage_words, (float *)out, s, tm);
+    else if (P.ndim == 2) launch_dec_t<float, 2>(P, blob, A, W.P, W.codes, W.tmp, stage_words, (float *)out, s, tm);
+    else launch_dec_t<float, 3>(P, blob, A, W.P, W.codes, W.tmp, stage_words, (float *)out, s, tm);
   } else {
-    if (P.ndim == 1) launch_dec_t<double, 1>(P, blob, A, W.P, W.codes, W.tmp, (double *)out, s, tm);
-    else if (P.ndim == 2) launch_dec_t<double, 2>(P, blob, A, W.P, W.codes, W.tmp, (double *)out, s, tm);
-    else launch_dec_t<double, 3>(P, blob, A, W.P, W.codes, W.tmp, (double *)out, s, tm);
+    if (P.ndim == 1) launch_dec_t<double, 1>(P, blob, A, W.P, W.codes, W.tmp, stage_words, (double *)out, s, tm);
+    else if (P.ndim == 2) launch_dec_t<double, 2>(P, blob, A, W.P, W.codes, W.tmp, stage_words, (double *)out, s, tm);
+    else launch_dec_t<double, 3>(P, blob, A, W.P, W.codes, W.tmp, stage_words, (double *)out, s, tm);
   }
   return hipGetLastError();
 }

@@ -338,8 +338,9 @@ struct DecompressWs {
   uint32_t *lut;       // 2048 entries: (symbol << 5) | length, 0 = long/invalid
   uint32_t *ltab;      // first[19], count[19], base[19]
   uint16_t *sorted;    // symbols in canonical order
-  uint32_t *fz, *fy, *fx;  // tile-face projection arrays (GLOBAL domain)
-  uint32_t *tmp;           // segment sums of the face scans
+  uint32_t *fz, *fy, *fx;  // per-tile faces (GLOBAL domain)
+  uint32_t *gx, *gy, *gz, *tt;  // per-tile edge vectors and totals
+  uint32_t *tmp;           // segment sums of the scans
   int16_t *codes;          // decoded residual codes, stream order
   uint64_t zero_bytes;
 };
