@@ -40,15 +40,53 @@ def parse():
                     help="planes of the field the CPU oracle is timed on")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-kernel HIP-event timing")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, copy the field once with a plain device copy "
+                         "(the reference kernel for scaling HBM byte counters)")
     return ap.parse_args()
+
+
+# Source files whose kernels the HBM traffic figures under profiles/ were
+# measured on; a figure whose recorded hash differs is stale and not reported.
+SRC_FILES = ["paper_1805_07384_amd/csrc/compress.hip", "paper_1805_07384_amd/csrc/decompress.hip",
+             "paper_1805_07384_amd/csrc/api.hip", "paper_1805_07384_amd/csrc/fpsz_internal.h",
+             "paper_1805_07384_amd/build.py", "include/fpsz.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_lognormal512_sweep.txt")
+
+
+def source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in SRC_FILES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read() + b"\0")
+    return h.hexdigest()
+
+
+def measured_traffic(domain: str):
+    """Per-launch HBM bytes of each stage (FETCH_SIZE + WRITE_SIZE, scaled by
+    the copy-kernel calibration) from the committed counter summary, or {}
+    when the summary is missing or was taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return {}
+    rec, tr = None, {}
+    with open(TRAFFIC_FILE) as fh:
+        for ln in fh:
+            f = ln.split()
+            if len(f) == 2 and f[0] == "source_sha256":
+                rec = f[1]
+            elif len(f) == 4 and f[0] == "traffic" and f[1] == domain:
+                tr[f[2]] = float(f[3])
+    return tr if rec == source_hash() else {}
 
 
 # Algorithmic bytes per element of each kernel (s = element size, b = bits
 # per value of the blob).  Compression must read the field twice (the bound
 # needs the global value range before any point is quantized) and write the
 # blob; decompression reads the blob and writes the field; the check reads
-# both fields.  The residual-code intermediate, halos and face arrays are
-# implementation traffic, not algorithmic.
+# both fields.  The residual-code intermediate (2 B per point, written by
+# quant and read by encode; written by decode and read by rec), halos and
+# face arrays are implementation traffic, not algorithmic.
 def algorithmic_bytes(stage: str, n: int, s: int, b: float) -> float:
     per = {
         "range": s,
@@ -150,6 +188,9 @@ def main():
         one_step(rec)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if args.copy_calibration:
+        out.copy_(x)
+        torch.cuda.synchronize()
     ms_per_step = (t1 - t0) / args.steps * 1e3
     total_bytes = n * s * len(psnrs)
     value = total_bytes / ((t1 - t0) / args.steps) / 1e9
@@ -162,6 +203,7 @@ def main():
         d = float(np.median(r["d"]))
         v = float(np.median(r["v"]))
         info, stats = r["info"], r["stats"]
+        stage_avg = {nm: round(float(np.mean(v)), 4) for nm, v in r["stages"].items()}
         per_target.append({
             "psnr": p, "achieved_psnr": round(stats["psnr"], 4),
             "dpsnr": round(stats["psnr"] - p, 4), "bits_per_value": round(info["bits_per_value"], 4),
@@ -169,6 +211,7 @@ def main():
             "verify_gbps": round(n * s / v / 1e9, 2),
             "n_outliers": info["n_outliers"], "n_patches": info["n_patches"],
             "max_abs_err_over_eb": stats["max_abs_err"] / info["eb"], "n_over_eb": stats["n_over_eb"],
+            "kernel_ms": stage_avg,
         })
         for nm, ms_list in r["stages"].items():
             kernel_ms.setdefault(nm, []).append((float(np.mean(ms_list)), p, info["bits_per_value"]))
@@ -188,9 +231,15 @@ def main():
             kernels[nm] = entry
         timed = {k: v for k, v in kernels.items() if "alg_gbps" in v}
         dom = max(timed, key=lambda k: timed[k]["ms"])
+        tr = measured_traffic(args.domain) if shape == (512, 512, 512) else {}
         roofline = {"bound": "hbm", "kernel": dom, "achieved": timed[dom]["alg_gbps"],
                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": timed[dom]["frac"],
-                    "traffic": None}
+                    "traffic": tr.get(dom),
+                    "algorithmic_bytes_per_launch": round(float(np.mean(
+                        [algorithmic_bytes(dom, n, s, b) for _, _, b in kernel_ms[dom]])))}
+        for k, v in tr.items():
+            if k in kernels:
+                kernels[k]["traffic"] = v
 
     line = {
         "metric": "compress+decompress+verify GB/s at target PSNR (sweep), |dPSNR| dB",

@@ -142,7 +142,7 @@ DecompressLayout decompress_layout(const Plan &P) {
   const uint64_t fx = (uint64_t)P.tz * P.ty;
   uint64_t o = align256(sizeof(DevParams));
   L.off_lut = o;
-  o = align256(o + 4 * 2048);
+  o = align256(o + 4 * 4096);
   L.off_ltab = o;
   o = align256(o + 4 * 96);
   L.off_sorted = o;
@@ -426,7 +426,7 @@ fpsz_status fpsz_compress(fpsz_ctx *ctx, const void *field_dev, int ndim, const 
     return fail(ctx, FPSZ_E_RANGE, "max|x| / (2 eb) exceeds the integer range of %s",
                 dtype == FPSZ_F32 ? "float32 (2^23)" : "float64 (2^27)");
   if (D.status != 0) return fail(ctx, (fpsz_status)D.status, "device status %u", D.status);
-  if (D.spin_fail) return fail(ctx, FPSZ_E_DEVICE, "look-back wait gave up");
+  if (D.spin_fail) return fail(ctx, FPSZ_E_DEVICE, "device-side wait or invariant failed (code %u)", D.spin_fail);
   *blob_bytes = D.blob_bytes;
   if (D.overflow || D.blob_bytes > blob_capacity)
     return fail(ctx, FPSZ_E_CAPACITY, "blob needs %llu bytes, capacity %llu",

@@ -704,17 +704,78 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(Plan P, DevParams *__re
     }
     __syncthreads();
     if (s_maxl > kLMax) {
-      if (tid == 0) {
-        for (int d = s_maxl < 63 ? s_maxl : 63; d > kLMax; d--) {
-          while (bits[d] > 0) {
-            int j = d - 2;
-            while (j > 0 && bits[j] == 0) j--;
-            bits[d] -= 2;
-            bits[d - 1] += 1;
-            bits[j + 1] += 2;
-            bits[j] -= 1;
+      // Wave 0 holds the per-length counts in registers (lane = length) and
+      // computes, level by level, the state that moving one pair at a time
+      // reaches.  At level i, m = bits[i] / 2 moves each put one code on
+      // level i - 1 and take one split from the deepest non-empty level
+      // j <= i - 2.  Those splits walk the levels 1..i-2 depth first: fully
+      // using a code on level j costs 2^(i-1-j) - 1 moves and leaves
+      // 2^(i-1-j) codes on level i - 1.  A suffix sum of these costs finds
+      // the levels used up, the one partly used, and how far; the partly
+      // used code is then split down its path.
+      if (tid < 64) {
+        constexpr uint64_t kSat = 1ull << 40;  // above any move count
+        const int lane = tid;
+        uint32_t b = bits[lane];
+        const int dtop = s_maxl < 63 ? s_maxl : 63;
+        bool broken = false;
+        for (int i = dtop; i > kLMax; i--) {
+          const uint32_t Bi = __shfl(b, i, 64);
+          if (Bi & 1u) { broken = true; break; }  // not a full code tree
+          const uint64_t m = Bi >> 1;
+          if (lane == i) b = 0;
+          if (lane == i - 1) b += (uint32_t)m;
+          if (m == 0) continue;
+          const bool reg = lane >= 1 && lane <= i - 2;
+          const int sh = reg ? i - 1 - lane : 0;  // 1..61 inside the region
+          const uint64_t cj = reg ? (1ull << sh) - 1 : 0;
+          const uint64_t cs = cj < kSat ? cj : kSat;
+          uint64_t T = (uint64_t)b * cs;
+          T = T < kSat ? T : kSat;
+          uint64_t suf = T;  // inclusive suffix sum over lanes >= lane
+#pragma unroll
+          for (int o = 1; o < 64; o <<= 1) {
+            const uint64_t u = __shfl_down(suf, o, 64);
+            if (lane + o < 64) suf += u;
+          }
+          const uint64_t total = __shfl(suf, 1, 64);
+          if (total < m) { broken = true; break; }  // would split past level 1
+          const uint64_t before = suf - T;
+          uint64_t k = 0, r = 0;
+          if (reg && before < m) {
+            const uint64_t avail = m - before;
+            const uint64_t q = avail / cj;
+            k = q < (uint64_t)b ? q : (uint64_t)b;
+            r = avail - k * cj;
+          }
+          const bool part = reg && before < m && k < (uint64_t)b && r > 0;
+          b -= (uint32_t)k;
+          const uint64_t out = wave_sum_u64(k ? (k << sh) : 0);
+          if (lane == i - 1) b += (uint32_t)out;
+          const uint64_t pm = __ballot(part);
+          if (pm) {
+            int j = __ffsll((unsigned long long)pm) - 1;
+            uint64_t rr = __shfl(r, j, 64);
+            while (rr > 0 && j < i - 2) {
+              if (lane == j) b -= 1;
+              if (lane == j + 1) b += 2;
+              rr -= 1;
+              j += 1;
+              const uint64_t c = (1ull << (i - 1 - j)) - 1;
+              if (rr >= c) {
+                if (lane == j) b -= 1;
+                if (lane == i - 1) b += 1u << (i - 1 - j);
+                rr -= c;
+              }
+            }
+            if (rr > 0) { broken = true; break; }
           }
         }
+        bits[lane] = b;
+        if (broken && lane == 0) atomicOr(&dp->spin_fail, 4u);
+      }
+      __syncthreads();
+      if (tid == 0) {
         // sorted position ranges per length, longest first
         uint32_t st = 0;
         for (int l = kLMax; l >= 1; l--) { lstart[l] = st; st += bits[l]; }
@@ -950,14 +1011,21 @@ __global__ __launch_bounds__(kBlock) void k_checksum(const uint8_t *__restrict__
                                                      int use_dp_bytes) {
   if (use_dp_bytes && (dp->status != 0 || dp->overflow)) return;
   const uint64_t bytes = use_dp_bytes ? dp->blob_bytes : bytes_limit;
-  const uint64_t nw = bytes / 4;
+  const uint64_t nw = bytes / 4;  // a multiple of 2 (blobs are 8-byte sized)
   const uint32_t *w = reinterpret_cast<const uint32_t *>(blob);
+  const uint4 *w4 = reinterpret_cast<const uint4 *>(blob);
   uint64_t s = 0;
-  for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < nw;
-       j += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t v = (j == 50 || j == 51) ? 0u : w[j];
-    s += mix64(v, j);
+  // 16-byte loads when the blob allows them (it is only required to be 8-aligned)
+  const uint64_t n4 = (uintptr_t)blob % 16 == 0 ? nw / 4 : 0;
+  const uint64_t gsz = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < n4; q += gsz) {
+    const uint4 v = w4[q];
+    const uint64_t j = 4 * q;
+    s += mix64(v.x, j) + mix64(v.y, j + 1);
+    s += mix64((j + 2 == 50) ? 0u : v.z, j + 2) + mix64((j + 3 == 51) ? 0u : v.w, j + 3);
   }
+  for (uint64_t j = n4 * 4 + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < nw; j += gsz)
+    s += mix64((j == 50 || j == 51) ? 0u : w[j], j);
   s = wave_sum_u64(s);
   if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long *)&dp->checksum, (unsigned long long)s);
 }
@@ -977,10 +1045,11 @@ __global__ void k_checksum_store(DevParams *__restrict__ dp, uint8_t *__restrict
 // ---------------------------------------------------------------------------
 template <typename T, int NDIM, bool GLOBAL>
 static void launch_quant_d(const Plan &P, const T *x, const CompressWs &W, uint8_t *blob,
-                           hipStream_t s) {
+                           hipStream_t s, Timer *tm) {
   const uint32_t grid = (uint32_t)(P.n_tiles < 2048 ? P.n_tiles : 2048);
   hipLaunchKernelGGL((k_quant<T, NDIM, GLOBAL, false>), dim3(grid), dim3(kBlock), 0, s, x, P, W.P,
                      W.hist, W.exc_cnt, W.stage, (const uint64_t *)W.exc_off, W.codes, blob);
+  tm->mark(s, "quant");
   hipLaunchKernelGGL(k_exc_scan, dim3(1), dim3(kScanThreads), 0, s, P, W.P, W.exc_cnt, W.exc_off,
                      blob);
   const uint32_t cgrid = (uint32_t)ceil_div(P.n_tiles, kBlock / 64);
@@ -993,9 +1062,9 @@ static void launch_quant_d(const Plan &P, const T *x, const CompressWs &W, uint8
 
 template <typename T, int NDIM>
 static void launch_quant(const Plan &P, const T *x, const CompressWs &W, uint8_t *blob,
-                         hipStream_t s) {
-  if (P.domain == FPSZ_DOMAIN_GLOBAL) launch_quant_d<T, NDIM, true>(P, x, W, blob, s);
-  else launch_quant_d<T, NDIM, false>(P, x, W, blob, s);
+                         hipStream_t s, Timer *tm) {
+  if (P.domain == FPSZ_DOMAIN_GLOBAL) launch_quant_d<T, NDIM, true>(P, x, W, blob, s, tm);
+  else launch_quant_d<T, NDIM, false>(P, x, W, blob, s, tm);
 }
 
 template <typename T>
@@ -1006,10 +1075,10 @@ static void launch_compress_t(const Plan &P, const T *x, const CompressWs &W, ui
   hipLaunchKernelGGL(k_range<T>, dim3(rgrid), dim3(kBlock), 0, s, x, P, W.P,
                      (uint64_t *)W.range_part);
   tm->mark(s, "range");
-  if (P.ndim == 1) launch_quant<T, 1>(P, x, W, blob, s);
-  else if (P.ndim == 2) launch_quant<T, 2>(P, x, W, blob, s);
-  else launch_quant<T, 3>(P, x, W, blob, s);
-  tm->mark(s, "quant");
+  if (P.ndim == 1) launch_quant<T, 1>(P, x, W, blob, s, tm);
+  else if (P.ndim == 2) launch_quant<T, 2>(P, x, W, blob, s, tm);
+  else launch_quant<T, 3>(P, x, W, blob, s, tm);
+  tm->mark(s, "exceptions");
   hipLaunchKernelGGL(k_codebook, dim3(1), dim3(kCbThreads), 0, s, P, W.P, W.hist, W.code_len,
                      W.code, blob);
   tm->mark(s, "codebook");
@@ -1018,11 +1087,12 @@ static void launch_compress_t(const Plan &P, const T *x, const CompressWs &W, ui
                      W.code, W.word_state, blob);
   tm->mark(s, "encode");
   hipLaunchKernelGGL(k_header, dim3(1), dim3(kBlock), 0, s, P, W.P, blob);
+  tm->mark(s, "header");
   const uint64_t cw = P.capacity / 4 / kBlock + 1;
   const uint32_t cgrid = (uint32_t)(cw < 1024 ? cw : 1024);
   hipLaunchKernelGGL(k_checksum, dim3(cgrid), dim3(kBlock), 0, s, blob, (uint64_t)0, W.P, 1);
   hipLaunchKernelGGL(k_checksum_store, dim3(1), dim3(1), 0, s, W.P, blob);
-  tm->mark(s, "header+checksum");
+  tm->mark(s, "checksum");
 }
 
 hipError_t launch_compress(const Plan &P, const void *x, const CompressWs &W, uint8_t *blob,

@@ -28,6 +28,8 @@ template <> struct DGeo<3> { static constexpr int TZ = 16, TY = 16, TX = 32; };
 
 __device__ __host__ constexpr int dphys(int L) { return L + (L >> 5); }
 
+constexpr int kDecLut = 12;  // bits of the decoder lookup table
+
 struct DecodeArgs {
   uint64_t off_words, n_words, n_exc;
   double e2;
@@ -67,12 +69,12 @@ __global__ __launch_bounds__(1024) void k_dec_tables(Plan P, const uint8_t *__re
     return;
   }
   canonical_from_lengths(lens, code, lcount, lfirst, lbase, sorted, wcnt);
-  for (int i = tid; i < (1 << kLutBits); i += blockDim.x) lut[i] = 0;
+  for (int i = tid; i < (1 << kDecLut); i += blockDim.x) lut[i] = 0;
   __syncthreads();
   for (int s = tid; s < kNSym; s += blockDim.x) {
     const int l = lens[s];
-    if (l == 0 || l > kLutBits) continue;
-    const uint32_t lo = code[s] << (kLutBits - l), hi = (code[s] + 1) << (kLutBits - l);
+    if (l == 0 || l > kDecLut) continue;
+    const uint32_t lo = code[s] << (kDecLut - l), hi = (code[s] + 1) << (kDecLut - l);
     for (uint32_t i = lo; i < hi; i++) lut[i] = ((uint32_t)s << 5) | (uint32_t)l;
   }
   if (tid <= kLMax) {
@@ -84,111 +86,102 @@ __global__ __launch_bounds__(1024) void k_dec_tables(Plan P, const uint8_t *__re
 
 // ---------------------------------------------------------------------------
 // Decode: one wave per tile, lane k decodes chunk k (128 symbols).  The
-// tile's words are staged in LDS when they fit (kStageWords per wave, sized
-// by the host from the average bits per tile); the reader takes the 64 bits
-// at any bit position p from words p/32 and p/32 + 1, so there is no refill
-// state.  Symbols go through an 11-bit table in LDS with a canonical search
-// for longer codes.  The residual codes are written in stream order, eight
-// per 16-byte store (outliers as -32768; their residual is in the exception
-// list).
+// tile's words are staged in LDS in windows of `stage_words`; lanes whose
+// chunk lies in the window decode it (tiles larger than a window take
+// several rounds).  The reader takes the 64 bits at bit position p from words
+// p/32 and p/32 + 1, so there is no refill state, and the symbol step has no
+// branch except for codes longer than the 12-bit table.  The residual codes
+// are written in stream order, eight per 16-byte store (outliers as -32768;
+// their residual is in the exception list, whose outlier count is checked).
 constexpr int kDecWaves = 4;
+constexpr int kLut = 12;  // bits of the decoder table
 
-struct WordsLds {
-  const uint32_t *w;  // nw + 1 staged words (the last is zero)
-  uint32_t nw;
-  __device__ uint32_t operator()(uint32_t i) const { return w[i <= nw ? i : nw]; }
-};
-struct WordsGlobal {
-  const uint32_t *w;  // tile's first word
-  uint32_t nw;        // words in the tile
-  __device__ uint32_t operator()(uint32_t i) const { return i < nw ? w[i] : 0u; }
+struct DecTabs {
+  const uint16_t *lut;     // (symbol << 5) | length, 0 = longer than kLut
+  const uint32_t *lim;     // [l]: left-justified (18-bit) end of the codes of length <= l
+  const int32_t *off;      // [l]: base index - first code of length l
+  const uint16_t *sorted;  // symbols in canonical order
 };
 
-// Decode symbols [k0, k1) of a tile starting at bit p (relative to the
-// tile's first word).  Returns false on an invalid code or a missing outlier
-// record; *used receives the bits consumed.
-template <typename RD>
-__device__ inline bool decode_chunk(const RD &rd, uint32_t p, int k0, int k1, const uint16_t *lut,
-                                    const uint32_t *lfirst, const uint32_t *lcnt,
-                                    const uint32_t *lbase, const uint16_t *sorted,
-                                    const uint32_t *exc, uint64_t e0, uint64_t e1, uint64_t start,
-                                    int16_t *dst, bool vec, uint32_t *used) {
+// Decode `cnt` symbols starting at bit p of the staged words `wb` (nw + 1
+// words, the last one zero).  Codes go to dst (8-aligned when vec).
+// Returns the number of outlier symbols; sets *bad on an invalid code.
+template <bool VEC>
+__device__ inline uint32_t decode_run(const uint32_t *wb, uint32_t nw, uint32_t p, int cnt,
+                                      const DecTabs &T, int16_t *dst, uint32_t *used, bool *bad) {
   const uint32_t p0 = p;
-  for (int kb = k0; kb < k1; kb += 8) {
+  uint32_t nout = 0;
+  bool badv = false;
+  for (int kb = 0; kb < cnt; kb += 8) {
     uint32_t pk[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int h = 0; h < 8; h++) {
-      const int k = kb + h;
-      if (k < k1) {
-        const uint32_t i = p >> 5;
-        const uint64_t win = (((uint64_t)rd(i) << 32) | (uint64_t)rd(i + 1)) << (p & 31);
-        const uint32_t e = lut[(uint32_t)(win >> (64 - kLutBits))];
-        int L = (int)(e & 31u);
-        int s = (int)(e >> 5);
-        if (L == 0) {
-          const uint32_t v = (uint32_t)(win >> (64 - kLMax));
-          s = -1;
-          for (int l = kLutBits + 1; l <= kLMax; l++) {
-            const uint32_t c = v >> (kLMax - l);
-            if (c - lfirst[l] < lcnt[l]) { s = sorted[lbase[l] + (c - lfirst[l])]; L = l; break; }
-          }
-          if (s < 0) return false;
-        }
-        int32_t code;
-        if (s >= 1024) {
-          const int kk = (s - 1024) / 2 + 9;
-          const uint32_t ev = (uint32_t)((win << L) >> (64 - kk));
-          const int32_t mag = (1 << kk) + (int32_t)ev;
-          code = (s & 1) ? -mag : mag;
-          L += kk;
-        } else if (s == 0) {
-          // the residual must be in the exception list
-          const uint32_t want = (uint32_t)(start + (uint64_t)k);
-          uint64_t lo = e0, hi = e1;
-          while (lo < hi) {  // records sorted by position; outlier before patch
-            const uint64_t mid = (lo + hi) >> 1;
-            if ((exc[2 * mid] & ~kTagPatch) < want) lo = mid + 1;
-            else hi = mid;
-          }
-          if (!(lo < e1 && exc[2 * lo] == want)) return false;
-          code = -32768;
-        } else {
-          code = s - 512;
-        }
-        p += (uint32_t)L;
-        pk[h >> 1] |= ((uint32_t)code & 0xffffu) << (16 * (h & 1));
-        if (!vec) dst[k] = (int16_t)code;
+      const bool live = kb + h < cnt;  // the last group of a short chunk
+      uint32_t i = p >> 5;
+      i = i < nw ? i : nw;
+      const uint32_t a = wb[i], b = wb[i + (i < nw ? 1 : 0)];
+      const uint32_t sh = p & 31;
+      // top 32 bits of the 64-bit window starting at bit p
+      const uint32_t top = sh ? ((a << sh) | (b >> (32 - sh))) : a;
+      const uint32_t nx = sh ? (b << sh) : b;  // the next 32 bits (only 32 - sh valid)
+      uint32_t e = T.lut[top >> (32 - kLut)];
+      uint32_t L = e & 31u, s = e >> 5;
+      if (L == 0) {
+        // canonical search over lengths kLut+1..18 (left-justified 18-bit limits)
+        const uint32_t v = top >> (32 - kLMax);
+        uint32_t l = kLut + 1;
+        while (l < kLMax && v >= T.lim[l]) l++;
+        const int32_t idx = T.off[l] + (int32_t)(v >> (kLMax - l));
+        const bool ok = v >= T.lim[l - 1] && v < T.lim[l] && idx >= 0 && idx < kNSym;
+        s = ok ? T.sorted[idx] : 0u;
+        L = l;
+        badv |= !ok && live;
       }
+      // escape classes: k raw bits of |d| - 2^k follow the code
+      const bool esc = s >= 1024u;
+      const uint32_t kk = esc ? (s >> 1) - 503u : 0u;  // (s - 1024) / 2 + 9
+      // bits [L, L + kk) of the window lie in `top` because L + kk <= 32
+      const uint32_t ev = kk ? __builtin_amdgcn_ubfe(top, 32u - L - kk, kk) : 0u;
+      const int32_t mag = (int32_t)((1u << kk) + ev);
+      int32_t code = esc ? ((s & 1u) ? -mag : mag) : (int32_t)s - 512;
+      code = s == 0 ? -32768 : code;
+      nout += (s == 0 && live) ? 1u : 0u;
+      (void)nx;
+      p += live ? L + kk : 0u;
+      pk[h >> 1] |= ((uint32_t)code & 0xffffu) << (16 * (h & 1));
+      if (!VEC && live) dst[kb + h] = (int16_t)code;
     }
-    if (vec) {
-      if (kb + 8 <= k1) {
+    if (VEC) {
+      if (kb + 8 <= cnt) {
         *reinterpret_cast<int4 *>(dst + kb) = make_int4((int)pk[0], (int)pk[1], (int)pk[2], (int)pk[3]);
       } else {
-        for (int h = 0; kb + h < k1; h++) dst[kb + h] = (int16_t)(pk[h >> 1] >> (16 * (h & 1)));
+        for (int h = 0; kb + h < cnt; h++) dst[kb + h] = (int16_t)(pk[h >> 1] >> (16 * (h & 1)));
       }
     }
   }
   *used = p - p0;
-  return true;
+  *bad = badv;
+  return nout;
 }
 
 template <int NDIM>
 __global__ __launch_bounds__(kBlock) void k_decode(Plan P, const uint8_t *__restrict__ blob,
                                                    DecodeArgs A, DevParams *__restrict__ dp,
                                                    int16_t *__restrict__ codes, uint32_t stage_words) {
-  __shared__ uint16_t lut[1 << kLutBits];
-  __shared__ uint32_t lfirst[kLMax + 1], lcnt[kLMax + 1], lbase[kLMax + 1];
+  __shared__ uint16_t lut[1 << kLut];
+  __shared__ uint32_t lim[kLMax + 1];
+  __shared__ int32_t off[kLMax + 1];
   __shared__ uint16_t sorted[kNSym];
   extern __shared__ uint32_t wstage[];  // kDecWaves * (stage_words + 1)
 
   if (dp->corrupt) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int i = tid; i < (1 << kLutBits); i += kBlock) lut[i] = (uint16_t)A.lut[i];
+  for (int i = tid; i < (1 << kLut); i += kBlock) lut[i] = (uint16_t)A.lut[i];
   for (int i = tid; i < kNSym; i += kBlock) sorted[i] = A.sorted[i];
   if (tid <= kLMax) {
-    lfirst[tid] = A.ltab[tid];
-    lcnt[tid] = A.ltab[32 + tid];
-    lbase[tid] = A.ltab[64 + tid];
+    const uint32_t first = A.ltab[tid], cnt = A.ltab[32 + tid], base = A.ltab[64 + tid];
+    lim[tid] = tid ? (first + cnt) << (kLMax - tid) : 0u;
+    off[tid] = (int32_t)base - (int32_t)first;
   }
   __syncthreads();
   const uint64_t t = (uint64_t)blockIdx.x * kDecWaves + wv;
@@ -205,14 +198,6 @@ __global__ __launch_bounds__(kBlock) void k_decode(Plan P, const uint8_t *__rest
   }
   const uint32_t nw = (uint32_t)(w1 - w0);
   const uint32_t *gw = reinterpret_cast<const uint32_t *>(blob + A.off_words) + w0;
-  uint32_t *mine = wstage + (size_t)wv * (stage_words + 1);
-  const bool in_lds = nw <= stage_words;
-  if (in_lds) {
-    for (uint32_t i = lane; i <= nw; i += 64) mine[i] = i < nw ? gw[i] : 0u;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
   const uint16_t *cbits = reinterpret_cast<const uint16_t *>(blob + P.off_cb);
   const uint32_t cb = lane < (int)g.nck ? cbits[g.chunk_base + lane] : 0u;
   const uint32_t incl = wave_incl_scan_u32(cb);
@@ -221,21 +206,50 @@ __global__ __launch_bounds__(kBlock) void k_decode(Plan P, const uint8_t *__rest
     if (lane == 0) atomicOr(&dp->corrupt, 1u);
     return;
   }
-  if (lane >= (int)g.nck) return;
-  const uint32_t *exc = reinterpret_cast<const uint32_t *>(blob + P.off_exc);
+  const DecTabs T{lut, lim, off, sorted};
+  uint32_t *mine = wstage + (size_t)wv * (stage_words + 1);
   const int k0 = lane * kChunk;
-  const int k1 = k0 + kChunk < nt ? k0 + kChunk : nt;
-  int16_t *dst = codes + g.start;
-  const bool vec = ((g.start + (uint64_t)k0) & 7) == 0;
-  uint32_t used = 0;
-  bool ok;
-  if (in_lds)
-    ok = decode_chunk(WordsLds{mine, nw}, incl - cb, k0, k1, lut, lfirst, lcnt, lbase, sorted, exc, e0,
-                      e1, g.start, dst, vec, &used);
-  else
-    ok = decode_chunk(WordsGlobal{gw, nw}, incl - cb, k0, k1, lut, lfirst, lcnt, lbase, sorted, exc,
-                      e0, e1, g.start, dst, vec, &used);
-  if (!ok || used != cb) atomicOr(&dp->corrupt, 1u);
+  const int cnt = lane < (int)g.nck ? (k0 + kChunk < nt ? kChunk : nt - k0) : 0;
+  const uint32_t cstart = incl - cb;                 // chunk's first bit
+  const uint32_t cfw = cstart >> 5;                  // first word
+  const uint32_t clw = incl ? (incl - 1) >> 5 : 0;   // last word holding its bits
+  int16_t *dst = codes + g.start + k0;
+  // uniform over the wave: k0 is a multiple of 128
+  const bool vec = __builtin_amdgcn_readfirstlane((uint32_t)((g.start & 7) == 0)) != 0;
+  bool todo = cnt > 0;
+  bool bad = false;
+  uint32_t used = cb, nout = 0;
+  uint32_t base = 0;
+  for (int round = 0; round < 64; round++) {
+    if (!__any(todo)) break;
+    // next window starts at the first word of the earliest pending chunk
+    uint32_t st = todo ? cfw : 0xffffffffu;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) { const uint32_t u = __shfl_xor(st, o, 64); st = u < st ? u : st; }
+    base = st;
+    const uint32_t wn = nw - base < stage_words ? nw - base : stage_words;
+    for (uint32_t i = lane; i <= wn; i += 64) mine[i] = i < wn ? gw[base + i] : 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const bool fits = todo && clw < base + wn;
+    if (fits) {
+      bool b2;
+      if (vec) nout += decode_run<true>(mine, wn, cstart - 32 * base, cnt, T, dst, &used, &b2);
+      else nout += decode_run<false>(mine, wn, cstart - 32 * base, cnt, T, dst, &used, &b2);
+      bad |= b2;
+      todo = false;
+    }
+    __builtin_amdgcn_wave_barrier();  // the window is rewritten next round
+  }
+  if (todo) bad = true;
+  // every outlier symbol must have its record
+  uint32_t nrec = 0;
+  const uint32_t *exc = reinterpret_cast<const uint32_t *>(blob + P.off_exc);
+  for (uint64_t e = e0 + lane; e < e1; e += 64) nrec += (exc[2 * e] & kTagPatch) ? 0u : 1u;
+  nrec = wave_sum_u32(nrec);
+  nout = wave_sum_u32(nout);
+  if (bad || used != cb || nrec != nout) atomicOr(&dp->corrupt, 1u);
 }
 
 // ---------------------------------------------------------------------------
@@ -662,7 +676,7 @@ hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const Deco
   e = launch_checksum(blob, P.capacity, W.P, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_csum_check, dim3(1), dim3(1), 0, s, blob, W.P);
-  tm->mark(s, "checksum");
+  tm->mark(s, "checksum_check");
   hipLaunchKernelGGL(k_dec_tables, dim3(1), dim3(1024), 0, s, P, blob, W.P, W.lut, W.ltab,
                      W.sorted);
   tm->mark(s, "tables");
@@ -682,11 +696,11 @@ hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const Deco
   A.gy = W.gy;
   A.gz = W.gz;
   A.tt = W.tt;
-  // LDS staging per wave: ~1.25x the average words per tile, 256..3328 (the
-  // workgroup stays under 64 KiB of LDS); larger tiles read global memory
+  // LDS window per wave: about the average words per tile, 512..2048; larger
+  // tiles are decoded in several windows
   const uint64_t avg = P.n_tiles ? n_words / P.n_tiles : 0;
-  uint64_t sw = (avg + avg / 4 + 255) & ~(uint64_t)255;
-  sw = sw < 256 ? 256 : (sw > 3328 ? 3328 : sw);
+  uint64_t sw = (avg + 255) & ~(uint64_t)255;
+  sw = sw < 512 ? 512 : (sw > 2048 ? 2048 : sw);
   const uint32_t stage_words = (uint32_t)sw;
   if (P.dtype == FPSZ_F32) {
     if (P.ndim == 1) launch_dec_t<float, 1>(P, blob, A, W.P, W.codes, W.tmp, stage_words, (float *)out, s, tm);
@@ -725,21 +739,51 @@ hipError_t launch_const_fill_bits(const Plan &P, uint64_t bits, void *out, hipSt
 // ---------------------------------------------------------------------------
 // a12: SSE, max |e| and #(|e| > eb) in float64 with a fixed reduction tree:
 // block b owns a fixed contiguous span; partials are combined in block order.
-template <typename T>
+template <typename T, bool VEC> struct Vec16 { using V = T; static constexpr int W = 1; };
+template <> struct Vec16<float, true> { using V = float4; static constexpr int W = 4; };
+template <> struct Vec16<double, true> { using V = double2; static constexpr int W = 2; };
+
+// Thread t of the grid takes 16-byte vectors t, t + G, t + 2G, ... (G the
+// number of threads); the vector tail goes to thread 0.  The assignment and
+// the per-thread order depend only on n and the grid size, so the float64
+// sum is reproducible.
+template <typename T, bool VEC>
 __global__ __launch_bounds__(kBlock) void k_verify(const T *__restrict__ x, const T *__restrict__ y,
                                                    uint64_t n, double eb, double *__restrict__ part) {
-  const uint64_t span = (n + gridDim.x - 1) / gridDim.x;
-  const uint64_t b0 = blockIdx.x * span;
-  const uint64_t b1 = b0 + span < n ? b0 + span : n;
+  using V = typename Vec16<T, VEC>::V;
+  constexpr int W = Vec16<T, VEC>::W;
+  const uint64_t G = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t nv = n / W;
+  const V *xv = reinterpret_cast<const V *>(x);
+  const V *yv = reinterpret_cast<const V *>(y);
   double sse = 0.0, mx = 0.0;
   uint64_t over = 0;
-  for (uint64_t i = b0 + threadIdx.x; i < b1; i += kBlock) {
-    const double e = (double)x[i] - (double)y[i];
+  auto acc = [&](T a, T b) {
+    const double e = (double)a - (double)b;
     sse += e * e;
     const double ae = fabs(e);
     mx = ae > mx ? ae : mx;
     over += ae > eb ? 1 : 0;
+  };
+  uint64_t v = t;
+  for (; v + G < nv; v += 2 * G) {
+    const V a0 = xv[v], b0 = yv[v], a1 = xv[v + G], b1 = yv[v + G];
+    const T *pa0 = reinterpret_cast<const T *>(&a0), *pb0 = reinterpret_cast<const T *>(&b0);
+    const T *pa1 = reinterpret_cast<const T *>(&a1), *pb1 = reinterpret_cast<const T *>(&b1);
+#pragma unroll
+    for (int k = 0; k < W; k++) acc(pa0[k], pb0[k]);
+#pragma unroll
+    for (int k = 0; k < W; k++) acc(pa1[k], pb1[k]);
   }
+  if (v < nv) {
+    const V a0 = xv[v], b0 = yv[v];
+    const T *pa0 = reinterpret_cast<const T *>(&a0), *pb0 = reinterpret_cast<const T *>(&b0);
+#pragma unroll
+    for (int k = 0; k < W; k++) acc(pa0[k], pb0[k]);
+  }
+  if (t == 0)
+    for (uint64_t i = nv * W; i < n; i++) acc(x[i], y[i]);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     sse += __shfl_xor(sse, o, 64);
@@ -796,14 +840,18 @@ __global__ __launch_bounds__(kBlock) void k_verify_final(const double *__restric
 hipError_t launch_verify(const void *x, const void *y, uint64_t n, int dtype, double eb,
                          DevParams *P, void *part, hipStream_t s, Timer *tm) {
   tm->mark(s, "begin");
-  const uint64_t want = n / (kBlock * 8) + 1;
+  const uint64_t want = n / (kBlock * 16) + 1;
   const int nb = (int)(want < (uint64_t)kVerifyBlocks ? want : kVerifyBlocks);
-  if (dtype == FPSZ_F32)
-    hipLaunchKernelGGL(k_verify<float>, dim3(nb), dim3(kBlock), 0, s, (const float *)x,
-                       (const float *)y, n, eb, (double *)part);
-  else
-    hipLaunchKernelGGL(k_verify<double>, dim3(nb), dim3(kBlock), 0, s, (const double *)x,
-                       (const double *)y, n, eb, (double *)part);
+  const bool vec = ((uintptr_t)x | (uintptr_t)y) % 16 == 0;
+  if (dtype == FPSZ_F32) {
+    auto k = vec ? k_verify<float, true> : k_verify<float, false>;
+    hipLaunchKernelGGL(k, dim3(nb), dim3(kBlock), 0, s, (const float *)x, (const float *)y, n, eb,
+                       (double *)part);
+  } else {
+    auto k = vec ? k_verify<double, true> : k_verify<double, false>;
+    hipLaunchKernelGGL(k, dim3(nb), dim3(kBlock), 0, s, (const double *)x, (const double *)y, n,
+                       eb, (double *)part);
+  }
   tm->mark(s, "verify");
   hipLaunchKernelGGL(k_verify_final, dim3(1), dim3(kBlock), 0, s, (const double *)part, nb, P);
   tm->mark(s, "verify_final");

@@ -139,6 +139,43 @@ def test_parity_config1_full_size(ctx, orc):
     assert abs(info["eb"] - 100 * orc.eb_rel(80.0)) < 1e-12
 
 
+def _fibonacci_walk(n_sym=30, seed=4):
+    """1D random walk whose Lorenzo residuals take n_sym values with
+    Fibonacci counts, at the PSNR where 2 eb = 1: the unlimited Huffman tree
+    is n_sym - 1 deep, so the 18-bit limit rebalances many levels."""
+    fib = [1, 1]
+    while len(fib) < n_sym:
+        fib.append(fib[-1] + fib[-2])
+    vals = [0]
+    for k in range(1, n_sym):
+        vals += [k, -k]
+    steps = np.repeat(np.array(vals[:n_sym]), fib[::-1])
+    np.random.default_rng(seed).shuffle(steps)
+    s = np.cumsum(steps)
+    r = float(s.max() - s.min())
+    return s.astype(np.float32), float(-20 * np.log10((1 / (2 * r)) / np.sqrt(3)))
+
+
+def test_parity_length_limit(ctx, orc):
+    x, psnr = _fibonacci_walk()
+    _, t = orc.compress(x, psnr, trace=True)
+    h = t["hist"]
+    assert orc.huffman_unlimited(h[h > 0]).max() >= 28 and t["code_len"].max() == 18
+    _parity(ctx, orc, x, psnr, 0)
+    # fewer symbols: a shallower overflow (only the last levels rebalanced)
+    x, psnr = _fibonacci_walk(21, seed=5)
+    _parity(ctx, orc, x, psnr, 1)
+
+
+@pytest.mark.timeout(400)
+def test_parity_config2_full_size(ctx, orc):
+    # 3D float32 512^3 lognormal field, 80 dB: the benchmark workload, whole
+    # blob and whole reconstruction compared
+    x = synth.field_3d_lognormal(shape=(512, 512, 512), seed=2)
+    info, _ = _parity(ctx, orc, x, 80.0, 0)
+    assert info["bits_per_value"] > 0
+
+
 def test_constant_and_tiny(ctx, orc):
     from paper_1805_07384_amd import fpsz
     for shape in [(1,), (7,), (3, 3), (2, 2, 2)]:
