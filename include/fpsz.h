@@ -172,6 +172,69 @@ fpsz_status fpsz_last_stage_times(const fpsz_ctx *ctx, fpsz_stage_time *out, int
 fpsz_status fpsz_compress_workspace_offset(int ndim, const uint64_t *dims, fpsz_dtype dtype,
                                            int which, uint64_t *offset);
 
+/* ---- batched compression ------------------------------------------------
+ * Many fields, each with its own shape, dtype, target PSNR and Lorenzo
+ * domain, compressed together: applications write 100+ fields per snapshot
+ * and the user fixes the PSNR of each (Sec. I; the fixed-PSNR workflow after
+ * Eq. 7 applied per field).  Fields are grouped by (dtype, ndim, domain);
+ * every pipeline step is one launch per group over all its fields.  The
+ * blobs are byte-identical to those of one fpsz_compress call per field. */
+typedef struct {
+  const void *field_dev;  /* device, C order, element-aligned */
+  int32_t ndim;           /* 1..3 */
+  int32_t dtype;          /* fpsz_dtype */
+  uint64_t dims[3];       /* slowest-first; entries past ndim ignored */
+  double target_psnr;
+  int32_t domain;         /* fpsz_domain */
+  int32_t reserved;       /* 0 */
+  void *blob_dev;         /* device output, 8-byte aligned */
+  uint64_t blob_capacity;
+} fpsz_field_desc;
+
+typedef struct fpsz_batch fpsz_batch;
+
+/* Workspace (device, 256-aligned) for a batch of these fields: a job table,
+ * a parameter table and one compress workspace per field. */
+fpsz_status fpsz_batch_workspace_bytes(int n, const fpsz_field_desc *fields, uint64_t *bytes);
+
+/* Plan a batch of n (1..65535) fields: checks every field (INVALID_ARG /
+ * CAPACITY name the field in fpsz_last_error), lays out the workspace,
+ * uploads the job table (synchronously) and, with use_graph != 0, captures
+ * the whole launch sequence into a hipGraph on a private stream.  The
+ * workspace, fields and blobs must stay allocated, and the workspace unused
+ * by anything else, until fpsz_batch_destroy.  Host memory of the batch
+ * object: O(n). */
+fpsz_status fpsz_batch_create(fpsz_ctx *ctx, int n, const fpsz_field_desc *fields,
+                              void *workspace_dev, uint64_t workspace_bytes, int use_graph,
+                              fpsz_batch **out);
+
+/* Run the batch on `stream` (graph replay when captured), synchronize, and
+ * report per field (caller's order): blob_bytes[i] (the size needed on
+ * CAPACITY), info[i] (may be NULL) and status[i].  Returns OK when every
+ * field succeeded, else the first failing field's status. */
+fpsz_status fpsz_batch_run(fpsz_batch *b, void *stream, uint64_t *blob_bytes, fpsz_info *info,
+                           fpsz_status *status);
+
+/* Time the batch for candidate launch shapes (grid sizes of the range,
+ * quantization, encoding and checksum kernels per field group, one at a time,
+ * `reps` runs each, median) and keep the fastest; re-captures the graph.  The
+ * shapes do not change any output bit.  *best_ms (may be NULL) receives the
+ * best batch time.  The blobs hold valid output of the last timed run. */
+fpsz_status fpsz_batch_autotune(fpsz_batch *b, void *stream, int reps, double *best_ms);
+
+/* Current launch shape of field group `cls` (groups in (dtype, ndim, domain)
+ * order): shape4 = {range blocks, quantization grid, encode grid, checksum
+ * blocks} per field. */
+fpsz_status fpsz_batch_launch_shape(const fpsz_batch *b, int cls, uint32_t *shape4);
+
+void fpsz_batch_destroy(fpsz_batch *b);
+
+/* One-shot convenience: create (no graph), run, destroy. */
+fpsz_status fpsz_compress_batch(fpsz_ctx *ctx, int n, const fpsz_field_desc *fields,
+                                void *workspace_dev, uint64_t workspace_bytes,
+                                uint64_t *blob_bytes, fpsz_info *info, fpsz_status *status,
+                                void *stream);
+
 #ifdef __cplusplus
 }
 #endif

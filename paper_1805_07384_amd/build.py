@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfpsz.so")
-SOURCES = ["compress.hip", "decompress.hip", "api.hip"]
+SOURCES = ["compress.hip", "decompress.hip", "api.hip", "batch.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -20,7 +20,26 @@
 namespace fpsz {
 
 // ---------------------------------------------------------------------------
+// The field a block works on: the by-value job, or entry blockIdx.y of the
+// batch array.
+__device__ inline CJob select_job(const CJob &one, const CJob *__restrict__ jobs) {
+  CJob j;
+  if (jobs) j = jobs[blockIdx.y];
+  else j = one;
+  return j;
+}
+
 __global__ void k_fill_zero(uint32_t *p, uint64_t nwords) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nwords;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+// clears each field's parameter block and counters
+__global__ void k_zero_jobs(CJob one, const CJob *__restrict__ jobs) {
+  const CJob J = select_job(one, jobs);
+  uint32_t *p = reinterpret_cast<uint32_t *>(J.W.P);
+  const uint64_t nwords = J.W.zero_bytes / 4;
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nwords;
        i += (uint64_t)gridDim.x * blockDim.x)
     p[i] = 0;
@@ -54,9 +73,12 @@ __device__ inline void acc_range(T v, T &mn, T &mx, uint32_t &bad) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_range(const T *__restrict__ x, Plan P,
-                                                  DevParams *__restrict__ dp,
-                                                  uint64_t *__restrict__ part) {
+__global__ __launch_bounds__(kBlock) void k_range(CJob one, const CJob *__restrict__ jobs) {
+  const CJob J = select_job(one, jobs);
+  const T *__restrict__ x = static_cast<const T *>(J.x);
+  const Plan P = J.P;
+  DevParams *__restrict__ dp = J.W.P;
+  uint64_t *__restrict__ part = static_cast<uint64_t *>(J.W.range_part);
   using V = typename VecOf<T>::V;
   constexpr int W = VecOf<T>::W;
   const uint64_t n = P.n;
@@ -284,14 +306,17 @@ __device__ inline void load_row(const T *__restrict__ x, const Plan &P, const Ti
 }
 
 template <typename T, int NDIM, bool GLOBAL, bool RECORDS>
-__global__ __launch_bounds__(kBlock) void k_quant(const T *__restrict__ x, Plan P,
-                                                  DevParams *__restrict__ dp,
-                                                  uint32_t *__restrict__ hist_g,
-                                                  uint32_t *__restrict__ exc_cnt,
-                                                  uint32_t *__restrict__ stage,
-                                                  const uint64_t *__restrict__ exc_off,
-                                                  int16_t *__restrict__ codes,
-                                                  uint8_t *__restrict__ blob) {
+__global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restrict__ jobs) {
+  const CJob J = select_job(one, jobs);
+  const T *__restrict__ x = static_cast<const T *>(J.x);
+  const Plan P = J.P;
+  DevParams *__restrict__ dp = J.W.P;
+  uint32_t *__restrict__ hist_g = J.W.hist;
+  uint32_t *__restrict__ exc_cnt = J.W.exc_cnt;
+  uint32_t *__restrict__ stage = J.W.stage;
+  const uint64_t *__restrict__ exc_off = J.W.exc_off;
+  int16_t *__restrict__ codes = J.W.codes;
+  uint8_t *__restrict__ blob = J.blob;
   using G = Geo<NDIM>;
   using B = BoxAddr<NDIM>;
   __shared__ int32_t box[B::SIZE];
@@ -471,10 +496,13 @@ __global__ __launch_bounds__(kBlock) void k_quant(const T *__restrict__ x, Plan 
 // Exclusive scan of the per-tile record counts (one workgroup): tile offsets
 // into the blob's tile_exc_offset section and the workspace, the total.
 constexpr int kScanThreads = 1024;
-__global__ __launch_bounds__(kScanThreads) void k_exc_scan(Plan P, DevParams *__restrict__ dp,
-                                                           const uint32_t *__restrict__ cnt,
-                                                           uint64_t *__restrict__ off,
-                                                           uint8_t *__restrict__ blob) {
+__global__ __launch_bounds__(kScanThreads) void k_exc_scan(CJob one, const CJob *__restrict__ jobs) {
+  const CJob J = select_job(one, jobs);
+  const Plan P = J.P;
+  DevParams *__restrict__ dp = J.W.P;
+  const uint32_t *__restrict__ cnt = J.W.exc_cnt;
+  uint64_t *__restrict__ off = J.W.exc_off;
+  uint8_t *__restrict__ blob = J.blob;
   __shared__ uint64_t wsum[kScanThreads / 64];
   __shared__ uint64_t carry;
   if (dp->status != 0 || dp->is_const) return;
@@ -512,11 +540,14 @@ __global__ __launch_bounds__(kScanThreads) void k_exc_scan(Plan P, DevParams *__
 }
 
 // Place staged records (one wave per tile).
-__global__ __launch_bounds__(kBlock) void k_exc_copy(Plan P, DevParams *__restrict__ dp,
-                                                     const uint32_t *__restrict__ cnt,
-                                                     const uint32_t *__restrict__ stage,
-                                                     const uint64_t *__restrict__ off,
-                                                     uint8_t *__restrict__ blob) {
+__global__ __launch_bounds__(kBlock) void k_exc_copy(CJob one, const CJob *__restrict__ jobs) {
+  const CJob J = select_job(one, jobs);
+  const Plan P = J.P;
+  DevParams *__restrict__ dp = J.W.P;
+  const uint32_t *__restrict__ cnt = J.W.exc_cnt;
+  const uint32_t *__restrict__ stage = J.W.stage;
+  const uint64_t *__restrict__ off = J.W.exc_off;
+  uint8_t *__restrict__ blob = J.blob;
   if (dp->status != 0 || dp->is_const) return;
   const uint64_t t = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -577,11 +608,14 @@ __device__ inline int count_leq(const uint32_t *a, int n, uint32_t w) {
   return lo;
 }
 
-__global__ __launch_bounds__(kCbThreads) void k_codebook(Plan P, DevParams *__restrict__ dp,
-                                                         const uint32_t *__restrict__ hist_g,
-                                                         uint8_t *__restrict__ len_out,
-                                                         uint32_t *__restrict__ code_out,
-                                                         uint8_t *__restrict__ blob) {
+__global__ __launch_bounds__(kCbThreads) void k_codebook(CJob one, const CJob *__restrict__ jobs) {
+  const CJob J = select_job(one, jobs);
+  const Plan P = J.P;
+  DevParams *__restrict__ dp = J.W.P;
+  const uint32_t *__restrict__ hist_g = J.W.hist;
+  uint8_t *__restrict__ len_out = J.W.code_len;
+  uint32_t *__restrict__ code_out = J.W.code;
+  uint8_t *__restrict__ blob = J.blob;
   __shared__ uint64_t key[2048];
   __shared__ uint32_t Lw[kNSym];
   __shared__ uint16_t Ls[kNSym];
@@ -813,12 +847,15 @@ __device__ inline void put_bits_lds(uint32_t *words, uint32_t o, uint32_t pat, i
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_encode(Plan P, DevParams *__restrict__ dp,
-                                                   const int16_t *__restrict__ codes,
-                                                   const uint8_t *__restrict__ len_g,
-                                                   const uint32_t *__restrict__ code_g,
-                                                   uint64_t *__restrict__ word_state,
-                                                   uint8_t *__restrict__ blob) {
+__global__ __launch_bounds__(kBlock) void k_encode(CJob one, const CJob *__restrict__ jobs) {
+  const CJob J = select_job(one, jobs);
+  const Plan P = J.P;
+  DevParams *__restrict__ dp = J.W.P;
+  const int16_t *__restrict__ codes = J.W.codes;
+  const uint8_t *__restrict__ len_g = J.W.code_len;
+  const uint32_t *__restrict__ code_g = J.W.code;
+  uint64_t *__restrict__ word_state = J.W.word_state;
+  uint8_t *__restrict__ blob = J.blob;
   __shared__ uint32_t words[kTilePts + 1];
   __shared__ uint8_t slen[kNSym];
   __shared__ uint32_t scode[kNSym];
@@ -928,7 +965,11 @@ __global__ __launch_bounds__(kBlock) void k_encode(Plan P, DevParams *__restrict
 
 // ---------------------------------------------------------------------------
 // header, padding and total size (one workgroup)
-__global__ void k_header(Plan P, DevParams *__restrict__ dp, uint8_t *__restrict__ blob) {
+__global__ void k_header(CJob one, const CJob *__restrict__ jobs) {
+  const CJob J = select_job(one, jobs);
+  const Plan P = J.P;
+  DevParams *__restrict__ dp = J.W.P;
+  uint8_t *__restrict__ blob = J.blob;
   const int tid = threadIdx.x;
   if (dp->status != 0) return;
   __shared__ uint8_t h[kHdr];
@@ -1004,11 +1045,10 @@ __global__ void k_header(Plan P, DevParams *__restrict__ dp, uint8_t *__restrict
 }
 
 // checksum over the blob's 32-bit words; the checksum field reads as zero.
-// mode 0: accumulate into dp->checksum; run after k_header.
-__global__ __launch_bounds__(kBlock) void k_checksum(const uint8_t *__restrict__ blob,
-                                                     uint64_t bytes_limit,
-                                                     DevParams *__restrict__ dp,
-                                                     int use_dp_bytes) {
+// Accumulates into dp->checksum; use_dp_bytes: the blob size is dp->blob_bytes
+// (compress, after k_header), else bytes_limit (decompress).
+__device__ inline void checksum_body(const uint8_t *__restrict__ blob, uint64_t bytes_limit,
+                                     DevParams *__restrict__ dp, int use_dp_bytes) {
   if (use_dp_bytes && (dp->status != 0 || dp->overflow)) return;
   const uint64_t bytes = use_dp_bytes ? dp->blob_bytes : bytes_limit;
   const uint64_t nw = bytes / 4;  // a multiple of 2 (blobs are 8-byte sized)
@@ -1030,79 +1070,97 @@ __global__ __launch_bounds__(kBlock) void k_checksum(const uint8_t *__restrict__
   if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long *)&dp->checksum, (unsigned long long)s);
 }
 
+__global__ __launch_bounds__(kBlock) void k_checksum(const uint8_t *__restrict__ blob,
+                                                     uint64_t bytes_limit,
+                                                     DevParams *__restrict__ dp) {
+  checksum_body(blob, bytes_limit, dp, 0);
+}
+
 hipError_t launch_checksum(const uint8_t *blob, uint64_t bytes, DevParams *dp, hipStream_t s) {
   const uint64_t cw = bytes / 4 / kBlock + 1;
   const uint32_t cgrid = (uint32_t)(cw < 1024 ? cw : 1024);
-  hipLaunchKernelGGL(k_checksum, dim3(cgrid), dim3(kBlock), 0, s, blob, bytes, dp, 0);
+  hipLaunchKernelGGL(k_checksum, dim3(cgrid), dim3(kBlock), 0, s, blob, bytes, dp);
   return hipGetLastError();
 }
 
-__global__ void k_checksum_store(DevParams *__restrict__ dp, uint8_t *__restrict__ blob) {
+// compress: checksum of each field's finished blob (its size from dp)
+__global__ __launch_bounds__(kBlock) void k_checksum_jobs(CJob one, const CJob *__restrict__ jobs) {
+  const CJob J = select_job(one, jobs);
+  checksum_body(J.blob, 0, J.W.P, 1);
+}
+
+__global__ void k_checksum_store(CJob one, const CJob *__restrict__ jobs) {
+  const CJob J = select_job(one, jobs);
+  DevParams *__restrict__ dp = J.W.P;
+  uint8_t *__restrict__ blob = J.blob;
   if (dp->status != 0 || dp->overflow) return;
   *reinterpret_cast<uint64_t *>(blob + H_CSUM) = dp->checksum;
 }
 
 // ---------------------------------------------------------------------------
+LaunchCfg default_launch_cfg(const Plan &maxP) {
+  LaunchCfg c;
+  const uint64_t want = maxP.n / (kBlock * 16) + 1;
+  c.range_blocks = (uint32_t)(want < (uint64_t)kRangeBlocks ? want : kRangeBlocks);
+  c.quant_grid = (uint32_t)(maxP.n_tiles < 2048 ? maxP.n_tiles : 2048);
+  c.encode_grid = c.quant_grid;
+  const uint64_t cw = maxP.capacity / 4 / kBlock + 1;
+  c.csum_blocks = (uint32_t)(cw < 1024 ? cw : 1024);
+  return c;
+}
+
 template <typename T, int NDIM, bool GLOBAL>
-static void launch_quant_d(const Plan &P, const T *x, const CompressWs &W, uint8_t *blob,
-                           hipStream_t s, Timer *tm) {
-  const uint32_t grid = (uint32_t)(P.n_tiles < 2048 ? P.n_tiles : 2048);
-  hipLaunchKernelGGL((k_quant<T, NDIM, GLOBAL, false>), dim3(grid), dim3(kBlock), 0, s, x, P, W.P,
-                     W.hist, W.exc_cnt, W.stage, (const uint64_t *)W.exc_off, W.codes, blob);
+static void launch_quant_d(const CJob &one, const CJob *jobs, int nf, const Plan &maxP,
+                           const LaunchCfg &cfg, hipStream_t s, Timer *tm) {
+  const dim3 grid(cfg.quant_grid, nf);
+  hipLaunchKernelGGL((k_quant<T, NDIM, GLOBAL, false>), grid, dim3(kBlock), 0, s, one, jobs);
   tm->mark(s, "quant");
-  hipLaunchKernelGGL(k_exc_scan, dim3(1), dim3(kScanThreads), 0, s, P, W.P, W.exc_cnt, W.exc_off,
-                     blob);
-  const uint32_t cgrid = (uint32_t)ceil_div(P.n_tiles, kBlock / 64);
-  hipLaunchKernelGGL(k_exc_copy, dim3(cgrid), dim3(kBlock), 0, s, P, W.P, W.exc_cnt, W.stage,
-                     W.exc_off, blob);
+  hipLaunchKernelGGL(k_exc_scan, dim3(1, nf), dim3(kScanThreads), 0, s, one, jobs);
+  const uint32_t cgrid = (uint32_t)ceil_div(maxP.n_tiles, kBlock / 64);
+  hipLaunchKernelGGL(k_exc_copy, dim3(cgrid, nf), dim3(kBlock), 0, s, one, jobs);
   // tiles with more than kStage records recompute them in place
-  hipLaunchKernelGGL((k_quant<T, NDIM, GLOBAL, true>), dim3(grid), dim3(kBlock), 0, s, x, P, W.P,
-                     W.hist, W.exc_cnt, W.stage, (const uint64_t *)W.exc_off, W.codes, blob);
+  hipLaunchKernelGGL((k_quant<T, NDIM, GLOBAL, true>), grid, dim3(kBlock), 0, s, one, jobs);
 }
 
 template <typename T, int NDIM>
-static void launch_quant(const Plan &P, const T *x, const CompressWs &W, uint8_t *blob,
-                         hipStream_t s, Timer *tm) {
-  if (P.domain == FPSZ_DOMAIN_GLOBAL) launch_quant_d<T, NDIM, true>(P, x, W, blob, s, tm);
-  else launch_quant_d<T, NDIM, false>(P, x, W, blob, s, tm);
+static void launch_quant(const CJob &one, const CJob *jobs, int nf, const Plan &maxP,
+                         const LaunchCfg &cfg, hipStream_t s, Timer *tm) {
+  if (maxP.domain == FPSZ_DOMAIN_GLOBAL)
+    launch_quant_d<T, NDIM, true>(one, jobs, nf, maxP, cfg, s, tm);
+  else
+    launch_quant_d<T, NDIM, false>(one, jobs, nf, maxP, cfg, s, tm);
 }
 
 template <typename T>
-static void launch_compress_t(const Plan &P, const T *x, const CompressWs &W, uint8_t *blob,
-                              hipStream_t s, Timer *tm) {
-  const uint64_t want = P.n / (kBlock * 16) + 1;
-  const uint32_t rgrid = (uint32_t)(want < (uint64_t)kRangeBlocks ? want : kRangeBlocks);
-  hipLaunchKernelGGL(k_range<T>, dim3(rgrid), dim3(kBlock), 0, s, x, P, W.P,
-                     (uint64_t *)W.range_part);
+static void launch_compress_t(const CJob &one, const CJob *jobs, int nf, const Plan &maxP,
+                              const LaunchCfg &cfg, hipStream_t s, Timer *tm) {
+  hipLaunchKernelGGL(k_range<T>, dim3(cfg.range_blocks, nf), dim3(kBlock), 0, s, one, jobs);
   tm->mark(s, "range");
-  if (P.ndim == 1) launch_quant<T, 1>(P, x, W, blob, s, tm);
-  else if (P.ndim == 2) launch_quant<T, 2>(P, x, W, blob, s, tm);
-  else launch_quant<T, 3>(P, x, W, blob, s, tm);
+  if (maxP.ndim == 1) launch_quant<T, 1>(one, jobs, nf, maxP, cfg, s, tm);
+  else if (maxP.ndim == 2) launch_quant<T, 2>(one, jobs, nf, maxP, cfg, s, tm);
+  else launch_quant<T, 3>(one, jobs, nf, maxP, cfg, s, tm);
   tm->mark(s, "exceptions");
-  hipLaunchKernelGGL(k_codebook, dim3(1), dim3(kCbThreads), 0, s, P, W.P, W.hist, W.code_len,
-                     W.code, blob);
+  hipLaunchKernelGGL(k_codebook, dim3(1, nf), dim3(kCbThreads), 0, s, one, jobs);
   tm->mark(s, "codebook");
-  const uint32_t egrid = (uint32_t)(P.n_tiles < 2048 ? P.n_tiles : 2048);
-  hipLaunchKernelGGL(k_encode, dim3(egrid), dim3(kBlock), 0, s, P, W.P, W.codes, W.code_len,
-                     W.code, W.word_state, blob);
+  hipLaunchKernelGGL(k_encode, dim3(cfg.encode_grid, nf), dim3(kBlock), 0, s, one, jobs);
   tm->mark(s, "encode");
-  hipLaunchKernelGGL(k_header, dim3(1), dim3(kBlock), 0, s, P, W.P, blob);
+  hipLaunchKernelGGL(k_header, dim3(1, nf), dim3(kBlock), 0, s, one, jobs);
   tm->mark(s, "header");
-  const uint64_t cw = P.capacity / 4 / kBlock + 1;
-  const uint32_t cgrid = (uint32_t)(cw < 1024 ? cw : 1024);
-  hipLaunchKernelGGL(k_checksum, dim3(cgrid), dim3(kBlock), 0, s, blob, (uint64_t)0, W.P, 1);
-  hipLaunchKernelGGL(k_checksum_store, dim3(1), dim3(1), 0, s, W.P, blob);
+  hipLaunchKernelGGL(k_checksum_jobs, dim3(cfg.csum_blocks, nf), dim3(kBlock), 0, s, one, jobs);
+  hipLaunchKernelGGL(k_checksum_store, dim3(1, nf), dim3(1), 0, s, one, jobs);
   tm->mark(s, "checksum");
 }
 
-hipError_t launch_compress(const Plan &P, const void *x, const CompressWs &W, uint8_t *blob,
-                           hipStream_t s, Timer *tm) {
+hipError_t launch_compress_jobs(const CJob &one, const CJob *jobs_dev, int nf, const Plan &maxP,
+                                const LaunchCfg &cfg, hipStream_t s, Timer *tm) {
+  if (nf < 1 || nf > 65535 || (nf > 1 && !jobs_dev)) return hipErrorInvalidValue;
+  if (!cfg.range_blocks || !cfg.quant_grid || !cfg.encode_grid || !cfg.csum_blocks)
+    return hipErrorInvalidValue;
   tm->mark(s, "begin");
-  hipError_t e = launch_fill_zero(W.P, W.zero_bytes, s);
-  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_zero_jobs, dim3(8, nf), dim3(kBlock), 0, s, one, jobs_dev);
   tm->mark(s, "init");
-  if (P.dtype == FPSZ_F32) launch_compress_t<float>(P, (const float *)x, W, blob, s, tm);
-  else launch_compress_t<double>(P, (const double *)x, W, blob, s, tm);
+  if (maxP.dtype == FPSZ_F32) launch_compress_t<float>(one, jobs_dev, nf, maxP, cfg, s, tm);
+  else launch_compress_t<double>(one, jobs_dev, nf, maxP, cfg, s, tm);
   return hipGetLastError();
 }
 

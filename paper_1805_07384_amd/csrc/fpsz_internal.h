@@ -345,9 +345,36 @@ struct DecompressWs {
   uint64_t zero_bytes;
 };
 
+// One field of a compress launch.  Kernels take a job by value (a single
+// field) and a device array of jobs indexed by blockIdx.y (a batched launch
+// over many fields); a null array selects the by-value job.  Every field of a
+// batched launch has the same dtype, ndim and Lorenzo domain (the kernel's
+// template class); sizes and targets may differ.
+struct CJob {
+  Plan P;
+  const void *x;
+  CompressWs W;
+  uint8_t *blob;
+};
+
+// Launch shape of the compress kernels (grid x per field).  None of these
+// changes a single output bit: tiles are fixed by the format, every
+// reduction is order-independent or has a fixed order.
+struct LaunchCfg {
+  uint32_t range_blocks;  // k_range blocks per field
+  uint32_t quant_grid;    // k_quant workgroups per field (persistent over tiles)
+  uint32_t encode_grid;   // k_encode workgroups per field (tickets over tiles)
+  uint32_t csum_blocks;   // k_checksum blocks per field
+};
+LaunchCfg default_launch_cfg(const Plan &maxP);
+
+// Launch the whole compress pipeline for `nf` fields (nf == 1 and jobs_dev ==
+// nullptr: the single field `one`).  maxP carries the class (dtype, ndim,
+// domain) and the largest n / n_tiles / capacity of the fields.
+hipError_t launch_compress_jobs(const CJob &one, const CJob *jobs_dev, int nf, const Plan &maxP,
+                                const LaunchCfg &cfg, hipStream_t s, Timer *tm);
+
 hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t s);
-hipError_t launch_compress(const Plan &P, const void *x, const CompressWs &W, uint8_t *blob,
-                           hipStream_t s, Timer *tm);
 hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const DecompressWs &W,
                                   uint64_t off_words, uint64_t n_words, uint64_t n_exc, double e2,
                                   float e2_f, void *out, hipStream_t s, Timer *tm);

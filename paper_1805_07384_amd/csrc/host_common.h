@@ -1,0 +1,301 @@
+// host_common.h -- host-side helpers shared by the C ABI sources: the
+// context, error reporting, the per-field plan (shape, tile grid, fixed blob
+// sections), workspace layouts and the stage timer.
+#ifndef FPSZ_HOST_COMMON_H
+#define FPSZ_HOST_COMMON_H
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "fpsz_internal.h"
+
+struct fpsz_ctx {
+  int device;
+  char err[512];
+  fpsz::DevParams *host;  // pinned read-back buffer
+  bool profiling;
+  bool events_made;
+  fpsz::Timer timer;
+  int n_stages;
+  fpsz_stage_time stages[fpsz::Timer::kMax];
+};
+
+namespace fpsz {
+
+
+inline fpsz_status fail(fpsz_ctx *c, fpsz_status s, const char *fmt, ...) {
+  if (c) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(c->err, sizeof(c->err), fmt, ap);
+    va_end(ap);
+  }
+  return s;
+}
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// Normalized shape, tile grid and fixed blob sections.
+inline fpsz_status make_plan(int ndim, const uint64_t *dims, fpsz_dtype dtype, Plan *P) {
+  if (ndim < 1 || ndim > 3 || !dims) return FPSZ_E_INVALID_ARG;
+  if (dtype != FPSZ_F32 && dtype != FPSZ_F64) return FPSZ_E_INVALID_ARG;
+  memset(P, 0, sizeof(*P));
+  P->ndim = ndim;
+  P->dtype = dtype;
+  uint64_t d[3] = {1, 1, 1};
+  for (int i = 0; i < 3; i++) P->dims[i] = 1;
+  for (int i = 0; i < ndim; i++) {
+    if (dims[i] == 0 || dims[i] >= (1ull << 31)) return FPSZ_E_INVALID_ARG;
+    d[3 - ndim + i] = dims[i];
+    P->dims[i] = dims[i];
+  }
+  P->nz = d[0];
+  P->ny = d[1];
+  P->nx = d[2];
+  const unsigned __int128 n = (unsigned __int128)d[0] * d[1] * d[2];
+  if (n >= ((unsigned __int128)1 << 31)) return FPSZ_E_INVALID_ARG;
+  P->n = (uint64_t)n;
+  if (ndim == 1) { P->tz = 1; P->ty = 1; P->tx = 8192; }
+  else if (ndim == 2) { P->tz = 1; P->ty = 64; P->tx = 128; }
+  else { P->tz = 16; P->ty = 16; P->tx = 32; }
+  P->gz = (uint32_t)ceil_div(P->nz, P->tz);
+  P->gy = (uint32_t)ceil_div(P->ny, P->ty);
+  P->gx = (uint32_t)ceil_div(P->nx, P->tx);
+  P->n_tiles = (uint64_t)P->gz * P->gy * P->gx;
+  // total chunks = chunk_base of a one-past-the-end tile: sum over all tiles
+  {
+    const uint64_t ex_last = P->nx - (uint64_t)(P->gx - 1) * P->tx;
+    const uint64_t ey_last = P->ny - (uint64_t)(P->gy - 1) * P->ty;
+    const uint64_t ez_last = P->nz - (uint64_t)(P->gz - 1) * P->tz;
+    auto row = [&](uint64_t ez, uint64_t ey) {
+      return (uint64_t)(P->gx - 1) * chunks_of(ez, ey, P->tx) + chunks_of(ez, ey, ex_last);
+    };
+    auto slab = [&](uint64_t ez) { return (uint64_t)(P->gy - 1) * row(ez, P->ty) + row(ez, ey_last); };
+    P->n_chunks = (uint64_t)(P->gz - 1) * slab(P->tz) + slab(ez_last);
+  }
+  uint64_t o = kHdr;
+  P->off_len = o;
+  o = align8(o + kNSym);
+  P->off_two = o;
+  o = align8(o + 8 * (P->n_tiles + 1));
+  P->off_teo = o;
+  o = align8(o + 8 * (P->n_tiles + 1));
+  P->off_cb = o;
+  o = align8(o + 2 * P->n_chunks);
+  P->off_exc = o;
+  return FPSZ_OK;
+}
+
+struct CompressLayout {
+  uint64_t off_part, off_hist, off_len, off_code, off_word_state, off_exc_cnt, off_exc_off,
+      off_stage, off_codes, zero, total;
+};
+
+inline CompressLayout compress_layout(const Plan &P) {
+  CompressLayout L;
+  uint64_t o = align256(sizeof(DevParams));
+  L.off_part = o;
+  o = align256(o + 3 * 8 * (uint64_t)kRangeBlocks);
+  L.off_hist = o;
+  o = align256(o + 4 * (uint64_t)kNSym);
+  L.off_len = o;
+  o = align256(o + (uint64_t)kNSym);
+  L.off_code = o;
+  o = align256(o + 4 * (uint64_t)kNSym);
+  L.off_word_state = o;
+  o = align256(o + 8 * P.n_tiles);
+  L.zero = o;  // everything before this is cleared at the start of a call
+  L.off_exc_cnt = o;
+  o = align256(o + 4 * P.n_tiles);
+  L.off_exc_off = o;
+  o = align256(o + 8 * P.n_tiles);
+  L.off_stage = o;
+  o = align256(o + 8 * 64 * P.n_tiles);  // kStage records of 8 bytes per tile
+  L.off_codes = o;
+  o = align256(o + 2 * P.n);
+  L.total = o;
+  return L;
+}
+
+struct DecompressLayout {
+  uint64_t off_lut, off_ltab, off_sorted, off_fz, off_fy, off_fx, off_gx, off_gy, off_gz, off_tt,
+      off_tmp, off_codes, total;
+};
+
+inline DecompressLayout decompress_layout(const Plan &P) {
+  DecompressLayout L;
+  const uint64_t T = P.n_tiles;
+  const uint64_t fz = P.ndim == 3 ? (uint64_t)P.ty * P.tx : 0, fy = P.ndim >= 2 ? (uint64_t)P.tz * P.tx : 0;
+  const uint64_t fx = (uint64_t)P.tz * P.ty;
+  uint64_t o = align256(sizeof(DevParams));
+  L.off_lut = o;
+  o = align256(o + 4 * 4096);
+  L.off_ltab = o;
+  o = align256(o + 4 * 96);
+  L.off_sorted = o;
+  o = align256(o + 2 * (uint64_t)kNSym);
+  L.off_fz = o;
+  o = align256(o + 4 * T * fz);
+  L.off_fy = o;
+  o = align256(o + 4 * T * fy);
+  L.off_fx = o;
+  o = align256(o + 4 * T * fx);
+  L.off_gx = o;
+  o = align256(o + 4 * T * (P.ndim == 3 ? P.tx : 0));
+  L.off_gy = o;
+  o = align256(o + 4 * T * (P.ndim == 3 ? P.ty : 0));
+  L.off_gz = o;
+  o = align256(o + 4 * T * (P.ndim >= 2 ? P.tz : 0));
+  L.off_tt = o;
+  o = align256(o + 4 * T);
+  // segment sums of a scan with len > 32 along its axis: ceil(len / 32) <=
+  // len / 16 per column, so at most one per 16 elements of the largest array
+  uint64_t big = T * fz;
+  if (T * fy > big) big = T * fy;
+  if (T * fx > big) big = T * fx;
+  if (T * P.tx > big) big = T * P.tx;
+  L.off_tmp = o;
+  o = align256(o + 4 * (big / 16 + 64));
+  L.off_codes = o;
+  o = align256(o + 2 * P.n);
+  L.total = o;
+  return L;
+}
+
+inline uint64_t verify_ws_bytes() { return align256(sizeof(DevParams)) + align256(3 * 8 * (uint64_t)kVerifyBlocks); }
+
+template <typename V> V rd(const uint8_t *p) {
+  V v;
+  memcpy(&v, p, sizeof(V));
+  return v;
+}
+
+inline fpsz_status hip_fail(fpsz_ctx *c, hipError_t e, const char *what) {
+  return fail(c, FPSZ_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+inline Timer *timer_begin(fpsz_ctx *c) {
+  c->timer.n = 0;
+  c->timer.on = c->profiling && c->events_made;
+  c->n_stages = 0;
+  return &c->timer;
+}
+
+// after the stream has been synchronized: stage i spans marks i-1 .. i
+inline void timer_collect(fpsz_ctx *c) {
+  Timer &t = c->timer;
+  c->n_stages = 0;
+  for (int i = 1; i < t.n; i++) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.ev[i - 1], t.ev[i]) != hipSuccess) ms = -1.f;
+    fpsz_stage_time &st = c->stages[c->n_stages++];
+    memset(st.name, 0, sizeof(st.name));
+    strncpy(st.name, t.names[i], sizeof(st.name) - 1);
+    st.ms = ms;
+  }
+  t.on = false;
+}
+
+
+// Checks one compress request and fills its job: plan, input, workspace
+// carved from ws (compress_layout), output.  Sets *blob_bytes = 256 when the
+// capacity cannot even hold the header.
+inline fpsz_status prepare_compress(fpsz_ctx *ctx, const void *field_dev, int ndim,
+                                    const uint64_t *dims, fpsz_dtype dtype, double target_psnr,
+                                    fpsz_domain domain, void *workspace_dev,
+                                    uint64_t workspace_bytes, void *blob_dev,
+                                    uint64_t blob_capacity, uint64_t *blob_bytes, CJob *job) {
+  if (!field_dev || !workspace_dev || !blob_dev || !blob_bytes)
+    return fail(ctx, FPSZ_E_INVALID_ARG, "null pointer argument");
+  if (!isfinite(target_psnr)) return fail(ctx, FPSZ_E_INVALID_ARG, "target PSNR is not finite");
+  if (domain != FPSZ_DOMAIN_GLOBAL && domain != FPSZ_DOMAIN_TILE)
+    return fail(ctx, FPSZ_E_INVALID_ARG, "bad domain %d", (int)domain);
+  Plan P;
+  fpsz_status st = make_plan(ndim, dims, dtype, &P);
+  if (st != FPSZ_OK) return fail(ctx, st, "bad shape or dtype");
+  const size_t esz = dtype == FPSZ_F32 ? 4 : 8;
+  if ((uintptr_t)field_dev % esz) return fail(ctx, FPSZ_E_INVALID_ARG, "field not element-aligned");
+  if ((uintptr_t)workspace_dev % 256 || (uintptr_t)blob_dev % 8)
+    return fail(ctx, FPSZ_E_INVALID_ARG, "workspace must be 256-aligned, blob 8-aligned");
+  const CompressLayout L = compress_layout(P);
+  if (workspace_bytes < L.total)
+    return fail(ctx, FPSZ_E_CAPACITY, "workspace needs %llu bytes", (unsigned long long)L.total);
+  *blob_bytes = 0;
+  if (blob_capacity < kHdr) {
+    *blob_bytes = kHdr;
+    return fail(ctx, FPSZ_E_CAPACITY, "blob capacity below the 256-byte header");
+  }
+  P.domain = domain;
+  P.capacity = blob_capacity;
+  P.target_psnr = target_psnr;
+  P.eb_rel = sqrt(3.0) * pow(10.0, -target_psnr / 20.0);  // Eq. 7, as fpsz_eb_rel
+  uint8_t *ws = (uint8_t *)workspace_dev;
+  CompressWs &W = job->W;
+  W.P = (DevParams *)ws;
+  W.range_part = ws + L.off_part;
+  W.hist = (uint32_t *)(ws + L.off_hist);
+  W.code_len = ws + L.off_len;
+  W.code = (uint32_t *)(ws + L.off_code);
+  W.exc_cnt = (uint32_t *)(ws + L.off_exc_cnt);
+  W.exc_off = (uint64_t *)(ws + L.off_exc_off);
+  W.stage = (uint32_t *)(ws + L.off_stage);
+  W.word_state = (uint64_t *)(ws + L.off_word_state);
+  W.codes = (int16_t *)(ws + L.off_codes);
+  W.zero_bytes = L.zero;
+  job->P = P;
+  job->x = field_dev;
+  job->blob = (uint8_t *)blob_dev;
+  return FPSZ_OK;
+}
+
+inline void fill_compress_info(fpsz_info *info, const Plan &P, const DevParams &D) {
+  memset(info, 0, sizeof(*info));
+  info->target_psnr = P.target_psnr;
+  info->eb_rel = P.eb_rel;
+  info->vr = D.vr;
+  info->eb = D.eb;
+  info->min = D.mn;
+  info->max = D.mx;
+  info->n = P.n;
+  info->n_outliers = D.n_out;
+  info->n_patches = D.n_pat;
+  info->n_exceptions = D.n_exc;
+  info->blob_bytes = D.blob_bytes;
+  info->bits_per_value = 8.0 * (double)D.blob_bytes / (double)P.n;
+  info->is_const = D.is_const;
+  info->domain = (uint32_t)P.domain;
+}
+
+// Status of a finished compress from its parameter block.
+inline fpsz_status compress_result(fpsz_ctx *ctx, const Plan &P, const DevParams &D,
+                                   uint64_t *blob_bytes) {
+  if (D.status == FPSZ_E_NONFINITE)
+    return fail(ctx, FPSZ_E_NONFINITE, "%llu non-finite values", (unsigned long long)D.nonfinite);
+  if (D.status == FPSZ_E_RANGE)
+    return fail(ctx, FPSZ_E_RANGE, "max|x| / (2 eb) exceeds the integer range of %s",
+                P.dtype == FPSZ_F32 ? "float32 (2^23)" : "float64 (2^27)");
+  if (D.status != 0) return fail(ctx, (fpsz_status)D.status, "device status %u", D.status);
+  if (D.spin_fail)
+    return fail(ctx, FPSZ_E_DEVICE, "device-side wait or invariant failed (code %u)", D.spin_fail);
+  *blob_bytes = D.blob_bytes;
+  if (D.overflow || D.blob_bytes > P.capacity)
+    return fail(ctx, FPSZ_E_CAPACITY, "blob needs %llu bytes, capacity %llu",
+                (unsigned long long)D.blob_bytes, (unsigned long long)P.capacity);
+  return FPSZ_OK;
+}
+}  // namespace fpsz
+
+#endif

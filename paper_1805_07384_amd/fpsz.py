@@ -54,6 +54,13 @@ class StageTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("ms", ctypes.c_double)]
 
 
+class FieldDesc(ctypes.Structure):
+    _fields_ = [("field_dev", ctypes.c_void_p), ("ndim", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("dims", ctypes.c_uint64 * 3), ("target_psnr", ctypes.c_double),
+                ("domain", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("blob_dev", ctypes.c_void_p), ("blob_capacity", ctypes.c_uint64)]
+
+
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _vp = ctypes.c_void_p
 
@@ -83,6 +90,17 @@ SIGNATURES = {
     "fpsz_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
     "fpsz_last_stage_times": (ctypes.c_int, [_vp, ctypes.POINTER(StageTime), ctypes.c_int,
                                              ctypes.POINTER(ctypes.c_int)]),
+    "fpsz_batch_workspace_bytes": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(FieldDesc), _u64p]),
+    "fpsz_batch_create": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(FieldDesc), _vp,
+                                         ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(_vp)]),
+    "fpsz_batch_run": (ctypes.c_int, [_vp, _vp, _u64p, ctypes.POINTER(Info),
+                                      ctypes.POINTER(ctypes.c_int)]),
+    "fpsz_batch_autotune": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
+    "fpsz_batch_launch_shape": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint32)]),
+    "fpsz_batch_destroy": (None, [_vp]),
+    "fpsz_compress_batch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(FieldDesc), _vp,
+                                           ctypes.c_uint64, _u64p, ctypes.POINTER(Info),
+                                           ctypes.POINTER(ctypes.c_int), _vp]),
 }
 
 _lib = None
@@ -296,6 +314,93 @@ class Context:
         if st != OK:
             raise self._err(st, "fpsz_verify")
         return stats.as_dict()
+
+
+def field_descs(fields, psnrs, blobs, domains=None):
+    """ctypes array of fpsz_field_desc for device tensors ``fields`` (each
+    contiguous float32/float64) with targets ``psnrs`` and output buffers
+    ``blobs`` (uint8 device tensors)."""
+    n = len(fields)
+    arr = (FieldDesc * n)()
+    for i, (x, p, b) in enumerate(zip(fields, psnrs, blobs)):
+        assert x.is_contiguous() and x.is_cuda and b.is_cuda
+        d = arr[i]
+        d.field_dev = x.data_ptr()
+        d.ndim = x.dim()
+        d.dtype = _dtype_code(x)
+        for k, v in enumerate(list(x.shape) + [1] * (3 - x.dim())):
+            d.dims[k] = int(v)
+        d.target_psnr = float(p)
+        d.domain = int(domains[i]) if domains is not None else GLOBAL
+        d.blob_dev = b.data_ptr()
+        d.blob_capacity = b.numel()
+    return arr
+
+
+def batch_workspace_bytes(descs) -> int:
+    out = ctypes.c_uint64()
+    st = load_library().fpsz_batch_workspace_bytes(len(descs), descs, ctypes.byref(out))
+    if st != OK:
+        raise FpszError(st, "batch workspace size")
+    return out.value
+
+
+class Batch:
+    """A planned batch of fields (fpsz_batch_*).  Keeps references to the
+    tensors it was created with; they must not be freed before close()."""
+
+    def __init__(self, ctx: Context, fields, psnrs, blobs, domains=None, graph: bool = False,
+                 workspace: torch.Tensor | None = None):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.fields, self.blobs = list(fields), list(blobs)
+        self.descs = field_descs(self.fields, psnrs, self.blobs, domains)
+        self.n = len(self.fields)
+        need = batch_workspace_bytes(self.descs)
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=self.fields[0].device)
+        self.workspace = workspace
+        h = _vp()
+        st = self.lib.fpsz_batch_create(ctx.handle, self.n, self.descs, workspace.data_ptr(),
+                                        workspace.numel(), 1 if graph else 0, ctypes.byref(h))
+        if st != OK:
+            raise ctx._err(st, "fpsz_batch_create")
+        self.handle = h
+
+    def run(self, stream=None, check: bool = True):
+        """Returns (status, blob_bytes list, info list of dicts, per-field status list)."""
+        nb = (ctypes.c_uint64 * self.n)()
+        info = (Info * self.n)()
+        sts = (ctypes.c_int * self.n)()
+        st = self.lib.fpsz_batch_run(self.handle, _stream(stream), nb, info, sts)
+        if check and st != OK:
+            raise self.ctx._err(st, "fpsz_batch_run")
+        return st, list(nb), [i.as_dict() for i in info], list(sts)
+
+    def autotune(self, reps: int = 3, stream=None) -> float:
+        best = ctypes.c_double()
+        st = self.lib.fpsz_batch_autotune(self.handle, _stream(stream), int(reps), ctypes.byref(best))
+        if st != OK:
+            raise self.ctx._err(st, "fpsz_batch_autotune")
+        return best.value
+
+    def launch_shape(self, cls: int = 0):
+        out = (ctypes.c_uint32 * 4)()
+        st = self.lib.fpsz_batch_launch_shape(self.handle, int(cls), out)
+        if st != OK:
+            raise FpszError(st, "launch shape")
+        return list(out)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.fpsz_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 _default = {}

@@ -1,0 +1,166 @@
+"""Batched compression on the GPU, through the C ABI.
+
+A batch must give, for every field, the blob that one plain fpsz_compress
+call gives (byte for byte), whatever the mix of shapes, dtypes, domains and
+targets, with or without the captured hipGraph, and whatever launch shapes
+the autotuner picks.  Sampled fields are also checked against the oracle.
+"""
+import numpy as np
+import pytest
+
+from paper_1805_07384_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1805_07384_amd import fpsz
+    return fpsz.Context(0)
+
+
+def _plain(ctx, x, psnr, domain):
+    from paper_1805_07384_amd import fpsz
+    ws = torch.empty(fpsz.compress_workspace_bytes(tuple(x.shape), x.dtype), dtype=torch.uint8,
+                     device="cuda")
+    blob = torch.empty(fpsz.compress_bound(tuple(x.shape), x.dtype), dtype=torch.uint8,
+                       device="cuda")
+    st, nb, info = ctx.compress_into(x, psnr, ws, blob, domain)
+    assert st == 0, ctx._err(st, "plain compress")
+    return blob[:nb].cpu().numpy().tobytes(), info.as_dict()
+
+
+def _mixed_fields():
+    rng = np.random.default_rng(21)
+    shapes = [(20000,), (8193,), (150, 300), (65, 129), (3, 5), (17, 17, 33), (40, 37, 70),
+              (33, 17, 65), (7,), (2, 3, 4), (129, 257), (1, 5, 8200)]
+    out = []
+    for i, sh in enumerate(shapes):
+        dt = np.float32 if i % 3 else np.float64
+        x = (synth.grf_numpy(sh, -3.0, 100 + i) * (10.0 ** rng.uniform(-2, 3)) + 1.0).astype(dt)
+        psnr = float(rng.uniform(30, 120))
+        out.append((x, psnr, int(i % 2)))
+    return out
+
+
+def _make_batch(ctx, items, graph):
+    from paper_1805_07384_amd import fpsz
+    xs = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x, _, _ in items]
+    blobs = [torch.full((fpsz.compress_bound(tuple(x.shape), x.dtype),), 0x5A, dtype=torch.uint8,
+                        device="cuda") for x in xs]
+    b = fpsz.Batch(ctx, xs, [p for _, p, _ in items], blobs, [d for _, _, d in items], graph=graph)
+    b.workspace.fill_(0xA5)  # garbage: nothing may rely on a clean workspace
+    # the job table lives in the workspace: re-plan after the fill
+    b.close()
+    b = fpsz.Batch(ctx, xs, [p for _, p, _ in items], blobs, [d for _, _, d in items], graph=graph,
+                   workspace=b.workspace)
+    return b, xs, blobs
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_equals_plain_calls(ctx, graph):
+    print("case mixed batch graph=%s" % graph, flush=True)
+    items = _mixed_fields()
+    b, xs, blobs = _make_batch(ctx, items, graph)
+    plain = [_plain(ctx, x, p, d) for x, (_, p, d) in zip(xs, items)]
+    for rep in range(3 if graph else 1):
+        # eager work between graph replays
+        torch.cuda.synchronize()
+        _ = (xs[0] * 2).sum().item()
+        st, nb, info, sts = b.run()
+        assert st == 0 and all(s == 0 for s in sts)
+        for i, (pb, pi) in enumerate(plain):
+            got = blobs[i][:nb[i]].cpu().numpy().tobytes()
+            assert got == pb, "field %d differs (replay %d)" % (i, rep)
+            assert info[i]["blob_bytes"] == pi["blob_bytes"] and info[i]["eb"] == pi["eb"]
+    b.close()
+
+
+def test_batch_matches_oracle_and_decompresses(ctx, orc):
+    print("case batch vs oracle", flush=True)
+    items = _mixed_fields()
+    b, xs, blobs = _make_batch(ctx, items, False)
+    st, nb, info, sts = b.run()
+    assert st == 0
+    for i, (x, p, d) in enumerate(items):
+        ob, _ = orc.compress(x, p, domain=d)
+        assert blobs[i][:nb[i]].cpu().numpy().tobytes() == ob, "field %d vs oracle" % i
+        y = ctx.decompress(blobs[i][:nb[i]])
+        assert np.array_equal(y.cpu().numpy(), orc.decompress(ob))
+    b.close()
+
+
+def test_batch_autotune_is_bit_neutral(ctx):
+    print("case autotune", flush=True)
+    items = _mixed_fields()
+    b, xs, blobs = _make_batch(ctx, items, True)
+    st, nb, _, _ = b.run()
+    before = [blobs[i][:nb[i]].clone() for i in range(len(items))]
+    shapes0 = b.launch_shape(0)
+    best = b.autotune(reps=2)
+    assert best > 0
+    for i in range(len(items)):
+        blobs[i].fill_(0)
+    st, nb2, _, _ = b.run()
+    assert st == 0 and nb2 == nb
+    for i in range(len(items)):
+        assert torch.equal(blobs[i][:nb[i]], before[i]), "field %d changed after tuning" % i
+    print("shapes before", shapes0, "after", b.launch_shape(0), flush=True)
+    b.close()
+
+
+def test_batch_per_field_status(ctx):
+    from paper_1805_07384_amd import fpsz
+    print("case batch statuses", flush=True)
+    good = torch.from_numpy(synth.field_2d_grf(100, 120, seed=3)).cuda()
+    bad = good.clone()
+    bad[5, 7] = float("nan")
+    small = torch.empty(300, dtype=torch.uint8, device="cuda")
+    big = [torch.empty(fpsz.compress_bound((100, 120)), dtype=torch.uint8, device="cuda")
+           for _ in range(3)]
+    b = fpsz.Batch(ctx, [good, bad, good, good], [80.0, 80.0, 200.0, 60.0],
+                   [big[0], big[1], big[2], small])
+    st, nb, info, sts = b.run(check=False)
+    assert sts == [fpsz.OK, fpsz.E_NONFINITE, fpsz.E_RANGE, fpsz.E_CAPACITY]
+    assert st == fpsz.E_NONFINITE
+    plain, _ = _plain(ctx, good, 60.0, 0)
+    assert nb[3] == len(plain)  # size needed is reported
+    b.close()
+
+
+@pytest.mark.timeout(600)
+def test_batch_120_fields_1800x3600(ctx, orc):
+    """The 120-field workload (2D f32 1800 x 3600, slope U[-4,-2], range
+    10^U(-3,4), target U[40,120] dB): one batch (graph) vs 120 plain calls,
+    every blob byte-identical; three fields against the oracle; every point of
+    every field within its bound."""
+    from paper_1805_07384_amd import fpsz
+    print("case C3 batch", flush=True)
+    spec = synth.batch_fields_spec(120, seed=3)
+    xs = [synth.batch_field(s, backend="torch", device="cuda").contiguous() for s in spec]
+    psnrs = [s["psnr"] for s in spec]
+    cap = [fpsz.compress_bound(tuple(x.shape)) // 2 for x in xs]
+    blobs = [torch.empty(c, dtype=torch.uint8, device="cuda") for c in cap]
+    b = fpsz.Batch(ctx, xs, psnrs, blobs, graph=True)
+    st, nb, info, sts = b.run()
+    assert st == 0
+    ws = torch.empty(fpsz.compress_workspace_bytes((1800, 3600)), dtype=torch.uint8, device="cuda")
+    tmp = torch.empty(max(cap), dtype=torch.uint8, device="cuda")
+    dws = torch.empty(fpsz.decompress_workspace_bytes((1800, 3600)), dtype=torch.uint8, device="cuda")
+    out = torch.empty((1800, 3600), dtype=torch.float32, device="cuda")
+    for i, x in enumerate(xs):
+        st, n1, _ = ctx.compress_into(x, psnrs[i], ws, tmp)
+        assert st == 0 and n1 == nb[i], "field %d size" % i
+        assert torch.equal(tmp[:n1], blobs[i][:n1]), "field %d differs from the plain call" % i
+        assert ctx.decompress_into(blobs[i], nb[i], dws, out) == 0
+        s = ctx.verify(x, out, info[i]["vr"], info[i]["eb"])
+        assert s["n_over_eb"] == 0
+    for i in (0, 57, 119):
+        xh = xs[i].cpu().numpy()
+        ob, _ = orc.compress(xh, psnrs[i])
+        assert blobs[i][:nb[i]].cpu().numpy().tobytes() == ob, "field %d vs oracle" % i
+    b.close()
