@@ -235,6 +235,74 @@ fpsz_status fpsz_compress_batch(fpsz_ctx *ctx, int n, const fpsz_field_desc *fie
                                 uint64_t *blob_bytes, fpsz_info *info, fpsz_status *status,
                                 void *stream);
 
+/* ---- serving ---------------------------------------------------------------
+ * A request loop for compress / decompress requests arriving over time, each
+ * compress with its own target PSNR (the fixed-PSNR workflow after Eq. 7 per
+ * request).  A worker thread admits requests in arrival order while their
+ * HBM footprint (input + output + workspace bytes) fits `hbm_budget_bytes`
+ * and one of `max_inflight` result slots is free; requests arriving while
+ * others run join the next admission round (continuous batching).  Compress
+ * requests of one round that share (dtype, ndim, domain) run as one batched
+ * launch; rounds go to `n_streams` streams (default priority) and overlap on
+ * the device.  Workspaces come from a device arena of `arena_bytes`
+ * allocated at creation; no device memory is allocated per request.  Every
+ * result is bit-identical to the plain call on the same inputs.
+ *
+ * Buffers named in a request are the caller's: inputs must be complete
+ * (their producing work synchronized) before submission and stay untouched,
+ * and outputs must not be read, until the request is done. */
+enum { FPSZ_REQ_COMPRESS = 0, FPSZ_REQ_DECOMPRESS = 1 };
+
+typedef struct {
+  int32_t kind;         /* FPSZ_REQ_COMPRESS or FPSZ_REQ_DECOMPRESS */
+  int32_t ndim;         /* shape of the field (compress input / decompress output) */
+  int32_t dtype;        /* fpsz_dtype */
+  int32_t domain;       /* fpsz_domain (compress) */
+  uint64_t dims[3];     /* slowest-first */
+  double target_psnr;   /* compress */
+  const void *src_dev;  /* compress: field; decompress: blob */
+  uint64_t src_bytes;   /* decompress: blob bytes */
+  void *dst_dev;        /* compress: blob buffer; decompress: field buffer */
+  uint64_t dst_capacity;
+} fpsz_request;
+
+typedef struct {
+  fpsz_status status;
+  uint32_t reserved;
+  uint64_t out_bytes;   /* blob bytes (the size needed on CAPACITY) or field bytes */
+  fpsz_info info;       /* compress report, or the decompressed blob's header */
+  double t_submit, t_start, t_done; /* seconds on the server's clock */
+} fpsz_result;
+
+typedef struct {
+  uint64_t submitted, completed, failed;
+  uint64_t rounds;            /* admission rounds launched */
+  uint64_t batched_launches;  /* compress groups launched as one batch */
+  uint64_t peak_inflight;
+  uint64_t peak_held_bytes;
+  uint64_t held_bytes;        /* now */
+  double now;                 /* server clock, seconds */
+} fpsz_server_stats;
+
+typedef struct fpsz_server fpsz_server;
+
+/* Create a server on ctx's device (the server uses a private context).
+ * INVALID_ARG for zero budgets, max_inflight outside 1..4096 or n_streams
+ * outside 1..16; DEVICE / NOMEM when its memory cannot be had. */
+fpsz_status fpsz_server_create(fpsz_ctx *ctx, uint64_t hbm_budget_bytes, uint64_t arena_bytes,
+                               int max_inflight, int n_streams, fpsz_server **out);
+/* Queue a request; *id identifies it.  Malformed requests complete at once
+ * with INVALID_ARG; requests larger than the budget complete with CAPACITY. */
+fpsz_status fpsz_server_submit(fpsz_server *srv, const fpsz_request *req, uint64_t *id);
+/* Non-blocking: *done = 1 and *res filled when the request has finished (its
+ * record is then released; an id is reported once). */
+fpsz_status fpsz_server_poll(fpsz_server *srv, uint64_t id, int *done, fpsz_result *res);
+/* Blocking variant of fpsz_server_poll. */
+fpsz_status fpsz_server_wait(fpsz_server *srv, uint64_t id, fpsz_result *res);
+fpsz_status fpsz_server_get_stats(fpsz_server *srv, fpsz_server_stats *out);
+/* Finishes every submitted request, then frees the server. */
+void fpsz_server_destroy(fpsz_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -214,9 +214,9 @@ fpsz_status fpsz_decompress(fpsz_ctx *ctx, const void *blob_dev, uint64_t blob_b
   ctx->err[0] = 0;
   if (!blob_dev || !workspace_dev || !field_out_dev)
     return fail(ctx, FPSZ_E_INVALID_ARG, "null pointer argument");
-  if (blob_bytes < kHdr || blob_bytes % 8) return fail(ctx, FPSZ_E_CORRUPT, "blob size %llu", (unsigned long long)blob_bytes);
-  if ((uintptr_t)blob_dev % 8 || (uintptr_t)workspace_dev % 256)
-    return fail(ctx, FPSZ_E_INVALID_ARG, "blob must be 8-aligned, workspace 256-aligned");
+  if (blob_bytes < kHdr || blob_bytes % 8)
+    return fail(ctx, FPSZ_E_CORRUPT, "blob size %llu", (unsigned long long)blob_bytes);
+  if ((uintptr_t)blob_dev % 8) return fail(ctx, FPSZ_E_INVALID_ARG, "blob must be 8-aligned");
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, FPSZ_E_DEVICE, "hipSetDevice failed");
   hipStream_t s = (hipStream_t)stream;
@@ -227,84 +227,18 @@ fpsz_status fpsz_decompress(fpsz_ctx *ctx, const void *blob_dev, uint64_t blob_b
   if (e != hipSuccess) return hip_fail(ctx, e, "header read");
   uint8_t h[kHdr];
   memcpy(h, hh, kHdr);
-  int nd;
-  uint64_t dims[3];
-  fpsz_dtype dt;
-  if (fpsz_blob_header(h, kHdr, &nd, dims, &dt, nullptr) != FPSZ_OK)
-    return fail(ctx, FPSZ_E_CORRUPT, "bad magic, version, ndim or dtype");
-  Plan P;
-  if (make_plan(nd, dims, dt, &P) != FPSZ_OK) return fail(ctx, FPSZ_E_CORRUPT, "bad dims in header");
-  if (rd<uint64_t>(h + H_BYTES) != blob_bytes || rd<uint64_t>(h + H_N) != P.n)
-    return fail(ctx, FPSZ_E_CORRUPT, "size fields disagree with the blob");
-  const size_t esz = dt == FPSZ_F32 ? 4 : 8;
-  if (out_bytes < P.n * esz)
-    return fail(ctx, FPSZ_E_CAPACITY, "output needs %llu bytes", (unsigned long long)(P.n * esz));
-  if ((uintptr_t)field_out_dev % esz) return fail(ctx, FPSZ_E_INVALID_ARG, "output not element-aligned");
-  const uint16_t flags = rd<uint16_t>(h + H_FLAGS);
-  P.domain = (flags & kFlagTile) ? FPSZ_DOMAIN_TILE : FPSZ_DOMAIN_GLOBAL;
-  P.capacity = blob_bytes;
-  if (flags & kFlagConst) {
-    if (blob_bytes != kHdr) return fail(ctx, FPSZ_E_CORRUPT, "constant blob size");
-    // the header checksum still has to hold
-    if (workspace_bytes < align256(sizeof(DevParams)))
-      return fail(ctx, FPSZ_E_CAPACITY, "workspace too small");
-    DevParams *dp = (DevParams *)workspace_dev;
-    e = launch_fill_zero(dp, sizeof(DevParams), s);
-    if (e == hipSuccess) e = launch_checksum((const uint8_t *)blob_dev, kHdr, dp, s);
-    if (e == hipSuccess) e = launch_const_fill_bits(P, rd<uint64_t>(h + H_CONST), field_out_dev, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(ctx->host, dp, sizeof(DevParams), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(ctx, e, "constant fill");
-    if (ctx->host->checksum != rd<uint64_t>(h + H_CSUM)) return fail(ctx, FPSZ_E_CORRUPT, "checksum mismatch");
-    return FPSZ_OK;
-  }
-  if (rd<uint64_t>(h + H_NTILES) != P.n_tiles || rd<uint64_t>(h + H_NCHUNKS) != P.n_chunks)
-    return fail(ctx, FPSZ_E_CORRUPT, "tile / chunk counts disagree with the shape");
-  if (rd<uint32_t>(h + H_TILE) != P.tz || rd<uint32_t>(h + H_TILE + 4) != P.ty ||
-      rd<uint32_t>(h + H_TILE + 8) != P.tx || rd<uint32_t>(h + H_CHUNK) != (uint32_t)kChunk ||
-      h[H_LMAX] != kLMax)
-    return fail(ctx, FPSZ_E_CORRUPT, "format constants differ");
-  const uint64_t n_words = rd<uint64_t>(h + H_NWORDS), n_exc = rd<uint64_t>(h + H_NEXC);
-  if (n_exc > 3 * P.n || n_words > blob_bytes / 4)
-    return fail(ctx, FPSZ_E_CORRUPT, "section counts out of range");
-  const uint64_t off_words = align8(P.off_exc + 8 * n_exc);
-  if (align8(off_words + 4 * n_words) != blob_bytes)
-    return fail(ctx, FPSZ_E_CORRUPT, "section sizes disagree with the blob size");
-  const DecompressLayout L = decompress_layout(P);
-  if (workspace_bytes < L.total)
-    return fail(ctx, FPSZ_E_CAPACITY, "workspace needs %llu bytes", (unsigned long long)L.total);
-  const uint64_t e2b = rd<uint64_t>(h + H_E2T);
-  double e2;
-  float e2_f;
-  memcpy(&e2, &e2b, 8);
-  const uint32_t e2fb = (uint32_t)e2b;
-  memcpy(&e2_f, &e2fb, 4);
-  uint8_t *ws = (uint8_t *)workspace_dev;
-  DecompressWs W;
-  W.P = (DevParams *)ws;
-  W.lut = (uint32_t *)(ws + L.off_lut);
-  W.ltab = (uint32_t *)(ws + L.off_ltab);
-  W.sorted = (uint16_t *)(ws + L.off_sorted);
-  W.fz = (uint32_t *)(ws + L.off_fz);
-  W.fy = (uint32_t *)(ws + L.off_fy);
-  W.fx = (uint32_t *)(ws + L.off_fx);
-  W.gx = (uint32_t *)(ws + L.off_gx);
-  W.gy = (uint32_t *)(ws + L.off_gy);
-  W.gz = (uint32_t *)(ws + L.off_gz);
-  W.tt = (uint32_t *)(ws + L.off_tt);
-  W.tmp = (uint32_t *)(ws + L.off_tmp);
-  W.codes = (int16_t *)(ws + L.off_codes);
-  W.zero_bytes = align256(sizeof(DevParams));
+  DJob J;
+  fpsz_status st = prepare_decompress(ctx, h, blob_dev, blob_bytes, workspace_dev, workspace_bytes,
+                                      field_out_dev, out_bytes, &J);
+  if (st != FPSZ_OK) return st;
   Timer *tm = timer_begin(ctx);
-  e = launch_decompress_args(P, (const uint8_t *)blob_dev, W, off_words, n_words, n_exc, e2, e2_f,
-                             field_out_dev, s, tm);
+  e = launch_decompress_job(J, s, tm);
   if (e != hipSuccess) return hip_fail(ctx, e, "decompress launch");
-  e = hipMemcpyAsync(ctx->host, W.P, sizeof(DevParams), hipMemcpyDeviceToHost, s);
+  e = hipMemcpyAsync(ctx->host, J.W.P, sizeof(DevParams), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(ctx, e, "decompress");
   timer_collect(ctx);
-  if (ctx->host->corrupt) return fail(ctx, FPSZ_E_CORRUPT, "blob failed a consistency check");
-  return FPSZ_OK;
+  return decompress_result(ctx, J, *ctx->host);
 }
 
 fpsz_status fpsz_verify(fpsz_ctx *ctx, const void *orig_dev, const void *recon_dev, uint64_t n,

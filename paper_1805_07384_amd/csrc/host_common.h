@@ -296,6 +296,123 @@ inline fpsz_status compress_result(fpsz_ctx *ctx, const Plan &P, const DevParams
                 (unsigned long long)D.blob_bytes, (unsigned long long)P.capacity);
   return FPSZ_OK;
 }
+
+// One decompression after its header (a host copy) has been checked.
+struct DJob {
+  Plan P;
+  const uint8_t *blob;
+  void *out;
+  DecompressWs W;
+  uint64_t off_words, n_words, n_exc;
+  double e2;
+  float e2_f;
+  bool is_const;
+  uint64_t const_bits, csum;
+};
+
+// Checks a blob header held in host memory against the blob size, the output
+// buffer and the workspace, and fills the job.
+inline fpsz_status prepare_decompress(fpsz_ctx *ctx, const uint8_t *h, const void *blob_dev,
+                                      uint64_t blob_bytes, void *workspace_dev,
+                                      uint64_t workspace_bytes, void *field_out_dev,
+                                      uint64_t out_bytes, DJob *J) {
+  if (!blob_dev || !workspace_dev || !field_out_dev)
+    return fail(ctx, FPSZ_E_INVALID_ARG, "null pointer argument");
+  if (blob_bytes < kHdr || blob_bytes % 8)
+    return fail(ctx, FPSZ_E_CORRUPT, "blob size %llu", (unsigned long long)blob_bytes);
+  if ((uintptr_t)blob_dev % 8 || (uintptr_t)workspace_dev % 256)
+    return fail(ctx, FPSZ_E_INVALID_ARG, "blob must be 8-aligned, workspace 256-aligned");
+  if (rd<uint32_t>(h + H_MAGIC) != kMagic || rd<uint16_t>(h + H_VERSION) != kVersion)
+    return fail(ctx, FPSZ_E_CORRUPT, "bad magic or version");
+  const int nd = h[H_NDIM], dtc = h[H_DTYPE];
+  if (nd < 1 || nd > 3 || dtc > 1) return fail(ctx, FPSZ_E_CORRUPT, "bad ndim or dtype");
+  uint64_t dims[3];
+  for (int i = 0; i < 3; i++) dims[i] = rd<uint64_t>(h + H_DIMS + 8 * i);
+  const fpsz_dtype dt = (fpsz_dtype)dtc;
+  Plan &P = J->P;
+  if (make_plan(nd, dims, dt, &P) != FPSZ_OK) return fail(ctx, FPSZ_E_CORRUPT, "bad dims in header");
+  if (rd<uint64_t>(h + H_BYTES) != blob_bytes || rd<uint64_t>(h + H_N) != P.n)
+    return fail(ctx, FPSZ_E_CORRUPT, "size fields disagree with the blob");
+  const size_t esz = dt == FPSZ_F32 ? 4 : 8;
+  if (out_bytes < P.n * esz)
+    return fail(ctx, FPSZ_E_CAPACITY, "output needs %llu bytes", (unsigned long long)(P.n * esz));
+  if ((uintptr_t)field_out_dev % esz) return fail(ctx, FPSZ_E_INVALID_ARG, "output not element-aligned");
+  const uint16_t flags = rd<uint16_t>(h + H_FLAGS);
+  P.domain = (flags & kFlagTile) ? FPSZ_DOMAIN_TILE : FPSZ_DOMAIN_GLOBAL;
+  P.capacity = blob_bytes;
+  J->blob = (const uint8_t *)blob_dev;
+  J->out = field_out_dev;
+  J->csum = rd<uint64_t>(h + H_CSUM);
+  J->is_const = (flags & kFlagConst) != 0;
+  uint8_t *ws = (uint8_t *)workspace_dev;
+  if (J->is_const) {
+    if (blob_bytes != kHdr) return fail(ctx, FPSZ_E_CORRUPT, "constant blob size");
+    if (workspace_bytes < align256(sizeof(DevParams)))
+      return fail(ctx, FPSZ_E_CAPACITY, "workspace too small");
+    memset(&J->W, 0, sizeof(J->W));
+    J->W.P = (DevParams *)ws;
+    J->const_bits = rd<uint64_t>(h + H_CONST);
+    return FPSZ_OK;
+  }
+  if (rd<uint64_t>(h + H_NTILES) != P.n_tiles || rd<uint64_t>(h + H_NCHUNKS) != P.n_chunks)
+    return fail(ctx, FPSZ_E_CORRUPT, "tile / chunk counts disagree with the shape");
+  if (rd<uint32_t>(h + H_TILE) != P.tz || rd<uint32_t>(h + H_TILE + 4) != P.ty ||
+      rd<uint32_t>(h + H_TILE + 8) != P.tx || rd<uint32_t>(h + H_CHUNK) != (uint32_t)kChunk ||
+      h[H_LMAX] != kLMax)
+    return fail(ctx, FPSZ_E_CORRUPT, "format constants differ");
+  J->n_words = rd<uint64_t>(h + H_NWORDS);
+  J->n_exc = rd<uint64_t>(h + H_NEXC);
+  if (J->n_exc > 3 * P.n || J->n_words > blob_bytes / 4)
+    return fail(ctx, FPSZ_E_CORRUPT, "section counts out of range");
+  J->off_words = align8(P.off_exc + 8 * J->n_exc);
+  if (align8(J->off_words + 4 * J->n_words) != blob_bytes)
+    return fail(ctx, FPSZ_E_CORRUPT, "section sizes disagree with the blob size");
+  const DecompressLayout L = decompress_layout(P);
+  if (workspace_bytes < L.total)
+    return fail(ctx, FPSZ_E_CAPACITY, "workspace needs %llu bytes", (unsigned long long)L.total);
+  const uint64_t e2b = rd<uint64_t>(h + H_E2T);
+  memcpy(&J->e2, &e2b, 8);
+  const uint32_t e2fb = (uint32_t)e2b;
+  memcpy(&J->e2_f, &e2fb, 4);
+  DecompressWs &W = J->W;
+  W.P = (DevParams *)ws;
+  W.lut = (uint32_t *)(ws + L.off_lut);
+  W.ltab = (uint32_t *)(ws + L.off_ltab);
+  W.sorted = (uint16_t *)(ws + L.off_sorted);
+  W.fz = (uint32_t *)(ws + L.off_fz);
+  W.fy = (uint32_t *)(ws + L.off_fy);
+  W.fx = (uint32_t *)(ws + L.off_fx);
+  W.gx = (uint32_t *)(ws + L.off_gx);
+  W.gy = (uint32_t *)(ws + L.off_gy);
+  W.gz = (uint32_t *)(ws + L.off_gz);
+  W.tt = (uint32_t *)(ws + L.off_tt);
+  W.tmp = (uint32_t *)(ws + L.off_tmp);
+  W.codes = (int16_t *)(ws + L.off_codes);
+  W.zero_bytes = align256(sizeof(DevParams));
+  return FPSZ_OK;
+}
+
+// Enqueues the decompression (no synchronization).
+inline hipError_t launch_decompress_job(const DJob &J, hipStream_t s, Timer *tm) {
+  if (J.is_const) {
+    hipError_t e = launch_fill_zero(J.W.P, sizeof(DevParams), s);
+    if (e == hipSuccess) e = launch_checksum(J.blob, kHdr, J.W.P, s);
+    if (e == hipSuccess) e = launch_const_fill_bits(J.P, J.const_bits, J.out, s);
+    return e;
+  }
+  return launch_decompress_args(J.P, J.blob, J.W, J.off_words, J.n_words, J.n_exc, J.e2, J.e2_f,
+                                J.out, s, tm);
+}
+
+// Status of a finished decompression from its parameter block.
+inline fpsz_status decompress_result(fpsz_ctx *ctx, const DJob &J, const DevParams &D) {
+  if (J.is_const) {
+    if (D.checksum != J.csum) return fail(ctx, FPSZ_E_CORRUPT, "checksum mismatch");
+    return FPSZ_OK;
+  }
+  if (D.corrupt) return fail(ctx, FPSZ_E_CORRUPT, "blob failed a consistency check");
+  return FPSZ_OK;
+}
 }  // namespace fpsz
 
 #endif

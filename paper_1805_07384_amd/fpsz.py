@@ -61,6 +61,37 @@ class FieldDesc(ctypes.Structure):
                 ("blob_dev", ctypes.c_void_p), ("blob_capacity", ctypes.c_uint64)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("ndim", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("domain", ctypes.c_int32), ("dims", ctypes.c_uint64 * 3),
+                ("target_psnr", ctypes.c_double), ("src_dev", ctypes.c_void_p),
+                ("src_bytes", ctypes.c_uint64), ("dst_dev", ctypes.c_void_p),
+                ("dst_capacity", ctypes.c_uint64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("reserved", ctypes.c_uint32),
+                ("out_bytes", ctypes.c_uint64), ("info", Info), ("t_submit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"status": self.status, "out_bytes": self.out_bytes, "info": self.info.as_dict(),
+                "t_submit": self.t_submit, "t_start": self.t_start, "t_done": self.t_done}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("rounds", ctypes.c_uint64),
+                ("batched_launches", ctypes.c_uint64), ("peak_inflight", ctypes.c_uint64),
+                ("peak_held_bytes", ctypes.c_uint64), ("held_bytes", ctypes.c_uint64),
+                ("now", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+REQ_COMPRESS, REQ_DECOMPRESS = 0, 1
+
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _vp = ctypes.c_void_p
 
@@ -101,6 +132,14 @@ SIGNATURES = {
     "fpsz_compress_batch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(FieldDesc), _vp,
                                            ctypes.c_uint64, _u64p, ctypes.POINTER(Info),
                                            ctypes.POINTER(ctypes.c_int), _vp]),
+    "fpsz_server_create": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
+                                          ctypes.c_int, ctypes.POINTER(_vp)]),
+    "fpsz_server_submit": (ctypes.c_int, [_vp, ctypes.POINTER(Request), _u64p]),
+    "fpsz_server_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(Result)]),
+    "fpsz_server_wait": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(Result)]),
+    "fpsz_server_get_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ServerStats)]),
+    "fpsz_server_destroy": (None, [_vp]),
 }
 
 _lib = None
@@ -395,6 +434,100 @@ class Batch:
         if getattr(self, "handle", None):
             self.lib.fpsz_batch_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """fpsz_server_*: a request loop with HBM-budget admission and continuous
+    batching.  Keeps the tensors of each request alive until it is reported."""
+
+    def __init__(self, ctx: Context, hbm_budget: int, arena_bytes: int, max_inflight: int = 64,
+                 n_streams: int = 4):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        h = _vp()
+        st = self.lib.fpsz_server_create(ctx.handle, int(hbm_budget), int(arena_bytes),
+                                         int(max_inflight), int(n_streams), ctypes.byref(h))
+        if st != OK:
+            raise ctx._err(st, "fpsz_server_create")
+        self.handle = h
+        self._keep = {}
+
+    def submit_compress(self, x: torch.Tensor, psnr: float, blob: torch.Tensor,
+                        domain: int = GLOBAL) -> int:
+        assert x.is_contiguous() and x.is_cuda
+        r = Request()
+        r.kind = REQ_COMPRESS
+        r.ndim = x.dim()
+        r.dtype = _dtype_code(x)
+        r.domain = int(domain)
+        for k, v in enumerate(list(x.shape) + [1] * (3 - x.dim())):
+            r.dims[k] = int(v)
+        r.target_psnr = float(psnr)
+        r.src_dev = x.data_ptr()
+        r.dst_dev = blob.data_ptr()
+        r.dst_capacity = blob.numel()
+        return self._submit(r, (x, blob))
+
+    def submit_decompress(self, blob: torch.Tensor, nbytes: int, out: torch.Tensor) -> int:
+        assert out.is_contiguous() and out.is_cuda
+        r = Request()
+        r.kind = REQ_DECOMPRESS
+        r.ndim = out.dim()
+        r.dtype = _dtype_code(out)
+        for k, v in enumerate(list(out.shape) + [1] * (3 - out.dim())):
+            r.dims[k] = int(v)
+        r.src_dev = blob.data_ptr()
+        r.src_bytes = int(nbytes)
+        r.dst_dev = out.data_ptr()
+        r.dst_capacity = out.numel() * out.element_size()
+        return self._submit(r, (blob, out))
+
+    def _submit(self, r, keep) -> int:
+        rid = ctypes.c_uint64()
+        st = self.lib.fpsz_server_submit(self.handle, ctypes.byref(r), ctypes.byref(rid))
+        if st != OK:
+            raise FpszError(st, "fpsz_server_submit")
+        self._keep[rid.value] = keep
+        return rid.value
+
+    def poll(self, rid: int):
+        """Result dict when request ``rid`` has finished, else None."""
+        done = ctypes.c_int()
+        res = Result()
+        st = self.lib.fpsz_server_poll(self.handle, int(rid), ctypes.byref(done), ctypes.byref(res))
+        if st != OK:
+            raise FpszError(st, "fpsz_server_poll(%d)" % rid)
+        if not done.value:
+            return None
+        self._keep.pop(rid, None)
+        return res.as_dict()
+
+    def wait(self, rid: int) -> dict:
+        res = Result()
+        st = self.lib.fpsz_server_wait(self.handle, int(rid), ctypes.byref(res))
+        if st != OK:
+            raise FpszError(st, "fpsz_server_wait(%d)" % rid)
+        self._keep.pop(rid, None)
+        return res.as_dict()
+
+    def stats(self) -> dict:
+        out = ServerStats()
+        st = self.lib.fpsz_server_get_stats(self.handle, ctypes.byref(out))
+        if st != OK:
+            raise FpszError(st, "fpsz_server_get_stats")
+        return out.as_dict()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.fpsz_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
 
     def __del__(self):
         try:
