@@ -40,6 +40,11 @@ def parse():
                     help="planes of the field the CPU oracle is timed on")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-kernel HIP-event timing")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 120-field batched-vs-plain leg")
+    ap.add_argument("--no-served", action="store_true",
+                    help="skip the served-vs-plain request-trace leg")
+    ap.add_argument("--served-requests", type=int, default=400)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy the field once with a plain device copy "
                          "(the reference kernel for scaling HBM byte counters)")
@@ -49,8 +54,10 @@ def parse():
 # Source files whose kernels the HBM traffic figures under profiles/ were
 # measured on; a figure whose recorded hash differs is stale and not reported.
 SRC_FILES = ["paper_1805_07384_amd/csrc/compress.hip", "paper_1805_07384_amd/csrc/decompress.hip",
-             "paper_1805_07384_amd/csrc/api.hip", "paper_1805_07384_amd/csrc/fpsz_internal.h",
-             "paper_1805_07384_amd/build.py", "include/fpsz.h"]
+             "paper_1805_07384_amd/csrc/api.hip", "paper_1805_07384_amd/csrc/batch.hip",
+             "paper_1805_07384_amd/csrc/serve.hip", "paper_1805_07384_amd/csrc/fpsz_internal.h",
+             "paper_1805_07384_amd/csrc/host_common.h", "paper_1805_07384_amd/build.py",
+             "include/fpsz.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_lognormal512_sweep.txt")
 
 
@@ -119,6 +126,124 @@ def cpu_baseline(x_cpu, psnrs, planes):
                       " (%.1f s)" % (list(sample.shape), "/".join("%g" % p for p in psnrs), dt)}
 
 
+def progress(msg):
+    print("[bench %.1fs] %s" % (time.perf_counter() - _T0, msg), file=sys.stderr, flush=True)
+
+
+_T0 = time.perf_counter()
+
+
+def batched_leg(ctx, dev):
+    """120 2D f32 1800x3600 fields (slope U[-4,-2], range 10^U(-3,4), target
+    U[40,120] dB): 120 plain calls vs one batch (captured graph, autotuned
+    launch shapes).  Compress only, inputs resident; median of 3 runs each."""
+    import numpy as np
+    import torch
+
+    from paper_1805_07384_amd import fpsz, synth
+
+    spec = synth.batch_fields_spec(120, seed=3)
+    progress("batched leg: generating 120 fields")
+    xs = [synth.batch_field(sp, backend="torch", device=dev).contiguous() for sp in spec]
+    torch.cuda.synchronize()
+    progress("batched leg: plain calls")
+    psnrs = [sp["psnr"] for sp in spec]
+    caps = [fpsz.compress_bound(tuple(x.shape)) // 2 for x in xs]
+    blobs = [torch.empty(c, dtype=torch.uint8, device=dev) for c in caps]
+    total = sum(x.numel() * 4 for x in xs)
+    ws = torch.empty(fpsz.compress_workspace_bytes((1800, 3600)), dtype=torch.uint8, device=dev)
+    pblob = torch.empty(max(caps), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def plain_once():
+        sizes = []
+        for x, p in zip(xs, psnrs):
+            st, nb, _ = ctx.compress_into(x, p, ws, pblob, fpsz.GLOBAL, stream)
+            if st != fpsz.OK:
+                raise fpsz.FpszError(st, "plain compress")
+            sizes.append(nb)
+        return sizes
+
+    plain_once()
+    tp = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        psz = plain_once()
+        tp.append(time.perf_counter() - t0)
+    progress("batched leg: batch + autotune")
+    b = fpsz.Batch(ctx, xs, psnrs, blobs, graph=True)
+    b.run()
+    tuned_ms = b.autotune(reps=2)
+    progress("batched leg: timed batch runs")
+    tb = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, nb, info, sts = b.run()
+        tb.append(time.perf_counter() - t0)
+    shape = b.launch_shape(0)
+    b.close()
+    progress("batched leg: accuracy check")
+    # accuracy per field (untimed): decompress + Eq. 4
+    dws = torch.empty(fpsz.decompress_workspace_bytes((1800, 3600)), dtype=torch.uint8, device=dev)
+    out = torch.empty((1800, 3600), dtype=torch.float32, device=dev)
+    dps, over = [], 0
+    for i, x in enumerate(xs):
+        if ctx.decompress_into(blobs[i], nb[i], dws, out, stream) != fpsz.OK:
+            raise fpsz.FpszError(fpsz.E_CORRUPT, "batched blob %d" % i)
+        stt = ctx.verify(x, out, info[i]["vr"], info[i]["eb"])
+        dps.append(stt["psnr"] - psnrs[i])
+        over += stt["n_over_eb"]
+    tp_m, tb_m = float(np.median(tp)), float(np.median(tb))
+    res = {"workload": "120 2D float32 1800x3600 GRF fields, slope U[-4,-2], range 10^U(-3,4), "
+                       "target U[40,120] dB, seed 3",
+           "bytes": total, "plain_gbps": round(total / tp_m / 1e9, 2),
+           "batched_gbps": round(total / tb_m / 1e9, 2), "speedup": round(tp_m / tb_m, 3),
+           "plain_ms": round(tp_m * 1e3, 3), "batched_ms": round(tb_m * 1e3, 3),
+           "autotuned_ms": round(tuned_ms, 3), "launch_shape": shape,
+           "identical_sizes": psz == list(nb),
+           "mean_abs_dpsnr": round(float(np.mean(np.abs(dps))), 4),
+           "meet_rate": round(float(np.mean([d >= 0 for d in dps])), 4), "n_over_eb": int(over)}
+    del xs, blobs, ws, pblob, dws, out
+    torch.cuda.empty_cache()
+    return res
+
+
+def served_leg(ctx, dev, n_req):
+    """Seeded request trace (Poisson 200/s, 70 % compress / 30 % decompress,
+    lognormal sizes median 16 MiB in [1 MiB, 2 GiB], 1D/2D/3D, targets
+    U[40,120] dB) replayed in real time through the server and through
+    one-at-a-time plain calls."""
+    import torch
+
+    from paper_1805_07384_amd import serving, synth
+
+    trace = synth.serve_trace(n_req=n_req, rate=200.0, seed=4)
+    progress("served leg: building %d requests" % n_req)
+    work = serving.build_workload(trace, device=dev, pool_size=64, ctx=ctx, log=progress)
+    progress("served leg: plain replay")
+    plain, ps = serving.replay_plain(ctx, work, device=dev)
+    progress("served leg: served replay")
+    served, ss = serving.replay_served(ctx, work, hbm_budget=64 << 30, arena_bytes=24 << 30,
+                                       max_inflight=64, n_streams=4, device=dev)
+    progress("served leg: comparing results")
+    diff = serving.same_results(plain, served)
+    res = {"workload": "%d requests, Poisson 200/s, 70/30 compress/decompress, lognormal size "
+                       "median 16 MiB [1 MiB, 2 GiB], 1D/2D/3D GRF k^-3, target U[40,120] dB, "
+                       "seed 4; budget 64 GiB, 4 streams, 64 slots" % n_req,
+           "plain": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in
+                     {**ps["latency"], "gbps": ps["gbps"], "span_s": ps["span_s"]}.items()},
+           "served": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in
+                      {**ss["latency"], "gbps": ss["gbps"], "span_s": ss["span_s"]}.items()},
+           "results_differing": diff,
+           "server": {k: ss["server"][k] for k in ("rounds", "batched_launches", "peak_inflight",
+                                                   "peak_held_bytes", "failed")}}
+    del work, plain, served
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -179,8 +304,10 @@ def main():
                 for nm, ms in stages_c + stages_d + stages_v:
                     r["stages"].setdefault(nm, []).append(ms)
 
+    progress("sweep: warm-up")
     for _ in range(args.warmup):
         one_step(None)
+    progress("sweep: timed steps")
     rec = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -265,8 +392,14 @@ def main():
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
+        progress("cpu baseline (oracle)")
         planes = min(args.cpu_planes, args.edge)
         line["cpu_baseline"] = cpu_baseline(x.cpu().numpy(), psnrs, planes)
+    del ws_c, ws_d, blob, out
+    if not args.no_batched:
+        line["batched"] = batched_leg(ctx, dev)
+    if not args.no_served:
+        line["served"] = served_leg(ctx, dev, args.served_requests)
     print(json.dumps(line), flush=True)
 
 

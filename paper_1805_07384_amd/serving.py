@@ -17,27 +17,34 @@ import torch
 from . import fpsz, synth
 
 
-def build_workload(trace, device="cuda", pool_size=64, ctx=None, alpha=-3.0):
+def build_workload(trace, device="cuda", pool_size=64, ctx=None, alpha=-3.0, log=None):
     """Device-resident inputs for every request of ``trace``.
 
-    Compress requests get a float32 GRF (spectrum k^alpha) of their shape.
+    Compress requests get a float32 field of their shape cut from a periodic
+    GRF (spectrum k^alpha) of the same dimensionality at a seeded offset.
     Decompress requests pick one blob from a pool of ``pool_size`` blobs made
     beforehand (by plain calls) from fields of the trace's own size mix; the
     request's output shape is that blob's field shape."""
     ctx = ctx or fpsz.default_context(torch.device(device).index or 0)
+    bases = synth.periodic_bases(alpha, device=device)
     comp = [r for r in trace if r["kind"] == "compress"]
     pool_src = comp[:pool_size] if len(comp) >= pool_size else comp
     pool = []
+    if log:
+        log("blob pool of %d" % len(pool_src))
     for r in pool_src:
-        x = synth.grf_torch(r["shape"], alpha, r["seed"] + 7, device=device).float().contiguous()
+        x = synth.periodic_crop(bases, r["shape"], r["seed"] + 7)
         b, info = ctx.compress(x, r["psnr"])
         pool.append({"blob": b, "nbytes": int(b.numel()), "shape": tuple(x.shape)})
         del x
     work = []
-    for r in trace:
+    for i, r in enumerate(trace):
+        if log and i % 50 == 0:
+            torch.cuda.synchronize()
+            log("request inputs %d / %d" % (i, len(trace)))
         w = dict(r)
         if r["kind"] == "compress":
-            x = synth.grf_torch(r["shape"], alpha, r["seed"], device=device).float().contiguous()
+            x = synth.periodic_crop(bases, r["shape"], r["seed"])
             w["x"] = x
             w["bytes"] = x.numel() * 4
             w["cap"] = fpsz.compress_bound(tuple(x.shape)) // 2

@@ -183,3 +183,27 @@ def serve_trace(n_req=2000, rate=200.0, seed=4, median_bytes=16 << 20, sigma_ln=
                      "psnr": float(rng.uniform(40.0, 120.0)), "seed": seed * 1000003 + i,
                      "pick": float(rng.random())})
     return reqs
+
+
+def periodic_bases(alpha: float = -3.0, seed: int = 9, device="cuda",
+                   sizes=((1 << 22,), (2048, 2048), (128, 128, 128))):
+    """One unit-variance float32 GRF per dimensionality (power-of-two
+    periodic boxes), from which request fields of any shape are cut."""
+    return {len(sh): grf_torch(sh, alpha, seed + len(sh), device=device).float()
+            for sh in sizes}
+
+
+def periodic_crop(bases, shape, seed: int):
+    """A field of ``shape`` cut from the periodic extension of the base GRF of
+    its dimensionality at a seeded offset.  A GRF made by FFT is periodic, so
+    the tiling has no seams; structure repeats every base length."""
+    import torch
+
+    base = bases[len(shape)]
+    rng = np.random.default_rng(seed)
+    off = [int(rng.integers(0, b)) for b in base.shape]
+    reps = [-(-(o + n) // b) for o, n, b in zip(off, shape, base.shape)]
+    t = base.repeat(*reps)
+    sl = tuple(slice(o, o + n) for o, n in zip(off, shape))
+    return t[sl].contiguous() if t.dtype == torch.float32 else t[sl].float().contiguous()
+
