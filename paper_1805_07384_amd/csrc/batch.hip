@@ -211,6 +211,7 @@ fpsz_status fpsz_batch_create(fpsz_ctx *ctx, int n, const fpsz_field_desc *field
     c.maxP.n = std::max(c.maxP.n, P.n);
     c.maxP.n_tiles = std::max(c.maxP.n_tiles, P.n_tiles);
     c.maxP.capacity = std::max(c.maxP.capacity, P.capacity);
+    c.maxP.pad_ |= P.pad_;
   }
   for (BatchClass &c : b->classes) c.cfg = default_launch_cfg(c.maxP);
 

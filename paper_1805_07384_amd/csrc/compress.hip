@@ -305,7 +305,183 @@ __device__ inline void load_row(const T *__restrict__ x, const Plan &P, const Ti
   }
 }
 
-template <typename T, int NDIM, bool GLOBAL, bool RECORDS>
+// Full tiles (the common case) take a leaner path: each thread owns one
+// 32-point row segment of the stream, loads it with 16-byte loads, keeps its
+// q in registers and computes its patch bits directly.  LDS holds the q
+// segments of the tile and of the halo (the preceding plane and row), each
+// padded to kSegW words with its left neighbour just before the 16-byte
+// aligned values, so a neighbouring segment is 8 + 1 LDS reads without bank
+// conflicts.  The halo points are loaded by all threads together.
+constexpr int kSegW = 36;
+template <int NDIM> struct FastGeo;
+template <> struct FastGeo<1> { static constexpr int NSEG = 256, HROWS = 0, ROWS = 1; };
+template <> struct FastGeo<2> { static constexpr int NSEG = 4, HROWS = 1, ROWS = 65; };
+template <> struct FastGeo<3> { static constexpr int NSEG = 1, HROWS = 33, ROWS = 17 * 17; };
+
+// LDS word of value k (k = -1 is the left neighbour) of segment s of box row
+// (bz, by) (box coordinates include the halo)
+template <int NDIM> __device__ inline int seg_at(int bz, int by, int s, int k) {
+  using G = Geo<NDIM>;
+  const int row = bz * (G::TY + G::HY) + by;
+  return (row * FastGeo<NDIM>::NSEG + s) * kSegW + 4 + k;
+}
+
+// Patch test |x - x'| > eb.  For float32 input a float32 pre-filter marks
+// candidates: below thr (eb lowered by a relative 2^-22, rounded down) the
+// rounded float32 difference proves |x - x'| <= eb; candidates (rare) take
+// the exact float64 test afterwards.
+template <typename T> struct PatchTest;
+template <> struct PatchTest<float> {
+  __device__ static bool candidate(float v, int32_t q, float e2f, double, double, float thr) {
+    const float xr = (float)q * e2f;
+    return fabsf(v - xr) > thr;
+  }
+  __device__ static bool exact(float v, int32_t q, float e2f, double, double eb) {
+    const float xr = (float)q * e2f;
+    return fabs((double)v - (double)xr) > eb;
+  }
+};
+template <> struct PatchTest<double> {
+  __device__ static bool candidate(double v, int32_t q, float, double e2, double eb, float) {
+    return fabs(v - (double)q * e2) > eb;
+  }
+  __device__ static bool exact(double v, int32_t q, float, double e2, double eb) {
+    return fabs(v - (double)q * e2) > eb;
+  }
+};
+
+// global-memory views of the input (the pointers reach the kernels inside
+// job structures, where the compiler cannot see their address space)
+template <typename T> using gptr_t = __attribute__((address_space(1))) const T *;
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+template <typename T> struct GVec;
+template <> struct GVec<float> { using V = f32x4_t; };
+template <> struct GVec<double> { using V = f64x2_t; };
+
+// Full tile, phase 1: quantize this thread's segment (and its left
+// neighbour) into LDS, the halo points with the other threads; patch bits of
+// the segment.  Ends with the LDS written, before the barrier.
+template <typename T, int NDIM, bool GLOBAL>
+__device__ inline uint32_t fast_tile_load(const T *__restrict__ x_, const Plan &P,
+                                          const TileGeo &g, int tid, int32_t *lds, float rf,
+                                          double r, float e2f, double e2, double eb, float thr) {
+  using G = Geo<NDIM>;
+  using F = FastGeo<NDIM>;
+  gptr_t<T> x = (gptr_t<T>)x_;
+  const int z = NDIM == 3 ? tid >> 4 : 0;
+  const int y = NDIM == 3 ? tid & 15 : NDIM == 2 ? tid >> 2 : 0;
+  const int sg = NDIM == 3 ? 0 : NDIM == 2 ? tid & 3 : tid;
+  const int x0l = 32 * sg;
+  const uint64_t rowbase = ((g.z0 + z) * P.ny + (g.y0 + y)) * P.nx + g.x0 + x0l;
+  T v[32];
+  constexpr int VW = 16 / sizeof(T);
+  if ((rowbase % VW) == 0) {
+    using V = typename GVec<T>::V;
+    gptr_t<V> src = (gptr_t<V>)(x + rowbase);
+#pragma unroll
+    for (int k = 0; k < 32 / VW; k++) {
+      const V a = src[k];
+#pragma unroll
+      for (int h = 0; h < VW; h++) v[k * VW + h] = a[h];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 32; j++) v[j] = x[rowbase + j];
+  }
+  int32_t ql = 0;
+  if (x0l > 0 || (GLOBAL && g.x0 > 0)) ql = Quant<T>::q(x[rowbase - 1], rf, r);
+  int32_t *dst = lds + seg_at<NDIM>(z + G::HZ, y + G::HY, sg, 0);
+  dst[-1] = ql;
+  uint32_t cand = 0;
+#pragma unroll
+  for (int k = 0; k < 8; k++) {
+    int32_t q4[4];
+#pragma unroll
+    for (int h = 0; h < 4; h++) {
+      const int j = 4 * k + h;
+      q4[h] = Quant<T>::q(v[j], rf, r);
+      cand |= (PatchTest<T>::candidate(v[j], q4[h], e2f, e2, eb, thr) ? 1u : 0u) << j;
+    }
+    reinterpret_cast<int4 *>(dst)[k] = make_int4(q4[0], q4[1], q4[2], q4[3]);
+  }
+  uint32_t pb = 0;
+  while (cand) {  // rare: exact test, value reloaded
+    const int j = __ffs(cand) - 1;
+    cand &= cand - 1;
+    if (PatchTest<T>::exact(x[rowbase + j], dst[j], e2f, e2, eb)) pb |= 1u << j;
+  }
+  // halo rows: 3D the plane z = -1 (17 rows) and the rows y = -1 of z >= 0
+  // (16 rows); 2D the row y = -1; 33 values per segment (k = -1 .. 31)
+  constexpr int NH = F::HROWS * F::NSEG * 33;
+  for (int i = tid; i < NH; i += kBlock) {
+    const int hr = i / (F::NSEG * 33), rem = i - hr * (F::NSEG * 33);
+    const int s2 = rem / 33, k = rem - s2 * 33 - 1;
+    const int bz = NDIM == 3 ? (hr < 17 ? 0 : hr - 16) : 0;
+    const int by = NDIM == 3 ? (hr < 17 ? hr : 0) : 0;
+    int32_t qv = 0;
+    if (GLOBAL) {
+      const int64_t fz = (int64_t)g.z0 + bz - G::HZ, fy = (int64_t)g.y0 + by - G::HY;
+      const int64_t fx = (int64_t)g.x0 + 32 * s2 + k;
+      if (fz >= 0 && fy >= 0 && fx >= 0)
+        qv = Quant<T>::q(x[((uint64_t)fz * P.ny + (uint64_t)fy) * P.nx + (uint64_t)fx], rf, r);
+    }
+    lds[seg_at<NDIM>(bz, by, s2, k)] = qv;
+  }
+  return pb;
+}
+
+// LDS pointers of this thread's segment and its y, z, (z, y) neighbours
+template <int NDIM> struct SegPtrs {
+  const int32_t *o, *y, *z, *zy;
+  __device__ SegPtrs(const int32_t *lds, int tid) {
+    using G = Geo<NDIM>;
+    const int z_ = NDIM == 3 ? tid >> 4 : 0;
+    const int y_ = NDIM == 3 ? tid & 15 : NDIM == 2 ? tid >> 2 : 0;
+    const int sg = NDIM == 3 ? 0 : NDIM == 2 ? tid & 3 : tid;
+    o = lds + seg_at<NDIM>(z_ + G::HZ, y_ + G::HY, sg, 0);
+    y = NDIM >= 2 ? lds + seg_at<NDIM>(z_ + G::HZ, y_ + G::HY - 1, sg, 0) : o;
+    z = NDIM == 3 ? lds + seg_at<NDIM>(z_ + G::HZ - 1, y_ + G::HY, sg, 0) : o;
+    zy = NDIM == 3 ? lds + seg_at<NDIM>(z_ + G::HZ - 1, y_ + G::HY - 1, sg, 0) : o;
+  }
+  // residual of point j (0..31) of the segment
+  __device__ int32_t d_at(int j) const {
+    int32_t dv = o[j] - o[j - 1];
+    if (NDIM >= 2) dv -= y[j] - y[j - 1];
+    if (NDIM == 3) dv += (zy[j] - zy[j - 1]) - (z[j] - z[j - 1]);
+    return dv;
+  }
+};
+
+// Symbol of residual d (|d| <= 511 direct, escape classes, 0 = outlier)
+__device__ inline uint32_t symbol_of(int32_t dv, bool &outlier) {
+  const int32_t a = dv < 0 ? -dv : dv;
+  outlier = a >= 32768;
+  const uint32_t esc = 1024u + 2u * (uint32_t)(22 - __clz(a)) + (dv < 0 ? 1u : 0u);
+  return a <= 511 ? (uint32_t)(dv + 512) : (outlier ? 0u : esc);
+}
+
+// XCD-aware tile order for persistent grids whose size is a multiple of 8:
+// workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2), so block b runs on XCD b % 8.  Tiles are grouped in units (3D: a
+// layer of the tile grid, 2D: a row of tiles, 1D: 16 consecutive tiles) and
+// unit u goes to XCD u % 8: a tile and its x / y neighbours (whose halo it
+// reads) are handled on the same XCD at about the same time.
+__device__ inline bool xcd_tile(const Plan &P, int ndim, uint64_t k, uint64_t *t) {
+  if ((gridDim.x & 7) != 0) {
+    *t = blockIdx.x + k * gridDim.x;
+    return *t < P.n_tiles;
+  }
+  const uint64_t U = ndim == 3 ? (uint64_t)P.gy * P.gx : ndim == 2 ? (uint64_t)P.gx : 16;
+  const uint64_t per = gridDim.x >> 3;
+  const uint64_t L = (blockIdx.x >> 3) + k * per;
+  const uint64_t u = (blockIdx.x & 7) + 8 * (L / U);
+  *t = u * U + L % U;
+  return *t < P.n_tiles;
+}
+
+template <typename T, int NDIM, bool GLOBAL, bool RECORDS, bool FULL>
 __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restrict__ jobs) {
   const CJob J = select_job(one, jobs);
   const T *__restrict__ x = static_cast<const T *>(J.x);
@@ -319,7 +495,8 @@ __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restri
   uint8_t *__restrict__ blob = J.blob;
   using G = Geo<NDIM>;
   using B = BoxAddr<NDIM>;
-  __shared__ int32_t box[B::SIZE];
+  constexpr int FAST_SIZE = FastGeo<NDIM>::ROWS * FastGeo<NDIM>::NSEG * kSegW;
+  __shared__ __align__(16) int32_t box[B::SIZE > FAST_SIZE ? B::SIZE : FAST_SIZE];
   __shared__ uint32_t hist[RECORDS ? 1 : kNSym];
   __shared__ uint32_t pmask[kTilePts / 32 + 1];
   __shared__ uint32_t scr[8];
@@ -328,16 +505,78 @@ __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restri
   const int tid = threadIdx.x;
   const float rf = dp->r_f, e2f = dp->e2_f;
   const double r = dp->r, e2 = dp->e2, eb = dp->eb;
+  // float32 pre-filter bound of PatchTest<float>, rounded down; huge bounds
+  // always take the exact test
+  const float thr = eb < 0x1p126 ? __double2float_rd(eb * (1.0 - 0x1p-22)) : -1.0f;
   constexpr int RW = sizeof(T) / 4;  // exception records per patch
   if (!RECORDS)
     for (int s = tid; s < kNSym; s += kBlock) hist[s] = 0;
   uint64_t my_out = 0, my_pat = 0;
 
-  for (uint64_t t = blockIdx.x; t < P.n_tiles; t += gridDim.x) {
+  uint64_t t;
+  for (uint64_t it_k = 0; xcd_tile(P, NDIM, it_k, &t); it_k++) {
     if (RECORDS && exc_cnt[t] <= (uint32_t)kStage) continue;  // uniform
     const TileGeo g = tile_geo(P, t);
     const int ez = (int)g.ez, ey = (int)g.ey, ex = (int)g.ex, nt = (int)g.nt;
+    if ((nt == kTilePts) != FULL) continue;  // uniform: the other kernel's tile
+    const int i0 = 32 * tid;
+    int32_t d[32];
+    uint32_t flags = 0;   // bit j: outlier
+    uint32_t pflags = 0;  // bit j: patch
+    int cnt;
+    constexpr bool full = FULL;  // full tiles: residuals live in LDS, codes written
     __syncthreads();
+    if (FULL) {
+      // full tile: quantize into LDS, then residuals 4 points at a time
+      pflags = fast_tile_load<T, NDIM, GLOBAL>(x, P, g, tid, box, rf, r, e2f, e2, eb, thr);
+      __syncthreads();
+      cnt = 32;
+      const SegPtrs<NDIM> sp(box, tid);
+      int32_t po = sp.o[-1], py = sp.y[-1], pz = sp.z[-1], pzy = sp.zy[-1];
+      uint32_t run_sym = 0xffffffffu, run_n = 0;
+      __attribute__((address_space(1))) u32x2_t *cdst =
+          (__attribute__((address_space(1))) u32x2_t *)(codes + g.start + (uint64_t)i0);
+#pragma unroll 1
+      for (int k = 0; k < 8; k++) {
+        const int4 O = reinterpret_cast<const int4 *>(sp.o)[k];
+        int4 Y = O, Z = O, ZY = O;
+        if (NDIM >= 2) Y = reinterpret_cast<const int4 *>(sp.y)[k];
+        if (NDIM == 3) {
+          Z = reinterpret_cast<const int4 *>(sp.z)[k];
+          ZY = reinterpret_cast<const int4 *>(sp.zy)[k];
+        }
+        const int32_t oa[4] = {O.x, O.y, O.z, O.w}, ya[4] = {Y.x, Y.y, Y.z, Y.w};
+        const int32_t za[4] = {Z.x, Z.y, Z.z, Z.w}, zya[4] = {ZY.x, ZY.y, ZY.z, ZY.w};
+        uint32_t c16[4];
+#pragma unroll
+        for (int h = 0; h < 4; h++) {
+          int32_t dv = oa[h] - po;
+          if (NDIM >= 2) dv -= ya[h] - py;
+          if (NDIM == 3) dv += (zya[h] - pzy) - (za[h] - pz);
+          po = oa[h];
+          py = ya[h];
+          pz = za[h];
+          pzy = zya[h];
+          bool outl;
+          const uint32_t sy = symbol_of(dv, outl);
+          flags |= (outl ? 1u : 0u) << (4 * k + h);
+          c16[h] = outl ? 0x8000u : ((uint32_t)dv & 0xffffu);
+          if (!RECORDS) {
+            const bool ch = sy != run_sym;
+            if (ch && run_n) atomicAdd(&hist[run_sym], run_n);
+            run_n = ch ? 1u : run_n + 1u;
+            run_sym = sy;
+          }
+        }
+        if (!RECORDS) {
+          u32x2_t w;
+          w.x = c16[0] | (c16[1] << 16);
+          w.y = c16[2] | (c16[3] << 16);
+          cdst[k] = w;
+        }
+      }
+      if (!RECORDS) atomicAdd(&hist[run_sym], run_n);
+    } else {
     for (int i = tid; i <= kTilePts / 32; i += kBlock) pmask[i] = 0;
     __syncthreads();
 
@@ -352,11 +591,8 @@ __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restri
     __syncthreads();
 
     // residuals of this thread's 32 consecutive stream points
-    const int i0 = 32 * tid;
-    const int cnt = nt - i0 < 0 ? 0 : (nt - i0 > 32 ? 32 : nt - i0);
-    int32_t d[32];
-    uint32_t flags = 0;   // bit j: outlier
-    const uint32_t pflags = cnt > 0 ? ((pmask[tid]) & (cnt == 32 ? ~0u : ((1u << cnt) - 1))) : 0;
+    cnt = nt - i0 < 0 ? 0 : (nt - i0 > 32 ? 32 : nt - i0);
+    pflags = cnt > 0 ? ((pmask[tid]) & (cnt == 32 ? ~0u : ((1u << cnt) - 1))) : 0;
     {
       int z = 0, y = 0, xx = 0;
       if (cnt > 0) {
@@ -408,11 +644,14 @@ __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restri
       }
       if (!RECORDS && run_n) atomicAdd(&hist[run_sym], run_n);
     }
+    }  // ragged tile
     const uint32_t nexc = __popc(flags) + RW * __popc(pflags);
 
     if (!RECORDS) {
       my_out += __popc(flags);
       my_pat += __popc(pflags);
+    }
+    if (!RECORDS && !full) {
       // residual codes, stream order
       const uint64_t base = g.start + (uint64_t)i0;
       if (cnt == 32 && (base & 7) == 0) {
@@ -452,7 +691,11 @@ __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restri
         const uint32_t pos = (uint32_t)(g.start + (uint64_t)(i0 + j));
         uint32_t recs[6];
         int nr = 0;
-        if ((flags >> j) & 1u) { recs[0] = pos; recs[1] = (uint32_t)d[j]; nr = 1; }
+        if ((flags >> j) & 1u) {
+          recs[0] = pos;
+          recs[1] = (uint32_t)(FULL ? SegPtrs<NDIM>(box, tid).d_at(j) : d[j]);
+          nr = 1;
+        }
         if ((pflags >> j) & 1u) {
           const uint64_t fi = ((g.z0 + z) * P.ny + (g.y0 + y)) * P.nx + (g.x0 + xx);
           uint32_t bits[2];
@@ -1113,13 +1356,19 @@ template <typename T, int NDIM, bool GLOBAL>
 static void launch_quant_d(const CJob &one, const CJob *jobs, int nf, const Plan &maxP,
                            const LaunchCfg &cfg, hipStream_t s, Timer *tm) {
   const dim3 grid(cfg.quant_grid, nf);
-  hipLaunchKernelGGL((k_quant<T, NDIM, GLOBAL, false>), grid, dim3(kBlock), 0, s, one, jobs);
+  // maxP.pad_ carries "some field of the launch has ragged tiles"
+  const bool ragged = maxP.pad_ != 0;
+  hipLaunchKernelGGL((k_quant<T, NDIM, GLOBAL, false, true>), grid, dim3(kBlock), 0, s, one, jobs);
+  if (ragged)
+    hipLaunchKernelGGL((k_quant<T, NDIM, GLOBAL, false, false>), grid, dim3(kBlock), 0, s, one, jobs);
   tm->mark(s, "quant");
   hipLaunchKernelGGL(k_exc_scan, dim3(1, nf), dim3(kScanThreads), 0, s, one, jobs);
   const uint32_t cgrid = (uint32_t)ceil_div(maxP.n_tiles, kBlock / 64);
   hipLaunchKernelGGL(k_exc_copy, dim3(cgrid, nf), dim3(kBlock), 0, s, one, jobs);
   // tiles with more than kStage records recompute them in place
-  hipLaunchKernelGGL((k_quant<T, NDIM, GLOBAL, true>), grid, dim3(kBlock), 0, s, one, jobs);
+  hipLaunchKernelGGL((k_quant<T, NDIM, GLOBAL, true, true>), grid, dim3(kBlock), 0, s, one, jobs);
+  if (ragged)
+    hipLaunchKernelGGL((k_quant<T, NDIM, GLOBAL, true, false>), grid, dim3(kBlock), 0, s, one, jobs);
 }
 
 template <typename T, int NDIM>

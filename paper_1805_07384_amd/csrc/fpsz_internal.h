@@ -49,7 +49,8 @@ __host__ __device__ inline uint64_t align256(uint64_t v) { return (v + 255) & ~u
 
 // Per-call geometry, computed on the host and passed by value.
 struct Plan {
-  int32_t ndim, dtype, domain, pad_;
+  int32_t ndim, dtype, domain;
+  int32_t pad_;                 // 1: some tile is clipped by the field's edge
   uint64_t dims[3];             // as given (slowest-first), unused = 1
   uint64_t nz, ny, nx, n;       // normalized to 3D
   uint32_t tz, ty, tx, pad2_;   // tile extents

@@ -75,6 +75,8 @@ inline fpsz_status make_plan(int ndim, const uint64_t *dims, fpsz_dtype dtype, P
   P->gy = (uint32_t)ceil_div(P->ny, P->ty);
   P->gx = (uint32_t)ceil_div(P->nx, P->tx);
   P->n_tiles = (uint64_t)P->gz * P->gy * P->gx;
+  // pad_: 1 when some tile is clipped by the field's edge
+  P->pad_ = (P->nz % P->tz) || (P->ny % P->ty) || (P->nx % P->tx) ? 1 : 0;
   // total chunks = chunk_base of a one-past-the-end tile: sum over all tiles
   {
     const uint64_t ex_last = P->nx - (uint64_t)(P->gx - 1) * P->tx;

@@ -198,6 +198,7 @@ void launch_compress_group(fpsz_server *S, const std::vector<uint64_t> &ids, int
     maxP.n = std::max(maxP.n, P.n);
     maxP.n_tiles = std::max(maxP.n_tiles, P.n_tiles);
     maxP.capacity = std::max(maxP.capacity, P.capacity);
+    maxP.pad_ |= P.pad_;
   }
   const LaunchCfg cfg = default_launch_cfg(maxP);
   hipError_t e = hipSuccess;
