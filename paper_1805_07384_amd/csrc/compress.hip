@@ -1078,130 +1078,222 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CJob one, const CJob *_
 
 // ---------------------------------------------------------------------------
 // a9: encode.  One tile per step; bit offsets inside the tile by a block
-// scan, the tile's word offset by look-back, bits ORed into an LDS image of
-// the tile's words and stored coalesced.
-__device__ inline void put_bits_lds(uint32_t *words, uint32_t o, uint32_t pat, int len) {
-  const uint32_t w = o >> 5, b = o & 31;
-  if (b + len <= 32) {
-    atomicOr(&words[w], pat << (32 - b - len));
-  } else {
-    atomicOr(&words[w], pat >> (b + len - 32));
-    atomicOr(&words[w + 1], pat << (64 - b - len));
-  }
+// scan, the tile's word offset by look-back, each thread's bits packed into
+// an LDS image of the tile's words and stored coalesced.
+
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) uint32_t gu32_t;
+typedef __attribute__((address_space(1))) uint16_t gu16_t;
+
+// symbol, extra-bit count and extra bits of a residual code (branch-free form
+// of the symbol map)
+__device__ inline uint32_t sym_ne_ev(int32_t c, uint32_t *ne, uint32_t *ev) {
+  const bool outl = c == -32768;
+  const int32_t a = c < 0 ? -c : c;
+  const bool direct = a <= 511;
+  const int k = 31 - __clz(a | 1);
+  const bool esc = !direct && !outl;
+  *ne = esc ? (uint32_t)k : 0u;
+  *ev = esc ? (uint32_t)(a - (1 << k)) : 0u;
+  const uint32_t se = 1024u + 2u * (uint32_t)(k - 9) + (c < 0 ? 1u : 0u);
+  return outl ? 0u : (direct ? (uint32_t)(c + 512) : se);
 }
 
-__global__ __launch_bounds__(kBlock) void k_encode(CJob one, const CJob *__restrict__ jobs) {
+// Encoding runs as three kernels: count (bits per thread, chunk and tile),
+// an exclusive scan of the tile word counts (one workgroup per field), and
+// pack.  No workgroup waits on another.  Per-thread bit counts (u16) go to
+// the exception staging area, which is free once the records are placed.
+struct EncCodes {
+  const int16_t *codes;
+  uint64_t base;
+  int cnt;
+  bool fast;  // 32 codes, 16-byte aligned (full tiles)
+  u32x4_t q0, q1, q2, q3;  // the 32 codes of a fast thread, loaded up front
+  __device__ void prefetch() {
+    if (fast) {
+      gptr_t<u32x4_t> src = (gptr_t<u32x4_t>)(codes + base);
+      q0 = src[0];
+      q1 = src[1];
+      q2 = src[2];
+      q3 = src[3];
+    }
+  }
+  __device__ void load8(int v, int32_t c[8]) const {
+    if (fast) {
+      const u32x4_t qv = v == 0 ? q0 : v == 1 ? q1 : v == 2 ? q2 : q3;
+#pragma unroll
+      for (int h = 0; h < 8; h++) c[h] = (int32_t)(int16_t)((qv[h >> 1] >> (16 * (h & 1))) & 0xffffu);
+    } else {
+#pragma unroll
+      for (int h = 0; h < 8; h++) c[h] = 8 * v + h < cnt ? (int32_t)codes[base + 8 * v + h] : 0;
+    }
+  }
+};
+
+__device__ inline EncCodes enc_codes(const Plan &P, const int16_t *codes, const TileGeo &g, int tid) {
+  EncCodes E;
+  const int nt = (int)g.nt, i0 = 32 * tid;
+  E.codes = codes;
+  E.base = g.start + (uint64_t)i0;
+  E.cnt = nt - i0 < 0 ? 0 : (nt - i0 > 32 ? 32 : nt - i0);
+  E.fast = nt == kTilePts && (E.base & 7) == 0;  // uniform over the tile
+  return E;
+}
+
+__device__ inline void load_code_table(const CJob &J, uint32_t *sct) {
+  for (int s = threadIdx.x; s < kNSym; s += kBlock) sct[s] = (J.W.code[s] << 8) | J.W.code_len[s];
+}
+
+__global__ __launch_bounds__(kBlock) void k_enc_count(CJob one, const CJob *__restrict__ jobs) {
   const CJob J = select_job(one, jobs);
   const Plan P = J.P;
   DevParams *__restrict__ dp = J.W.P;
-  const int16_t *__restrict__ codes = J.W.codes;
-  const uint8_t *__restrict__ len_g = J.W.code_len;
-  const uint32_t *__restrict__ code_g = J.W.code;
-  uint64_t *__restrict__ word_state = J.W.word_state;
+  uint16_t *__restrict__ tb = reinterpret_cast<uint16_t *>(J.W.stage);
+  uint64_t *__restrict__ tw = J.W.word_state;
   uint8_t *__restrict__ blob = J.blob;
-  __shared__ uint32_t words[kTilePts + 1];
-  __shared__ uint8_t slen[kNSym];
-  __shared__ uint32_t scode[kNSym];
+  __shared__ uint32_t sct[kNSym];
   __shared__ uint32_t scr[8];
-  __shared__ uint64_t sh_t, sh_off;
   if (dp->status != 0 || dp->is_const) return;
   const int tid = threadIdx.x;
-  for (int s = tid; s < kNSym; s += kBlock) { slen[s] = len_g[s]; scode[s] = code_g[s]; }
-  const uint64_t off_words = dp->off_words;
-
-  while (true) {
-    __syncthreads();
-    if (tid == 0) sh_t = atomicAdd(&dp->ticket_e, 1u);
-    __syncthreads();
-    const uint64_t t = sh_t;
-    if (t >= P.n_tiles) break;
+  load_code_table(J, sct);
+  __syncthreads();
+  for (uint64_t t = blockIdx.x; t < P.n_tiles; t += gridDim.x) {
     const TileGeo g = tile_geo(P, t);
-    const int nt = (int)g.nt;
-    const int i0 = 32 * tid;
-    const int cnt = nt - i0 < 0 ? 0 : (nt - i0 > 32 ? 32 : nt - i0);
-    int32_t c16[32];
-    const uint64_t base = g.start + (uint64_t)i0;
-    if (cnt == 32 && (base & 7) == 0) {
-      const int4 *src = reinterpret_cast<const int4 *>(codes + base);
-#pragma unroll
-      for (int v = 0; v < 4; v++) {
-        const int4 q = src[v];
-        const uint32_t w[4] = {(uint32_t)q.x, (uint32_t)q.y, (uint32_t)q.z, (uint32_t)q.w};
-#pragma unroll
-        for (int h = 0; h < 4; h++) {
-          c16[8 * v + 2 * h] = (int32_t)(int16_t)(w[h] & 0xffffu);
-          c16[8 * v + 2 * h + 1] = (int32_t)(int16_t)(w[h] >> 16);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < 32; j++) c16[j] = j < cnt ? (int32_t)codes[base + j] : 0;
-    }
-    uint32_t pat[32];
-    uint32_t plen_pack[8];  // 4 lengths (<= 32) per word
+    EncCodes E = enc_codes(P, J.W.codes, g, tid);
+    E.prefetch();
     uint32_t bits = 0;
+#pragma unroll 1
+    for (int v = 0; v < 4; v++) {
+      int32_t c[8];
+      E.load8(v, c);
+      uint32_t sy[8], ne[8], ev[8], e[8];
 #pragma unroll
-    for (int j = 0; j < 8; j++) plen_pack[j] = 0;
+      for (int h = 0; h < 8; h++) sy[h] = sym_ne_ev(c[h], &ne[h], &ev[h]);
 #pragma unroll
-    for (int j = 0; j < 32; j++) {
-      if (j < cnt) {
-        int ne;
-        uint32_t ev;
-        const int s = sym_of_code(c16[j], &ne, &ev);
-        const int L = slen[s];
-        const uint32_t p = ne ? ((scode[s] << ne) | ev) : scode[s];
-        pat[j] = p;
-        const uint32_t pl = (uint32_t)(L + ne);
-        plen_pack[j >> 2] |= pl << (8 * (j & 3));
-        bits += pl;
-      } else {
-        pat[j] = 0;
-      }
+      for (int h = 0; h < 8; h++) e[h] = sct[sy[h]];
+#pragma unroll
+      for (int h = 0; h < 8; h++) bits += 8 * v + h < E.cnt ? (e[h] & 0xffu) + ne[h] : 0u;
     }
+    tb[t * kBlock + tid] = (uint16_t)bits;
     // chunk = 4 consecutive threads (128 symbols)
     uint32_t cb = bits;
     cb += __shfl_xor(cb, 1, 64);
     cb += __shfl_xor(cb, 2, 64);
-    if ((tid & 3) == 0 && i0 < nt) {
+    if ((tid & 3) == 0 && 32 * tid < (int)g.nt) {
       const uint64_t o = P.off_cb + 2 * (g.chunk_base + (uint64_t)(tid >> 2));
-      if (o + 2 <= P.capacity) *reinterpret_cast<uint16_t *>(blob + o) = (uint16_t)cb;
+      if (o + 2 <= P.capacity) *(gu16_t *)(blob + o) = (uint16_t)cb;
       else atomicOr(&dp->overflow, 1u);
     }
     uint32_t tile_bits;
-    const uint32_t my_bit = block_excl_scan_u32(bits, scr, &tile_bits);
-    const uint32_t W = (tile_bits + 31) >> 5;
-    for (uint32_t i = tid; i <= W; i += kBlock) words[i] = 0;
-    if (tid < 64) {
-      const uint64_t o0 = lookback_excl(word_state, t, W, &dp->spin_fail);
-      if (tid == 0) sh_off = o0;
+    (void)block_excl_scan_u32(bits, scr, &tile_bits);
+    if (tid == 0) tw[t] = (tile_bits + 31) >> 5;
+  }
+}
+
+// exclusive scan of the tile word counts: word offsets in place, the blob's
+// tile_word_offset section and the total
+__global__ __launch_bounds__(kScanThreads) void k_enc_scan(CJob one, const CJob *__restrict__ jobs) {
+  const CJob J = select_job(one, jobs);
+  const Plan P = J.P;
+  DevParams *__restrict__ dp = J.W.P;
+  uint64_t *__restrict__ tw = J.W.word_state;
+  uint8_t *__restrict__ blob = J.blob;
+  __shared__ uint64_t wsum[kScanThreads / 64];
+  __shared__ uint64_t carry;
+  if (dp->status != 0 || dp->is_const) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  const uint64_t nt = P.n_tiles;
+  for (uint64_t base = 0; base < nt; base += kScanThreads) {
+    const uint64_t t = base + tid;
+    const uint64_t v = t < nt ? tw[t] : 0;
+    const uint64_t inc = wave_incl_scan_u64(v);
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    uint64_t pre = carry;
+    for (int w = 0; w < wv; w++) pre += wsum[w];
+    const uint64_t ex0 = pre + inc - v;
+    if (t < nt) {
+      tw[t] = ex0;
+      const uint64_t o = P.off_two + 8 * t;
+      if (o + 8 <= P.capacity) *reinterpret_cast<uint64_t *>(blob + o) = ex0;
+      else atomicOr(&dp->overflow, 1u);
     }
     __syncthreads();
+    if (tid == kScanThreads - 1) carry = ex0 + v;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const uint64_t tot = carry;
+    dp->n_words = tot;
+    const uint64_t o = P.off_two + 8 * nt;
+    if (o + 8 <= P.capacity) *reinterpret_cast<uint64_t *>(blob + o) = tot;
+    else atomicOr(&dp->overflow, 1u);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_enc_pack(CJob one, const CJob *__restrict__ jobs) {
+  const CJob J = select_job(one, jobs);
+  const Plan P = J.P;
+  DevParams *__restrict__ dp = J.W.P;
+  const uint16_t *__restrict__ tb = reinterpret_cast<const uint16_t *>(J.W.stage);
+  const uint64_t *__restrict__ tw = J.W.word_state;
+  uint8_t *__restrict__ blob = J.blob;
+  __shared__ uint32_t words[kTilePts + 2];
+  __shared__ uint32_t sct[kNSym];
+  __shared__ uint32_t scr[8];
+  if (dp->status != 0 || dp->is_const) return;
+  const int tid = threadIdx.x;
+  load_code_table(J, sct);
+  const uint64_t off_words = dp->off_words;
+  for (uint64_t t = blockIdx.x; t < P.n_tiles; t += gridDim.x) {
+    const TileGeo g = tile_geo(P, t);
+    EncCodes E = enc_codes(P, J.W.codes, g, tid);
+    E.prefetch();
+    const uint32_t bits = tb[t * kBlock + tid];
+    __syncthreads();  // previous tile's words stored; table loaded
+    uint32_t tile_bits;
+    const uint32_t my_bit = block_excl_scan_u32(bits, scr, &tile_bits);
+    const uint32_t W = (tile_bits + 31) >> 5;
+    for (uint32_t i = tid; i <= W + 1; i += kBlock) words[i] = 0;
+    __syncthreads();
+    // each pattern (<= 32 bits) lands in at most two words: OR both, no
+    // branch; only the running bit offset links consecutive symbols
     uint32_t o = my_bit;
+    auto put = [&](uint32_t pat, uint32_t pl) {
+      const uint32_t w = o >> 5, b = o & 31;
+      const uint64_t v = (uint64_t)pat << (64 - b - pl);
+      atomicOr(&words[w], (uint32_t)(v >> 32));
+      atomicOr(&words[w + 1], (uint32_t)v);
+      o += pl;
+    };
+#pragma unroll 1
+    for (int v = 0; v < 4; v++) {
+      int32_t c[8];
+      E.load8(v, c);
+      uint32_t sy[8], ne[8], ev[8], e[8];
 #pragma unroll
-    for (int j = 0; j < 32; j++) {
-      if (j < cnt) {
-        const int pl = (int)((plen_pack[j >> 2] >> (8 * (j & 3))) & 0xffu);
-        put_bits_lds(words, o, pat[j], pl);
-        o += (uint32_t)pl;
+      for (int h = 0; h < 8; h++) sy[h] = sym_ne_ev(c[h], &ne[h], &ev[h]);
+#pragma unroll
+      for (int h = 0; h < 8; h++) e[h] = sct[sy[h]];
+      if (E.fast) {
+#pragma unroll
+        for (int h = 0; h < 8; h++) put(((e[h] >> 8) << ne[h]) | ev[h], (e[h] & 0xffu) + ne[h]);
+      } else {
+#pragma unroll
+        for (int h = 0; h < 8; h++)
+          if (8 * v + h < E.cnt) put(((e[h] >> 8) << ne[h]) | ev[h], (e[h] & 0xffu) + ne[h]);
       }
     }
     __syncthreads();
-    const uint64_t woff = sh_off;
+    const uint64_t woff = tw[t];
     const uint64_t dst = off_words + 4 * woff;
     if (dst + 4ull * W <= P.capacity) {
-      uint32_t *bw = reinterpret_cast<uint32_t *>(blob + dst);
+      gu32_t *bw = (gu32_t *)(blob + dst);
       for (uint32_t i = tid; i < W; i += kBlock) bw[i] = words[i];
     } else if (tid == 0) {
       atomicOr(&dp->overflow, 1u);
-    }
-    if (tid == 0) {
-      const uint64_t ot = P.off_two + 8 * t;
-      if (ot + 8 <= P.capacity) *reinterpret_cast<uint64_t *>(blob + ot) = woff;
-      if (t == P.n_tiles - 1) {
-        const uint64_t o2 = P.off_two + 8 * P.n_tiles;
-        if (o2 + 8 <= P.capacity) *reinterpret_cast<uint64_t *>(blob + o2) = woff + W;
-        dp->n_words = woff + W;
-      }
     }
   }
 }
@@ -1391,7 +1483,10 @@ static void launch_compress_t(const CJob &one, const CJob *jobs, int nf, const P
   tm->mark(s, "exceptions");
   hipLaunchKernelGGL(k_codebook, dim3(1, nf), dim3(kCbThreads), 0, s, one, jobs);
   tm->mark(s, "codebook");
-  hipLaunchKernelGGL(k_encode, dim3(cfg.encode_grid, nf), dim3(kBlock), 0, s, one, jobs);
+  hipLaunchKernelGGL(k_enc_count, dim3(cfg.encode_grid, nf), dim3(kBlock), 0, s, one, jobs);
+  hipLaunchKernelGGL(k_enc_scan, dim3(1, nf), dim3(kScanThreads), 0, s, one, jobs);
+  tm->mark(s, "encode_count");
+  hipLaunchKernelGGL(k_enc_pack, dim3(cfg.encode_grid, nf), dim3(kBlock), 0, s, one, jobs);
   tm->mark(s, "encode");
   hipLaunchKernelGGL(k_header, dim3(1, nf), dim3(kBlock), 0, s, one, jobs);
   tm->mark(s, "header");
