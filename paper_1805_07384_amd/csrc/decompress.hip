@@ -321,6 +321,7 @@ __global__ __launch_bounds__(kBlock) void k_proj(Plan P, const uint8_t *__restri
   const int tid = threadIdx.x;
   const uint64_t t = blockIdx.x;
   const TileGeo g = tile_geo(P, t);
+  if (g.nt == (uint32_t)kTilePts) return;  // uniform: full tiles in k_proj_full
   const int ez = (int)g.ez, ey = (int)g.ey, ex = (int)g.ex;
   const uint64_t *teo = reinterpret_cast<const uint64_t *>(blob + P.off_teo);
   const uint64_t e0 = teo[t], e1 = teo[t + 1];
@@ -443,6 +444,7 @@ __global__ __launch_bounds__(kBlock) void k_rec(Plan P, const uint8_t *__restric
   const int tid = threadIdx.x;
   const uint64_t t = blockIdx.x;
   const TileGeo g = tile_geo(P, t);
+  if (g.nt == (uint32_t)kTilePts) return;  // uniform: full tiles in k_rec_full
   const int ez = (int)g.ez, ey = (int)g.ey, ex = (int)g.ex, nt = (int)g.nt;
   const bool full = ez == TZ && ey == TY && ex == TX;
   const uint64_t *teo = reinterpret_cast<const uint64_t *>(blob + P.off_teo);
@@ -563,6 +565,377 @@ __global__ __launch_bounds__(kBlock) void k_rec(Plan P, const uint8_t *__restric
 }
 
 // ---------------------------------------------------------------------------
+// Full tiles: one thread per 32-point row segment of the stream (the mapping
+// of compression), the tile's inclusive prefix sum kept in registers:
+// x serially, y / z across lanes (16-lane row shifts and wave shuffles) and
+// across waves through LDS.  Exceptions are located without a search: per
+// segment, bit masks of outliers and patches plus an exclusive scan of their
+// record counts give the index of every record directly.
+template <typename T> using dgptr_t = __attribute__((address_space(1))) const T *;
+typedef uint32_t du32x4_t __attribute__((ext_vector_type(4)));
+typedef float df32x4_t __attribute__((ext_vector_type(4)));
+typedef double df64x2_t __attribute__((ext_vector_type(2)));
+
+template <int NDIM> struct RowMap {
+  int z, y, sg;
+  __device__ explicit RowMap(int tid)
+      : z(NDIM == 3 ? tid >> 4 : 0),
+        y(NDIM == 3 ? tid & 15 : NDIM == 2 ? tid >> 2 : 0),
+        sg(NDIM == 3 ? 0 : NDIM == 2 ? tid & 3 : tid) {}
+};
+
+// v from lane - K of the same 16-lane row, 0 for the first K lanes
+template <int K> __device__ inline uint32_t row_shr(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x110 + K, 0xf, 0xf, true);
+}
+
+struct SegExc {
+  uint32_t om = 0, pm = 0;  // outlier / patch bits of this segment
+  uint64_t rbase = 0;       // record index of the segment's first exception
+};
+
+// Residuals of this thread's segment, outliers applied.  lds_m needs 512
+// words; scr 8 words.  Sets *bad (uniform after the final barrier of the
+// caller) on an inconsistent exception list.
+template <int NDIM, int RW>
+__device__ inline SegExc load_segment(const TileGeo &g, const int16_t *codes, const uint32_t *exc,
+                                      uint64_t e0, uint64_t e1, uint32_t r[32], uint32_t *lds_m,
+                                      uint32_t *scr, uint32_t *s_bad) {
+  const int tid = threadIdx.x;
+  SegExc X;
+  {
+    dgptr_t<du32x4_t> src = (dgptr_t<du32x4_t>)(codes + g.start + 32 * (uint64_t)tid);
+    const du32x4_t q0 = src[0], q1 = src[1], q2 = src[2], q3 = src[3];
+    const du32x4_t qq[4] = {q0, q1, q2, q3};
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+      const uint32_t w = qq[k >> 2][k & 3];
+      r[2 * k] = (uint32_t)(int32_t)(int16_t)(w & 0xffffu);
+      r[2 * k + 1] = (uint32_t)(int32_t)(int16_t)(w >> 16);
+    }
+  }
+  if (e1 == e0) return X;  // uniform: no exceptions in the tile
+  uint32_t *om_l = lds_m, *pm_l = lds_m + kBlock;
+  om_l[tid] = 0;
+  pm_l[tid] = 0;
+  __syncthreads();
+  for (uint64_t e = e0 + tid; e < e1; e += kBlock) {
+    const uint32_t key = exc[2 * e];
+    const uint64_t pos = key & ~kTagPatch;
+    if (pos < g.start || pos >= g.start + (uint64_t)kTilePts) { atomicOr(s_bad, 1u); continue; }
+    const uint32_t si = (uint32_t)(pos - g.start);
+    if (key & kTagPatch) {
+      if (RW == 2 && e > e0 && exc[2 * (e - 1)] == key) continue;  // high half of a pair
+      if (atomicOr(&pm_l[si >> 5], 1u << (si & 31)) & (1u << (si & 31))) atomicOr(s_bad, 1u);
+    } else {
+      if (atomicOr(&om_l[si >> 5], 1u << (si & 31)) & (1u << (si & 31))) atomicOr(s_bad, 1u);
+    }
+  }
+  __syncthreads();
+  X.om = om_l[tid];
+  X.pm = pm_l[tid];
+  uint32_t total;
+  const uint32_t mine = __popc(X.om) + RW * __popc(X.pm);
+  X.rbase = e0 + block_excl_scan_u32(mine, scr, &total);
+  if (tid == 0 && total != (uint32_t)(e1 - e0)) atomicOr(s_bad, 1u);
+  if (X.om) {
+    const uint32_t pos0 = (uint32_t)(g.start + 32 * (uint64_t)tid);
+#pragma unroll
+    for (int j = 0; j < 32; j++) {
+      if ((X.om >> j) & 1u) {
+        const uint32_t lo = (1u << j) - 1u;
+        const uint64_t idx = X.rbase + __popc(X.om & lo) + RW * __popc(X.pm & lo);
+        const bool ok = idx < e1 && exc[2 * idx] == pos0 + (uint32_t)j && r[j] == 0xffff8000u;
+        if (!ok) atomicOr(s_bad, 1u);
+        r[j] = ok ? exc[2 * idx + 1] : 0u;
+      }
+    }
+  }
+  return X;
+}
+
+// inclusive prefix sums (mod 2^32) of the tile, in place; lds_t needs
+// 4 * 16 * kSegWD words
+constexpr int kSegWD = 36;
+template <int NDIM> __device__ inline void tile_prefix(uint32_t r[32], uint32_t *lds_t) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int j = 1; j < 32; j++) r[j] += r[j - 1];
+  if (NDIM == 1) {
+    __shared__ uint32_t scr1[8];
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan_u32(r[31], scr1, &tot);
+#pragma unroll
+    for (int j = 0; j < 32; j++) r[j] += ex;
+    return;
+  }
+  if (NDIM == 2) {
+    // across the 4 segments of a row (lanes 4k .. 4k + 3)
+    const int sg = lane & 3;
+    uint32_t v = r[31];
+    uint32_t u = __shfl_up(v, 1, 64);
+    v += sg >= 1 ? u : 0u;
+    u = __shfl_up(v, 2, 64);
+    v += sg >= 2 ? u : 0u;
+    const uint32_t ex = v - r[31];
+#pragma unroll
+    for (int j = 0; j < 32; j++) r[j] += ex;
+    // along y inside a 16-lane row (4 rows of 4 segments), then across rows
+#pragma unroll
+    for (int j = 0; j < 32; j++) {
+      r[j] += row_shr<4>(r[j]);
+      r[j] += row_shr<8>(r[j]);
+    }
+  } else {
+    // along y: the 16 lanes of a row are y = 0..15 of one plane
+#pragma unroll
+    for (int j = 0; j < 32; j++) {
+      r[j] += row_shr<1>(r[j]);
+      r[j] += row_shr<2>(r[j]);
+      r[j] += row_shr<4>(r[j]);
+      r[j] += row_shr<8>(r[j]);
+    }
+  }
+  if (NDIM == 3) {
+    // along z across the 4 planes of the wave (same y: lane offsets 16, 32)
+#pragma unroll
+    for (int j = 0; j < 32; j++) {
+      const uint32_t u = __shfl_up(r[j], 16, 64);
+      r[j] += lane >= 16 ? u : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < 32; j++) {
+      const uint32_t u = __shfl_up(r[j], 32, 64);
+      r[j] += lane >= 32 ? u : 0u;
+    }
+  } else {
+    // along y across the 4 groups of 4 rows of the wave: each group's total
+    // (its last row) is broadcast, scanned over groups, its exclusive part added
+    const int src = (lane & 48) + 12 + (lane & 3);
+#pragma unroll
+    for (int j = 0; j < 32; j++) {
+      const uint32_t tot = __shfl(r[j], src, 64);
+      uint32_t inc = tot;
+      uint32_t u = __shfl_up(inc, 16, 64);
+      inc += lane >= 16 ? u : 0u;
+      u = __shfl_up(inc, 32, 64);
+      inc += lane >= 32 ? u : 0u;
+      r[j] += inc - tot;
+    }
+  }
+  // across waves: the last row of each wave holds the wave's total
+  const int slot = NDIM == 3 ? (lane & 15) : (lane & 3);
+  if (lane >= 48 && (NDIM == 3 || lane >= 60)) {
+    uint32_t *dst = lds_t + (wv * 16 + slot) * kSegWD + 4;
+#pragma unroll
+    for (int k = 0; k < 8; k++)
+      reinterpret_cast<uint4 *>(dst)[k] = make_uint4(r[4 * k], r[4 * k + 1], r[4 * k + 2], r[4 * k + 3]);
+  }
+  __syncthreads();
+  for (int w = 0; w < wv; w++) {
+    const uint32_t *src = lds_t + (w * 16 + slot) * kSegWD + 4;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      const uint4 a = reinterpret_cast<const uint4 *>(src)[k];
+      r[4 * k] += a.x;
+      r[4 * k + 1] += a.y;
+      r[4 * k + 2] += a.z;
+      r[4 * k + 3] += a.w;
+    }
+  }
+}
+
+template <int NDIM>
+__global__ __launch_bounds__(kBlock) void k_proj_full(Plan P, const uint8_t *__restrict__ blob,
+                                                      DecodeArgs A, DevParams *__restrict__ dp,
+                                                      const int16_t *__restrict__ codes) {
+  using G = DGeo<NDIM>;
+  constexpr int TZ = G::TZ, TY = G::TY, TX = G::TX;
+  constexpr int FZ = NDIM == 3 ? TY * TX : 1, FY = TZ * TX, FX = TZ * TY;
+  __shared__ uint32_t lds_m[2 * kBlock];
+  __shared__ __align__(16) uint32_t lds_t[4 * 16 * kSegWD];
+  __shared__ uint32_t scr[8];
+  __shared__ uint32_t s_bad;
+  if (dp->corrupt) return;
+  const int tid = threadIdx.x;
+  const uint64_t t = blockIdx.x;
+  const TileGeo g = tile_geo(P, t);
+  if (g.nt != (uint32_t)kTilePts) return;  // uniform: ragged tiles elsewhere
+  const uint64_t *teo = reinterpret_cast<const uint64_t *>(blob + P.off_teo);
+  const uint64_t e0 = teo[t], e1 = teo[t + 1];
+  if (e0 > e1 || e1 > A.n_exc) return;  // reported by the decode kernel
+  const uint32_t *exc = reinterpret_cast<const uint32_t *>(blob + P.off_exc);
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  uint32_t r[32];
+  (void)load_segment<NDIM, 1>(g, codes, exc, e0, e1, r, lds_m, scr, &s_bad);
+  tile_prefix<NDIM>(r, lds_t);
+  __syncthreads();
+  if (s_bad) {
+    if (tid == 0) atomicOr(&dp->corrupt, 1u);
+    return;
+  }
+  const RowMap<NDIM> m(tid);
+  typedef __attribute__((address_space(1))) uint32_t gu32;
+  typedef __attribute__((address_space(1))) du32x4_t gu32x4;
+  auto store_row = [&](uint32_t *dst32) {
+    gu32x4 *d = (gu32x4 *)dst32;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      du32x4_t v;
+      v.x = r[4 * k];
+      v.y = r[4 * k + 1];
+      v.z = r[4 * k + 2];
+      v.w = r[4 * k + 3];
+      d[k] = v;
+    }
+  };
+  if (NDIM == 3) {
+    // Fz[y][x] = L(last z, y, x); Fy[z][x] = L(z, last y, x); Fx[z][y] = L(z, y, last x)
+    if (m.z == TZ - 1) store_row(A.fz + t * FZ + m.y * TX);
+    if (m.y == TY - 1) store_row(A.fy + t * FY + m.z * TX);
+    ((gu32 *)A.fx)[t * FX + m.z * TY + m.y] = r[31];
+    if (m.z == TZ - 1 && m.y == TY - 1) store_row(A.gx + t * TX);   // Gx[x] = Fz[last y][x]
+    if (m.z == TZ - 1) ((gu32 *)A.gy)[t * TY + m.y] = r[31];        // Gy[y] = Fz[y][last x]
+    if (m.y == TY - 1) ((gu32 *)A.gz)[t * TZ + m.z] = r[31];        // Gz[z] = Fy[z][last x]
+    if (m.z == TZ - 1 && m.y == TY - 1) ((gu32 *)A.tt)[t] = r[31];
+  } else if (NDIM == 2) {
+    // Fy[x] = L(last y, x); Fx[y] = L(y, last x); Gz = T
+    if (m.y == TY - 1) store_row(A.fy + t * FY + 32 * m.sg);
+    if (m.sg == 3) ((gu32 *)A.fx)[t * FX + m.y] = r[31];
+    if (m.y == TY - 1 && m.sg == 3) ((gu32 *)A.gz)[t * TZ] = r[31];
+  } else {
+    if (tid == kBlock - 1) ((gu32 *)A.fx)[t * FX] = r[31];
+  }
+}
+
+template <typename T, int NDIM, bool GLOBAL>
+__global__ __launch_bounds__(kBlock) void k_rec_full(Plan P, const uint8_t *__restrict__ blob,
+                                                     DecodeArgs A, DevParams *__restrict__ dp,
+                                                     const int16_t *__restrict__ codes,
+                                                     T *__restrict__ out) {
+  using G = DGeo<NDIM>;
+  constexpr int TZ = G::TZ, TY = G::TY, TX = G::TX;
+  constexpr int FZ = NDIM == 3 ? TY * TX : 1, FY = TZ * TX, FX = TZ * TY;
+  constexpr int RW = sizeof(T) / 4;
+  __shared__ uint32_t lds_m[2 * kBlock];
+  __shared__ __align__(16) uint32_t lds_t[4 * 16 * kSegWD];
+  __shared__ uint32_t scr[8];
+  __shared__ uint32_t s_bad;
+  if (dp->corrupt) return;
+  const int tid = threadIdx.x;
+  const uint64_t t = blockIdx.x;
+  const TileGeo g = tile_geo(P, t);
+  if (g.nt != (uint32_t)kTilePts) return;  // uniform: ragged tiles elsewhere
+  const uint64_t *teo = reinterpret_cast<const uint64_t *>(blob + P.off_teo);
+  const uint64_t e0 = teo[t], e1 = teo[t + 1];
+  if (e0 > e1 || e1 > A.n_exc) return;  // reported by the decode kernel
+  const uint32_t *exc = reinterpret_cast<const uint32_t *>(blob + P.off_exc);
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  const RowMap<NDIM> m(tid);
+  uint32_t r[32];
+  const SegExc X = load_segment<NDIM, RW>(g, codes, exc, e0, e1, r, lds_m, scr, &s_bad);
+  tile_prefix<NDIM>(r, lds_t);
+  if (GLOBAL) {
+    // q = L + A[y][x] + B[z][x] + C[z][y] (the halo terms)
+    typedef dgptr_t<du32x4_t> g4;
+    if (NDIM == 3) {
+      g4 ha = (g4)(A.fz + t * FZ + m.y * TX);
+#pragma unroll
+      for (int k = 0; k < 8; k++) {
+        const du32x4_t a = ha[k];
+        r[4 * k] += a.x; r[4 * k + 1] += a.y; r[4 * k + 2] += a.z; r[4 * k + 3] += a.w;
+      }
+    }
+    if (NDIM >= 2) {
+      g4 hb = (g4)(A.fy + t * FY + (NDIM == 3 ? m.z * TX : 32 * m.sg));
+#pragma unroll
+      for (int k = 0; k < 8; k++) {
+        const du32x4_t a = hb[k];
+        r[4 * k] += a.x; r[4 * k + 1] += a.y; r[4 * k + 2] += a.z; r[4 * k + 3] += a.w;
+      }
+    }
+    if (NDIM == 3) {
+      g4 hg = (g4)(A.gx + t * TX);
+#pragma unroll
+      for (int k = 0; k < 8; k++) {
+        const du32x4_t a = hg[k];
+        r[4 * k] += a.x; r[4 * k + 1] += a.y; r[4 * k + 2] += a.z; r[4 * k + 3] += a.w;
+      }
+    }
+    uint32_t c = ((dgptr_t<uint32_t>)A.fx)[t * FX + (NDIM == 3 ? m.z * TY + m.y : NDIM == 2 ? m.y : 0)];
+    if (NDIM >= 2) c += ((dgptr_t<uint32_t>)A.gz)[t * TZ + m.z];
+    if (NDIM == 3) c += ((dgptr_t<uint32_t>)A.gy)[t * TY + m.y] + ((dgptr_t<uint32_t>)A.tt)[t];
+#pragma unroll
+    for (int j = 0; j < 32; j++) r[j] += c;
+  }
+  // bin midpoints, patches exact
+  T v[32];
+#pragma unroll
+  for (int j = 0; j < 32; j++) {
+    if (sizeof(T) == 4) v[j] = (T)((float)(int32_t)r[j] * A.e2_f);
+    else v[j] = (T)((double)(int32_t)r[j] * A.e2);
+  }
+  if (X.pm) {
+    const uint32_t pos0 = (uint32_t)(g.start + 32 * (uint64_t)tid) | kTagPatch;
+#pragma unroll
+    for (int j = 0; j < 32; j++) {
+      if ((X.pm >> j) & 1u) {
+        const uint32_t lo = (1u << j) - 1u, upto = (2u << j) - 1u;
+        const uint64_t idx = X.rbase + __popc(X.om & upto) + RW * __popc(X.pm & lo);
+        const uint32_t want = pos0 + (uint32_t)j;
+        bool ok = idx + RW <= e1 && exc[2 * idx] == want;
+        if (RW == 2) ok = ok && exc[2 * idx + 2] == want;
+        if (!ok) {
+          atomicOr(&dp->corrupt, 1u);
+        } else if (sizeof(T) == 4) {
+          const uint32_t b = exc[2 * idx + 1];
+          __builtin_memcpy(&v[j], &b, 4);
+        } else {
+          const uint64_t b = (uint64_t)exc[2 * idx + 1] | ((uint64_t)exc[2 * idx + 3] << 32);
+          __builtin_memcpy(&v[j], &b, 8);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (s_bad) {
+    if (tid == 0) atomicOr(&dp->corrupt, 1u);
+    return;
+  }
+  const uint64_t rowbase = ((g.z0 + m.z) * P.ny + g.y0 + m.y) * P.nx + g.x0 + 32 * m.sg;
+  if (sizeof(T) == 4) {
+    typedef __attribute__((address_space(1))) df32x4_t gf4;
+    if (((uintptr_t)(out + rowbase) & 15) == 0) {
+      gf4 *d = (gf4 *)(out + rowbase);
+#pragma unroll
+      for (int k = 0; k < 8; k++) {
+        df32x4_t a;
+        a.x = (float)v[4 * k]; a.y = (float)v[4 * k + 1]; a.z = (float)v[4 * k + 2]; a.w = (float)v[4 * k + 3];
+        d[k] = a;
+      }
+      return;
+    }
+  } else {
+    typedef __attribute__((address_space(1))) df64x2_t gd2;
+    if (((uintptr_t)(out + rowbase) & 15) == 0) {
+      gd2 *d = (gd2 *)(out + rowbase);
+#pragma unroll
+      for (int k = 0; k < 16; k++) {
+        df64x2_t a;
+        a.x = (double)v[2 * k]; a.y = (double)v[2 * k + 1];
+        d[k] = a;
+      }
+      return;
+    }
+  }
+  typedef __attribute__((address_space(1))) T gT;
+#pragma unroll
+  for (int j = 0; j < 32; j++) ((gT *)out)[rowbase + j] = v[j];
+}
+
+// ---------------------------------------------------------------------------
 // Exclusive scans (modulo 2^32) of a row-major u32 array along one axis.
 // Element (o, k, i) sits at (o * len + k) * inner + i.  The axis is cut into
 // segments of 32; each thread scans one segment of one column after adding
@@ -637,8 +1010,10 @@ static void launch_dec_t(const Plan &P, const uint8_t *blob, const DecodeArgs &A
   const size_t dyn = (size_t)kDecWaves * (stage_words + 1) * 4;
   hipLaunchKernelGGL((k_decode<NDIM>), dgrid, blk, dyn, s, P, blob, A, dp, codes, stage_words);
   tm->mark(s, "decode");
+  const bool ragged = P.pad_ != 0;
   if (P.domain == FPSZ_DOMAIN_GLOBAL) {
-    hipLaunchKernelGGL((k_proj<NDIM>), grid, blk, 0, s, P, blob, A, dp, codes);
+    hipLaunchKernelGGL((k_proj_full<NDIM>), grid, blk, 0, s, P, blob, A, dp, codes);
+    if (ragged) hipLaunchKernelGGL((k_proj<NDIM>), grid, blk, 0, s, P, blob, A, dp, codes);
     tm->mark(s, "proj");
     const uint64_t gz = P.gz, gy = P.gy, gx = P.gx;
     constexpr uint64_t TZ = G::TZ, TY = G::TY, TX = G::TX;
@@ -660,9 +1035,11 @@ static void launch_dec_t(const Plan &P, const uint8_t *blob, const DecodeArgs &A
     }
     excl_axis(A.fx, gz * gy, gx, FX, tmp, s);                        // Fx along x tiles
     tm->mark(s, "face_scan");
-    hipLaunchKernelGGL((k_rec<T, NDIM, true>), grid, blk, 0, s, P, blob, A, dp, codes, out);
+    hipLaunchKernelGGL((k_rec_full<T, NDIM, true>), grid, blk, 0, s, P, blob, A, dp, codes, out);
+    if (ragged) hipLaunchKernelGGL((k_rec<T, NDIM, true>), grid, blk, 0, s, P, blob, A, dp, codes, out);
   } else {
-    hipLaunchKernelGGL((k_rec<T, NDIM, false>), grid, blk, 0, s, P, blob, A, dp, codes, out);
+    hipLaunchKernelGGL((k_rec_full<T, NDIM, false>), grid, blk, 0, s, P, blob, A, dp, codes, out);
+    if (ragged) hipLaunchKernelGGL((k_rec<T, NDIM, false>), grid, blk, 0, s, P, blob, A, dp, codes, out);
   }
   tm->mark(s, "rec");
 }
