@@ -41,6 +41,12 @@ struct DecodeArgs {
   uint32_t *fz, *fy, *fx, *gx, *gy, *gz, *tt;
 };
 
+// global-memory views (pointers that reach kernels inside structures)
+template <typename T> using dgptr_t = __attribute__((address_space(1))) const T *;
+typedef uint32_t du32x4_t __attribute__((ext_vector_type(4)));
+typedef float df32x4_t __attribute__((ext_vector_type(4)));
+typedef double df64x2_t __attribute__((ext_vector_type(2)));
+
 // ---------------------------------------------------------------------------
 // decoder tables from the code lengths in the blob (one workgroup)
 __global__ __launch_bounds__(1024) void k_dec_tables(Plan P, const uint8_t *__restrict__ blob,
@@ -106,57 +112,78 @@ struct DecTabs {
 // Decode `cnt` symbols starting at bit p of the staged words `wb` (nw + 1
 // words, the last one zero).  Codes go to dst (8-aligned when vec).
 // Returns the number of outlier symbols; sets *bad on an invalid code.
-template <bool VEC>
+// One symbol at bit p of the staged window: returns the residual code and
+// advances p (by nothing for a dead symbol of a short last chunk).
+__device__ inline int32_t decode_one(const uint32_t *wb, uint32_t nw, uint32_t &p, bool live,
+                                     const DecTabs &T, uint32_t &nout, bool &badv) {
+  uint32_t i = p >> 5;
+  i = i < nw ? i : nw;
+  const uint32_t a = wb[i], b = wb[i + (i < nw ? 1 : 0)];
+  const uint32_t sh = p & 31;
+  // top 32 bits of the 64-bit window starting at bit p
+  const uint32_t top = sh ? ((a << sh) | (b >> (32 - sh))) : a;
+  uint32_t e = T.lut[top >> (32 - kLut)];
+  uint32_t L = e & 31u, s = e >> 5;
+  if (__builtin_expect(L == 0, 0)) {
+    // canonical search over lengths kLut+1..18 (left-justified 18-bit limits)
+    const uint32_t v = top >> (32 - kLMax);
+    uint32_t l = kLut + 1;
+    while (l < kLMax && v >= T.lim[l]) l++;
+    const int32_t idx = T.off[l] + (int32_t)(v >> (kLMax - l));
+    const bool ok = v >= T.lim[l - 1] && v < T.lim[l] && idx >= 0 && idx < kNSym;
+    s = ok ? T.sorted[idx] : 0u;
+    L = l;
+    badv |= !ok && live;
+  }
+  // escape classes: k raw bits of |d| - 2^k follow the code
+  const bool esc = s >= 1024u;
+  const uint32_t kk = esc ? (s >> 1) - 503u : 0u;  // (s - 1024) / 2 + 9
+  // bits [L, L + kk) of the window lie in `top` because L + kk <= 32
+  const uint32_t ev = kk ? __builtin_amdgcn_ubfe(top, 32u - L - kk, kk) : 0u;
+  const int32_t mag = (int32_t)((1u << kk) + ev);
+  int32_t code = esc ? ((s & 1u) ? -mag : mag) : (int32_t)s - 512;
+  code = s == 0 ? -32768 : code;
+  nout += (s == 0 && live) ? 1u : 0u;
+  p += live ? L + kk : 0u;
+  return code;
+}
+
+// Decode one chunk of cnt symbols starting at bit p of the window into dst.
+// FULL (128 symbols, 16-byte aligned destination): the codes of 32 symbols
+// are held in registers and stored as four 16-byte pieces of one lane, so
+// the cache sees whole 64-byte pieces rather than scattered 16-byte ones.
+template <bool FULL>
 __device__ inline uint32_t decode_run(const uint32_t *wb, uint32_t nw, uint32_t p, int cnt,
                                       const DecTabs &T, int16_t *dst, uint32_t *used, bool *bad) {
   const uint32_t p0 = p;
   uint32_t nout = 0;
   bool badv = false;
-  for (int kb = 0; kb < cnt; kb += 8) {
-    uint32_t pk[4] = {0, 0, 0, 0};
+  if (FULL) {
+    typedef __attribute__((address_space(1))) du32x4_t gq;
+#pragma unroll 1
+    for (int part = 0; part < 4; part++) {
+      uint32_t pk[16];
 #pragma unroll
-    for (int h = 0; h < 8; h++) {
-      const bool live = kb + h < cnt;  // the last group of a short chunk
-      uint32_t i = p >> 5;
-      i = i < nw ? i : nw;
-      const uint32_t a = wb[i], b = wb[i + (i < nw ? 1 : 0)];
-      const uint32_t sh = p & 31;
-      // top 32 bits of the 64-bit window starting at bit p
-      const uint32_t top = sh ? ((a << sh) | (b >> (32 - sh))) : a;
-      const uint32_t nx = sh ? (b << sh) : b;  // the next 32 bits (only 32 - sh valid)
-      uint32_t e = T.lut[top >> (32 - kLut)];
-      uint32_t L = e & 31u, s = e >> 5;
-      if (L == 0) {
-        // canonical search over lengths kLut+1..18 (left-justified 18-bit limits)
-        const uint32_t v = top >> (32 - kLMax);
-        uint32_t l = kLut + 1;
-        while (l < kLMax && v >= T.lim[l]) l++;
-        const int32_t idx = T.off[l] + (int32_t)(v >> (kLMax - l));
-        const bool ok = v >= T.lim[l - 1] && v < T.lim[l] && idx >= 0 && idx < kNSym;
-        s = ok ? T.sorted[idx] : 0u;
-        L = l;
-        badv |= !ok && live;
+      for (int h = 0; h < 32; h++) {
+        const int32_t code = decode_one(wb, nw, p, true, T, nout, badv);
+        if (h & 1) pk[h >> 1] |= ((uint32_t)code & 0xffffu) << 16;
+        else pk[h >> 1] = (uint32_t)code & 0xffffu;
       }
-      // escape classes: k raw bits of |d| - 2^k follow the code
-      const bool esc = s >= 1024u;
-      const uint32_t kk = esc ? (s >> 1) - 503u : 0u;  // (s - 1024) / 2 + 9
-      // bits [L, L + kk) of the window lie in `top` because L + kk <= 32
-      const uint32_t ev = kk ? __builtin_amdgcn_ubfe(top, 32u - L - kk, kk) : 0u;
-      const int32_t mag = (int32_t)((1u << kk) + ev);
-      int32_t code = esc ? ((s & 1u) ? -mag : mag) : (int32_t)s - 512;
-      code = s == 0 ? -32768 : code;
-      nout += (s == 0 && live) ? 1u : 0u;
-      (void)nx;
-      p += live ? L + kk : 0u;
-      pk[h >> 1] |= ((uint32_t)code & 0xffffu) << (16 * (h & 1));
-      if (!VEC && live) dst[kb + h] = (int16_t)code;
+      gq *d = (gq *)(dst + 32 * part);
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        du32x4_t v;
+        v.x = pk[4 * k];
+        v.y = pk[4 * k + 1];
+        v.z = pk[4 * k + 2];
+        v.w = pk[4 * k + 3];
+        d[k] = v;
+      }
     }
-    if (VEC) {
-      if (kb + 8 <= cnt) {
-        *reinterpret_cast<int4 *>(dst + kb) = make_int4((int)pk[0], (int)pk[1], (int)pk[2], (int)pk[3]);
-      } else {
-        for (int h = 0; kb + h < cnt; h++) dst[kb + h] = (int16_t)(pk[h >> 1] >> (16 * (h & 1)));
-      }
+  } else {
+    for (int k = 0; k < cnt; k++) {
+      const int32_t code = decode_one(wb, nw, p, true, T, nout, badv);
+      dst[k] = (int16_t)code;
     }
   }
   *used = p - p0;
@@ -214,8 +241,8 @@ __global__ __launch_bounds__(kBlock) void k_decode(Plan P, const uint8_t *__rest
   const uint32_t cfw = cstart >> 5;                  // first word
   const uint32_t clw = incl ? (incl - 1) >> 5 : 0;   // last word holding its bits
   int16_t *dst = codes + g.start + k0;
-  // uniform over the wave: k0 is a multiple of 128
-  const bool vec = __builtin_amdgcn_readfirstlane((uint32_t)((g.start & 7) == 0)) != 0;
+  // full chunks with a 16-byte aligned destination (k0 is a multiple of 128)
+  const bool full = cnt == kChunk && (g.start & 7) == 0;
   bool todo = cnt > 0;
   bool bad = false;
   uint32_t used = cb, nout = 0;
@@ -235,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_decode(Plan P, const uint8_t *__rest
     const bool fits = todo && clw < base + wn;
     if (fits) {
       bool b2;
-      if (vec) nout += decode_run<true>(mine, wn, cstart - 32 * base, cnt, T, dst, &used, &b2);
+      if (full) nout += decode_run<true>(mine, wn, cstart - 32 * base, cnt, T, dst, &used, &b2);
       else nout += decode_run<false>(mine, wn, cstart - 32 * base, cnt, T, dst, &used, &b2);
       bad |= b2;
       todo = false;
@@ -571,10 +598,6 @@ __global__ __launch_bounds__(kBlock) void k_rec(Plan P, const uint8_t *__restric
 // across waves through LDS.  Exceptions are located without a search: per
 // segment, bit masks of outliers and patches plus an exclusive scan of their
 // record counts give the index of every record directly.
-template <typename T> using dgptr_t = __attribute__((address_space(1))) const T *;
-typedef uint32_t du32x4_t __attribute__((ext_vector_type(4)));
-typedef float df32x4_t __attribute__((ext_vector_type(4)));
-typedef double df64x2_t __attribute__((ext_vector_type(2)));
 
 template <int NDIM> struct RowMap {
   int z, y, sg;
@@ -889,7 +912,7 @@ __global__ __launch_bounds__(kBlock) void k_rec_full(Plan P, const uint8_t *__re
         if (RW == 2) ok = ok && exc[2 * idx + 2] == want;
         if (!ok) {
           atomicOr(&dp->corrupt, 1u);
-        } else if (sizeof(T) == 4) {
+        } else if constexpr (sizeof(T) == 4) {
           const uint32_t b = exc[2 * idx + 1];
           __builtin_memcpy(&v[j], &b, 4);
         } else {
