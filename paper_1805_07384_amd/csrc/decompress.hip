@@ -112,39 +112,85 @@ struct DecTabs {
 // Decode `cnt` symbols starting at bit p of the staged words `wb` (nw + 1
 // words, the last one zero).  Codes go to dst (8-aligned when vec).
 // Returns the number of outlier symbols; sets *bad on an invalid code.
-// One symbol at bit p of the staged window: returns the residual code and
-// advances p (by nothing for a dead symbol of a short last chunk).
-__device__ inline int32_t decode_one(const uint32_t *wb, uint32_t nw, uint32_t &p, bool live,
-                                     const DecTabs &T, uint32_t &nout, bool &badv) {
-  uint32_t i = p >> 5;
-  i = i < nw ? i : nw;
-  const uint32_t a = wb[i], b = wb[i + (i < nw ? 1 : 0)];
-  const uint32_t sh = p & 31;
-  // top 32 bits of the 64-bit window starting at bit p
-  const uint32_t top = sh ? ((a << sh) | (b >> (32 - sh))) : a;
-  uint32_t e = T.lut[top >> (32 - kLut)];
-  uint32_t L = e & 31u, s = e >> 5;
-  if (__builtin_expect(L == 0, 0)) {
-    // canonical search over lengths kLut+1..18 (left-justified 18-bit limits)
-    const uint32_t v = top >> (32 - kLMax);
-    uint32_t l = kLut + 1;
-    while (l < kLMax && v >= T.lim[l]) l++;
-    const int32_t idx = T.off[l] + (int32_t)(v >> (kLMax - l));
-    const bool ok = v >= T.lim[l - 1] && v < T.lim[l] && idx >= 0 && idx < kNSym;
-    s = ok ? T.sorted[idx] : 0u;
-    L = l;
-    badv |= !ok && live;
+// Bit reader over the staged window: 32..64 pending bits left-aligned in a
+// 64-bit register; the next window word is read ahead and shifted in when
+// fewer than 32 bits remain.  Reads stay inside the window plus its zero pad
+// word (index nw).
+struct BitReader {
+  const uint32_t *wb;
+  uint32_t nw, nb, wp, nextw;
+  uint64_t buf;
+  __device__ void init(const uint32_t *w, uint32_t n, uint32_t p) {
+    wb = w;
+    nw = n;
+    const uint32_t i = (p >> 5) < n ? (p >> 5) : n;
+    const uint32_t i1 = i + 1 < n ? i + 1 : n;
+    buf = (((uint64_t)wb[i] << 32) | wb[i1]) << (p & 31);
+    nb = 64 - (p & 31);
+    wp = i + 2 < n ? i + 2 : n;
+    nextw = wb[wp];
   }
-  // escape classes: k raw bits of |d| - 2^k follow the code
+  __device__ uint32_t top() const { return (uint32_t)(buf >> 32); }
+  __device__ void consume(uint32_t n) {  // n <= 32 <= nb
+    buf <<= n;
+    nb -= n;
+    const bool need = nb < 32;
+    buf |= need ? ((uint64_t)nextw << (32 - nb)) : 0ull;
+    nb += need ? 32u : 0u;
+    wp = need ? (wp + 1 < nw ? wp + 1 : nw) : wp;
+    nextw = wb[wp];
+  }
+};
+
+// Limits and offsets of the code lengths longer than the lookup table
+// (kLut + 1 .. 18), wave-uniform: held in scalar registers.
+struct LongTabs {
+  uint32_t lim[kLMax - kLut + 1];  // lim[l - kLut] for l = kLut .. 18
+  int32_t off[kLMax - kLut + 1];
+};
+
+// One symbol: returns its residual code; *n = its bits (code + extra bits).
+__device__ inline int32_t decode_sym(uint32_t top, const DecTabs &T, const LongTabs &LT,
+                                     uint32_t *n, bool &badv) {
+  const uint32_t e = T.lut[top >> (32 - kLut)];
+  uint32_t L = e & 31u, s = e >> 5;
+  const bool slow = L == 0;
+  if (__builtin_amdgcn_ballot_w64(slow)) {  // wave-uniform test: long codes are rare
+    // canonical decode of lengths kLut+1..18 from left-justified 18-bit
+    // limits (nondecreasing): the length is one past the limits <= v
+    constexpr int NL = kLMax - kLut;
+    const uint32_t v = top >> (32 - kLMax);
+    uint32_t k = 1;
+#pragma unroll
+    for (int m = 1; m < NL; m++) k += v >= LT.lim[m] ? 1u : 0u;
+    uint32_t lo = LT.lim[0], hi = LT.lim[1];
+    int32_t of = LT.off[1];
+#pragma unroll
+    for (int m = 2; m <= NL; m++) {
+      const bool at = k == (uint32_t)m;
+      lo = at ? LT.lim[m - 1] : lo;
+      hi = at ? LT.lim[m] : hi;
+      of = at ? LT.off[m] : of;
+    }
+    const uint32_t l = kLut + k;
+    const int32_t idx = of + (int32_t)(v >> (kLMax - l));
+    const bool ok = v >= lo && v < hi && idx >= 0 && idx < kNSym;
+    const uint32_t sl = T.sorted[ok ? idx : 0];
+    s = slow ? (ok ? sl : 0u) : s;
+    L = slow ? l : L;
+    badv |= slow && !ok;
+  }
+  // escape classes: k raw bits of |d| - 2^k follow the code (within `top`
+  // because L + k <= 32); a zero-width field extracts as 0
   const bool esc = s >= 1024u;
   const uint32_t kk = esc ? (s >> 1) - 503u : 0u;  // (s - 1024) / 2 + 9
-  // bits [L, L + kk) of the window lie in `top` because L + kk <= 32
-  const uint32_t ev = kk ? __builtin_amdgcn_ubfe(top, 32u - L - kk, kk) : 0u;
-  const int32_t mag = (int32_t)((1u << kk) + ev);
-  int32_t code = esc ? ((s & 1u) ? -mag : mag) : (int32_t)s - 512;
+  const uint32_t ev = __builtin_amdgcn_ubfe(top, 32u - L - kk, kk);
+  const uint32_t mag = (1u << kk) + ev;
+  const uint32_t neg = 0u - (s & 1u);
+  const int32_t cesc = (int32_t)((mag ^ neg) - neg);
+  int32_t code = esc ? cesc : (int32_t)s - 512;
   code = s == 0 ? -32768 : code;
-  nout += (s == 0 && live) ? 1u : 0u;
-  p += live ? L + kk : 0u;
+  *n = L + kk;
   return code;
 }
 
@@ -154,10 +200,12 @@ __device__ inline int32_t decode_one(const uint32_t *wb, uint32_t nw, uint32_t &
 // the cache sees whole 64-byte pieces rather than scattered 16-byte ones.
 template <bool FULL>
 __device__ inline uint32_t decode_run(const uint32_t *wb, uint32_t nw, uint32_t p, int cnt,
-                                      const DecTabs &T, int16_t *dst, uint32_t *used, bool *bad) {
-  const uint32_t p0 = p;
-  uint32_t nout = 0;
+                                      const DecTabs &T, const LongTabs &LT, int16_t *dst,
+                                      uint32_t *used, bool *bad) {
+  uint32_t nout = 0, tot = 0;
   bool badv = false;
+  BitReader R;
+  R.init(wb, nw, p);
   if (FULL) {
     typedef __attribute__((address_space(1))) du32x4_t gq;
 #pragma unroll 1
@@ -165,7 +213,11 @@ __device__ inline uint32_t decode_run(const uint32_t *wb, uint32_t nw, uint32_t 
       uint32_t pk[16];
 #pragma unroll
       for (int h = 0; h < 32; h++) {
-        const int32_t code = decode_one(wb, nw, p, true, T, nout, badv);
+        uint32_t n;
+        const int32_t code = decode_sym(R.top(), T, LT, &n, badv);
+        R.consume(n);
+        tot += n;
+        nout += code == -32768 ? 1u : 0u;
         if (h & 1) pk[h >> 1] |= ((uint32_t)code & 0xffffu) << 16;
         else pk[h >> 1] = (uint32_t)code & 0xffffu;
       }
@@ -182,17 +234,21 @@ __device__ inline uint32_t decode_run(const uint32_t *wb, uint32_t nw, uint32_t 
     }
   } else {
     for (int k = 0; k < cnt; k++) {
-      const int32_t code = decode_one(wb, nw, p, true, T, nout, badv);
+      uint32_t n;
+      const int32_t code = decode_sym(R.top(), T, LT, &n, badv);
+      R.consume(n);
+      tot += n;
+      nout += code == -32768 ? 1u : 0u;
       dst[k] = (int16_t)code;
     }
   }
-  *used = p - p0;
+  *used = tot;
   *bad = badv;
   return nout;
 }
 
 template <int NDIM>
-__global__ __launch_bounds__(kBlock) void k_decode(Plan P, const uint8_t *__restrict__ blob,
+__global__ __launch_bounds__(kBlock, 3) void k_decode(Plan P, const uint8_t *__restrict__ blob,
                                                    DecodeArgs A, DevParams *__restrict__ dp,
                                                    int16_t *__restrict__ codes, uint32_t stage_words) {
   __shared__ uint16_t lut[1 << kLut];
@@ -234,6 +290,12 @@ __global__ __launch_bounds__(kBlock) void k_decode(Plan P, const uint8_t *__rest
     return;
   }
   const DecTabs T{lut, lim, off, sorted};
+  LongTabs LT;
+#pragma unroll
+  for (int m = 0; m <= kLMax - kLut; m++) {
+    LT.lim[m] = __builtin_amdgcn_readfirstlane(lim[kLut + m]);
+    LT.off[m] = __builtin_amdgcn_readfirstlane(off[kLut + m]);
+  }
   uint32_t *mine = wstage + (size_t)wv * (stage_words + 1);
   const int k0 = lane * kChunk;
   const int cnt = lane < (int)g.nck ? (k0 + kChunk < nt ? kChunk : nt - k0) : 0;
@@ -262,8 +324,8 @@ __global__ __launch_bounds__(kBlock) void k_decode(Plan P, const uint8_t *__rest
     const bool fits = todo && clw < base + wn;
     if (fits) {
       bool b2;
-      if (full) nout += decode_run<true>(mine, wn, cstart - 32 * base, cnt, T, dst, &used, &b2);
-      else nout += decode_run<false>(mine, wn, cstart - 32 * base, cnt, T, dst, &used, &b2);
+      if (full) nout += decode_run<true>(mine, wn, cstart - 32 * base, cnt, T, LT, dst, &used, &b2);
+      else nout += decode_run<false>(mine, wn, cstart - 32 * base, cnt, T, LT, dst, &used, &b2);
       bad |= b2;
       todo = false;
     }
