@@ -28,13 +28,19 @@ template <> struct DGeo<3> { static constexpr int TZ = 16, TY = 16, TX = 32; };
 
 __device__ __host__ constexpr int dphys(int L) { return L + (L >> 5); }
 
-constexpr int kDecLut = 12;  // bits of the decoder lookup table
+constexpr int kLut = 13;  // bits of the decoder lookup table
+// Decoder table entry: (symbol << 5) | code length.  Symbols 1..1023 (residual
+// + 512, bit 15 clear) are decoded by the table alone; escape classes
+// (1024..1035), the outlier symbol (stored as kSymOutlierTag) and codes longer
+// than the table (kLutLong) have bit 15 set.
+constexpr uint32_t kSymOutlierTag = 2047;
+constexpr uint16_t kLutLong = 0xffff;
 
 struct DecodeArgs {
   uint64_t off_words, n_words, n_exc;
   double e2;
   float e2_f;
-  const uint32_t *lut;
+  const uint16_t *lut;
   const uint32_t *ltab;
   const uint16_t *sorted;
   // GLOBAL domain: per-tile faces and edge vectors, tile-major slots
@@ -51,7 +57,7 @@ typedef double df64x2_t __attribute__((ext_vector_type(2)));
 // decoder tables from the code lengths in the blob (one workgroup)
 __global__ __launch_bounds__(1024) void k_dec_tables(Plan P, const uint8_t *__restrict__ blob,
                                                      DevParams *__restrict__ dp,
-                                                     uint32_t *__restrict__ lut,
+                                                     uint16_t *__restrict__ lut,
                                                      uint32_t *__restrict__ ltab,
                                                      uint16_t *__restrict__ sorted) {
   __shared__ uint8_t lens[kNSym];
@@ -75,13 +81,14 @@ __global__ __launch_bounds__(1024) void k_dec_tables(Plan P, const uint8_t *__re
     return;
   }
   canonical_from_lengths(lens, code, lcount, lfirst, lbase, sorted, wcnt);
-  for (int i = tid; i < (1 << kDecLut); i += blockDim.x) lut[i] = 0;
+  for (int i = tid; i < (1 << kLut); i += blockDim.x) lut[i] = kLutLong;
   __syncthreads();
   for (int s = tid; s < kNSym; s += blockDim.x) {
     const int l = lens[s];
-    if (l == 0 || l > kDecLut) continue;
-    const uint32_t lo = code[s] << (kDecLut - l), hi = (code[s] + 1) << (kDecLut - l);
-    for (uint32_t i = lo; i < hi; i++) lut[i] = ((uint32_t)s << 5) | (uint32_t)l;
+    if (l == 0 || l > kLut) continue;
+    const uint32_t lo = code[s] << (kLut - l), hi = (code[s] + 1) << (kLut - l);
+    const uint32_t e = (s == 0 ? kSymOutlierTag : (uint32_t)s) << 5 | (uint32_t)l;
+    for (uint32_t i = lo; i < hi; i++) lut[i] = (uint16_t)e;
   }
   if (tid <= kLMax) {
     ltab[tid] = lfirst[tid];
@@ -91,56 +98,28 @@ __global__ __launch_bounds__(1024) void k_dec_tables(Plan P, const uint8_t *__re
 }
 
 // ---------------------------------------------------------------------------
-// Decode: one wave per tile, lane k decodes chunk k (128 symbols).  The
-// tile's words are staged in LDS in windows of `stage_words`; lanes whose
-// chunk lies in the window decode it (tiles larger than a window take
-// several rounds).  The reader takes the 64 bits at bit position p from words
-// p/32 and p/32 + 1, so there is no refill state, and the symbol step has no
-// branch except for codes longer than the 12-bit table.  The residual codes
-// are written in stream order, eight per 16-byte store (outliers as -32768;
-// their residual is in the exception list, whose outlier count is checked).
-constexpr int kDecWaves = 4;
-constexpr int kLut = 12;  // bits of the decoder table
+// Decode: one wave per tile, lane k decodes chunk k (128 symbols) in one
+// pass.  The first `stage_words` words of the tile are staged in LDS; lanes
+// whose chunk ends inside that window read from LDS, the others (the tail of
+// tiles larger than the window) read the blob directly.  Each lane holds two
+// words of its chunk in registers and one read ahead, so a symbol step is a
+// funnel shift, a table lookup and a pack, with no LDS read on the path from
+// one symbol to the next but the table's.  Table entries with bit 15 set
+// (escapes, outliers, codes longer than the table) take a wave-uniform slow
+// step.
+// Residual codes are written in stream order, eight per 16-byte store
+// (outliers as -32768; their residual is in the exception list, whose outlier
+// count is checked).
+constexpr int kDecWaves = 8;
+constexpr int kDecBlock = 64 * kDecWaves;
 
-struct DecTabs {
-  const uint16_t *lut;     // (symbol << 5) | length, 0 = longer than kLut
-  const uint32_t *lim;     // [l]: left-justified (18-bit) end of the codes of length <= l
-  const int32_t *off;      // [l]: base index - first code of length l
-  const uint16_t *sorted;  // symbols in canonical order
-};
+typedef __attribute__((address_space(3))) const uint32_t lds_cu32;
+typedef __attribute__((address_space(3))) const uint16_t lds_cu16;
+typedef unsigned short du16x2_t __attribute__((ext_vector_type(2)));
 
-// Decode `cnt` symbols starting at bit p of the staged words `wb` (nw + 1
-// words, the last one zero).  Codes go to dst (8-aligned when vec).
-// Returns the number of outlier symbols; sets *bad on an invalid code.
-// Bit reader over the staged window: 32..64 pending bits left-aligned in a
-// 64-bit register; the next window word is read ahead and shifted in when
-// fewer than 32 bits remain.  Reads stay inside the window plus its zero pad
-// word (index nw).
-struct BitReader {
-  const uint32_t *wb;
-  uint32_t nw, nb, wp, nextw;
-  uint64_t buf;
-  __device__ void init(const uint32_t *w, uint32_t n, uint32_t p) {
-    wb = w;
-    nw = n;
-    const uint32_t i = (p >> 5) < n ? (p >> 5) : n;
-    const uint32_t i1 = i + 1 < n ? i + 1 : n;
-    buf = (((uint64_t)wb[i] << 32) | wb[i1]) << (p & 31);
-    nb = 64 - (p & 31);
-    wp = i + 2 < n ? i + 2 : n;
-    nextw = wb[wp];
-  }
-  __device__ uint32_t top() const { return (uint32_t)(buf >> 32); }
-  __device__ void consume(uint32_t n) {  // n <= 32 <= nb
-    buf <<= n;
-    nb -= n;
-    const bool need = nb < 32;
-    buf |= need ? ((uint64_t)nextw << (32 - nb)) : 0ull;
-    nb += need ? 32u : 0u;
-    wp = need ? (wp + 1 < nw ? wp + 1 : nw) : wp;
-    nextw = wb[wp];
-  }
-};
+__device__ inline uint32_t lds_addr(const void *p) {
+  return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const void *)p;
+}
 
 // Limits and offsets of the code lengths longer than the lookup table
 // (kLut + 1 .. 18), wave-uniform: held in scalar registers.
@@ -149,20 +128,72 @@ struct LongTabs {
   int32_t off[kLMax - kLut + 1];
 };
 
-// One symbol: returns its residual code; *n = its bits (code + extra bits).
-__device__ inline int32_t decode_sym(uint32_t top, const DecTabs &T, const LongTabs &LT,
-                                     uint32_t *n, bool &badv) {
-  const uint32_t e = T.lut[top >> (32 - kLut)];
-  uint32_t L = e & 31u, s = e >> 5;
-  const bool slow = L == 0;
-  if (__builtin_amdgcn_ballot_w64(slow)) {  // wave-uniform test: long codes are rare
-    // canonical decode of lengths kLut+1..18 from left-justified 18-bit
-    // limits (nondecreasing): the length is one past the limits <= v
+// Per-lane bit reader over the tile's words, from the LDS window (byte
+// address `win`) or, for lanes whose chunk ends past the window, from global
+// memory (`gw`).  The next 32 bits are a funnel shift of two register words
+// a:b by s (0..31); a third word c is read ahead.  Every step reads c again
+// (the same word unless the step moved on to the next one), so a read never
+// has to be merged into a register that is still waiting for it.  Word
+// indexes are clamped (to the window's two zero words for LDS lanes, to the
+// tile's last word for the others): for a valid chunk the clamp only changes
+// bits past its end, and a corrupt one cannot read outside the window or the
+// blob.  MIXED: some lane of the wave reads global memory.
+template <bool MIXED>
+struct BitReader {
+  uint32_t a, b, s, idx;  // idx: index of the word read ahead
+  uint32_t cl, cg;        // that word, as read from LDS / from global memory
+  uint32_t wlim, glim, win;
+  bool lds;
+  dgptr_t<uint32_t> gw;
+  __device__ uint32_t lword(uint32_t i) const {
+    return *(lds_cu32 *)(uintptr_t)(win + 4u * (i < wlim ? i : wlim));
+  }
+  __device__ uint32_t gword(uint32_t i) const { return gw[i < glim ? i : glim]; }
+  __device__ uint32_t word(uint32_t i) const { return (!MIXED || lds) ? lword(i) : gword(i); }
+  __device__ void init(uint32_t p) {  // first bit at word-relative bit p
+    const uint32_t i = p >> 5, r = p & 31u;
+    // r == 0: the first word goes to b with a shift of 0
+    const uint32_t j = r ? i : i - 1u;
+    a = r ? word(j) : 0u;
+    b = word(j + 1u);
+    idx = j + 2u;
+    cl = cg = word(idx);
+    s = (32u - r) & 31u;
+  }
+  __device__ uint32_t top() const { return __builtin_amdgcn_alignbit(a, b, s); }
+  __device__ void consume(uint32_t n) {  // n <= 32
+    const uint32_t t = s - n;
+    const bool need = (int32_t)t < 0;
+    s = t & 31u;
+    a = need ? b : a;
+    const uint32_t c = (!MIXED || lds) ? cl : cg;
+    b = need ? c : b;
+    idx += need ? 1u : 0u;
+    // the window is read again every step (the same word unless the step
+    // moved on), so the read never merges into a register still waiting
+    // for it; lanes outside the window read global memory only on a move
+    cl = lword(idx);
+    if (MIXED && need && !lds) cg = gword(idx);
+  }
+};
+
+// Slow symbol step, taken by the whole wave when some lane's table entry has
+// bit 15 set.  For those lanes: *v becomes residual + 512 (mod 2^16), *n the
+// bits of code and extra bits.  Long codes are decoded canonically from the
+// left-justified 18-bit limits (nondecreasing): the length is one past the
+// limits <= the next 18 bits.
+__device__ inline void slow_step(uint32_t top, uint32_t e, const LongTabs &LT,
+                                 const uint32_t sorted_lds, uint32_t *v, uint32_t *n,
+                                 uint32_t *nout, bool &badv) {
+  const bool nd = e >= 0x8000u;
+  uint32_t S = e >> 5, L = e & 31u;
+  const bool lg = nd && L == 31u;
+  if (__builtin_amdgcn_ballot_w64(lg)) {
     constexpr int NL = kLMax - kLut;
-    const uint32_t v = top >> (32 - kLMax);
+    const uint32_t x = top >> (32 - kLMax);
     uint32_t k = 1;
 #pragma unroll
-    for (int m = 1; m < NL; m++) k += v >= LT.lim[m] ? 1u : 0u;
+    for (int m = 1; m < NL; m++) k += x >= LT.lim[m] ? 1u : 0u;
     uint32_t lo = LT.lim[0], hi = LT.lim[1];
     int32_t of = LT.off[1];
 #pragma unroll
@@ -173,53 +204,65 @@ __device__ inline int32_t decode_sym(uint32_t top, const DecTabs &T, const LongT
       of = at ? LT.off[m] : of;
     }
     const uint32_t l = kLut + k;
-    const int32_t idx = of + (int32_t)(v >> (kLMax - l));
-    const bool ok = v >= lo && v < hi && idx >= 0 && idx < kNSym;
-    const uint32_t sl = T.sorted[ok ? idx : 0];
-    s = slow ? (ok ? sl : 0u) : s;
-    L = slow ? l : L;
-    badv |= slow && !ok;
+    const int32_t idx = of + (int32_t)(x >> (kLMax - l));
+    const bool ok = x >= lo && x < hi && idx >= 0 && idx < kNSym;
+    const uint32_t sl = *(lds_cu16 *)(uintptr_t)(sorted_lds + 2u * (uint32_t)(ok ? idx : 0));
+    S = lg ? (ok ? sl : 0u) : S;
+    L = lg ? l : L;
+    badv |= lg && !ok;
   }
   // escape classes: k raw bits of |d| - 2^k follow the code (within `top`
   // because L + k <= 32); a zero-width field extracts as 0
-  const bool esc = s >= 1024u;
-  const uint32_t kk = esc ? (s >> 1) - 503u : 0u;  // (s - 1024) / 2 + 9
+  const bool out = S == kSymOutlierTag;
+  const bool esc = S >= 1024u && !out;
+  const uint32_t kk = esc ? (S >> 1) - 503u : 0u;  // (S - 1024) / 2 + 9
   const uint32_t ev = __builtin_amdgcn_ubfe(top, 32u - L - kk, kk);
   const uint32_t mag = (1u << kk) + ev;
-  const uint32_t neg = 0u - (s & 1u);
-  const int32_t cesc = (int32_t)((mag ^ neg) - neg);
-  int32_t code = esc ? cesc : (int32_t)s - 512;
-  code = s == 0 ? -32768 : code;
-  *n = L + kk;
-  return code;
+  const uint32_t neg = 0u - (S & 1u);
+  const uint32_t cesc = ((mag ^ neg) - neg) + 512u;
+  uint32_t val = esc ? cesc : S;
+  val = out ? (uint32_t)(512 - 32768) : val;
+  *nout += nd && out ? 1u : 0u;
+  *v = nd ? (val & 0xffffu) : *v;
+  *n = nd ? L + kk : *n;
 }
 
-// Decode one chunk of cnt symbols starting at bit p of the window into dst.
-// FULL (128 symbols, 16-byte aligned destination): the codes of 32 symbols
-// are held in registers and stored as four 16-byte pieces of one lane, so
-// the cache sees whole 64-byte pieces rather than scattered 16-byte ones.
-template <bool FULL>
-__device__ inline uint32_t decode_run(const uint32_t *wb, uint32_t nw, uint32_t p, int cnt,
-                                      const DecTabs &T, const LongTabs &LT, int16_t *dst,
-                                      uint32_t *used, bool *bad) {
+// One symbol: returns residual + 512 (mod 2^16) and consumes its bits.
+template <class Reader>
+__device__ inline uint32_t decode_sym(Reader &R, uint32_t lut_lds, uint32_t sorted_lds,
+                                      const LongTabs &LT, uint32_t *tot, uint32_t *nout,
+                                      bool &badv) {
+  const uint32_t top = R.top();
+  const uint32_t e = *(lds_cu16 *)(uintptr_t)(lut_lds + ((top >> (32 - kLut)) << 1));
+  uint32_t v = e >> 5, n = e & 31u;
+  if (__builtin_amdgcn_ballot_w64(e >= 0x8000u)) slow_step(top, e, LT, sorted_lds, &v, &n, nout, badv);
+  R.consume(n);
+  *tot += n;
+  return v;
+}
+
+// Decode one chunk of cnt symbols into dst.  FULL (128 symbols, 16-byte
+// aligned destination): the codes of 32 symbols are held in registers and
+// stored as four 16-byte pieces of one lane, so the cache sees whole 64-byte
+// pieces rather than scattered ones.
+template <bool FULL, class Reader>
+__device__ inline uint32_t decode_run(Reader &R, int cnt, uint32_t lut_lds, uint32_t sorted_lds,
+                                      const LongTabs &LT, int16_t *dst, uint32_t *used,
+                                      bool *bad) {
   uint32_t nout = 0, tot = 0;
   bool badv = false;
-  BitReader R;
-  R.init(wb, nw, p);
   if (FULL) {
     typedef __attribute__((address_space(1))) du32x4_t gq;
 #pragma unroll 1
     for (int part = 0; part < 4; part++) {
       uint32_t pk[16];
 #pragma unroll
-      for (int h = 0; h < 32; h++) {
-        uint32_t n;
-        const int32_t code = decode_sym(R.top(), T, LT, &n, badv);
-        R.consume(n);
-        tot += n;
-        nout += code == -32768 ? 1u : 0u;
-        if (h & 1) pk[h >> 1] |= ((uint32_t)code & 0xffffu) << 16;
-        else pk[h >> 1] = (uint32_t)code & 0xffffu;
+      for (int h = 0; h < 32; h += 2) {
+        const uint32_t a = decode_sym(R, lut_lds, sorted_lds, LT, &tot, &nout, badv);
+        const uint32_t b = decode_sym(R, lut_lds, sorted_lds, LT, &tot, &nout, badv);
+        du16x2_t p2 = __builtin_bit_cast(du16x2_t, a | (b << 16));
+        p2 -= (du16x2_t)(512);
+        pk[h >> 1] = __builtin_bit_cast(uint32_t, p2);
       }
       gq *d = (gq *)(dst + 32 * part);
 #pragma unroll
@@ -234,12 +277,8 @@ __device__ inline uint32_t decode_run(const uint32_t *wb, uint32_t nw, uint32_t 
     }
   } else {
     for (int k = 0; k < cnt; k++) {
-      uint32_t n;
-      const int32_t code = decode_sym(R.top(), T, LT, &n, badv);
-      R.consume(n);
-      tot += n;
-      nout += code == -32768 ? 1u : 0u;
-      dst[k] = (int16_t)code;
+      const uint32_t a = decode_sym(R, lut_lds, sorted_lds, LT, &tot, &nout, badv);
+      dst[k] = (int16_t)(uint16_t)(a - 512u);
     }
   }
   *used = tot;
@@ -248,26 +287,34 @@ __device__ inline uint32_t decode_run(const uint32_t *wb, uint32_t nw, uint32_t 
 }
 
 template <int NDIM>
-__global__ __launch_bounds__(kBlock, 3) void k_decode(Plan P, const uint8_t *__restrict__ blob,
-                                                   DecodeArgs A, DevParams *__restrict__ dp,
-                                                   int16_t *__restrict__ codes, uint32_t stage_words) {
-  __shared__ uint16_t lut[1 << kLut];
+__global__ __launch_bounds__(kDecBlock) void k_decode(Plan P, const uint8_t *__restrict__ blob,
+                                                      DecodeArgs A, DevParams *__restrict__ dp,
+                                                      int16_t *__restrict__ codes, uint32_t stage_words) {
+  __shared__ __attribute__((aligned(16))) uint16_t lut[1 << kLut];
   __shared__ uint32_t lim[kLMax + 1];
   __shared__ int32_t off[kLMax + 1];
   __shared__ uint16_t sorted[kNSym];
-  extern __shared__ uint32_t wstage[];  // kDecWaves * (stage_words + 1)
+  extern __shared__ uint32_t wstage[];  // kDecWaves windows of stage_words + 2
 
   if (dp->corrupt) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int i = tid; i < (1 << kLut); i += kBlock) lut[i] = (uint16_t)A.lut[i];
-  for (int i = tid; i < kNSym; i += kBlock) sorted[i] = A.sorted[i];
+  {
+    const du32x4_t *src = reinterpret_cast<const du32x4_t *>(A.lut);
+    du32x4_t *d = reinterpret_cast<du32x4_t *>(lut);
+    for (int i = tid; i < (1 << kLut) / 8; i += kDecBlock) d[i] = src[i];
+  }
+  for (int i = tid; i < kNSym; i += kDecBlock) {
+    const uint16_t v = A.sorted[i];
+    sorted[i] = v == 0 ? (uint16_t)kSymOutlierTag : v;
+  }
   if (tid <= kLMax) {
     const uint32_t first = A.ltab[tid], cnt = A.ltab[32 + tid], base = A.ltab[64 + tid];
     lim[tid] = tid ? (first + cnt) << (kLMax - tid) : 0u;
     off[tid] = (int32_t)base - (int32_t)first;
   }
   __syncthreads();
-  const uint64_t t = (uint64_t)blockIdx.x * kDecWaves + wv;
+  // the tile is wave-uniform: its values live in scalar registers
+  const uint64_t t = (uint64_t)blockIdx.x * kDecWaves + __builtin_amdgcn_readfirstlane(wv);
   if (t >= P.n_tiles) return;  // no barrier follows
   const TileGeo g = tile_geo(P, t);
   const int nt = (int)g.nt;
@@ -289,49 +336,54 @@ __global__ __launch_bounds__(kBlock, 3) void k_decode(Plan P, const uint8_t *__r
     if (lane == 0) atomicOr(&dp->corrupt, 1u);
     return;
   }
-  const DecTabs T{lut, lim, off, sorted};
   LongTabs LT;
 #pragma unroll
   for (int m = 0; m <= kLMax - kLut; m++) {
     LT.lim[m] = __builtin_amdgcn_readfirstlane(lim[kLut + m]);
     LT.off[m] = __builtin_amdgcn_readfirstlane(off[kLut + m]);
   }
-  uint32_t *mine = wstage + (size_t)wv * (stage_words + 1);
+  // stage the window: its words and two zero words after them
+  uint32_t *mine = wstage + (size_t)wv * (stage_words + 2);
+  const uint32_t wn = nw < stage_words ? nw : stage_words;
+  for (uint32_t i = lane; i < wn + 2; i += 64) mine[i] = i < wn ? gw[i] : 0u;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
   const int k0 = lane * kChunk;
   const int cnt = lane < (int)g.nck ? (k0 + kChunk < nt ? kChunk : nt - k0) : 0;
   const uint32_t cstart = incl - cb;                 // chunk's first bit
-  const uint32_t cfw = cstart >> 5;                  // first word
   const uint32_t clw = incl ? (incl - 1) >> 5 : 0;   // last word holding its bits
   int16_t *dst = codes + g.start + k0;
   // full chunks with a 16-byte aligned destination (k0 is a multiple of 128)
   const bool full = cnt == kChunk && (g.start & 7) == 0;
-  bool todo = cnt > 0;
   bool bad = false;
   uint32_t used = cb, nout = 0;
-  uint32_t base = 0;
-  for (int round = 0; round < 64; round++) {
-    if (!__any(todo)) break;
-    // next window starts at the first word of the earliest pending chunk
-    uint32_t st = todo ? cfw : 0xffffffffu;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) { const uint32_t u = __shfl_xor(st, o, 64); st = u < st ? u : st; }
-    base = st;
-    const uint32_t wn = nw - base < stage_words ? nw - base : stage_words;
-    for (uint32_t i = lane; i <= wn; i += 64) mine[i] = i < wn ? gw[base + i] : 0u;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const bool fits = todo && clw < base + wn;
-    if (fits) {
-      bool b2;
-      if (full) nout += decode_run<true>(mine, wn, cstart - 32 * base, cnt, T, LT, dst, &used, &b2);
-      else nout += decode_run<false>(mine, wn, cstart - 32 * base, cnt, T, LT, dst, &used, &b2);
-      bad |= b2;
-      todo = false;
+  const bool lds = clw < wn;
+  const uint32_t lut_lds = lds_addr(lut), sorted_lds = lds_addr(sorted);
+  if (__builtin_amdgcn_ballot_w64(cnt > 0 && !lds)) {
+    if (cnt > 0) {
+      BitReader<true> R;
+      R.lds = lds;
+      R.win = lds_addr(mine);
+      R.gw = (dgptr_t<uint32_t>)gw;
+      R.wlim = wn + 1;
+      R.glim = nw - 1;
+      R.init(cstart);
+      if (full) nout = decode_run<true>(R, cnt, lut_lds, sorted_lds, LT, dst, &used, &bad);
+      else nout = decode_run<false>(R, cnt, lut_lds, sorted_lds, LT, dst, &used, &bad);
     }
-    __builtin_amdgcn_wave_barrier();  // the window is rewritten next round
+  } else if (cnt > 0) {
+    BitReader<false> R;
+    R.lds = true;
+    R.win = lds_addr(mine);
+    R.gw = (dgptr_t<uint32_t>)gw;
+    R.wlim = wn + 1;
+    R.glim = 0;
+    R.init(cstart);
+    if (full) nout = decode_run<true>(R, cnt, lut_lds, sorted_lds, LT, dst, &used, &bad);
+    else nout = decode_run<false>(R, cnt, lut_lds, sorted_lds, LT, dst, &used, &bad);
   }
-  if (todo) bad = true;
   // every outlier symbol must have its record
   uint32_t nrec = 0;
   const uint32_t *exc = reinterpret_cast<const uint32_t *>(blob + P.off_exc);
@@ -1092,8 +1144,8 @@ static void launch_dec_t(const Plan &P, const uint8_t *blob, const DecodeArgs &A
                          hipStream_t s, Timer *tm) {
   using G = DGeo<NDIM>;
   const dim3 dgrid((uint32_t)ceil_div(P.n_tiles, kDecWaves)), grid((uint32_t)P.n_tiles), blk(kBlock);
-  const size_t dyn = (size_t)kDecWaves * (stage_words + 1) * 4;
-  hipLaunchKernelGGL((k_decode<NDIM>), dgrid, blk, dyn, s, P, blob, A, dp, codes, stage_words);
+  const size_t dyn = (size_t)kDecWaves * (stage_words + 2) * 4;
+  hipLaunchKernelGGL((k_decode<NDIM>), dgrid, dim3(kDecBlock), dyn, s, P, blob, A, dp, codes, stage_words);
   tm->mark(s, "decode");
   const bool ragged = P.pad_ != 0;
   if (P.domain == FPSZ_DOMAIN_GLOBAL) {
@@ -1129,6 +1181,33 @@ static void launch_dec_t(const Plan &P, const uint8_t *blob, const DecodeArgs &A
   tm->mark(s, "rec");
 }
 
+// Largest decode window (words per wave) that keeps two decode workgroups
+// resident per CU next to their decoder tables (at most 20 KB each): one
+// workgroup per CU leaves too few waves to hide the LDS latency of the symbol
+// loop, and the chunks past the window are read from global memory instead.
+static uint64_t decode_window_limit() {
+  static int cached[64][2];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (cached[dev][0] == 0) {
+    int blk = 0, cu = 0;
+    if (hipDeviceGetAttribute(&blk, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        blk <= 0)
+      blk = 65536;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+            hipSuccess ||
+        cu <= 0)
+      cu = blk;
+    cached[dev][1] = cu;
+    cached[dev][0] = blk;
+  }
+  int64_t lds = cached[dev][1] / 2;
+  if (lds > cached[dev][0]) lds = cached[dev][0];
+  const int64_t words = (lds - 20480) / 4;
+  const int64_t per_wave = words / kDecWaves - 2;
+  return per_wave < 512 ? 512 : (uint64_t)(per_wave & ~(int64_t)63);
+}
+
 hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const DecompressWs &W,
                                   uint64_t off_words, uint64_t n_words, uint64_t n_exc, double e2,
                                   float e2_f, void *out, hipStream_t s, Timer *tm) {
@@ -1158,11 +1237,12 @@ hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const Deco
   A.gy = W.gy;
   A.gz = W.gz;
   A.tt = W.tt;
-  // LDS window per wave: about the average words per tile, 512..2048; larger
-  // tiles are decoded in several windows
+  // LDS window per wave: a quarter above the average words per tile, so that
+  // most chunks are read from LDS; the rest are read from global memory.
   const uint64_t avg = P.n_tiles ? n_words / P.n_tiles : 0;
-  uint64_t sw = (avg + 255) & ~(uint64_t)255;
-  sw = sw < 512 ? 512 : (sw > 2048 ? 2048 : sw);
+  uint64_t sw = (avg + avg / 4 + 64 + 63) & ~(uint64_t)63;
+  const uint64_t sw_max = decode_window_limit();
+  sw = sw < 512 ? 512 : (sw > sw_max ? sw_max : sw);
   const uint32_t stage_words = (uint32_t)sw;
   if (P.dtype == FPSZ_F32) {
     if (P.ndim == 1) launch_dec_t<float, 1>(P, blob, A, W.P, W.codes, W.tmp, stage_words, (float *)out, s, tm);

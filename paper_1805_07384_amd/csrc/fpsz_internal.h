@@ -336,7 +336,7 @@ struct CompressWs {
 
 struct DecompressWs {
   DevParams *P;
-  uint32_t *lut;       // 2048 entries: (symbol << 5) | length, 0 = long/invalid
+  uint16_t *lut;       // 8192 entries: (symbol << 5) | length, 0 = long/invalid
   uint32_t *ltab;      // first[19], count[19], base[19]
   uint16_t *sorted;    // symbols in canonical order
   uint32_t *fz, *fy, *fx;  // per-tile faces (GLOBAL domain)

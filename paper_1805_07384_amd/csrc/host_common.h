@@ -144,7 +144,7 @@ inline DecompressLayout decompress_layout(const Plan &P) {
   const uint64_t fx = (uint64_t)P.tz * P.ty;
   uint64_t o = align256(sizeof(DevParams));
   L.off_lut = o;
-  o = align256(o + 4 * 4096);
+  o = align256(o + 2 * 8192);
   L.off_ltab = o;
   o = align256(o + 4 * 96);
   L.off_sorted = o;
@@ -378,7 +378,7 @@ inline fpsz_status prepare_decompress(fpsz_ctx *ctx, const uint8_t *h, const voi
   memcpy(&J->e2_f, &e2fb, 4);
   DecompressWs &W = J->W;
   W.P = (DevParams *)ws;
-  W.lut = (uint32_t *)(ws + L.off_lut);
+  W.lut = (uint16_t *)(ws + L.off_lut);
   W.ltab = (uint32_t *)(ws + L.off_ltab);
   W.sorted = (uint16_t *)(ws + L.off_sorted);
   W.fz = (uint32_t *)(ws + L.off_fz);
