@@ -22,10 +22,18 @@ namespace fpsz {
 // ---------------------------------------------------------------------------
 // The field a block works on: the by-value job, or entry blockIdx.y of the
 // batch array.
+// The copy is made wave-uniform word by word, so everything derived from it
+// (tile geometry, addresses) stays in scalar registers.
 __device__ inline CJob select_job(const CJob &one, const CJob *__restrict__ jobs) {
   CJob j;
   if (jobs) j = jobs[blockIdx.y];
   else j = one;
+  static_assert(sizeof(CJob) % 4 == 0, "CJob is copied in 32-bit words");
+  uint32_t w[sizeof(CJob) / 4];
+  __builtin_memcpy(w, &j, sizeof(CJob));
+#pragma unroll
+  for (unsigned i = 0; i < sizeof(CJob) / 4; i++) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  __builtin_memcpy(&j, w, sizeof(CJob));
   return j;
 }
 
@@ -329,12 +337,19 @@ template <int NDIM> __device__ inline int seg_at(int bz, int by, int s, int k) {
 // Patch test |x - x'| > eb.  For float32 input a float32 pre-filter marks
 // candidates: below thr (eb lowered by a relative 2^-22, rounded down) the
 // rounded float32 difference proves |x - x'| <= eb; candidates (rare) take
-// the exact float64 test afterwards.
+// the exact float64 test afterwards.  Full tiles keep only the largest
+// difference of a 32-point segment and test every point of a segment above
+// thr exactly.
 template <typename T> struct PatchTest;
 template <> struct PatchTest<float> {
-  __device__ static bool candidate(float v, int32_t q, float e2f, double, double, float thr) {
+  // |x - x'| rounded to float32 (x' itself rounded first, as the decoder
+  // forms it)
+  __device__ static float diff(float v, int32_t q, float e2f) {
     const float xr = (float)q * e2f;
-    return fabsf(v - xr) > thr;
+    return fabsf(v - xr);
+  }
+  __device__ static bool candidate(float v, int32_t q, float e2f, double, double, float thr) {
+    return diff(v, q, e2f) > thr;
   }
   __device__ static bool exact(float v, int32_t q, float e2f, double, double eb) {
     const float xr = (float)q * e2f;
@@ -374,7 +389,8 @@ __device__ inline uint32_t fast_tile_load(const T *__restrict__ x_, const Plan &
   const int y = NDIM == 3 ? tid & 15 : NDIM == 2 ? tid >> 2 : 0;
   const int sg = NDIM == 3 ? 0 : NDIM == 2 ? tid & 3 : tid;
   const int x0l = 32 * sg;
-  const uint64_t rowbase = ((g.z0 + z) * P.ny + (g.y0 + y)) * P.nx + g.x0 + x0l;
+  const uint32_t rowbase = (((uint32_t)g.z0 + z) * (uint32_t)P.ny + ((uint32_t)g.y0 + y)) *
+                               (uint32_t)P.nx + (uint32_t)g.x0 + x0l;
   T v[32];
   constexpr int VW = 16 / sizeof(T);
   if ((rowbase % VW) == 0) {
@@ -390,11 +406,41 @@ __device__ inline uint32_t fast_tile_load(const T *__restrict__ x_, const Plan &
 #pragma unroll
     for (int j = 0; j < 32; j++) v[j] = x[rowbase + j];
   }
-  int32_t ql = 0;
-  if (x0l > 0 || (GLOBAL && g.x0 > 0)) ql = Quant<T>::q(x[rowbase - 1], rf, r);
+  // left neighbour of the segment
+  const bool hasl = x0l > 0 || (GLOBAL && g.x0 > 0);
+  const T xl = hasl ? x[rowbase - 1] : (T)0;
+  // halo rows: 3D the plane z = -1 (17 rows) and the rows y = -1 of z >= 0
+  // (16 rows); 2D the row y = -1; 33 values per segment (k = -1 .. 31).
+  // All of a thread's halo values are loaded before any is used, so their
+  // latencies overlap.
+  constexpr int NH = F::HROWS * F::NSEG * 33;
+  constexpr int NIT = (NH + kBlock - 1) / kBlock;
+  T hv[NIT > 0 ? NIT : 1];
+  int hs[NIT > 0 ? NIT : 1];  // LDS word, -1: none
+  bool hin[NIT > 0 ? NIT : 1];
+#pragma unroll
+  for (int m = 0; m < NIT; m++) {
+    const int i = tid + m * kBlock;
+    const int hr = i / (F::NSEG * 33), rem = i - hr * (F::NSEG * 33);
+    const int s2 = rem / 33, k = rem - s2 * 33 - 1;
+    const int bz = NDIM == 3 ? (hr < 17 ? 0 : hr - 16) : 0;
+    const int by = NDIM == 3 ? (hr < 17 ? hr : 0) : 0;
+    hs[m] = i < NH ? seg_at<NDIM>(bz, by, s2, k) : -1;
+    hin[m] = false;
+    hv[m] = (T)0;
+    if (GLOBAL && i < NH) {
+      // fields hold fewer than 2^31 points: 32-bit element indexes
+      const int32_t fz = (int32_t)g.z0 + bz - G::HZ, fy = (int32_t)g.y0 + by - G::HY;
+      const int32_t fx = (int32_t)g.x0 + 32 * s2 + k;
+      hin[m] = fz >= 0 && fy >= 0 && fx >= 0;
+      const uint32_t fi = ((uint32_t)fz * (uint32_t)P.ny + (uint32_t)fy) * (uint32_t)P.nx + (uint32_t)fx;
+      if (hin[m]) hv[m] = x[fi];
+    }
+  }
   int32_t *dst = lds + seg_at<NDIM>(z + G::HZ, y + G::HY, sg, 0);
-  dst[-1] = ql;
+  dst[-1] = hasl ? Quant<T>::q(xl, rf, r) : 0;
   uint32_t cand = 0;
+  float dmax = 0.0f;  // float input: the largest pre-filter difference
 #pragma unroll
   for (int k = 0; k < 8; k++) {
     int32_t q4[4];
@@ -402,33 +448,50 @@ __device__ inline uint32_t fast_tile_load(const T *__restrict__ x_, const Plan &
     for (int h = 0; h < 4; h++) {
       const int j = 4 * k + h;
       q4[h] = Quant<T>::q(v[j], rf, r);
-      cand |= (PatchTest<T>::candidate(v[j], q4[h], e2f, e2, eb, thr) ? 1u : 0u) << j;
+      if constexpr (sizeof(T) == 4)
+        dmax = fmaxf(dmax, PatchTest<T>::diff(v[j], q4[h], e2f));
+      else
+        cand |= (PatchTest<T>::candidate(v[j], q4[h], e2f, e2, eb, thr) ? 1u : 0u) << j;
     }
     reinterpret_cast<int4 *>(dst)[k] = make_int4(q4[0], q4[1], q4[2], q4[3]);
   }
   uint32_t pb = 0;
-  while (cand) {  // rare: exact test, value reloaded
-    const int j = __ffs(cand) - 1;
-    cand &= cand - 1;
-    if (PatchTest<T>::exact(x[rowbase + j], dst[j], e2f, e2, eb)) pb |= 1u << j;
-  }
-  // halo rows: 3D the plane z = -1 (17 rows) and the rows y = -1 of z >= 0
-  // (16 rows); 2D the row y = -1; 33 values per segment (k = -1 .. 31)
-  constexpr int NH = F::HROWS * F::NSEG * 33;
-  for (int i = tid; i < NH; i += kBlock) {
-    const int hr = i / (F::NSEG * 33), rem = i - hr * (F::NSEG * 33);
-    const int s2 = rem / 33, k = rem - s2 * 33 - 1;
-    const int bz = NDIM == 3 ? (hr < 17 ? 0 : hr - 16) : 0;
-    const int by = NDIM == 3 ? (hr < 17 ? hr : 0) : 0;
-    int32_t qv = 0;
-    if (GLOBAL) {
-      const int64_t fz = (int64_t)g.z0 + bz - G::HZ, fy = (int64_t)g.y0 + by - G::HY;
-      const int64_t fx = (int64_t)g.x0 + 32 * s2 + k;
-      if (fz >= 0 && fy >= 0 && fx >= 0)
-        qv = Quant<T>::q(x[((uint64_t)fz * P.ny + (uint64_t)fy) * P.nx + (uint64_t)fx], rf, r);
+  if constexpr (sizeof(T) == 4) {
+    if (dmax > thr) {
+      // rare: every point of the segment takes the exact test, the values
+      // reloaded together and quantized again (so no quantized value has
+      // to stay in a register for this)
+      T w[32];
+      if ((rowbase % VW) == 0) {
+        using V = typename GVec<T>::V;
+        gptr_t<V> src = (gptr_t<V>)(x + rowbase);
+#pragma unroll
+        for (int k = 0; k < 32 / VW; k++) {
+          const V a = src[k];
+#pragma unroll
+          for (int h = 0; h < VW; h++) w[k * VW + h] = a[h];
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 32; j++) w[j] = x[rowbase + j];
+      }
+#pragma unroll
+      for (int j = 0; j < 32; j++)
+        pb |= (PatchTest<T>::exact(w[j], Quant<T>::q(w[j], rf, r), e2f, e2, eb) ? 1u : 0u) << j;
     }
-    lds[seg_at<NDIM>(bz, by, s2, k)] = qv;
+  } else {
+    // rare: exact test of each candidate, the value reloaded
+#pragma unroll 1
+    while (cand) {
+      const int j = __ffs(cand) - 1;
+      cand &= cand - 1;
+      const T xv = x[rowbase + j];
+      if (PatchTest<T>::exact(xv, Quant<T>::q(xv, rf, r), e2f, e2, eb)) pb |= 1u << j;
+    }
   }
+#pragma unroll
+  for (int m = 0; m < NIT; m++)
+    if (hs[m] >= 0) lds[hs[m]] = hin[m] ? Quant<T>::q(hv[m], rf, r) : 0;
   return pb;
 }
 
@@ -1144,6 +1207,31 @@ __device__ inline void load_code_table(const CJob &J, uint32_t *sct) {
   for (int s = threadIdx.x; s < kNSym; s += kBlock) sct[s] = (J.W.code[s] << 8) | J.W.code_len[s];
 }
 
+typedef unsigned short u16x2_t __attribute__((ext_vector_type(2)));
+
+// Bits of the 32 codes of a fast thread when every one is a direct symbol
+// (residual + 512 in 1..1023): one byte-table read per code.  *direct
+// tells whether that holds; the sum is meaningless otherwise.
+__device__ inline uint32_t direct_bits(const EncCodes &E, const uint8_t *len8, bool *direct) {
+  const u32x4_t qs[4] = {E.q0, E.q1, E.q2, E.q3};
+  u16x2_t mx = (u16x2_t)(0);
+  uint32_t bits = 0;
+#pragma unroll
+  for (int v = 0; v < 4; v++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      // (the element is copied out first: a bit cast of a vector element
+      // subscript read element 0 whatever the subscript)
+      const uint32_t w = qs[v][i];
+      const u16x2_t t = __builtin_bit_cast(u16x2_t, w) + (u16x2_t)(512);
+      // direct: t - 1 in 0..1022 for both halves (packed 16-bit, wrapping)
+      mx = __builtin_elementwise_max(mx, t - (u16x2_t)(1));
+      bits += (uint32_t)len8[t.x & 1023] + (uint32_t)len8[t.y & 1023];
+    }
+  *direct = mx.x < 1023 && mx.y < 1023;
+  return bits;
+}
+
 __global__ __launch_bounds__(kBlock) void k_enc_count(CJob one, const CJob *__restrict__ jobs) {
   const CJob J = select_job(one, jobs);
   const Plan P = J.P;
@@ -1152,27 +1240,36 @@ __global__ __launch_bounds__(kBlock) void k_enc_count(CJob one, const CJob *__re
   uint64_t *__restrict__ tw = J.W.word_state;
   uint8_t *__restrict__ blob = J.blob;
   __shared__ uint32_t sct[kNSym];
+  __shared__ uint8_t len8[1024];
   __shared__ uint32_t scr[8];
   if (dp->status != 0 || dp->is_const) return;
   const int tid = threadIdx.x;
   load_code_table(J, sct);
+  for (int s = tid; s < 1024; s += kBlock) len8[s] = J.W.code_len[s];
   __syncthreads();
   for (uint64_t t = blockIdx.x; t < P.n_tiles; t += gridDim.x) {
     const TileGeo g = tile_geo(P, t);
     EncCodes E = enc_codes(P, J.W.codes, g, tid);
     E.prefetch();
     uint32_t bits = 0;
+    bool direct = false;
+    if (E.fast) bits = direct_bits(E, len8, &direct);
+    // the general symbol map when some lane of the wave needs it
+    if (__builtin_amdgcn_ballot_w64(!direct)) {
+      uint32_t gb = 0;
 #pragma unroll 1
-    for (int v = 0; v < 4; v++) {
-      int32_t c[8];
-      E.load8(v, c);
-      uint32_t sy[8], ne[8], ev[8], e[8];
+      for (int v = 0; v < 4; v++) {
+        int32_t c[8];
+        E.load8(v, c);
+        uint32_t sy[8], ne[8], ev[8], e[8];
 #pragma unroll
-      for (int h = 0; h < 8; h++) sy[h] = sym_ne_ev(c[h], &ne[h], &ev[h]);
+        for (int h = 0; h < 8; h++) sy[h] = sym_ne_ev(c[h], &ne[h], &ev[h]);
 #pragma unroll
-      for (int h = 0; h < 8; h++) e[h] = sct[sy[h]];
+        for (int h = 0; h < 8; h++) e[h] = sct[sy[h]];
 #pragma unroll
-      for (int h = 0; h < 8; h++) bits += 8 * v + h < E.cnt ? (e[h] & 0xffu) + ne[h] : 0u;
+        for (int h = 0; h < 8; h++) gb += 8 * v + h < E.cnt ? (e[h] & 0xffu) + ne[h] : 0u;
+      }
+      bits = direct ? bits : gb;
     }
     tb[t * kBlock + tid] = (uint16_t)bits;
     // chunk = 4 consecutive threads (128 symbols)
@@ -1268,22 +1365,51 @@ __global__ __launch_bounds__(kBlock) void k_enc_pack(CJob one, const CJob *__res
       atomicOr(&words[w + 1], (uint32_t)v);
       o += pl;
     };
+    // direct symbols only (residual + 512 in 1..1023, no extra bits): the
+    // table entry is the whole pattern
+    bool direct = false;
+    if (E.fast) {
+      u16x2_t mx = (u16x2_t)(0);
+      const u32x4_t qs[4] = {E.q0, E.q1, E.q2, E.q3};
+#pragma unroll
+      for (int v = 0; v < 4; v++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          const uint32_t w = qs[v][i];  // copied out: see direct_bits
+          mx = __builtin_elementwise_max(mx, __builtin_bit_cast(u16x2_t, w) + (u16x2_t)(511));
+        }
+      direct = mx.x < 1023 && mx.y < 1023;
+    }
+    if (!__builtin_amdgcn_ballot_w64(!direct)) {
+      const u32x4_t qs[4] = {E.q0, E.q1, E.q2, E.q3};
+#pragma unroll
+      for (int v = 0; v < 4; v++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          const uint32_t w = qs[v][i];  // copied out: see direct_bits
+          const u16x2_t t = __builtin_bit_cast(u16x2_t, w) + (u16x2_t)(512);
+          const uint32_t e0 = sct[t.x & 1023], e1 = sct[t.y & 1023];
+          put(e0 >> 8, e0 & 0xffu);
+          put(e1 >> 8, e1 & 0xffu);
+        }
+    } else {
 #pragma unroll 1
-    for (int v = 0; v < 4; v++) {
-      int32_t c[8];
-      E.load8(v, c);
-      uint32_t sy[8], ne[8], ev[8], e[8];
+      for (int v = 0; v < 4; v++) {
+        int32_t c[8];
+        E.load8(v, c);
+        uint32_t sy[8], ne[8], ev[8], e[8];
 #pragma unroll
-      for (int h = 0; h < 8; h++) sy[h] = sym_ne_ev(c[h], &ne[h], &ev[h]);
+        for (int h = 0; h < 8; h++) sy[h] = sym_ne_ev(c[h], &ne[h], &ev[h]);
 #pragma unroll
-      for (int h = 0; h < 8; h++) e[h] = sct[sy[h]];
-      if (E.fast) {
+        for (int h = 0; h < 8; h++) e[h] = sct[sy[h]];
+        if (E.fast) {
 #pragma unroll
-        for (int h = 0; h < 8; h++) put(((e[h] >> 8) << ne[h]) | ev[h], (e[h] & 0xffu) + ne[h]);
-      } else {
+          for (int h = 0; h < 8; h++) put(((e[h] >> 8) << ne[h]) | ev[h], (e[h] & 0xffu) + ne[h]);
+        } else {
 #pragma unroll
-        for (int h = 0; h < 8; h++)
-          if (8 * v + h < E.cnt) put(((e[h] >> 8) << ne[h]) | ev[h], (e[h] & 0xffu) + ne[h]);
+          for (int h = 0; h < 8; h++)
+            if (8 * v + h < E.cnt) put(((e[h] >> 8) << ne[h]) | ev[h], (e[h] & 0xffu) + ne[h]);
+        }
       }
     }
     __syncthreads();
