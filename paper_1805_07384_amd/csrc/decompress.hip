@@ -957,6 +957,10 @@ __global__ __launch_bounds__(kBlock) void k_rec_full(Plan P, const uint8_t *__re
   constexpr int RW = sizeof(T) / 4;
   __shared__ uint32_t lds_m[2 * kBlock];
   __shared__ __align__(16) uint32_t lds_t[4 * 16 * kSegWD];
+  // halo rows of the tile (3D: Fz rows by y, then Fy + Gx rows by z; 2D: the
+  // Fy row), 36-word row stride so that 16 lanes reading 16 rows hit
+  // distinct banks
+  __shared__ __align__(16) uint32_t s_face[2 * 16 * kSegWD];
   __shared__ uint32_t scr[8];
   __shared__ uint32_t s_bad;
   if (dp->corrupt) return;
@@ -964,46 +968,59 @@ __global__ __launch_bounds__(kBlock) void k_rec_full(Plan P, const uint8_t *__re
   const uint64_t t = blockIdx.x;
   const TileGeo g = tile_geo(P, t);
   if (g.nt != (uint32_t)kTilePts) return;  // uniform: ragged tiles elsewhere
+  const RowMap<NDIM> m(tid);
+  typedef dgptr_t<du32x4_t> g4;
+  // the tile's halo data is read first, so that its latency overlaps the
+  // residual loads; it is parked in LDS before the prefix sums
+  du32x4_t fa = {0u, 0u, 0u, 0u};
+  int fslot = -1;  // s_face word of fa
+  uint32_t c = 0;
+  if (GLOBAL) {
+    if (NDIM == 3) {
+      if (tid < 128) {
+        fa = ((g4)(A.fz + t * FZ))[tid];  // Fz[y][4 (tid % 8) ..]
+        fslot = (tid >> 3) * kSegWD + 4 * (tid & 7);
+      } else {
+        const int k = tid - 128;  // Fy[z][4 (k % 8) ..] + Gx[4 (k % 8) ..]
+        fa = ((g4)(A.fy + t * FY))[k] + ((g4)(A.gx + t * TX))[k & 7];
+        fslot = (16 + (k >> 3)) * kSegWD + 4 * (k & 7);
+      }
+    } else if (NDIM == 2 && tid < 32) {
+      fa = ((g4)(A.fy + t * FY))[tid];  // Fy[4 tid ..]: segment tid / 8
+      fslot = (tid >> 3) * kSegWD + 4 * (tid & 7);
+    }
+    c = ((dgptr_t<uint32_t>)A.fx)[t * FX + (NDIM == 3 ? m.z * TY + m.y : NDIM == 2 ? m.y : 0)];
+    if (NDIM >= 2) c += ((dgptr_t<uint32_t>)A.gz)[t * TZ + m.z];
+    if (NDIM == 3) c += ((dgptr_t<uint32_t>)A.gy)[t * TY + m.y] + ((dgptr_t<uint32_t>)A.tt)[t];
+  }
   const uint64_t *teo = reinterpret_cast<const uint64_t *>(blob + P.off_teo);
   const uint64_t e0 = teo[t], e1 = teo[t + 1];
   if (e0 > e1 || e1 > A.n_exc) return;  // reported by the decode kernel
   const uint32_t *exc = reinterpret_cast<const uint32_t *>(blob + P.off_exc);
   if (tid == 0) s_bad = 0;
   __syncthreads();
-  const RowMap<NDIM> m(tid);
   uint32_t r[32];
   const SegExc X = load_segment<NDIM, RW>(g, codes, exc, e0, e1, r, lds_m, scr, &s_bad);
-  tile_prefix<NDIM>(r, lds_t);
+  if (fslot >= 0) *reinterpret_cast<du32x4_t *>(s_face + fslot) = fa;
+  tile_prefix<NDIM>(r, lds_t);  // its barrier also publishes s_face
   if (GLOBAL) {
     // q = L + A[y][x] + B[z][x] + C[z][y] (the halo terms)
-    typedef dgptr_t<du32x4_t> g4;
-    if (NDIM == 3) {
-      g4 ha = (g4)(A.fz + t * FZ + m.y * TX);
-#pragma unroll
-      for (int k = 0; k < 8; k++) {
-        const du32x4_t a = ha[k];
-        r[4 * k] += a.x; r[4 * k + 1] += a.y; r[4 * k + 2] += a.z; r[4 * k + 3] += a.w;
-      }
-    }
     if (NDIM >= 2) {
-      g4 hb = (g4)(A.fy + t * FY + (NDIM == 3 ? m.z * TX : 32 * m.sg));
+      const uint32_t *ra = s_face + (NDIM == 3 ? m.y : m.sg) * kSegWD;
 #pragma unroll
       for (int k = 0; k < 8; k++) {
-        const du32x4_t a = hb[k];
+        const du32x4_t a = reinterpret_cast<const du32x4_t *>(ra)[k];
         r[4 * k] += a.x; r[4 * k + 1] += a.y; r[4 * k + 2] += a.z; r[4 * k + 3] += a.w;
       }
     }
     if (NDIM == 3) {
-      g4 hg = (g4)(A.gx + t * TX);
+      const uint32_t *rb = s_face + (16 + m.z) * kSegWD;
 #pragma unroll
       for (int k = 0; k < 8; k++) {
-        const du32x4_t a = hg[k];
+        const du32x4_t a = reinterpret_cast<const du32x4_t *>(rb)[k];
         r[4 * k] += a.x; r[4 * k + 1] += a.y; r[4 * k + 2] += a.z; r[4 * k + 3] += a.w;
       }
     }
-    uint32_t c = ((dgptr_t<uint32_t>)A.fx)[t * FX + (NDIM == 3 ? m.z * TY + m.y : NDIM == 2 ? m.y : 0)];
-    if (NDIM >= 2) c += ((dgptr_t<uint32_t>)A.gz)[t * TZ + m.z];
-    if (NDIM == 3) c += ((dgptr_t<uint32_t>)A.gy)[t * TY + m.y] + ((dgptr_t<uint32_t>)A.tt)[t];
 #pragma unroll
     for (int j = 0; j < 32; j++) r[j] += c;
   }
