@@ -62,22 +62,32 @@ hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// a1: range reduction.  Each block reduces a grid-stride share, the last
-// block to finish combines the partials and derives the error bound.
+// a1: range reduction.  Each block reduces a grid-stride share into a
+// partial; one block per field combines the partials and derives the error
+// bound.  (No block waits on another and no atomics: a counter on one
+// address serializes every block that reaches it.)
+typedef float rf32x4_t __attribute__((ext_vector_type(4)));
+typedef double rf64x2_t __attribute__((ext_vector_type(2)));
 template <typename T> struct VecOf;
-template <> struct VecOf<float> { using V = float4; static constexpr int W = 4; };
-template <> struct VecOf<double> { using V = double2; static constexpr int W = 2; };
+template <> struct VecOf<float> { using V = rf32x4_t; static constexpr int W = 4; };
+template <> struct VecOf<double> { using V = rf64x2_t; static constexpr int W = 2; };
 
 __device__ inline bool finite_f(float v) { return (__float_as_uint(v) & 0x7f800000u) != 0x7f800000u; }
 __device__ inline bool finite_f(double v) {
   return ((unsigned long long)__double_as_longlong(v) & 0x7ff0000000000000ull) != 0x7ff0000000000000ull;
 }
 
-template <typename T>
-__device__ inline void acc_range(T v, T &mn, T &mx, uint32_t &bad) {
-  if (!finite_f(v)) { bad++; return; }
-  mn = v < mn ? v : mn;
-  mx = v > mx ? v : mx;
+// Branch-free: a non-finite value is counted (the field is then rejected,
+// so what min / max make of it does not matter).
+__device__ inline void acc_range(float v, float &mn, float &mx, uint32_t &bad) {
+  bad += finite_f(v) ? 0u : 1u;
+  mn = __builtin_fminf(mn, v);
+  mx = __builtin_fmaxf(mx, v);
+}
+__device__ inline void acc_range(double v, double &mn, double &mx, uint32_t &bad) {
+  bad += finite_f(v) ? 0u : 1u;
+  mn = __builtin_fmin(mn, v);
+  mx = __builtin_fmax(mx, v);
 }
 
 template <typename T>
@@ -85,9 +95,10 @@ __global__ __launch_bounds__(kBlock) void k_range(CJob one, const CJob *__restri
   const CJob J = select_job(one, jobs);
   const T *__restrict__ x = static_cast<const T *>(J.x);
   const Plan P = J.P;
-  DevParams *__restrict__ dp = J.W.P;
   uint64_t *__restrict__ part = static_cast<uint64_t *>(J.W.range_part);
   using V = typename VecOf<T>::V;
+  typedef __attribute__((address_space(1))) const V gV;
+  typedef __attribute__((address_space(1))) const T gT;
   constexpr int W = VecOf<T>::W;
   const uint64_t n = P.n;
   T mn = (T)INFINITY, mx = (T)-INFINITY;
@@ -98,88 +109,85 @@ __global__ __launch_bounds__(kBlock) void k_range(CJob one, const CJob *__restri
   const uint64_t nvec = (n - head) / W;
   const uint64_t gtid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   const uint64_t gsz = (uint64_t)gridDim.x * blockDim.x;
-  const V *xv = reinterpret_cast<const V *>(x + head);
+  gV *xv = (gV *)(x + head);
   uint64_t i = gtid;
   for (; i + 3 * gsz < nvec; i += 4 * gsz) {
-    V a = xv[i], b = xv[i + gsz], c = xv[i + 2 * gsz], d = xv[i + 3 * gsz];
-    const T *pa = reinterpret_cast<const T *>(&a);
-    const T *pb = reinterpret_cast<const T *>(&b);
-    const T *pc = reinterpret_cast<const T *>(&c);
-    const T *pd = reinterpret_cast<const T *>(&d);
+    const V a = xv[i], b = xv[i + gsz], c = xv[i + 2 * gsz], d = xv[i + 3 * gsz];
 #pragma unroll
     for (int k = 0; k < W; k++) {
-      acc_range(pa[k], mn, mx, bad);
-      acc_range(pb[k], mn, mx, bad);
-      acc_range(pc[k], mn, mx, bad);
-      acc_range(pd[k], mn, mx, bad);
+      acc_range((T)a[k], mn, mx, bad);
+      acc_range((T)b[k], mn, mx, bad);
+      acc_range((T)c[k], mn, mx, bad);
+      acc_range((T)d[k], mn, mx, bad);
     }
   }
   for (; i < nvec; i += gsz) {
-    V a = xv[i];
-    const T *pa = reinterpret_cast<const T *>(&a);
+    const V a = xv[i];
 #pragma unroll
-    for (int k = 0; k < W; k++) acc_range(pa[k], mn, mx, bad);
+    for (int k = 0; k < W; k++) acc_range((T)a[k], mn, mx, bad);
   }
-  if (gtid < head) acc_range(x[gtid], mn, mx, bad);
+  if (gtid < head) acc_range(((gT *)x)[gtid], mn, mx, bad);
   const uint64_t tail0 = head + nvec * W;
-  if (gtid < n - tail0) acc_range(x[tail0 + gtid], mn, mx, bad);
+  if (gtid < n - tail0) acc_range(((gT *)x)[tail0 + gtid], mn, mx, bad);
 
-  // block reduction
+  // block partial
   double dmn = (double)mn, dmx = (double)mx;
   uint64_t dbad = bad;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     double a = __shfl_xor(dmn, o, 64), b = __shfl_xor(dmx, o, 64);
-    dmn = a < dmn ? a : dmn;
-    dmx = b > dmx ? b : dmx;
+    dmn = __builtin_fmin(dmn, a);
+    dmx = __builtin_fmax(dmx, b);
     dbad += __shfl_xor(dbad, o, 64);
   }
   __shared__ double smn[kBlock / 64], smx[kBlock / 64];
   __shared__ uint64_t sbad[kBlock / 64];
-  __shared__ int is_last;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (lane == 0) { smn[wv] = dmn; smx[wv] = dmx; sbad[wv] = dbad; }
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < kBlock / 64; w++) {
-      dmn = smn[w] < dmn ? smn[w] : dmn;
-      dmx = smx[w] > dmx ? smx[w] : dmx;
+      dmn = __builtin_fmin(dmn, smn[w]);
+      dmx = __builtin_fmax(dmx, smx[w]);
       dbad += sbad[w];
     }
-    st_agent(&part[3 * blockIdx.x + 0], (uint64_t)__double_as_longlong(dmn));
-    st_agent(&part[3 * blockIdx.x + 1], (uint64_t)__double_as_longlong(dmx));
-    st_agent(&part[3 * blockIdx.x + 2], dbad);
-    __threadfence();
-    const uint32_t prev = atomicAdd(&dp->range_done, 1u);
-    is_last = (prev == gridDim.x - 1);
+    part[3 * blockIdx.x + 0] = (uint64_t)__double_as_longlong(dmn);
+    part[3 * blockIdx.x + 1] = (uint64_t)__double_as_longlong(dmx);
+    part[3 * blockIdx.x + 2] = dbad;
   }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  // last block: combine partials
+}
+
+// one block per field: combine the nb partials, derive eb (Eq. 7) and the
+// quantizer constants
+__global__ __launch_bounds__(kBlock) void k_range_final(CJob one, const CJob *__restrict__ jobs,
+                                                        uint32_t nb) {
+  const CJob J = select_job(one, jobs);
+  const Plan P = J.P;
+  DevParams *__restrict__ dp = J.W.P;
+  const uint64_t *__restrict__ part = static_cast<const uint64_t *>(J.W.range_part);
   double bmn = INFINITY, bmx = -INFINITY;
   uint64_t bbad = 0;
-  for (uint32_t b = threadIdx.x; b < gridDim.x; b += blockDim.x) {
-    double a = __longlong_as_double((long long)ld_agent(&part[3 * b + 0]));
-    double c = __longlong_as_double((long long)ld_agent(&part[3 * b + 1]));
-    bmn = a < bmn ? a : bmn;
-    bmx = c > bmx ? c : bmx;
-    bbad += ld_agent(&part[3 * b + 2]);
+  for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) {
+    bmn = __builtin_fmin(bmn, __longlong_as_double((long long)part[3 * b + 0]));
+    bmx = __builtin_fmax(bmx, __longlong_as_double((long long)part[3 * b + 1]));
+    bbad += part[3 * b + 2];
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     double a = __shfl_xor(bmn, o, 64), c = __shfl_xor(bmx, o, 64);
-    bmn = a < bmn ? a : bmn;
-    bmx = c > bmx ? c : bmx;
+    bmn = __builtin_fmin(bmn, a);
+    bmx = __builtin_fmax(bmx, c);
     bbad += __shfl_xor(bbad, o, 64);
   }
-  __syncthreads();
+  __shared__ double smn[kBlock / 64], smx[kBlock / 64];
+  __shared__ uint64_t sbad[kBlock / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (lane == 0) { smn[wv] = bmn; smx[wv] = bmx; sbad[wv] = bbad; }
   __syncthreads();
   if (threadIdx.x != 0) return;
   for (int w = 1; w < kBlock / 64; w++) {
-    bmn = smn[w] < bmn ? smn[w] : bmn;
-    bmx = smx[w] > bmx ? smx[w] : bmx;
+    bmn = __builtin_fmin(bmn, smn[w]);
+    bmx = __builtin_fmax(bmx, smx[w]);
     bbad += sbad[w];
   }
   dp->nonfinite = bbad;
@@ -1519,16 +1527,33 @@ __device__ inline void checksum_body(const uint8_t *__restrict__ blob, uint64_t 
   // 16-byte loads when the blob allows them (it is only required to be 8-aligned)
   const uint64_t n4 = (uintptr_t)blob % 16 == 0 ? nw / 4 : 0;
   const uint64_t gsz = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < n4; q += gsz) {
-    const uint4 v = w4[q];
+  auto quad = [&](const uint4 v, uint64_t q) {
     const uint64_t j = 4 * q;
     s += mix64(v.x, j) + mix64(v.y, j + 1);
     s += mix64((j + 2 == 50) ? 0u : v.z, j + 2) + mix64((j + 3 == 51) ? 0u : v.w, j + 3);
+  };
+  uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  for (; q + 3 * gsz < n4; q += 4 * gsz) {  // four loads in flight per thread
+    const uint4 a = w4[q], b = w4[q + gsz], c = w4[q + 2 * gsz], d = w4[q + 3 * gsz];
+    quad(a, q);
+    quad(b, q + gsz);
+    quad(c, q + 2 * gsz);
+    quad(d, q + 3 * gsz);
   }
+  for (; q < n4; q += gsz) quad(w4[q], q);
   for (uint64_t j = n4 * 4 + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < nw; j += gsz)
     s += mix64((j == 50 || j == 51) ? 0u : w[j], j);
+  // one atomic per block: atomics on one address are serialized, so their
+  // count, not the memory traffic, would set the kernel's time
+  __shared__ uint64_t part[kBlock / 64];
   s = wave_sum_u64(s);
-  if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long *)&dp->checksum, (unsigned long long)s);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t b = 0;
+    for (int i = 0; i < kBlock / 64; i++) b += part[i];
+    if (b) atomicAdd((unsigned long long *)&dp->checksum, (unsigned long long)b);
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_checksum(const uint8_t *__restrict__ blob,
@@ -1538,8 +1563,8 @@ __global__ __launch_bounds__(kBlock) void k_checksum(const uint8_t *__restrict__
 }
 
 hipError_t launch_checksum(const uint8_t *blob, uint64_t bytes, DevParams *dp, hipStream_t s) {
-  const uint64_t cw = bytes / 4 / kBlock + 1;
-  const uint32_t cgrid = (uint32_t)(cw < 1024 ? cw : 1024);
+  const uint64_t cw = bytes / 16 / kBlock + 1;
+  const uint32_t cgrid = (uint32_t)(cw < 256 ? cw : 256);
   hipLaunchKernelGGL(k_checksum, dim3(cgrid), dim3(kBlock), 0, s, blob, bytes, dp);
   return hipGetLastError();
 }
@@ -1565,8 +1590,8 @@ LaunchCfg default_launch_cfg(const Plan &maxP) {
   c.range_blocks = (uint32_t)(want < (uint64_t)kRangeBlocks ? want : kRangeBlocks);
   c.quant_grid = (uint32_t)(maxP.n_tiles < 2048 ? maxP.n_tiles : 2048);
   c.encode_grid = c.quant_grid;
-  const uint64_t cw = maxP.capacity / 4 / kBlock + 1;
-  c.csum_blocks = (uint32_t)(cw < 1024 ? cw : 1024);
+  const uint64_t cw = maxP.capacity / 16 / kBlock + 1;
+  c.csum_blocks = (uint32_t)(cw < 256 ? cw : 256);
   return c;
 }
 
@@ -1602,6 +1627,7 @@ template <typename T>
 static void launch_compress_t(const CJob &one, const CJob *jobs, int nf, const Plan &maxP,
                               const LaunchCfg &cfg, hipStream_t s, Timer *tm) {
   hipLaunchKernelGGL(k_range<T>, dim3(cfg.range_blocks, nf), dim3(kBlock), 0, s, one, jobs);
+  hipLaunchKernelGGL(k_range_final, dim3(1, nf), dim3(kBlock), 0, s, one, jobs, cfg.range_blocks);
   tm->mark(s, "range");
   if (maxP.ndim == 1) launch_quant<T, 1>(one, jobs, nf, maxP, cfg, s, tm);
   else if (maxP.ndim == 2) launch_quant<T, 2>(one, jobs, nf, maxP, cfg, s, tm);

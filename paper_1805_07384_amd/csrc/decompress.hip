@@ -61,7 +61,6 @@ __global__ __launch_bounds__(1024) void k_dec_tables(Plan P, const uint8_t *__re
                                                      uint32_t *__restrict__ ltab,
                                                      uint16_t *__restrict__ sorted) {
   __shared__ uint8_t lens[kNSym];
-  __shared__ uint32_t code[kNSym];
   __shared__ uint32_t lcount[kLMax + 2], lfirst[kLMax + 2], lbase[kLMax + 2];
   __shared__ unsigned long long kraft;
   __shared__ uint32_t bad;
@@ -80,15 +79,22 @@ __global__ __launch_bounds__(1024) void k_dec_tables(Plan P, const uint8_t *__re
     if (tid == 0) atomicOr(&dp->corrupt, 1u);
     return;
   }
-  canonical_from_lengths(lens, code, lcount, lfirst, lbase, sorted, wcnt);
-  for (int i = tid; i < (1 << kLut); i += blockDim.x) lut[i] = kLutLong;
+  canonical_from_lengths(lens, nullptr, lcount, lfirst, lbase, sorted, wcnt);
   __syncthreads();
-  for (int s = tid; s < kNSym; s += blockDim.x) {
-    const int l = lens[s];
-    if (l == 0 || l > kLut) continue;
-    const uint32_t lo = code[s] << (kLut - l), hi = (code[s] + 1) << (kLut - l);
-    const uint32_t e = (s == 0 ? kSymOutlierTag : (uint32_t)s) << 5 | (uint32_t)l;
-    for (uint32_t i = lo; i < hi; i++) lut[i] = (uint16_t)e;
+  // one thread per table entry: the code of length l <= kLut that is a
+  // prefix of the entry's bits, if any (canonical codes of one length are
+  // consecutive from lfirst[l])
+  for (int i = tid; i < (1 << kLut); i += blockDim.x) {
+    uint32_t e = kLutLong;
+    for (int l = 1; l <= kLut; l++) {
+      const uint32_t cp = (uint32_t)i >> (kLut - l);
+      if (cp >= lfirst[l] && cp - lfirst[l] < lcount[l]) {
+        const uint32_t s = sorted[lbase[l] + cp - lfirst[l]];
+        e = (s == 0 ? kSymOutlierTag : s) << 5 | (uint32_t)l;
+        break;
+      }
+    }
+    lut[i] = (uint16_t)e;
   }
   if (tid <= kLMax) {
     ltab[tid] = lfirst[tid];
