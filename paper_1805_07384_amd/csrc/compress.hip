@@ -798,7 +798,7 @@ __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restri
   if (RECORDS) return;
   __syncthreads();
   for (int s = tid; s < kNSym; s += kBlock)
-    if (hist[s]) atomicAdd(&hist_g[s], hist[s]);
+    if (hist[s]) atomicAdd(&hist_g[(blockIdx.x % kHistCopies) * kNSym + s], hist[s]);
   my_out = wave_sum_u64(my_out);
   my_pat = wave_sum_u64(my_pat);
   if ((tid & 63) == 0) {
@@ -926,7 +926,7 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CJob one, const CJob *_
   const CJob J = select_job(one, jobs);
   const Plan P = J.P;
   DevParams *__restrict__ dp = J.W.P;
-  const uint32_t *__restrict__ hist_g = J.W.hist;
+  uint32_t *__restrict__ hist_g = J.W.hist;
   uint8_t *__restrict__ len_out = J.W.code_len;
   uint32_t *__restrict__ code_out = J.W.code;
   uint8_t *__restrict__ blob = J.blob;
@@ -947,7 +947,12 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CJob one, const CJob *_
   if (dp->status != 0 || dp->is_const) return;
 
   for (int i = tid; i < 2048; i += kCbThreads) {
-    const uint32_t c = i < kNSym ? hist_g[i] : 0u;
+    uint32_t c = 0;
+    if (i < kNSym) {
+#pragma unroll
+      for (int k = 0; k < kHistCopies; k++) c += hist_g[k * kNSym + i];
+      hist_g[i] = c;  // copy 0 keeps the total
+    }
     key[i] = c ? (((uint64_t)c << 11) | (uint64_t)i) : ~0ull;
   }
   for (int s = tid; s < kNSym; s += kCbThreads) lens[s] = 0;

@@ -33,6 +33,10 @@ constexpr uint32_t kTagPatch = 0x80000000u;
 constexpr uint16_t kFlagConst = 1, kFlagTile = 2;
 constexpr int kBlock = 256;
 constexpr int kRangeBlocks = 1024;
+// The compressor's histogram is kept in this many copies (workgroup b adds
+// into copy b % kHistCopies), so that the hot bins of many workgroups do not
+// all contend for one address; the codebook kernel sums them into copy 0.
+constexpr int kHistCopies = 16;
 constexpr int kVerifyBlocks = 1024;
 
 // header byte offsets

@@ -112,7 +112,7 @@ inline CompressLayout compress_layout(const Plan &P) {
   L.off_part = o;
   o = align256(o + 3 * 8 * (uint64_t)kRangeBlocks);
   L.off_hist = o;
-  o = align256(o + 4 * (uint64_t)kNSym);
+  o = align256(o + 4 * (uint64_t)kNSym * kHistCopies);
   L.off_len = o;
   o = align256(o + (uint64_t)kNSym);
   L.off_code = o;
