@@ -810,6 +810,52 @@ __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restri
 // Exclusive scan of the per-tile record counts (one workgroup): tile offsets
 // into the blob's tile_exc_offset section and the workspace, the total.
 constexpr int kScanThreads = 1024;
+// Exclusive scan of v[0 .. n) by one workgroup of kScanThreads.  Wave w owns
+// the contiguous range of R rounds of 64 elements from w R 64 (R = ceil(n /
+// kScanThreads)); a round is read by the 64 lanes at once, four rounds'
+// loads in flight.  Pass 1 sums each wave's range, one block scan of the 16
+// wave sums follows, pass 2 scans the rounds in order within the wave and
+// calls emit(k, exclusive prefix of k) (v[k] is read before emit, so emit may
+// overwrite it).  Returns the total.
+template <typename In, typename Emit>
+__device__ inline uint64_t block_seg_scan(const In *__restrict__ v, uint64_t n, Emit emit) {
+  constexpr int NW = kScanThreads / 64;
+  __shared__ uint64_t wsum[NW];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const uint64_t R = (n + kScanThreads - 1) / kScanThreads;
+  const uint64_t w0 = (uint64_t)wv * R * 64 + lane;
+  auto ld = [&](uint64_t r) -> uint64_t {
+    const uint64_t k = w0 + 64 * r;
+    return r < R && k < n ? (uint64_t)v[k] : 0ull;
+  };
+  uint64_t part = 0;
+  for (uint64_t r = 0; r < R; r += 4) {
+    const uint64_t x0 = ld(r), x1 = ld(r + 1), x2 = ld(r + 2), x3 = ld(r + 3);
+    part += x0 + x1 + x2 + x3;
+  }
+  part = wave_sum_u64(part);
+  if (lane == 0) wsum[wv] = part;
+  __syncthreads();
+  uint64_t carry = 0, tot = 0;
+  for (int w = 0; w < NW; w++) {
+    carry += w < wv ? wsum[w] : 0;
+    tot += wsum[w];
+  }
+  for (uint64_t r = 0; r < R; r += 4) {
+    uint64_t x[4];
+#pragma unroll
+    for (int h = 0; h < 4; h++) x[h] = ld(r + h);
+#pragma unroll
+    for (int h = 0; h < 4; h++) {
+      const uint64_t inc = wave_incl_scan_u64(x[h]);
+      const uint64_t k = w0 + 64 * (r + h);
+      if (r + h < R && k < n) emit(k, carry + inc - x[h]);
+      carry += __shfl(inc, 63, 64);
+    }
+  }
+  return tot;
+}
+
 __global__ __launch_bounds__(kScanThreads) void k_exc_scan(CJob one, const CJob *__restrict__ jobs) {
   const CJob J = select_job(one, jobs);
   const Plan P = J.P;
@@ -817,34 +863,17 @@ __global__ __launch_bounds__(kScanThreads) void k_exc_scan(CJob one, const CJob 
   const uint32_t *__restrict__ cnt = J.W.exc_cnt;
   uint64_t *__restrict__ off = J.W.exc_off;
   uint8_t *__restrict__ blob = J.blob;
-  __shared__ uint64_t wsum[kScanThreads / 64];
-  __shared__ uint64_t carry;
   if (dp->status != 0 || dp->is_const) return;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (tid == 0) carry = 0;
-  __syncthreads();
   const uint64_t nt = P.n_tiles;
-  for (uint64_t base = 0; base < nt; base += kScanThreads) {
-    const uint64_t t = base + tid;
-    const uint64_t v = t < nt ? cnt[t] : 0;
-    const uint64_t inc = wave_incl_scan_u64(v);
-    if (lane == 63) wsum[wv] = inc;
-    __syncthreads();
-    uint64_t pre = carry;
-    for (int w = 0; w < wv; w++) pre += wsum[w];
-    const uint64_t ex0 = pre + inc - v;
-    if (t < nt) {
-      off[t] = ex0;
-      const uint64_t o = P.off_teo + 8 * t;
-      if (o + 8 <= P.capacity) *reinterpret_cast<uint64_t *>(blob + o) = ex0;
-      else atomicOr(&dp->overflow, 1u);
-    }
-    __syncthreads();
-    if (tid == kScanThreads - 1) carry = ex0 + v;
-    __syncthreads();
-  }
-  if (tid == 0) {
-    const uint64_t tot = carry;
+  uint32_t ovf = 0;
+  const uint64_t tot = block_seg_scan(cnt, nt, [&](uint64_t t, uint64_t ex) {
+    off[t] = ex;
+    const uint64_t o = P.off_teo + 8 * t;
+    if (o + 8 <= P.capacity) *reinterpret_cast<uint64_t *>(blob + o) = ex;
+    else ovf = 1;
+  });
+  if (ovf) atomicOr(&dp->overflow, 1u);
+  if (threadIdx.x == 0) {
     dp->n_exc = tot;
     dp->off_words = align8(P.off_exc + 8 * tot);
     const uint64_t o = P.off_teo + 8 * nt;
@@ -1308,34 +1337,17 @@ __global__ __launch_bounds__(kScanThreads) void k_enc_scan(CJob one, const CJob 
   DevParams *__restrict__ dp = J.W.P;
   uint64_t *__restrict__ tw = J.W.word_state;
   uint8_t *__restrict__ blob = J.blob;
-  __shared__ uint64_t wsum[kScanThreads / 64];
-  __shared__ uint64_t carry;
   if (dp->status != 0 || dp->is_const) return;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (tid == 0) carry = 0;
-  __syncthreads();
   const uint64_t nt = P.n_tiles;
-  for (uint64_t base = 0; base < nt; base += kScanThreads) {
-    const uint64_t t = base + tid;
-    const uint64_t v = t < nt ? tw[t] : 0;
-    const uint64_t inc = wave_incl_scan_u64(v);
-    if (lane == 63) wsum[wv] = inc;
-    __syncthreads();
-    uint64_t pre = carry;
-    for (int w = 0; w < wv; w++) pre += wsum[w];
-    const uint64_t ex0 = pre + inc - v;
-    if (t < nt) {
-      tw[t] = ex0;
-      const uint64_t o = P.off_two + 8 * t;
-      if (o + 8 <= P.capacity) *reinterpret_cast<uint64_t *>(blob + o) = ex0;
-      else atomicOr(&dp->overflow, 1u);
-    }
-    __syncthreads();
-    if (tid == kScanThreads - 1) carry = ex0 + v;
-    __syncthreads();
-  }
-  if (tid == 0) {
-    const uint64_t tot = carry;
+  uint32_t ovf = 0;
+  const uint64_t tot = block_seg_scan(tw, nt, [&](uint64_t t, uint64_t ex) {
+    tw[t] = ex;
+    const uint64_t o = P.off_two + 8 * t;
+    if (o + 8 <= P.capacity) *reinterpret_cast<uint64_t *>(blob + o) = ex;
+    else ovf = 1;
+  });
+  if (ovf) atomicOr(&dp->overflow, 1u);
+  if (threadIdx.x == 0) {
     dp->n_words = tot;
     const uint64_t o = P.off_two + 8 * nt;
     if (o + 8 <= P.capacity) *reinterpret_cast<uint64_t *>(blob + o) = tot;

@@ -17,6 +17,8 @@
 // result is exact.  TILE domain: decode and rec with zero halo.
 #include <math.h>
 
+#include <initializer_list>
+
 #include "fpsz_internal.h"
 
 namespace fpsz {
@@ -1155,6 +1157,66 @@ static void excl_axis(uint32_t *a, uint64_t outer, uint64_t len, uint64_t inner,
                      nseg > 1 ? (const uint32_t *)tmp : nullptr);
 }
 
+// Independent exclusive scans along axes of at most kSeg elements, all in one
+// launch: thread g belongs to the scan whose range of (outer, inner) columns
+// holds it.  Scans of the same array along different axes are issued in
+// separate sets (they commute, but each needs the other's input complete).
+struct ScanJob {
+  uint32_t *a;
+  uint64_t outer, len, inner, first;  // first: index of the job's first column
+};
+constexpr int kMaxScanJobs = 8;
+struct ScanSet {
+  ScanJob j[kMaxScanJobs];
+  int n;
+  uint64_t total;
+};
+
+__global__ __launch_bounds__(kBlock) void k_excl_set(ScanSet S) {
+  for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < S.total;
+       g += (uint64_t)gridDim.x * blockDim.x) {
+    int q = 0;
+    for (int k = 1; k < S.n; k++) q = g >= S.j[k].first ? k : q;
+    uint32_t *const a = S.j[q].a;
+    const uint64_t len = S.j[q].len, inner = S.j[q].inner, c = g - S.j[q].first;
+    const uint64_t i = c % inner, o = c / inner;
+    uint32_t *p = a + (o * len) * inner + i;
+    uint32_t v[kSeg];
+#pragma unroll
+    for (int k = 0; k < kSeg; k++) v[k] = (uint64_t)k < len ? p[k * inner] : 0u;
+    uint32_t run = 0;
+#pragma unroll
+    for (int k = 0; k < kSeg; k++) {
+      if ((uint64_t)k < len) p[k * inner] = run;
+      run += v[k];
+    }
+  }
+}
+
+// One set of independent scans: one launch when every axis is
+// at most kSeg long, else one excl_axis per scan.
+static void excl_set(std::initializer_list<ScanJob> jobs, uint32_t *tmp, hipStream_t s) {
+  ScanSet S;
+  S.n = 0;
+  S.total = 0;
+  bool short_axes = jobs.size() <= (size_t)kMaxScanJobs;
+  for (const ScanJob &j : jobs) short_axes = short_axes && j.len <= (uint64_t)kSeg;
+  if (!short_axes) {
+    for (const ScanJob &j : jobs) excl_axis(j.a, j.outer, j.len, j.inner, tmp, s);
+    return;
+  }
+  for (const ScanJob &j : jobs) {
+    if (j.outer == 0 || j.inner == 0 || j.len == 0) continue;
+    S.j[S.n] = j;
+    S.j[S.n].first = S.total;
+    S.total += j.outer * j.inner;
+    S.n++;
+  }
+  if (S.n == 0) return;
+  const uint64_t b = S.total / kBlock + 1;
+  hipLaunchKernelGGL(k_excl_set, dim3((uint32_t)(b < 65536 ? b : 65536)), dim3(kBlock), 0, s, S);
+}
+
 // ---------------------------------------------------------------------------
 __global__ void k_csum_check(const uint8_t *__restrict__ blob, DevParams *__restrict__ dp) {
   const uint64_t stored = *reinterpret_cast<const uint64_t *>(blob + H_CSUM);
@@ -1178,22 +1240,32 @@ static void launch_dec_t(const Plan &P, const uint8_t *blob, const DecodeArgs &A
     const uint64_t gz = P.gz, gy = P.gy, gx = P.gx;
     constexpr uint64_t TZ = G::TZ, TY = G::TY, TX = G::TX;
     constexpr uint64_t FZ = NDIM == 3 ? TY * TX : 1, FY = TZ * TX, FX = TZ * TY;
+    // exclusive scans of the faces along one tile axis each and of the edge
+    // vectors / totals over two or three tile axes (one axis per set)
     if (NDIM == 3) {
-      excl_axis(A.fz, 1, gz, gy * gx * FZ, tmp, s);                  // Fz along z tiles
-      excl_axis(A.gx, gz, gy, gx * TX, tmp, s);                      // Gx over (a, b)
-      excl_axis(A.gx, 1, gz, gy * gx * TX, tmp, s);
-      excl_axis(A.gy, gz * gy, gx, TY, tmp, s);                      // Gy over (a, c)
-      excl_axis(A.gy, 1, gz, gy * gx * TY, tmp, s);
-      excl_axis(A.tt, gz * gy, gx, 1, tmp, s);                       // T over (a, b, c)
-      excl_axis(A.tt, gz, gy, gx, tmp, s);
-      excl_axis(A.tt, 1, gz, gy * gx, tmp, s);
+      excl_set({{A.fz, 1, gz, gy * gx * FZ, 0},      // Fz along z tiles
+                {A.fy, gz, gy, gx * FY, 0},          // Fy along y tiles
+                {A.fx, gz * gy, gx, FX, 0},          // Fx along x tiles
+                {A.gx, gz, gy, gx * TX, 0},          // Gx over (a, b): b
+                {A.gy, gz * gy, gx, TY, 0},          // Gy over (a, c): c
+                {A.gz, gz * gy, gx, TZ, 0},          // Gz over (b, c): c
+                {A.tt, gz * gy, gx, 1, 0}},          // T over (a, b, c): c
+               tmp, s);
+      excl_set({{A.gx, 1, gz, gy * gx * TX, 0},      // Gx: a
+                {A.gy, 1, gz, gy * gx * TY, 0},      // Gy: a
+                {A.gz, gz, gy, gx * TZ, 0},          // Gz: b
+                {A.tt, gz, gy, gx, 0}},              // T: b
+               tmp, s);
+      excl_set({{A.tt, 1, gz, gy * gx, 0}}, tmp, s); // T: a
+    } else if (NDIM == 2) {
+      excl_set({{A.fy, gz, gy, gx * FY, 0},          // Fy along y tiles
+                {A.fx, gz * gy, gx, FX, 0},          // Fx along x tiles
+                {A.gz, gz * gy, gx, TZ, 0}},         // Gz over (b, c): c
+               tmp, s);
+      excl_set({{A.gz, gz, gy, gx * TZ, 0}}, tmp, s);  // Gz: b
+    } else {
+      excl_set({{A.fx, gz * gy, gx, FX, 0}}, tmp, s);  // Fx along x tiles
     }
-    if (NDIM >= 2) {
-      excl_axis(A.fy, gz, gy, gx * FY, tmp, s);                      // Fy along y tiles
-      excl_axis(A.gz, gz * gy, gx, TZ, tmp, s);                      // Gz over (b, c)
-      excl_axis(A.gz, gz, gy, gx * TZ, tmp, s);
-    }
-    excl_axis(A.fx, gz * gy, gx, FX, tmp, s);                        // Fx along x tiles
     tm->mark(s, "face_scan");
     hipLaunchKernelGGL((k_rec_full<T, NDIM, true>), grid, blk, 0, s, P, blob, A, dp, codes, out);
     if (ragged) hipLaunchKernelGGL((k_rec<T, NDIM, true>), grid, blk, 0, s, P, blob, A, dp, codes, out);
