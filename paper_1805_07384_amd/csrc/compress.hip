@@ -573,6 +573,7 @@ __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restri
   __shared__ uint32_t scr[8];
 
   if (dp->status != 0 || dp->is_const) return;
+  if (RECORDS && !dp->big_tiles) return;  // every tile's records fit its staging slot
   const int tid = threadIdx.x;
   const float rf = dp->r_f, e2f = dp->e2_f;
   const double r = dp->r, e2 = dp->e2, eb = dp->eb;
@@ -750,7 +751,10 @@ __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restri
     // recompute pass for tiles with more than kStage records)
     uint32_t tile_total;
     const uint32_t my_off = block_excl_scan_u32(nexc, scr, &tile_total);
-    if (!RECORDS && tid == 0) exc_cnt[t] = tile_total;
+    if (!RECORDS && tid == 0) {
+      exc_cnt[t] = tile_total;
+      if (tile_total > (uint32_t)kStage) atomicOr(&dp->big_tiles, 1u);  // rare
+    }
     const bool staged = tile_total <= (uint32_t)kStage;
     if (nexc && (RECORDS || staged)) {
       uint32_t e = my_off;

@@ -116,7 +116,7 @@ __host__ __device__ inline TileGeo tile_geo(const Plan &P, uint64_t t) {
 struct DevParams {
   uint32_t status;      // fpsz_status of the device-side pipeline
   uint32_t is_const;
-  uint32_t reserved0;   // unused
+  uint32_t big_tiles;   // some tile has more exception records than its staging slot
   uint32_t spin_fail;   // a bounded wait gave up (reported as FPSZ_E_DEVICE)
   uint32_t overflow;    // a blob write fell beyond the capacity
   uint32_t corrupt;     // decompress: inconsistency found
