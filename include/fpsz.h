@@ -145,6 +145,24 @@ fpsz_status fpsz_decompress(fpsz_ctx *ctx, const void *blob_dev, uint64_t blob_b
                             void *workspace_dev, uint64_t workspace_bytes, void *field_out_dev,
                             uint64_t out_bytes, void *stream);
 
+/* fpsz_decompress, and the Eq. 4 check of the reconstruction against the
+ * original in the same pass (Sec. V evaluates every compression by the PSNR
+ * it reaches): the statistics of each tile are taken while the tile is
+ * written, so field_out_dev is not read back.  vr and eb are the blob's.
+ *   orig_dev   device, the original field (n elements of the blob's dtype,
+ *              element-aligned); read only
+ *   out        host, receives the statistics (fpsz_verify's meaning; the
+ *              float64 sum runs over tiles in a fixed order, so repeated
+ *              calls return identical bits, which may differ from
+ *              fpsz_verify's in the last places)
+ * The workspace must hold fpsz_decompress_workspace_bytes for the blob's
+ * shape, also for a constant field.  Synchronizes `stream`.  Status: as
+ * fpsz_decompress; CAPACITY when the workspace is too small. */
+fpsz_status fpsz_decompress_verify(fpsz_ctx *ctx, const void *blob_dev, uint64_t blob_bytes,
+                                   void *workspace_dev, uint64_t workspace_bytes,
+                                   void *field_out_dev, uint64_t out_bytes, const void *orig_dev,
+                                   fpsz_stats *out, void *stream);
+
 /* Eq. 4 check of a reconstruction against the original (both device, n
  * elements of dtype).  vr and eb as reported by fpsz_compress.  The float64
  * reduction order is fixed, so repeated calls return identical bits.

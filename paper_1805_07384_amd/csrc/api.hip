@@ -241,6 +241,55 @@ fpsz_status fpsz_decompress(fpsz_ctx *ctx, const void *blob_dev, uint64_t blob_b
   return decompress_result(ctx, J, *ctx->host);
 }
 
+fpsz_status fpsz_decompress_verify(fpsz_ctx *ctx, const void *blob_dev, uint64_t blob_bytes,
+                                   void *workspace_dev, uint64_t workspace_bytes,
+                                   void *field_out_dev, uint64_t out_bytes, const void *orig_dev,
+                                   fpsz_stats *out, void *stream) {
+  if (!ctx) return FPSZ_E_INVALID_ARG;
+  ctx->err[0] = 0;
+  if (!blob_dev || !workspace_dev || !field_out_dev || !orig_dev || !out)
+    return fail(ctx, FPSZ_E_INVALID_ARG, "null pointer argument");
+  if (blob_bytes < kHdr || blob_bytes % 8)
+    return fail(ctx, FPSZ_E_CORRUPT, "blob size %llu", (unsigned long long)blob_bytes);
+  if ((uintptr_t)blob_dev % 8) return fail(ctx, FPSZ_E_INVALID_ARG, "blob must be 8-aligned");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, FPSZ_E_DEVICE, "hipSetDevice failed");
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t *hh = (uint8_t *)ctx->host;
+  hipError_t e = hipMemcpyAsync(hh, blob_dev, kHdr, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "header read");
+  uint8_t h[kHdr];
+  memcpy(h, hh, kHdr);
+  DJob J;
+  fpsz_status st = prepare_decompress(ctx, h, blob_dev, blob_bytes, workspace_dev, workspace_bytes,
+                                      field_out_dev, out_bytes, &J);
+  if (st != FPSZ_OK) return st;
+  if (!J.W.vpart)
+    return fail(ctx, FPSZ_E_CAPACITY, "workspace needs %llu bytes",
+                (unsigned long long)decompress_layout(J.P).total);
+  const size_t esz = J.P.dtype == FPSZ_F32 ? 4 : 8;
+  if ((uintptr_t)orig_dev % esz) return fail(ctx, FPSZ_E_INVALID_ARG, "original not element-aligned");
+  J.ref = orig_dev;
+  Timer *tm = timer_begin(ctx);
+  e = launch_decompress_job(J, s, tm);
+  if (e != hipSuccess) return hip_fail(ctx, e, "decompress launch");
+  e = hipMemcpyAsync(ctx->host, J.W.P, sizeof(DevParams), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "decompress");
+  timer_collect(ctx);
+  const DevParams D = *ctx->host;
+  st = decompress_result(ctx, J, D);
+  if (st != FPSZ_OK) return st;
+  out->sse = D.v_sse;
+  out->mse = D.v_sse / (double)J.P.n;
+  // Eq. 4: PSNR = -20 log10(NRMSE), NRMSE = sqrt(MSE) / vr
+  out->psnr = -20.0 * log10(sqrt(out->mse) / J.vr);
+  out->max_abs_err = D.v_max;
+  out->n_over_eb = D.v_over;
+  return FPSZ_OK;
+}
+
 fpsz_status fpsz_verify(fpsz_ctx *ctx, const void *orig_dev, const void *recon_dev, uint64_t n,
                         fpsz_dtype dtype, double vr, double eb, void *workspace_dev,
                         uint64_t workspace_bytes, fpsz_stats *out, void *stream) {

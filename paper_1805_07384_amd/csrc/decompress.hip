@@ -47,6 +47,53 @@ struct DecodeArgs {
   const uint16_t *sorted;
   // GLOBAL domain: per-tile faces and edge vectors, tile-major slots
   uint32_t *fz, *fy, *fx, *gx, *gy, *gz, *tt;
+  // check against the original (ref null: none): eb and per-tile partials
+  const void *ref;
+  double eb;
+  double *vpart;
+};
+
+// Eq. 4 statistics of one tile of the reconstruction against the original,
+// taken while the tile is written: sum of squared errors, largest |error|,
+// points beyond eb.  The block's sum has a fixed order (threads, then waves),
+// so the per-tile partials and their final reduction are reproducible.
+struct VStat {
+  double sse = 0.0, mx = 0.0;
+  uint32_t over = 0;
+  template <typename T> __device__ void add(T x, T y, double eb) {
+    const double e = (double)x - (double)y;
+    sse += e * e;
+    const double ae = fabs(e);
+    mx = ae > mx ? ae : mx;
+    over += ae > eb ? 1u : 0u;
+  }
+  // every thread of the block calls this (it has barriers)
+  __device__ void store(double *vpart, uint64_t t) {
+    __shared__ double s_sse[kBlock / 64], s_mx[kBlock / 64];
+    __shared__ uint32_t s_over[kBlock / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      sse += __shfl_xor(sse, o, 64);
+      const double m2 = __shfl_xor(mx, o, 64);
+      mx = m2 > mx ? m2 : mx;
+      over += __shfl_xor(over, o, 64);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) { s_sse[wv] = sse; s_mx[wv] = mx; s_over[wv] = over; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double a = 0.0, m = 0.0;
+      uint64_t c = 0;
+      for (int w = 0; w < kBlock / 64; w++) {
+        a += s_sse[w];
+        m = s_mx[w] > m ? s_mx[w] : m;
+        c += s_over[w];
+      }
+      vpart[3 * t] = a;
+      vpart[3 * t + 1] = m;
+      vpart[3 * t + 2] = __longlong_as_double((long long)c);
+    }
+  }
 };
 
 // global-memory views (pointers that reach kernels inside structures)
@@ -669,6 +716,7 @@ __global__ __launch_bounds__(kBlock) void k_rec(Plan P, const uint8_t *__restric
   __syncthreads();
 
   // bin midpoints q * 2eb, patched points exact, coalesced store
+  VStat vs;
   for (int i = tid; i < nt; i += kBlock) {
     int z, y, xx;
     if (full) { z = i / (TY * TX); y = (i / TX) % TY; xx = i % TX; }
@@ -709,8 +757,11 @@ __global__ __launch_bounds__(kBlock) void k_rec(Plan P, const uint8_t *__restric
         atomicOr(&dp->corrupt, 1u);
       }
     }
-    out[((g.z0 + z) * P.ny + g.y0 + y) * P.nx + g.x0 + xx] = v;
+    const uint64_t oi = ((g.z0 + z) * P.ny + g.y0 + y) * P.nx + g.x0 + xx;
+    out[oi] = v;
+    if (A.ref) vs.add(static_cast<const T *>(A.ref)[oi], v, A.eb);
   }
+  if (A.ref) vs.store(A.vpart, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -1001,6 +1052,37 @@ __global__ __launch_bounds__(kBlock) void k_rec_full(Plan P, const uint8_t *__re
     if (NDIM >= 2) c += ((dgptr_t<uint32_t>)A.gz)[t * TZ + m.z];
     if (NDIM == 3) c += ((dgptr_t<uint32_t>)A.gy)[t * TY + m.y] + ((dgptr_t<uint32_t>)A.tt)[t];
   }
+  const uint64_t rowbase = ((g.z0 + m.z) * P.ny + g.y0 + m.y) * P.nx + g.x0 + 32 * m.sg;
+  // the original's values of this row (check in the decompression pass),
+  // read first so that their latency overlaps the prefix sums
+  T xr[32];
+  const bool ref_vec = A.ref && ((uintptr_t)(static_cast<const T *>(A.ref) + rowbase) & 15) == 0;
+  if (A.ref) {
+    const T *ref = static_cast<const T *>(A.ref) + rowbase;
+    if (ref_vec) {
+      typedef __attribute__((address_space(1))) const df32x4_t gcf4;
+      typedef __attribute__((address_space(1))) const df64x2_t gcd2;
+      if constexpr (sizeof(T) == 4) {
+        gcf4 *src = (gcf4 *)ref;
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+          const df32x4_t a = src[k];
+          xr[4 * k] = a.x; xr[4 * k + 1] = a.y; xr[4 * k + 2] = a.z; xr[4 * k + 3] = a.w;
+        }
+      } else {
+        gcd2 *src = (gcd2 *)ref;
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+          const df64x2_t a = src[k];
+          xr[2 * k] = a.x; xr[2 * k + 1] = a.y;
+        }
+      }
+    } else {
+      typedef __attribute__((address_space(1))) const T gcT;
+#pragma unroll
+      for (int j = 0; j < 32; j++) xr[j] = ((gcT *)ref)[j];
+    }
+  }
   const uint64_t *teo = reinterpret_cast<const uint64_t *>(blob + P.off_teo);
   const uint64_t e0 = teo[t], e1 = teo[t + 1];
   if (e0 > e1 || e1 > A.n_exc) return;  // reported by the decode kernel
@@ -1066,7 +1148,12 @@ __global__ __launch_bounds__(kBlock) void k_rec_full(Plan P, const uint8_t *__re
     if (tid == 0) atomicOr(&dp->corrupt, 1u);
     return;
   }
-  const uint64_t rowbase = ((g.z0 + m.z) * P.ny + g.y0 + m.y) * P.nx + g.x0 + 32 * m.sg;
+  if (A.ref) {  // uniform: the check against the original
+    VStat vs;
+#pragma unroll
+    for (int j = 0; j < 32; j++) vs.add(xr[j], v[j], A.eb);
+    vs.store(A.vpart, t);
+  }
   if (sizeof(T) == 4) {
     typedef __attribute__((address_space(1))) df32x4_t gf4;
     if (((uintptr_t)(out + rowbase) & 15) == 0) {
@@ -1223,6 +1310,43 @@ __global__ void k_csum_check(const uint8_t *__restrict__ blob, DevParams *__rest
   if (stored != dp->checksum) dp->corrupt = 1;
 }
 
+// The check's per-tile partials combined in a fixed order: thread i takes
+// tiles i, i + kBlock, ..., then a fixed tree over lanes and waves.
+__global__ __launch_bounds__(kBlock) void k_vstat_final(const double *__restrict__ vpart,
+                                                        uint64_t nt, DevParams *__restrict__ dp) {
+  double sse = 0.0, mx = 0.0;
+  uint64_t over = 0;
+  for (uint64_t b = threadIdx.x; b < nt; b += kBlock) {
+    sse += vpart[3 * b];
+    mx = vpart[3 * b + 1] > mx ? vpart[3 * b + 1] : mx;
+    over += (uint64_t)__double_as_longlong(vpart[3 * b + 2]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    sse += __shfl_xor(sse, o, 64);
+    const double m2 = __shfl_xor(mx, o, 64);
+    mx = m2 > mx ? m2 : mx;
+    over += __shfl_xor(over, o, 64);
+  }
+  __shared__ double s_sse[kBlock / 64], s_mx[kBlock / 64];
+  __shared__ uint64_t s_over[kBlock / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) { s_sse[wv] = sse; s_mx[wv] = mx; s_over[wv] = over; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, m = 0.0;
+    uint64_t c = 0;
+    for (int w = 0; w < kBlock / 64; w++) {
+      a += s_sse[w];
+      m = s_mx[w] > m ? s_mx[w] : m;
+      c += s_over[w];
+    }
+    dp->v_sse = a;
+    dp->v_max = m;
+    dp->v_over = c;
+  }
+}
+
 template <typename T, int NDIM>
 static void launch_dec_t(const Plan &P, const uint8_t *blob, const DecodeArgs &A, DevParams *dp,
                          int16_t *codes, uint32_t *tmp, uint32_t stage_words, T *out,
@@ -1273,6 +1397,7 @@ static void launch_dec_t(const Plan &P, const uint8_t *blob, const DecodeArgs &A
     hipLaunchKernelGGL((k_rec_full<T, NDIM, false>), grid, blk, 0, s, P, blob, A, dp, codes, out);
     if (ragged) hipLaunchKernelGGL((k_rec<T, NDIM, false>), grid, blk, 0, s, P, blob, A, dp, codes, out);
   }
+  if (A.ref) hipLaunchKernelGGL(k_vstat_final, dim3(1), blk, 0, s, A.vpart, P.n_tiles, dp);
   tm->mark(s, "rec");
 }
 
@@ -1305,7 +1430,8 @@ static uint64_t decode_window_limit() {
 
 hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const DecompressWs &W,
                                   uint64_t off_words, uint64_t n_words, uint64_t n_exc, double e2,
-                                  float e2_f, void *out, hipStream_t s, Timer *tm) {
+                                  float e2_f, void *out, const void *ref, double eb, hipStream_t s,
+                                  Timer *tm) {
   tm->mark(s, "begin");
   hipError_t e = launch_fill_zero(W.P, W.zero_bytes, s);
   if (e != hipSuccess) return e;
@@ -1332,6 +1458,9 @@ hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const Deco
   A.gy = W.gy;
   A.gz = W.gz;
   A.tt = W.tt;
+  A.ref = ref;
+  A.eb = eb;
+  A.vpart = W.vpart;
   // LDS window per wave: a quarter above the average words per tile, so that
   // most chunks are read from LDS; the rest are read from global memory.
   const uint64_t avg = P.n_tiles ? n_words / P.n_tiles : 0;

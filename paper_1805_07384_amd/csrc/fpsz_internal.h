@@ -347,6 +347,7 @@ struct DecompressWs {
   uint32_t *gx, *gy, *gz, *tt;  // per-tile edge vectors and totals
   uint32_t *tmp;           // segment sums of the scans
   int16_t *codes;          // decoded residual codes, stream order
+  double *vpart;           // check against the original: per-tile (sse, max |e|, count > eb)
   uint64_t zero_bytes;
 };
 
@@ -382,7 +383,8 @@ hipError_t launch_compress_jobs(const CJob &one, const CJob *jobs_dev, int nf, c
 hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t s);
 hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const DecompressWs &W,
                                   uint64_t off_words, uint64_t n_words, uint64_t n_exc, double e2,
-                                  float e2_f, void *out, hipStream_t s, Timer *tm);
+                                  float e2_f, void *out, const void *ref, double eb, hipStream_t s,
+                                  Timer *tm);
 hipError_t launch_const_fill_bits(const Plan &P, uint64_t bits, void *out, hipStream_t s);
 hipError_t launch_checksum(const uint8_t *blob, uint64_t bytes, DevParams *dp, hipStream_t s);
 hipError_t launch_verify(const void *x, const void *y, uint64_t n, int dtype, double eb,

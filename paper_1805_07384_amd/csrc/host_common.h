@@ -134,7 +134,7 @@ inline CompressLayout compress_layout(const Plan &P) {
 
 struct DecompressLayout {
   uint64_t off_lut, off_ltab, off_sorted, off_fz, off_fy, off_fx, off_gx, off_gy, off_gz, off_tt,
-      off_tmp, off_codes, total;
+      off_tmp, off_vpart, off_codes, total;
 };
 
 inline DecompressLayout decompress_layout(const Plan &P) {
@@ -171,6 +171,10 @@ inline DecompressLayout decompress_layout(const Plan &P) {
   if (T * P.tx > big) big = T * P.tx;
   L.off_tmp = o;
   o = align256(o + 4 * (big / 16 + 64));
+  // per-tile partials of the check against the original (also the verify
+  // partials of a constant field)
+  L.off_vpart = o;
+  o = align256(o + 3 * 8 * (T > (uint64_t)kVerifyBlocks ? T : (uint64_t)kVerifyBlocks));
   L.off_codes = o;
   o = align256(o + 2 * P.n);
   L.total = o;
@@ -304,9 +308,10 @@ struct DJob {
   Plan P;
   const uint8_t *blob;
   void *out;
+  const void *ref;  // original field to check the reconstruction against, or null
   DecompressWs W;
   uint64_t off_words, n_words, n_exc;
-  double e2;
+  double e2, eb, vr;
   float e2_f;
   bool is_const;
   uint64_t const_bits, csum;
@@ -344,8 +349,11 @@ inline fpsz_status prepare_decompress(fpsz_ctx *ctx, const uint8_t *h, const voi
   P.capacity = blob_bytes;
   J->blob = (const uint8_t *)blob_dev;
   J->out = field_out_dev;
+  J->ref = nullptr;
   J->csum = rd<uint64_t>(h + H_CSUM);
   J->is_const = (flags & kFlagConst) != 0;
+  J->eb = rd<double>(h + H_EB);
+  J->vr = rd<double>(h + H_VR);
   uint8_t *ws = (uint8_t *)workspace_dev;
   if (J->is_const) {
     if (blob_bytes != kHdr) return fail(ctx, FPSZ_E_CORRUPT, "constant blob size");
@@ -353,6 +361,9 @@ inline fpsz_status prepare_decompress(fpsz_ctx *ctx, const uint8_t *h, const voi
       return fail(ctx, FPSZ_E_CAPACITY, "workspace too small");
     memset(&J->W, 0, sizeof(J->W));
     J->W.P = (DevParams *)ws;
+    const DecompressLayout L = decompress_layout(P);
+    if (workspace_bytes >= L.off_vpart + 3 * 8 * (uint64_t)kVerifyBlocks)
+      J->W.vpart = (double *)(ws + L.off_vpart);
     J->const_bits = rd<uint64_t>(h + H_CONST);
     return FPSZ_OK;
   }
@@ -390,6 +401,7 @@ inline fpsz_status prepare_decompress(fpsz_ctx *ctx, const uint8_t *h, const voi
   W.tt = (uint32_t *)(ws + L.off_tt);
   W.tmp = (uint32_t *)(ws + L.off_tmp);
   W.codes = (int16_t *)(ws + L.off_codes);
+  W.vpart = (double *)(ws + L.off_vpart);
   W.zero_bytes = align256(sizeof(DevParams));
   return FPSZ_OK;
 }
@@ -400,10 +412,13 @@ inline hipError_t launch_decompress_job(const DJob &J, hipStream_t s, Timer *tm)
     hipError_t e = launch_fill_zero(J.W.P, sizeof(DevParams), s);
     if (e == hipSuccess) e = launch_checksum(J.blob, kHdr, J.W.P, s);
     if (e == hipSuccess) e = launch_const_fill_bits(J.P, J.const_bits, J.out, s);
+    // a constant field is checked by the plain verify kernels
+    if (e == hipSuccess && J.ref)
+      e = launch_verify(J.ref, J.out, J.P.n, J.P.dtype, J.eb, J.W.P, J.W.vpart, s, tm);
     return e;
   }
   return launch_decompress_args(J.P, J.blob, J.W, J.off_words, J.n_words, J.n_exc, J.e2, J.e2_f,
-                                J.out, s, tm);
+                                J.out, J.ref, J.eb, s, tm);
 }
 
 // Status of a finished decompression from its parameter block.

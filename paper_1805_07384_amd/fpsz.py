@@ -114,6 +114,8 @@ SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(Info)]),
     "fpsz_decompress": (ctypes.c_int, [_vp, _vp, ctypes.c_uint64, _vp, ctypes.c_uint64, _vp,
                                        ctypes.c_uint64, _vp]),
+    "fpsz_decompress_verify": (ctypes.c_int, [_vp, _vp, ctypes.c_uint64, _vp, ctypes.c_uint64, _vp,
+                                              ctypes.c_uint64, _vp, ctypes.POINTER(Stats), _vp]),
     "fpsz_verify": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_uint64, ctypes.c_int, ctypes.c_double,
                                    ctypes.c_double, _vp, ctypes.c_uint64, ctypes.POINTER(Stats), _vp]),
     "fpsz_compress_workspace_offset": (ctypes.c_int, [ctypes.c_int, _u64p, ctypes.c_int, ctypes.c_int,
@@ -310,6 +312,18 @@ class Context:
                                          workspace.numel() * workspace.element_size(), out.data_ptr(),
                                          out.numel() * out.element_size(), _stream(stream))
 
+    def decompress_verify_into(self, blob: torch.Tensor, nbytes: int, workspace: torch.Tensor,
+                               out: torch.Tensor, x: torch.Tensor, stream=None):
+        """Decompress into ``out`` and check it against the original ``x`` in the
+        same pass (fpsz_decompress_verify); returns (status, Stats)."""
+        stats = Stats()
+        st = self.lib.fpsz_decompress_verify(self.handle, blob.data_ptr(), int(nbytes),
+                                             workspace.data_ptr(),
+                                             workspace.numel() * workspace.element_size(),
+                                             out.data_ptr(), out.numel() * out.element_size(),
+                                             x.data_ptr(), ctypes.byref(stats), _stream(stream))
+        return st, stats
+
     def verify_into(self, x: torch.Tensor, y: torch.Tensor, vr: float, eb: float,
                     workspace: torch.Tensor, stream=None):
         stats = Stats()
@@ -344,6 +358,17 @@ class Context:
         if st != OK:
             raise self._err(st, "fpsz_decompress")
         return out
+
+    def decompress_verify(self, blob: torch.Tensor, x: torch.Tensor, stream=None):
+        """Returns (reconstruction, stats dict) of one fused decompress + check pass."""
+        hdr = parse_header(blob[:HDR_BYTES].cpu().numpy().tobytes())
+        out = torch.empty(hdr.shape, dtype=hdr.dtype, device=blob.device)
+        ws = torch.empty(decompress_workspace_bytes(hdr.shape, hdr.dtype), dtype=torch.uint8,
+                         device=blob.device)
+        st, stats = self.decompress_verify_into(blob, blob.numel(), ws, out, x.contiguous(), stream)
+        if st != OK:
+            raise self._err(st, "fpsz_decompress_verify")
+        return out, stats.as_dict()
 
     def verify(self, x: torch.Tensor, y: torch.Tensor, vr: float, eb: float, stream=None) -> dict:
         ws_n = ctypes.c_uint64()

@@ -240,3 +240,58 @@ def test_deterministic_repeat(ctx):
     for _ in range(3):
         b, _ = ctx.compress(x, 100.0)
         assert torch.equal(a, b)
+
+
+FUSED_CASES = [((20000,), np.float32, 0), ((8193,), np.float64, 1), ((150, 300), np.float32, 0),
+               ((65, 129), np.float64, 0), ((40, 37, 70), np.float32, 0),
+               ((33, 17, 65), np.float64, 1), ((64, 64, 64), np.float32, 1),
+               ((16, 16, 32), np.float32, 0)]
+
+
+@pytest.mark.parametrize("shape,dt,domain", FUSED_CASES)
+def test_decompress_verify_fused(ctx, orc, shape, dt, domain):
+    # one pass that decompresses and takes the Eq. 4 statistics: the field is
+    # the oracle's bit for bit, the statistics the oracle's (max |e| and the
+    # count over eb exactly, the float64 SSE to rounding), repeated calls
+    # identical, and the separate verify agrees
+    from paper_1805_07384_amd import fpsz
+    x = (synth.grf_numpy(shape, -3.0, 11) * 3.0 + 0.5).astype(dt)
+    print("case fused shape=%s dtype=%s domain=%d" % (shape, x.dtype, domain), flush=True)
+    ob, ot = orc.compress(x, 90.0, domain=domain, trace=True)
+    oy = orc.decompress(ob)
+    os_ = orc.stats(x, oy, ot["vr"], ot["eb"])
+    blob = torch.from_numpy(np.frombuffer(ob, dtype=np.uint8).copy()).cuda()
+    xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    y, st1 = ctx.decompress_verify(blob, xt)
+    _, st2 = ctx.decompress_verify(blob, xt)
+    assert np.array_equal(_bits(y.cpu().numpy()), _bits(oy))
+    assert st1 == st2
+    assert st1["n_over_eb"] == os_["n_over_eb"] == 0
+    assert st1["max_abs_err"] == os_["max_abs_err"]
+    assert abs(st1["sse"] - os_["sse"]) <= 1e-9 * os_["sse"]
+    assert abs(st1["psnr"] - os_["psnr"]) <= 1e-9 * abs(os_["psnr"])
+    sv = ctx.verify(xt, y, ot["vr"], ot["eb"])
+    assert sv["max_abs_err"] == st1["max_abs_err"] and sv["n_over_eb"] == st1["n_over_eb"]
+    assert abs(sv["sse"] - st1["sse"]) <= 1e-12 * sv["sse"]
+
+
+def test_decompress_verify_constant_and_small_workspace(ctx, orc):
+    from paper_1805_07384_amd import fpsz
+    print("case fused constant", flush=True)
+    x = np.full((7, 9), 2.5, dtype=np.float32)
+    ob, _ = orc.compress(x, 80.0)
+    blob = torch.from_numpy(np.frombuffer(ob, dtype=np.uint8).copy()).cuda()
+    xt = torch.from_numpy(x).cuda()
+    y, st = ctx.decompress_verify(blob, xt)
+    assert np.array_equal(y.cpu().numpy(), x)
+    assert st["sse"] == 0.0 and st["max_abs_err"] == 0.0 and st["n_over_eb"] == 0
+    # a workspace too small for the check is refused, nothing is written
+    x2 = synth.grf_numpy((50, 60), -3.0, 3).astype(np.float32)
+    ob2, _ = orc.compress(x2, 80.0)
+    blob2 = torch.from_numpy(np.frombuffer(ob2, dtype=np.uint8).copy()).cuda()
+    out = torch.empty((50, 60), dtype=torch.float32, device="cuda")
+    need = fpsz.decompress_workspace_bytes((50, 60), torch.float32)
+    small = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
+    stt, _ = ctx.decompress_verify_into(blob2, blob2.numel(), small, out,
+                                        torch.from_numpy(x2).cuda())
+    assert stt == fpsz.E_CAPACITY
