@@ -62,9 +62,9 @@ struct VStat {
   uint32_t over = 0;
   template <typename T> __device__ void add(T x, T y, double eb) {
     const double e = (double)x - (double)y;
-    sse += e * e;
+    sse = __builtin_fma(e, e, sse);
     const double ae = fabs(e);
-    mx = ae > mx ? ae : mx;
+    mx = __builtin_fmax(mx, ae);  // |e| is never NaN: the inputs are finite
     over += ae > eb ? 1u : 0u;
   }
   // every thread of the block calls this (it has barriers)
@@ -1006,7 +1006,7 @@ __global__ __launch_bounds__(kBlock) void k_proj_full(Plan P, const uint8_t *__r
 }
 
 template <typename T, int NDIM, bool GLOBAL>
-__global__ __launch_bounds__(kBlock) void k_rec_full(Plan P, const uint8_t *__restrict__ blob,
+__global__ __launch_bounds__(kBlock, 4) void k_rec_full(Plan P, const uint8_t *__restrict__ blob,
                                                      DecodeArgs A, DevParams *__restrict__ dp,
                                                      const int16_t *__restrict__ codes,
                                                      T *__restrict__ out) {
