@@ -96,6 +96,17 @@ struct VStat {
   }
 };
 
+// Tile of a one-tile-per-workgroup grid, XCD-aware: workgroups are
+// dispatched round-robin over the 8 XCDs (block b on XCD b % 8), so XCD k is
+// given the k-th eighth of the tiles in order.  Tiles that neighbour in x
+// (whose rows share memory lines and DRAM pages) then run on one XCD at
+// about the same time.
+__device__ inline uint64_t xcd_block_tile(uint64_t n_tiles) {
+  const uint64_t b = blockIdx.x;
+  if (n_tiles % 8 != 0 || gridDim.x != n_tiles) return b;
+  return (b % 8) * (n_tiles / 8) + b / 8;
+}
+
 // global-memory views (pointers that reach kernels inside structures)
 template <typename T> using dgptr_t = __attribute__((address_space(1))) const T *;
 typedef uint32_t du32x4_t __attribute__((ext_vector_type(4)));
@@ -638,7 +649,7 @@ __global__ __launch_bounds__(kBlock) void k_rec(Plan P, const uint8_t *__restric
 
   if (dp->corrupt) return;
   const int tid = threadIdx.x;
-  const uint64_t t = blockIdx.x;
+  const uint64_t t = xcd_block_tile(P.n_tiles);
   const TileGeo g = tile_geo(P, t);
   if (g.nt == (uint32_t)kTilePts) return;  // uniform: full tiles in k_rec_full
   const int ez = (int)g.ez, ey = (int)g.ey, ex = (int)g.ex, nt = (int)g.nt;
@@ -1024,7 +1035,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_rec_full(Plan P, const uint8_t *_
   __shared__ uint32_t s_bad;
   if (dp->corrupt) return;
   const int tid = threadIdx.x;
-  const uint64_t t = blockIdx.x;
+  const uint64_t t = xcd_block_tile(P.n_tiles);
   const TileGeo g = tile_geo(P, t);
   if (g.nt != (uint32_t)kTilePts) return;  // uniform: ragged tiles elsewhere
   const RowMap<NDIM> m(tid);
