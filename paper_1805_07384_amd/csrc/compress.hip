@@ -1609,8 +1609,8 @@ LaunchCfg default_launch_cfg(const Plan &maxP) {
   LaunchCfg c;
   const uint64_t want = maxP.n / (kBlock * 16) + 1;
   c.range_blocks = (uint32_t)(want < (uint64_t)kRangeBlocks ? want : kRangeBlocks);
-  c.quant_grid = (uint32_t)(maxP.n_tiles < 2048 ? maxP.n_tiles : 2048);
-  c.encode_grid = c.quant_grid;
+  c.quant_grid = (uint32_t)(maxP.n_tiles < 1536 ? maxP.n_tiles : 1536);
+  c.encode_grid = (uint32_t)(maxP.n_tiles < 2048 ? maxP.n_tiles : 2048);
   const uint64_t cw = maxP.capacity / 16 / kBlock + 1;
   c.csum_blocks = (uint32_t)(cw < 256 ? cw : 256);
   return c;
