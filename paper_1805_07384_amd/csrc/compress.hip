@@ -620,6 +620,7 @@ __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restri
         const int32_t oa[4] = {O.x, O.y, O.z, O.w}, ya[4] = {Y.x, Y.y, Y.z, Y.w};
         const int32_t za[4] = {Z.x, Z.y, Z.z, Z.w}, zya[4] = {ZY.x, ZY.y, ZY.z, ZY.w};
         uint32_t c16[4];
+        int32_t dq[4];
 #pragma unroll
         for (int h = 0; h < 4; h++) {
           int32_t dv = oa[h] - po;
@@ -629,10 +630,27 @@ __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restri
           py = ya[h];
           pz = za[h];
           pzy = zya[h];
-          bool outl;
-          const uint32_t sy = symbol_of(dv, outl);
-          flags |= (outl ? 1u : 0u) << (4 * k + h);
-          c16[h] = outl ? 0x8000u : ((uint32_t)dv & 0xffffu);
+          dq[h] = dv;
+        }
+        // direct symbols only (|d| <= 511 for all four points of every lane):
+        // the symbol is d + 512, no escape or outlier; a wave-uniform test
+        uint32_t big = 0;
+#pragma unroll
+        for (int h = 0; h < 4; h++) big = __builtin_elementwise_max(big, (uint32_t)(dq[h] + 511));
+        const bool all_direct = !__builtin_amdgcn_ballot_w64(big > 1022u);
+#pragma unroll
+        for (int h = 0; h < 4; h++) {
+          const int32_t dv = dq[h];
+          uint32_t sy;
+          if (all_direct) {
+            sy = (uint32_t)(dv + 512);
+            c16[h] = (uint32_t)dv & 0xffffu;
+          } else {
+            bool outl;
+            sy = symbol_of(dv, outl);
+            flags |= (outl ? 1u : 0u) << (4 * k + h);
+            c16[h] = outl ? 0x8000u : ((uint32_t)dv & 0xffffu);
+          }
           if (!RECORDS) {
             const bool ch = sy != run_sym;
             if (ch && run_n) atomicAdd(&hist[run_sym], run_n);
