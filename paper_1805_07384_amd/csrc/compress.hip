@@ -934,8 +934,9 @@ __global__ __launch_bounds__(kBlock) void k_exc_copy(CJob one, const CJob *__res
 // ---------------------------------------------------------------------------
 // a8: Huffman code lengths and canonical codes, one workgroup.
 //
-// The two-queue construction (leaves sorted by (count, symbol); merged nodes
-// in a FIFO; a leaf wins ties) is run in batches: with v the weight of the
+// The two-queue construction (leaves sorted by (count, symbol), by a rank
+// sort of the nonzero bins; merged nodes in a FIFO; a leaf wins ties) is run
+// in batches: with v the weight of the
 // next merged node, every remaining leaf of weight <= v and every queued
 // merged node is consumed before v, in merge order, so all of them can be
 // ranked at once and paired.  A batch with an odd count pairs its last item
@@ -945,20 +946,6 @@ __global__ __launch_bounds__(kBlock) void k_exc_copy(CJob one, const CJob *__res
 // in two), and the lengths are handed out again along the (count, symbol)
 // order, longest first.
 constexpr int kCbThreads = 1024;
-
-__device__ inline void bitonic_sort_2048(uint64_t *key) {
-  const int tid = threadIdx.x;
-  for (int k = 2; k <= 2048; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      const int idx = 2 * tid - (tid & (j - 1));
-      const int ixj = idx + j;
-      const bool asc = (idx & k) == 0;
-      const uint64_t a = key[idx], b = key[ixj];
-      if ((a > b) == asc) { key[idx] = b; key[ixj] = a; }
-      __syncthreads();
-    }
-  }
-}
 
 // number of entries of sorted a[0..n) that are < w (lower bound)
 __device__ inline int count_less(const uint32_t *a, int n, uint32_t w) {
@@ -981,7 +968,8 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CJob one, const CJob *_
   uint8_t *__restrict__ len_out = J.W.code_len;
   uint32_t *__restrict__ code_out = J.W.code;
   uint8_t *__restrict__ blob = J.blob;
-  __shared__ uint64_t key[2048];
+  __shared__ uint64_t keyu[kNSym];  // the nonzero keys, unsorted
+  __shared__ uint64_t key[kNSym];   // the same, ascending
   __shared__ uint32_t Lw[kNSym];
   __shared__ uint16_t Ls[kNSym];
   __shared__ uint32_t Iw[kNSym];
@@ -992,27 +980,41 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CJob one, const CJob *_
   __shared__ uint32_t lcount[kLMax + 2], lfirst[kLMax + 2], lbase[kLMax + 2];
   __shared__ uint32_t wcnt[17 * 20];
   __shared__ uint32_t bits[64], lstart[64];
-  __shared__ int s_n, s_li, s_ii, s_ni, s_ml, s_maxl;
-  __shared__ uint32_t s_v;
+  __shared__ int s_n, s_maxl;
   const int tid = threadIdx.x;
   if (dp->status != 0 || dp->is_const) return;
 
-  for (int i = tid; i < 2048; i += kCbThreads) {
-    uint32_t c = 0;
-    if (i < kNSym) {
-#pragma unroll
-      for (int k = 0; k < kHistCopies; k++) c += hist_g[k * kNSym + i];
-      hist_g[i] = c;  // copy 0 keeps the total
-    }
-    key[i] = c ? (((uint64_t)c << 11) | (uint64_t)i) : ~0ull;
-  }
+  // nonzero bins (weight << 11 | symbol: distinct keys) in any order, then
+  // each key's rank = number of smaller keys (reads of one key by all
+  // threads are LDS broadcasts; no barrier inside)
+  if (tid == 0) { s_n = 0; s_maxl = 0; }
   for (int s = tid; s < kNSym; s += kCbThreads) lens[s] = 0;
   if (tid < 64) bits[tid] = 0;
-  if (tid == 0) { s_n = 0; s_maxl = 0; }
   __syncthreads();
-  bitonic_sort_2048(key);
-  for (int i = tid; i < 2048; i += kCbThreads)
-    if (key[i] != ~0ull && (i == 2047 || key[i + 1] == ~0ull)) s_n = i + 1;
+  for (int i = tid; i < kNSym; i += kCbThreads) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kHistCopies; k++) c += hist_g[k * kNSym + i];
+    hist_g[i] = c;  // copy 0 keeps the total
+    if (c) keyu[atomicAdd(&s_n, 1)] = ((uint64_t)c << 11) | (uint64_t)i;
+  }
+  __syncthreads();
+  {
+    const int nk = s_n;
+    for (int i = tid; i < nk; i += kCbThreads) {
+      const uint64_t me = keyu[i];
+      int r = 0;
+      int j = 0;
+      for (; j + 8 <= nk; j += 8) {  // eight independent reads in flight
+        int c = 0;
+#pragma unroll
+        for (int u = 0; u < 8; u++) c += keyu[j + u] < me ? 1 : 0;
+        r += c;
+      }
+      for (; j < nk; j++) r += keyu[j] < me ? 1 : 0;
+      key[r] = me;
+    }
+  }
   __syncthreads();
   const int n = s_n;
   if (n <= 1) {
@@ -1023,30 +1025,32 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CJob one, const CJob *_
       Lw[j] = (uint32_t)(key[j] >> 11);
       Ls[j] = (uint16_t)(key[j] & 2047);
     }
-    if (tid == 0) { s_li = 0; s_ii = 0; s_ni = 0; }
     __syncthreads();
-    // every batch creates at least one merged node, so n - 1 batches bound
-    // the loop; the guard only protects against a broken invariant
+    // Every thread derives a batch's bounds alike from the shared weights
+    // (broadcast reads; they stay in registers), so a batch needs barriers
+    // only after its ranked placement, its pairing and an odd last merge.
+    // Every batch creates at least one merged node, so n - 1 batches bound
+    // the loop; the guard only protects against a broken invariant.
+    int li = 0, ii = 0, ni = 0;
     for (int batch = 0; batch < n; batch++) {
-      const int ni = s_ni;
       if (ni >= n - 1) break;
-      if (tid == 0) {
-        int li = s_li, ii = s_ii;
-        uint32_t w[2];
-        for (int k = 0; k < 2; k++) {
-          if (li < n && (ii >= ni || Lw[li] <= Iw[ii])) w[k] = Lw[li++];
-          else w[k] = Iw[ii++];
-        }
-        s_v = w[0] + w[1];
-        s_ml = 0;
+      uint32_t w0, w1;
+      {
+        int a = li, c = ii;
+        if (a < n && (c >= ni || Lw[a] <= Iw[c])) w0 = Lw[a++];
+        else w0 = Iw[c++];
+        if (a < n && (c >= ni || Lw[a] <= Iw[c])) w1 = Lw[a++];
+        else w1 = Iw[c++];
       }
-      __syncthreads();
-      const uint32_t v = s_v;
-      const int li = s_li, ii = s_ii;
-      for (int j = li + tid; j < n; j += kCbThreads)
-        if (Lw[j] <= v && (j + 1 == n || Lw[j + 1] > v)) s_ml = j - li + 1;
-      __syncthreads();
-      const int ml = s_ml, nI = ni - ii, m = ml + nI;
+      const uint32_t v = w0 + w1;
+      // leaves from li not heavier than v (leaf weights ascend)
+      int lo = li, hi = n;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (Lw[mid] <= v) lo = mid + 1;
+        else hi = mid;
+      }
+      const int ml = lo - li, nI = ni - ii, m = ml + nI;
       if (m < 2) {  // cannot happen for positive weights
         if (tid == 0) atomicOr(&dp->spin_fail, 2u);
         break;
@@ -1069,19 +1073,19 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CJob one, const CJob *_
       const int half = m / 2;
       for (int p = tid; p < half; p += kCbThreads) Iw[ni + p] = tmpw[2 * p] + tmpw[2 * p + 1];
       __syncthreads();
-      if (tid == 0) {
-        if (m & 1) {
+      if (m & 1) {
+        if (tid == 0) {
           Iw[ni + half] = tmpw[m - 1] + Iw[ni];
           parI[ni] = (uint16_t)(ni + half);
-          s_ii = ni + 1;
-          s_ni = ni + half + 1;
-        } else {
-          s_ii = ni;
-          s_ni = ni + half;
         }
-        s_li = li + ml;
+        __syncthreads();
+        ii = ni + 1;
+        ni = ni + half + 1;
+      } else {
+        ii = ni;
+        ni = ni + half;
       }
-      __syncthreads();
+      li += ml;
     }
     // depths of merged nodes by pointer jumping (root = n - 2)
     const int root = n - 2;
