@@ -834,15 +834,18 @@ __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restri
 constexpr int kScanThreads = 1024;
 // Exclusive scan of v[0 .. n) by one workgroup of kScanThreads.  Wave w owns
 // the contiguous range of R rounds of 64 elements from w R 64 (R = ceil(n /
-// kScanThreads)); a round is read by the 64 lanes at once, four rounds'
-// loads in flight.  Pass 1 sums each wave's range, one block scan of the 16
-// wave sums follows, pass 2 scans the rounds in order within the wave and
-// calls emit(k, exclusive prefix of k) (v[k] is read before emit, so emit may
-// overwrite it).  Returns the total.
+// kScanThreads)); a round is read by the 64 lanes at once.  Pass 1 sums each
+// wave's range, one block scan of the 16 wave sums follows, pass 2 scans the
+// rounds in order within the wave and calls emit(k, exclusive prefix of k)
+// (v[k] is read before emit, so emit may overwrite it).  Up to 16 rounds
+// (n <= 16384) are all loaded at once and held in registers for pass 2;
+// longer inputs keep four rounds' loads in flight and read v again in pass 2.
+// Returns the total.
 template <typename In, typename Emit>
 __device__ inline uint64_t block_seg_scan(const In *__restrict__ v, uint64_t n, Emit emit) {
   constexpr int NW = kScanThreads / 64;
   __shared__ uint64_t wsum[NW];
+  if (n == 0) return 0;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const uint64_t R = (n + kScanThreads - 1) / kScanThreads;
   const uint64_t w0 = (uint64_t)wv * R * 64 + lane;
@@ -850,10 +853,30 @@ __device__ inline uint64_t block_seg_scan(const In *__restrict__ v, uint64_t n, 
     const uint64_t k = w0 + 64 * r;
     return r < R && k < n ? (uint64_t)v[k] : 0ull;
   };
+  // up to kHeld rounds per wave: all loads issued at once and kept in
+  // registers for pass 2
+  constexpr int kHeld = 16;
+  const bool held = R <= (uint64_t)kHeld;
+  uint64_t xh[kHeld];
   uint64_t part = 0;
-  for (uint64_t r = 0; r < R; r += 4) {
-    const uint64_t x0 = ld(r), x1 = ld(r + 1), x2 = ld(r + 2), x3 = ld(r + 3);
-    part += x0 + x1 + x2 + x3;
+  if (held) {
+    // clamped indexes: the loads issue together without branches; elements
+    // past n are masked afterwards
+#pragma unroll
+    for (int h = 0; h < kHeld; h++) {
+      const uint64_t k = w0 + 64 * (uint64_t)h;
+      xh[h] = (uint64_t)v[k < n ? k : n - 1];
+    }
+#pragma unroll
+    for (int h = 0; h < kHeld; h++) {
+      xh[h] = (uint64_t)h < R && w0 + 64 * (uint64_t)h < n ? xh[h] : 0ull;
+      part += xh[h];
+    }
+  } else {
+    for (uint64_t r = 0; r < R; r += 4) {
+      const uint64_t x0 = ld(r), x1 = ld(r + 1), x2 = ld(r + 2), x3 = ld(r + 3);
+      part += x0 + x1 + x2 + x3;
+    }
   }
   part = wave_sum_u64(part);
   if (lane == 0) wsum[wv] = part;
@@ -862,6 +885,17 @@ __device__ inline uint64_t block_seg_scan(const In *__restrict__ v, uint64_t n, 
   for (int w = 0; w < NW; w++) {
     carry += w < wv ? wsum[w] : 0;
     tot += wsum[w];
+  }
+  if (held) {
+#pragma unroll
+    for (int h = 0; h < kHeld; h++) {
+      if ((uint64_t)h >= R) break;
+      const uint64_t inc = wave_incl_scan_u64(xh[h]);
+      const uint64_t k = w0 + 64 * (uint64_t)h;
+      if (k < n) emit(k, carry + inc - xh[h]);
+      carry += __shfl(inc, 63, 64);
+    }
+    return tot;
   }
   for (uint64_t r = 0; r < R; r += 4) {
     uint64_t x[4];

@@ -1327,10 +1327,27 @@ __global__ __launch_bounds__(kBlock) void k_vstat_final(const double *__restrict
                                                         uint64_t nt, DevParams *__restrict__ dp) {
   double sse = 0.0, mx = 0.0;
   uint64_t over = 0;
-  for (uint64_t b = threadIdx.x; b < nt; b += kBlock) {
-    sse += vpart[3 * b];
-    mx = vpart[3 * b + 1] > mx ? vpart[3 * b + 1] : mx;
-    over += (uint64_t)__double_as_longlong(vpart[3 * b + 2]);
+  // kU rows of partials in flight per thread, combined in tile order
+  constexpr int kU = 16;
+  for (uint64_t b0 = threadIdx.x; b0 < nt; b0 += (uint64_t)kBlock * kU) {
+    double s[kU], m[kU], c[kU];
+    // clamped indexes, so that the loads are issued together without
+    // branches; rows past nt are masked afterwards
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      const uint64_t b = b0 + (uint64_t)u * kBlock;
+      const uint64_t bc = b < nt ? b : nt - 1;
+      s[u] = vpart[3 * bc];
+      m[u] = vpart[3 * bc + 1];
+      c[u] = vpart[3 * bc + 2];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      const bool in = b0 + (uint64_t)u * kBlock < nt;
+      sse += in ? s[u] : 0.0;
+      mx = in && m[u] > mx ? m[u] : mx;
+      over += in ? (uint64_t)__double_as_longlong(c[u]) : 0ull;
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {

@@ -120,7 +120,7 @@ struct DevParams {
   uint32_t spin_fail;   // a bounded wait gave up (reported as FPSZ_E_DEVICE)
   uint32_t overflow;    // a blob write fell beyond the capacity
   uint32_t corrupt;     // decompress: inconsistency found
-  uint32_t ticket_q, ticket_e;
+  uint32_t unused_[2];
   double mn, mx, vr, eb_rel, eb, e2, r, maxabs;
   float e2_f, r_f;
   uint64_t nonfinite;
@@ -180,68 +180,6 @@ __device__ inline uint32_t block_excl_scan_u32(uint32_t v, uint32_t *scratch, ui
   __syncthreads();
   *total = tot;
   return base + inc - v;
-}
-
-// Agent-scope atomics for cross-workgroup flags (coherent across XCDs).
-__device__ inline uint64_t ld_agent(const uint64_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline void st_agent(uint64_t *p, uint64_t v) {
-  __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Decoupled look-back over per-tile counts in ticket order.  state[t] holds
-// (flag << 62) | value; flag 1 = this tile's count, 2 = inclusive prefix.
-// Called by all 64 lanes of one wave; returns the exclusive prefix of tile t.
-// The wait is bounded: after `max_spins` rounds it flags *fail and returns 0
-// so that every wave exits.
-constexpr uint64_t kLbAgg = 1ull << 62, kLbInc = 2ull << 62, kLbMask = kLbAgg - 1;
-__device__ inline uint64_t lookback_excl(uint64_t *state, uint64_t t, uint64_t agg,
-                                         uint32_t *fail) {
-  const int lane = threadIdx.x & 63;
-  if (t == 0) {
-    if (lane == 0) st_agent(&state[0], kLbInc | agg);
-    return 0;
-  }
-  if (lane == 0) st_agent(&state[t], kLbAgg | agg);
-  uint64_t excl = 0;
-  int64_t base = (int64_t)t - 1;
-  uint32_t spins = 0;
-  while (true) {
-    const int64_t j = base - lane;
-    const uint64_t v = j >= 0 ? ld_agent(&state[j]) : kLbInc;
-    const uint64_t flag = v >> 62;
-    const uint64_t empty = __ballot(flag == 0);
-    const uint64_t incl = __ballot(flag == 2);
-    const int first_incl = incl ? __ffsll((long long)incl) - 1 : 64;
-    const uint64_t upto = first_incl >= 63 ? ~0ull : ((2ull << first_incl) - 1);
-    if (empty & upto) {
-      if (++spins > (1u << 24)) {
-        if (lane == 0) atomicOr(fail, 1u);
-        return 0;
-      }
-      __builtin_amdgcn_s_sleep(1);
-      continue;
-    }
-    const uint64_t val = (lane <= first_incl && j >= 0) ? (v & kLbMask) : 0;
-    excl += wave_sum_u64(val);
-    if (first_incl < 64) break;
-    base -= 64;
-  }
-  if (lane == 0) st_agent(&state[t], kLbInc | (excl + agg));
-  return excl;
-}
-
-// Symbol of a residual code (i16 stream value): returns the symbol; *ne and
-// *ev receive the raw-bit count and value of an escape class.
-__device__ inline int sym_of_code(int32_t d, int *ne, uint32_t *ev) {
-  if (d == -32768) { *ne = 0; *ev = 0; return 0; }
-  const int32_t a = d < 0 ? -d : d;
-  if (a <= 511) { *ne = 0; *ev = 0; return d + 512; }
-  const int k = 31 - __clz(a);
-  *ne = k;
-  *ev = (uint32_t)(a - (1 << k));
-  return 1024 + 2 * (k - 9) + (d < 0 ? 1 : 0);
 }
 
 __device__ inline uint64_t mix64(uint32_t w, uint64_t j) {
