@@ -128,12 +128,18 @@ __global__ __launch_bounds__(1024) void k_dec_tables(Plan P, const uint8_t *__re
   const int tid = threadIdx.x;
   if (tid == 0) { kraft = 0; bad = 0; }
   __syncthreads();
+  // Kraft sum and length check: per-thread sums, one atomic per wave
+  uint64_t kr = 0;
+  bool bl = false;
   for (int s = tid; s < kNSym; s += blockDim.x) {
     const uint8_t l = blob[P.off_len + s];
     lens[s] = l;
-    if (l > kLMax) atomicOr(&bad, 1u);
-    else if (l) atomicAdd(&kraft, 1ull << (kLMax - l));
+    bl |= l > kLMax;
+    kr += l && l <= kLMax ? 1ull << (kLMax - l) : 0ull;
   }
+  kr = wave_sum_u64(kr);
+  if (__builtin_amdgcn_ballot_w64(bl) && (tid & 63) == 0) atomicOr(&bad, 1u);
+  if (kr && (tid & 63) == 0) atomicAdd(&kraft, kr);
   __syncthreads();
   if (bad || kraft > (1ull << kLMax) || kraft == 0) {
     if (tid == 0) atomicOr(&dp->corrupt, 1u);
@@ -144,15 +150,28 @@ __global__ __launch_bounds__(1024) void k_dec_tables(Plan P, const uint8_t *__re
   // one thread per table entry: the code of length l <= kLut that is a
   // prefix of the entry's bits, if any (canonical codes of one length are
   // consecutive from lfirst[l])
+  // (the per-length limits are uniform: read once into registers)
+  uint32_t fst[kLut + 1], cnt[kLut + 1], bas[kLut + 1];
+#pragma unroll
+  for (int l = 1; l <= kLut; l++) {
+    fst[l] = lfirst[l];
+    cnt[l] = lcount[l];
+    bas[l] = lbase[l];
+  }
   for (int i = tid; i < (1 << kLut); i += blockDim.x) {
     uint32_t e = kLutLong;
-    for (int l = 1; l <= kLut; l++) {
+    int hit = 0;
+    uint32_t at = 0;
+#pragma unroll
+    for (int l = kLut; l >= 1; l--) {  // the shortest matching length wins
       const uint32_t cp = (uint32_t)i >> (kLut - l);
-      if (cp >= lfirst[l] && cp - lfirst[l] < lcount[l]) {
-        const uint32_t s = sorted[lbase[l] + cp - lfirst[l]];
-        e = (s == 0 ? kSymOutlierTag : s) << 5 | (uint32_t)l;
-        break;
-      }
+      const bool m = cp >= fst[l] && cp - fst[l] < cnt[l];
+      hit = m ? l : hit;
+      at = m ? bas[l] + cp - fst[l] : at;
+    }
+    if (hit) {
+      const uint32_t s = sorted[at];
+      e = (s == 0 ? kSymOutlierTag : s) << 5 | (uint32_t)hit;
     }
     lut[i] = (uint16_t)e;
   }

@@ -212,17 +212,20 @@ __device__ inline void canonical_from_lengths(const uint8_t *lens, uint32_t *cod
     }
   }
   __syncthreads();
+  // thread l - 1 counts the codes of length l over the chunks (in parallel:
+  // one thread walking all lengths would chain kLMax * kChunks LDS reads)
+  if (tid < kLMax) {
+    uint32_t cnt = 0;
+    for (int w = 0; w < kChunks; w++) cnt += wcnt[w * 20 + tid + 1];
+    lcount[tid + 1] = cnt;
+  }
+  __syncthreads();
   if (tid == 0) {
     // lcount[0] stays 0: unused symbols are not counted
     uint32_t c = 0, base = 0;
     lcount[0] = 0;
     lfirst[0] = 0;
     lbase[0] = 0;
-    for (int l = 1; l <= kLMax; l++) {
-      uint32_t cnt = 0;
-      for (int w = 0; w < kChunks; w++) cnt += wcnt[w * 20 + l];
-      lcount[l] = cnt;
-    }
     for (int l = 1; l <= kLMax; l++) {
       c = (c + lcount[l - 1]) << 1;
       lfirst[l] = c;
