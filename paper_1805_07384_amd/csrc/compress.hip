@@ -1589,6 +1589,15 @@ __global__ void k_header(CJob one, const CJob *__restrict__ jobs) {
   }
 }
 
+// Checksum workgroups for a blob: about 128 KiB per workgroup (32 rounds of
+// 16-byte loads per thread), at most 1024.  Small blobs want few workgroups
+// (each ends with a block reduction and an atomic), large ones more than one
+// per CU to hide the hashing's latency.
+__host__ __device__ inline uint32_t checksum_grid(uint64_t bytes) {
+  const uint64_t cw = bytes / (16ull * kBlock * 32) + 1;
+  return (uint32_t)(cw < 1024 ? cw : 1024);
+}
+
 // checksum over the blob's 32-bit words; the checksum field reads as zero.
 // Accumulates into dp->checksum; use_dp_bytes: the blob size is dp->blob_bytes
 // (compress, after k_header), else bytes_limit (decompress).
@@ -1596,13 +1605,16 @@ __device__ inline void checksum_body(const uint8_t *__restrict__ blob, uint64_t 
                                      DevParams *__restrict__ dp, int use_dp_bytes) {
   if (use_dp_bytes && (dp->status != 0 || dp->overflow)) return;
   const uint64_t bytes = use_dp_bytes ? dp->blob_bytes : bytes_limit;
+  // a grid sized for the capacity uses only the workgroups this blob needs
+  const uint32_t nblk = gridDim.x < checksum_grid(bytes) ? gridDim.x : checksum_grid(bytes);
+  if (blockIdx.x >= nblk) return;  // uniform over the block, before any barrier
   const uint64_t nw = bytes / 4;  // a multiple of 2 (blobs are 8-byte sized)
   const uint32_t *w = reinterpret_cast<const uint32_t *>(blob);
   const uint4 *w4 = reinterpret_cast<const uint4 *>(blob);
   uint64_t s = 0;
   // 16-byte loads when the blob allows them (it is only required to be 8-aligned)
   const uint64_t n4 = (uintptr_t)blob % 16 == 0 ? nw / 4 : 0;
-  const uint64_t gsz = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t gsz = (uint64_t)nblk * blockDim.x;
   auto quad = [&](const uint4 v, uint64_t q) {
     const uint64_t j = 4 * q;
     s += mix64(v.x, j) + mix64(v.y, j + 1);
@@ -1639,8 +1651,7 @@ __global__ __launch_bounds__(kBlock) void k_checksum(const uint8_t *__restrict__
 }
 
 hipError_t launch_checksum(const uint8_t *blob, uint64_t bytes, DevParams *dp, hipStream_t s) {
-  const uint64_t cw = bytes / 16 / kBlock + 1;
-  const uint32_t cgrid = (uint32_t)(cw < 256 ? cw : 256);
+  const uint32_t cgrid = checksum_grid(bytes);
   hipLaunchKernelGGL(k_checksum, dim3(cgrid), dim3(kBlock), 0, s, blob, bytes, dp);
   return hipGetLastError();
 }
@@ -1668,8 +1679,7 @@ LaunchCfg default_launch_cfg(const Plan &maxP) {
   c.range_blocks = (uint32_t)(want < (uint64_t)512 ? want : 512);
   c.quant_grid = (uint32_t)(maxP.n_tiles < 1536 ? maxP.n_tiles : 1536);
   c.encode_grid = (uint32_t)(maxP.n_tiles < 2048 ? maxP.n_tiles : 2048);
-  const uint64_t cw = maxP.capacity / 16 / kBlock + 1;
-  c.csum_blocks = (uint32_t)(cw < 256 ? cw : 256);
+  c.csum_blocks = checksum_grid(maxP.capacity);
   return c;
 }
 

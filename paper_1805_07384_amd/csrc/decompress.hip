@@ -1341,20 +1341,23 @@ __global__ void k_csum_check(const uint8_t *__restrict__ blob, DevParams *__rest
 }
 
 // The check's per-tile partials combined in a fixed order: thread i takes
-// tiles i, i + kBlock, ..., then a fixed tree over lanes and waves.
-__global__ __launch_bounds__(kBlock) void k_vstat_final(const double *__restrict__ vpart,
-                                                        uint64_t nt, DevParams *__restrict__ dp) {
+// tiles i, i + kVstatThreads, ..., then a fixed tree over lanes and waves.
+// 1024 threads with 16 rows each have the partials of 16384 tiles in flight
+// at once.
+constexpr int kVstatThreads = 1024;
+__global__ __launch_bounds__(kVstatThreads) void k_vstat_final(const double *__restrict__ vpart,
+                                                               uint64_t nt,
+                                                               DevParams *__restrict__ dp) {
   double sse = 0.0, mx = 0.0;
   uint64_t over = 0;
-  // kU rows of partials in flight per thread, combined in tile order
   constexpr int kU = 16;
-  for (uint64_t b0 = threadIdx.x; b0 < nt; b0 += (uint64_t)kBlock * kU) {
+  for (uint64_t b0 = threadIdx.x; b0 < nt; b0 += (uint64_t)kVstatThreads * kU) {
     double s[kU], m[kU], c[kU];
     // clamped indexes, so that the loads are issued together without
     // branches; rows past nt are masked afterwards
 #pragma unroll
     for (int u = 0; u < kU; u++) {
-      const uint64_t b = b0 + (uint64_t)u * kBlock;
+      const uint64_t b = b0 + (uint64_t)u * kVstatThreads;
       const uint64_t bc = b < nt ? b : nt - 1;
       s[u] = vpart[3 * bc];
       m[u] = vpart[3 * bc + 1];
@@ -1362,7 +1365,7 @@ __global__ __launch_bounds__(kBlock) void k_vstat_final(const double *__restrict
     }
 #pragma unroll
     for (int u = 0; u < kU; u++) {
-      const bool in = b0 + (uint64_t)u * kBlock < nt;
+      const bool in = b0 + (uint64_t)u * kVstatThreads < nt;
       sse += in ? s[u] : 0.0;
       mx = in && m[u] > mx ? m[u] : mx;
       over += in ? (uint64_t)__double_as_longlong(c[u]) : 0ull;
@@ -1375,15 +1378,15 @@ __global__ __launch_bounds__(kBlock) void k_vstat_final(const double *__restrict
     mx = m2 > mx ? m2 : mx;
     over += __shfl_xor(over, o, 64);
   }
-  __shared__ double s_sse[kBlock / 64], s_mx[kBlock / 64];
-  __shared__ uint64_t s_over[kBlock / 64];
+  __shared__ double s_sse[kVstatThreads / 64], s_mx[kVstatThreads / 64];
+  __shared__ uint64_t s_over[kVstatThreads / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (lane == 0) { s_sse[wv] = sse; s_mx[wv] = mx; s_over[wv] = over; }
   __syncthreads();
   if (threadIdx.x == 0) {
     double a = 0.0, m = 0.0;
     uint64_t c = 0;
-    for (int w = 0; w < kBlock / 64; w++) {
+    for (int w = 0; w < kVstatThreads / 64; w++) {
       a += s_sse[w];
       m = s_mx[w] > m ? s_mx[w] : m;
       c += s_over[w];
@@ -1444,8 +1447,11 @@ static void launch_dec_t(const Plan &P, const uint8_t *blob, const DecodeArgs &A
     hipLaunchKernelGGL((k_rec_full<T, NDIM, false>), grid, blk, 0, s, P, blob, A, dp, codes, out);
     if (ragged) hipLaunchKernelGGL((k_rec<T, NDIM, false>), grid, blk, 0, s, P, blob, A, dp, codes, out);
   }
-  if (A.ref) hipLaunchKernelGGL(k_vstat_final, dim3(1), blk, 0, s, A.vpart, P.n_tiles, dp);
   tm->mark(s, "rec");
+  if (A.ref) {
+    hipLaunchKernelGGL(k_vstat_final, dim3(1), dim3(kVstatThreads), 0, s, A.vpart, P.n_tiles, dp);
+    tm->mark(s, "check_final");
+  }
 }
 
 // Largest decode window (words per wave) that keeps two decode workgroups
