@@ -567,7 +567,10 @@ __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restri
   using B = BoxAddr<NDIM>;
   constexpr int FAST_SIZE = FastGeo<NDIM>::ROWS * FastGeo<NDIM>::NSEG * kSegW;
   __shared__ __align__(16) int32_t box[B::SIZE > FAST_SIZE ? B::SIZE : FAST_SIZE];
-  __shared__ uint32_t hist[RECORDS ? 1 : kNSym];
+  // two LDS histogram copies (even / odd lanes): escape classes put many
+  // lanes of a wave on the same bin, and LDS atomics on one address serialize
+  __shared__ uint32_t hist2[RECORDS ? 1 : 2 * kNSym];
+  uint32_t *const hist = hist2 + (RECORDS ? 0 : (threadIdx.x & 1) * kNSym);
   __shared__ uint32_t pmask[kTilePts / 32 + 1];
   __shared__ uint32_t scr[8];
 
@@ -581,7 +584,7 @@ __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restri
   const float thr = eb < 0x1p126 ? __double2float_rd(eb * (1.0 - 0x1p-22)) : -1.0f;
   constexpr int RW = sizeof(T) / 4;  // exception records per patch
   if (!RECORDS)
-    for (int s = tid; s < kNSym; s += kBlock) hist[s] = 0;
+    for (int s = tid; s < 2 * kNSym; s += kBlock) hist2[s] = 0;
   uint64_t my_out = 0, my_pat = 0;
 
   uint64_t t;
@@ -819,7 +822,8 @@ __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restri
   if (RECORDS) return;
   __syncthreads();
   for (int s = tid; s < kNSym; s += kBlock)
-    if (hist[s]) atomicAdd(&hist_g[(blockIdx.x % kHistCopies) * kNSym + s], hist[s]);
+    if (hist2[s] + hist2[kNSym + s])
+      atomicAdd(&hist_g[(blockIdx.x % kHistCopies) * kNSym + s], hist2[s] + hist2[kNSym + s]);
   my_out = wave_sum_u64(my_out);
   my_pat = wave_sum_u64(my_pat);
   if ((tid & 63) == 0) {
@@ -1076,14 +1080,24 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CJob one, const CJob *_
         else w1 = Iw[c++];
       }
       const uint32_t v = w0 + w1;
-      // leaves from li not heavier than v (leaf weights ascend)
-      int lo = li, hi = n;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (Lw[mid] <= v) lo = mid + 1;
-        else hi = mid;
+      // leaves from li not heavier than v (leaf weights ascend): 64 probes
+      // st apart, then the st - 1 positions after the last probe at or below
+      // v (two dependent reads per wave instead of a binary search's chain)
+      int ml;
+      {
+        const int lane = tid & 63, len = n - li, st = (len + 63) >> 6;
+        const bool le1 = lane * st < len && Lw[li + lane * st] <= v;
+        const int c1 = __popcll(__builtin_amdgcn_ballot_w64(le1));
+        int pos = li;  // first leaf heavier than v
+        if (c1 > 0) {
+          const int q0 = li + (c1 - 1) * st + 1;
+          const int q1 = li + c1 * st < n ? li + c1 * st : n;  // exclusive
+          const bool le2 = lane < st - 1 && q0 + lane < q1 && Lw[q0 + lane] <= v;
+          pos = q0 + __popcll(__builtin_amdgcn_ballot_w64(le2));
+        }
+        ml = pos - li;
       }
-      const int ml = lo - li, nI = ni - ii, m = ml + nI;
+      const int nI = ni - ii, m = ml + nI;
       if (m < 2) {  // cannot happen for positive weights
         if (tid == 0) atomicOr(&dp->spin_fail, 2u);
         break;
