@@ -144,22 +144,38 @@ __device__ inline uint32_t wave_sum_u32(uint32_t v) {
   return v;
 }
 // inclusive scan over the 64 lanes
+// Inclusive wave scans by DPP (the whole wave must be active): within each
+// row of 16 lanes, shifts by 1, 2, 4, 8 (lanes without a source add 0); then
+// row 0's total into row 1 and row 2's into row 3 (row_bcast:15), and the
+// total of rows 0-1 into rows 2-3 (row_bcast:31).  Each step is a lane move
+// inside the ALU, where a shuffle would be a round trip through the LDS
+// crossbar.
+template <int CTRL, int ROWS, bool BOUND>
+__device__ inline uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, BOUND);
+}
+template <int CTRL, int ROWS, bool BOUND>
+__device__ inline void dpp_add_u64(uint64_t &v) {
+  const uint32_t lo = dpp_u32<CTRL, ROWS, BOUND>((uint32_t)v);
+  const uint32_t hi = dpp_u32<CTRL, ROWS, BOUND>((uint32_t)(v >> 32));
+  v += ((uint64_t)hi << 32) | lo;
+}
 __device__ inline uint32_t wave_incl_scan_u32(uint32_t v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    uint32_t u = __shfl_up(v, o, 64);
-    if (lane >= o) v += u;
-  }
+  v += dpp_u32<0x111, 0xf, true>(v);   // row_shr:1
+  v += dpp_u32<0x112, 0xf, true>(v);   // row_shr:2
+  v += dpp_u32<0x114, 0xf, true>(v);   // row_shr:4
+  v += dpp_u32<0x118, 0xf, true>(v);   // row_shr:8
+  v += dpp_u32<0x142, 0xa, false>(v);  // row_bcast:15 into rows 1, 3
+  v += dpp_u32<0x143, 0xc, false>(v);  // row_bcast:31 into rows 2, 3
   return v;
 }
 __device__ inline uint64_t wave_incl_scan_u64(uint64_t v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    uint64_t u = __shfl_up(v, o, 64);
-    if (lane >= o) v += u;
-  }
+  dpp_add_u64<0x111, 0xf, true>(v);
+  dpp_add_u64<0x112, 0xf, true>(v);
+  dpp_add_u64<0x114, 0xf, true>(v);
+  dpp_add_u64<0x118, 0xf, true>(v);
+  dpp_add_u64<0x142, 0xa, false>(v);
+  dpp_add_u64<0x143, 0xc, false>(v);
   return v;
 }
 
