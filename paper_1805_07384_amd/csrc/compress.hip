@@ -378,6 +378,7 @@ template <typename T> using gptr_t = __attribute__((address_space(1))) const T *
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef double f64x2_t __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 template <typename T> struct GVec;
 template <> struct GVec<float> { using V = f32x4_t; };
 template <> struct GVec<double> { using V = f64x2_t; };
@@ -608,10 +609,16 @@ __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restri
       const SegPtrs<NDIM> sp(box, tid);
       int32_t po = sp.o[-1], py = sp.y[-1], pz = sp.z[-1], pzy = sp.zy[-1];
       uint32_t run_sym = 0xffffffffu, run_n = 0;
-      __attribute__((address_space(1))) u32x2_t *cdst =
-          (__attribute__((address_space(1))) u32x2_t *)(codes + g.start + (uint64_t)i0);
+      // codes of two steps go out as one 16-byte store (fewer scattered
+      // store instructions: lanes are 64 bytes apart)
+      __attribute__((address_space(1))) u32x4_t *cdst =
+          (__attribute__((address_space(1))) u32x4_t *)(codes + g.start + (uint64_t)i0);
 #pragma unroll 1
-      for (int k = 0; k < 8; k++) {
+      for (int k2 = 0; k2 < 4; k2++) {
+      uint32_t wq[4];
+#pragma unroll
+      for (int kk = 0; kk < 2; kk++) {
+        const int k = 2 * k2 + kk;
         const int4 O = reinterpret_cast<const int4 *>(sp.o)[k];
         int4 Y = O, Z = O, ZY = O;
         if (NDIM >= 2) Y = reinterpret_cast<const int4 *>(sp.y)[k];
@@ -660,12 +667,17 @@ __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restri
             run_sym = sy;
           }
         }
-        if (!RECORDS) {
-          u32x2_t w;
-          w.x = c16[0] | (c16[1] << 16);
-          w.y = c16[2] | (c16[3] << 16);
-          cdst[k] = w;
-        }
+        wq[2 * kk] = c16[0] | (c16[1] << 16);
+        wq[2 * kk + 1] = c16[2] | (c16[3] << 16);
+      }
+      if (!RECORDS) {
+        u32x4_t w;
+        w.x = wq[0];
+        w.y = wq[1];
+        w.z = wq[2];
+        w.w = wq[3];
+        cdst[k2] = w;
+      }
       }
       if (!RECORDS) atomicAdd(&hist[run_sym], run_n);
     } else {
@@ -1259,7 +1271,6 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CJob one, const CJob *_
 // scan, the tile's word offset by look-back, each thread's bits packed into
 // an LDS image of the tile's words and stored coalesced.
 
-typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) uint32_t gu32_t;
 typedef __attribute__((address_space(1))) uint16_t gu16_t;
 
