@@ -1184,8 +1184,53 @@ __global__ __launch_bounds__(kBlock, 4) void k_rec_full(Plan P, const uint8_t *_
     for (int j = 0; j < 32; j++) vs.add(xr[j], v[j], A.eb);
     vs.store(A.vpart, t);
   }
-  if (sizeof(T) == 4) {
+  if constexpr (sizeof(T) == 4) {
     typedef __attribute__((address_space(1))) df32x4_t gf4;
+    // Rows are transposed through LDS so that each store instruction writes
+    // eight whole 128-byte rows (lane l: piece l % 8 of row l / 8 of a group
+    // of eight) instead of one 16-byte piece of each of 64 rows.  Two rounds
+    // of 32 rows per wave; every row of the wave must be 16-byte aligned.
+    __shared__ __align__(16) uint32_t s_out[(kBlock / 64) * 32 * kSegWD];
+    const int lane = tid & 63, wv = tid >> 6;
+    if (!__builtin_amdgcn_ballot_w64(((uintptr_t)(out + rowbase) & 15) != 0)) {
+      uint32_t *wb = s_out + wv * 32 * kSegWD;
+#pragma unroll
+      for (int h = 0; h < 2; h++) {
+        if ((lane >> 5) == h) {
+          du32x4_t *dst = reinterpret_cast<du32x4_t *>(wb + (lane & 31) * kSegWD);
+#pragma unroll
+          for (int k = 0; k < 8; k++) {
+            du32x4_t a;
+            a.x = __float_as_uint((float)v[4 * k]);
+            a.y = __float_as_uint((float)v[4 * k + 1]);
+            a.z = __float_as_uint((float)v[4 * k + 2]);
+            a.w = __float_as_uint((float)v[4 * k + 3]);
+            dst[k] = a;
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int rr = (lane >> 3) + 8 * j;  // row within the round
+          const du32x4_t a = reinterpret_cast<const du32x4_t *>(wb + rr * kSegWD)[lane & 7];
+          const RowMap<NDIM> ms(wv * 64 + 32 * h + rr);
+          const uint64_t rb =
+              ((g.z0 + ms.z) * P.ny + g.y0 + ms.y) * P.nx + g.x0 + 32 * ms.sg;
+          df32x4_t f;
+          f.x = __uint_as_float(a.x);
+          f.y = __uint_as_float(a.y);
+          f.z = __uint_as_float(a.z);
+          f.w = __uint_as_float(a.w);
+          ((gf4 *)(out + rb))[lane & 7] = f;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+      return;
+    }
     if (((uintptr_t)(out + rowbase) & 15) == 0) {
       gf4 *d = (gf4 *)(out + rowbase);
 #pragma unroll
