@@ -1036,7 +1036,7 @@ __global__ __launch_bounds__(kBlock) void k_proj_full(Plan P, const uint8_t *__r
 }
 
 template <typename T, int NDIM, bool GLOBAL>
-__global__ __launch_bounds__(kBlock, 4) void k_rec_full(Plan P, const uint8_t *__restrict__ blob,
+__global__ __launch_bounds__(kBlock, 3) void k_rec_full(Plan P, const uint8_t *__restrict__ blob,
                                                      DecodeArgs A, DevParams *__restrict__ dp,
                                                      const int16_t *__restrict__ codes,
                                                      T *__restrict__ out) {
@@ -1085,9 +1085,33 @@ __global__ __launch_bounds__(kBlock, 4) void k_rec_full(Plan P, const uint8_t *_
   const uint64_t rowbase = ((g.z0 + m.z) * P.ny + g.y0 + m.y) * P.nx + g.x0 + 32 * m.sg;
   // the original's values of this row (check in the decompression pass),
   // read first so that their latency overlaps the prefix sums
+  // Float rows go out transposed through LDS (see the end of the kernel)
+  // when every row of the wave is 16-byte aligned in the output and the
+  // original: lane l then holds piece l % 8 (four floats) of rows l / 8 + 8 J
+  // of the wave, J = 0..7, and reads the original in that layout too, so
+  // that each load and store instruction covers eight whole 128-byte rows.
+  const int lane = tid & 63, wv = tid >> 6;
+  bool tr = false;
+  if constexpr (sizeof(T) == 4) {
+    const bool al = ((uintptr_t)(out + rowbase) & 15) == 0 &&
+                    (!A.ref || ((uintptr_t)(static_cast<const T *>(A.ref) + rowbase) & 15) == 0);
+    tr = !__builtin_amdgcn_ballot_w64(!al);
+  }
+  // the wave's row r (0..63) starts at field element row_at(r)
+  auto row_at = [&](int r) -> uint64_t {
+    const RowMap<NDIM> ms(wv * 64 + r);
+    return ((g.z0 + ms.z) * P.ny + g.y0 + ms.y) * P.nx + g.x0 + 32 * ms.sg;
+  };
   T xr[32];
   const bool ref_vec = A.ref && ((uintptr_t)(static_cast<const T *>(A.ref) + rowbase) & 15) == 0;
-  if (A.ref) {
+  if (A.ref && tr) {
+    typedef __attribute__((address_space(1))) const df32x4_t gcf4;
+#pragma unroll
+    for (int J = 0; J < 8; J++) {
+      const df32x4_t a = ((gcf4 *)(static_cast<const T *>(A.ref) + row_at((lane >> 3) + 8 * J)))[lane & 7];
+      xr[4 * J] = a.x; xr[4 * J + 1] = a.y; xr[4 * J + 2] = a.z; xr[4 * J + 3] = a.w;
+    }
+  } else if (A.ref) {
     const T *ref = static_cast<const T *>(A.ref) + rowbase;
     if (ref_vec) {
       typedef __attribute__((address_space(1))) const df32x4_t gcf4;
@@ -1178,21 +1202,20 @@ __global__ __launch_bounds__(kBlock, 4) void k_rec_full(Plan P, const uint8_t *_
     if (tid == 0) atomicOr(&dp->corrupt, 1u);
     return;
   }
-  if (A.ref) {  // uniform: the check against the original
-    VStat vs;
+  // the check against the original: per-thread sums in a fixed order (row
+  // order, or piece order in the transposed layout), then the block's
+  VStat vs;
+  if (A.ref && !tr) {
 #pragma unroll
     for (int j = 0; j < 32; j++) vs.add(xr[j], v[j], A.eb);
-    vs.store(A.vpart, t);
   }
   if constexpr (sizeof(T) == 4) {
     typedef __attribute__((address_space(1))) df32x4_t gf4;
-    // Rows are transposed through LDS so that each store instruction writes
-    // eight whole 128-byte rows (lane l: piece l % 8 of row l / 8 of a group
-    // of eight) instead of one 16-byte piece of each of 64 rows.  Two rounds
-    // of 32 rows per wave; every row of the wave must be 16-byte aligned.
-    __shared__ __align__(16) uint32_t s_out[(kBlock / 64) * 32 * kSegWD];
-    const int lane = tid & 63, wv = tid >> 6;
-    if (!__builtin_amdgcn_ballot_w64(((uintptr_t)(out + rowbase) & 15) != 0)) {
+    if (tr) {
+      // rows transposed through LDS: two rounds of 32 rows per wave; in
+      // round h lane l stores piece l % 8 of rows l / 8 + 8 j (j = 0..3) of
+      // that half, i.e. eight whole rows per store instruction
+      __shared__ __align__(16) uint32_t s_out[(kBlock / 64) * 32 * kSegWD];
       uint32_t *wb = s_out + wv * 32 * kSegWD;
 #pragma unroll
       for (int h = 0; h < 2; h++) {
@@ -1215,23 +1238,25 @@ __global__ __launch_bounds__(kBlock, 4) void k_rec_full(Plan P, const uint8_t *_
         for (int j = 0; j < 4; j++) {
           const int rr = (lane >> 3) + 8 * j;  // row within the round
           const du32x4_t a = reinterpret_cast<const du32x4_t *>(wb + rr * kSegWD)[lane & 7];
-          const RowMap<NDIM> ms(wv * 64 + 32 * h + rr);
-          const uint64_t rb =
-              ((g.z0 + ms.z) * P.ny + g.y0 + ms.y) * P.nx + g.x0 + 32 * ms.sg;
           df32x4_t f;
           f.x = __uint_as_float(a.x);
           f.y = __uint_as_float(a.y);
           f.z = __uint_as_float(a.z);
           f.w = __uint_as_float(a.w);
-          ((gf4 *)(out + rb))[lane & 7] = f;
+          ((gf4 *)(out + row_at(32 * h + rr)))[lane & 7] = f;
+          if (A.ref) {
+            const int J = 4 * h + j;  // the same rows' piece of the original
+            vs.add(xr[4 * J], f.x, A.eb);
+            vs.add(xr[4 * J + 1], f.y, A.eb);
+            vs.add(xr[4 * J + 2], f.z, A.eb);
+            vs.add(xr[4 * J + 3], f.w, A.eb);
+          }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
-      return;
-    }
-    if (((uintptr_t)(out + rowbase) & 15) == 0) {
+    } else if (((uintptr_t)(out + rowbase) & 15) == 0) {
       gf4 *d = (gf4 *)(out + rowbase);
 #pragma unroll
       for (int k = 0; k < 8; k++) {
@@ -1239,7 +1264,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_rec_full(Plan P, const uint8_t *_
         a.x = (float)v[4 * k]; a.y = (float)v[4 * k + 1]; a.z = (float)v[4 * k + 2]; a.w = (float)v[4 * k + 3];
         d[k] = a;
       }
-      return;
+    } else {
+      typedef __attribute__((address_space(1))) T gT;
+#pragma unroll
+      for (int j = 0; j < 32; j++) ((gT *)out)[rowbase + j] = v[j];
     }
   } else {
     typedef __attribute__((address_space(1))) df64x2_t gd2;
@@ -1251,12 +1279,13 @@ __global__ __launch_bounds__(kBlock, 4) void k_rec_full(Plan P, const uint8_t *_
         a.x = (double)v[2 * k]; a.y = (double)v[2 * k + 1];
         d[k] = a;
       }
-      return;
+    } else {
+      typedef __attribute__((address_space(1))) T gT;
+#pragma unroll
+      for (int j = 0; j < 32; j++) ((gT *)out)[rowbase + j] = v[j];
     }
   }
-  typedef __attribute__((address_space(1))) T gT;
-#pragma unroll
-  for (int j = 0; j < 32; j++) ((gT *)out)[rowbase + j] = v[j];
+  if (A.ref) vs.store(A.vpart, t);  // uniform over the block (it has barriers)
 }
 
 // ---------------------------------------------------------------------------
