@@ -128,8 +128,32 @@ def test_parity_outliers_and_patches(ctx, orc):
     xf = synth.field_2d_grf(300, 200, seed=3)
     info, _ = _parity(ctx, orc, xf, 120.0, 0)
     assert info["n_patches"] > 0
-    # float64 at 150 dB: deep escapes and 2-record patches
+    # float64 at 150 dB: deep escape classes and many outliers (no patches:
+    # the float64 patch path has its own case below)
     _parity(ctx, orc, xf.astype(np.float64) * 1.0001, 150.0, 0)
+
+
+@pytest.mark.parametrize("shape", [(17, 33, 70), (33, 48, 96)])
+def test_parity_f64_patches(ctx, orc, shape):
+    # float64 values within three ulps of bin edges: two-record patches in a
+    # full tile, in edge-clipped tiles, in a tile with more records than its
+    # 64-record staging slot and beside outliers in one 32-point segment;
+    # both Lorenzo domains, the separate and the fused check
+    import patchfield as pf
+    x = pf.f64_patch_field(shape=shape)
+    _, ot = orc.compress(x, pf.PSNR, trace=True)
+    assert ot["n_patches"] > 100 and ot["n_outliers"] > 0
+    info, y = _parity(ctx, orc, x, pf.PSNR, 0)
+    assert info["n_patches"] == ot["n_patches"]
+    _parity(ctx, orc, x, pf.PSNR, 1)
+    ob = orc.compress(x, pf.PSNR)[0]
+    oy = orc.decompress(ob)
+    blob = torch.from_numpy(np.frombuffer(ob, dtype=np.uint8).copy()).cuda()
+    y2, st = ctx.decompress_verify(blob, torch.from_numpy(x).cuda())
+    assert np.array_equal(_bits(y2.cpu().numpy()), _bits(oy))
+    os_ = orc.stats(x, oy, ot["vr"], ot["eb"])
+    assert st["n_over_eb"] == 0 and st["max_abs_err"] == os_["max_abs_err"]
+    assert abs(st["sse"] - os_["sse"]) <= 1e-9 * os_["sse"]
 
 
 def test_parity_config1_full_size(ctx, orc):

@@ -438,6 +438,67 @@ def test_outliers_and_patches_round_trip(orc):
     assert t["n_patches"] > 0
 
 
+def _exception_records(orc, blob):
+    """(key, value) u32 pairs of the blob's exception section, located from
+    the header by the section sizes of the format (code lengths, two tile
+    offset tables, chunk bit counts; 8-byte aligned)."""
+    h = orc.header(blob)
+    al = lambda v: (v + 7) & ~7
+    off = al(256 + 1036)
+    off = al(off + 8 * (h["n_tiles"] + 1))
+    off = al(off + 8 * (h["n_tiles"] + 1))
+    off = al(off + 2 * h["n_chunks"])
+    rec = np.frombuffer(bytes(blob), np.uint32, 2 * h["n_exc"], off)
+    return rec[0::2], rec[1::2]
+
+
+def test_f64_patch_records_pinned(orc):
+    # float64 input at 100 dB with values within three ulps of bin edges: a
+    # point whose float64 prequantization misses the bound (Sec. IV / Eq. 6:
+    # |x - x'| <= eb_abs) is stored as a patch of two records (position with
+    # the patch tag, low word), (same key, high word).  Expected records come
+    # from numpy alone: q = rint(x / 2eb) in float64, residuals by np.diff
+    # (Lorenzo, Eq. 1), patches where |x - q 2eb| > eb, all in stream order.
+    import patchfield as pf
+    x = pf.f64_patch_field()
+    blob, t = orc.compress(x, pf.PSNR, trace=True)
+    assert t["vr"] == 2.0 and t["eb"] == pf.eb_of(pf.PSNR)
+    q = np.rint(x * t["r"])
+    patched = np.abs(x - q * t["e2"]) > t["eb"]
+    d = _np_lorenzo(q.astype(np.int64))
+    outl = np.abs(d) >= 2 ** 15
+    assert patched.sum() == t["n_patches"] > 100 and outl.sum() == t["n_outliers"] > 0
+    pos = pf.stream_positions(x.shape)
+    order = np.argsort(pos, axis=None)
+    keys, vals = [], []
+    bits = x.view(np.uint64).ravel()
+    for i in order:
+        p = int(pos.flat[i])
+        if outl.flat[i]:
+            keys.append(p)
+            vals.append(int(d.flat[i]) & 0xFFFFFFFF)
+        if patched.flat[i]:
+            keys += [p | 0x80000000, p | 0x80000000]
+            vals += [int(bits[i]) & 0xFFFFFFFF, int(bits[i]) >> 32]
+    gk, gv = _exception_records(orc, blob)
+    assert np.array_equal(gk, np.array(keys, np.uint32))
+    assert np.array_equal(gv, np.array(vals, np.uint32))
+    # the cases the field is built to reach: a tile with more records than a
+    # 64-record staging slot, patches in edge-clipped tiles, a 32-point
+    # segment holding both an outlier and a patch
+    tile0 = gk & 0x7FFFFFFF < 8192
+    assert tile0.sum() > 64
+    assert np.any(patched[16:, :, :]) and np.any(patched[:, 32:, :]) and np.any(patched[:, :, 64:])
+    seg_o = set((pos[outl] // 32).tolist())
+    seg_p = set((pos[patched & (pos < 8192)] // 32).tolist())
+    assert seg_o & seg_p
+    # decompression writes the two halves back as the original 64 bits
+    y = orc.decompress(blob)
+    assert np.array_equal(y.view(np.uint64)[patched], x.view(np.uint64)[patched])
+    assert np.array_equal(y[~patched], (q * t["e2"])[~patched])
+    assert np.max(np.abs(x - y)) <= t["eb"]
+
+
 def test_error_statuses(orc):
     x = np.ones((10, 10), dtype=np.float32)
     blob = orc.compress(x, 80.0)[0]
