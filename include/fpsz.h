@@ -262,13 +262,18 @@ fpsz_status fpsz_compress_batch(fpsz_ctx *ctx, int n, const fpsz_field_desc *fie
  * others run join the next admission round (continuous batching).  Compress
  * requests of one round that share (dtype, ndim, domain) run as one batched
  * launch; rounds go to `n_streams` streams (default priority) and overlap on
- * the device.  Workspaces come from a device arena of `arena_bytes`
+ * the device, at most one unfinished round per stream: while every stream is
+ * busy, arrivals wait and then form one round together.  Workspaces come from a device arena of `arena_bytes`
  * allocated at creation; no device memory is allocated per request.  Every
  * result is bit-identical to the plain call on the same inputs.
  *
- * Buffers named in a request are the caller's: inputs must be complete
- * (their producing work synchronized) before submission and stay untouched,
- * and outputs must not be read, until the request is done. */
+ * Buffers named in a request are the caller's.  Inputs must be complete
+ * when the request starts on the device: either their producing work is
+ * synchronized before submission, or `ready_event` is a hipEvent_t the caller
+ * recorded on the producing stream after that work (the server's stream waits
+ * on it before the request's first copy or launch; the event must stay valid,
+ * and not be recorded again, until the request is done).  Inputs stay
+ * untouched, and outputs must not be read, until the request is done. */
 enum { FPSZ_REQ_COMPRESS = 0, FPSZ_REQ_DECOMPRESS = 1 };
 
 typedef struct {
@@ -282,6 +287,7 @@ typedef struct {
   uint64_t src_bytes;   /* decompress: blob bytes */
   void *dst_dev;        /* compress: blob buffer; decompress: field buffer */
   uint64_t dst_capacity;
+  void *ready_event;    /* hipEvent_t marking the inputs complete, or NULL */
 } fpsz_request;
 
 typedef struct {

@@ -971,7 +971,8 @@ template <int NDIM> __device__ inline void tile_prefix(uint32_t r[32], uint32_t 
   }
 }
 
-template <int NDIM>
+// RW: exception records per patch (1 for float32 blobs, 2 for float64)
+template <int NDIM, int RW>
 __global__ __launch_bounds__(kBlock) void k_proj_full(Plan P, const uint8_t *__restrict__ blob,
                                                       DecodeArgs A, DevParams *__restrict__ dp,
                                                       const int16_t *__restrict__ codes) {
@@ -994,7 +995,7 @@ __global__ __launch_bounds__(kBlock) void k_proj_full(Plan P, const uint8_t *__r
   if (tid == 0) s_bad = 0;
   __syncthreads();
   uint32_t r[32];
-  (void)load_segment<NDIM, 1>(g, codes, exc, e0, e1, r, lds_m, scr, &s_bad);
+  (void)load_segment<NDIM, RW>(g, codes, exc, e0, e1, r, lds_m, scr, &s_bad);
   tile_prefix<NDIM>(r, lds_t);
   __syncthreads();
   if (s_bad) {
@@ -1482,7 +1483,8 @@ static void launch_dec_t(const Plan &P, const uint8_t *blob, const DecodeArgs &A
   tm->mark(s, "decode");
   const bool ragged = P.pad_ != 0;
   if (P.domain == FPSZ_DOMAIN_GLOBAL) {
-    hipLaunchKernelGGL((k_proj_full<NDIM>), grid, blk, 0, s, P, blob, A, dp, codes);
+    hipLaunchKernelGGL((k_proj_full<NDIM, (int)(sizeof(T) / 4)>), grid, blk, 0, s, P, blob, A, dp,
+                       codes);
     if (ragged) hipLaunchKernelGGL((k_proj<NDIM>), grid, blk, 0, s, P, blob, A, dp, codes);
     tm->mark(s, "proj");
     const uint64_t gz = P.gz, gy = P.gy, gx = P.gx;

@@ -11,7 +11,9 @@
 // go out as one batched launch (one launch per pipeline step over all of
 // them); decompress requests first read their 256-byte header
 // asynchronously, then launch.  Rounds run on different streams, so their
-// work overlaps on the device.  Nothing is synchronized on the host: the
+// work overlaps on the device; a stream takes a new round only when its
+// previous one has finished, so under load arrivals accumulate into larger
+// rounds.  Nothing is synchronized on the host: the
 // worker polls events.  Every request computes exactly what a plain call
 // computes, so results are bit-identical alone and in the mix.
 #include <chrono>
@@ -192,6 +194,13 @@ void launch_compress_group(fpsz_server *S, const std::vector<uint64_t> &ids, int
   hipStream_t s = S->streams[si];
   Timer off;
   off.on = false;
+  hipError_t e = hipSuccess;
+  // the callers' inputs are complete before anything of the group runs
+  for (uint64_t id : ids) {
+    const SReq &q = S->reqs[id];
+    if (q.r.ready_event && e == hipSuccess)
+      e = hipStreamWaitEvent(s, (hipEvent_t)q.r.ready_event, 0);
+  }
   Plan maxP = S->reqs[ids[0]].cj.P;
   for (uint64_t id : ids) {
     const Plan &P = S->reqs[id].cj.P;
@@ -201,10 +210,9 @@ void launch_compress_group(fpsz_server *S, const std::vector<uint64_t> &ids, int
     maxP.pad_ |= P.pad_;
   }
   const LaunchCfg cfg = default_launch_cfg(maxP);
-  hipError_t e = hipSuccess;
   uint64_t toff = 0;
   const uint64_t tbytes = ids.size() * sizeof(CJob);
-  if (ids.size() > 1 && S->tab_arena.alloc(tbytes, &toff)) {
+  if (e == hipSuccess && ids.size() > 1 && S->tab_arena.alloc(tbytes, &toff)) {
     // one batched launch per step over the group
     const int64_t g = S->next_group++;
     Group &G = S->groups[g];
@@ -244,8 +252,29 @@ void launch_compress_group(fpsz_server *S, const std::vector<uint64_t> &ids, int
   }
 }
 
+// A stream with no unfinished request of an earlier round, or -1.  At most
+// one round is in flight per stream: while every stream is busy, arrivals
+// wait and the next round takes all of them (one batched launch per class)
+// instead of queueing one launch sequence per request behind the others.
+int free_stream(fpsz_server *S) {
+  const int ns = (int)S->streams.size();
+  std::vector<char> busy(ns, 0);
+  for (uint64_t id : S->active) {
+    const SReq &q = S->reqs[id];
+    if (q.st != R_DONE) busy[q.stream] = 1;
+  }
+  for (int k = 0; k < ns; k++) {
+    const int si = (S->next_stream + k) % ns;
+    if (!busy[si]) return si;
+  }
+  return -1;
+}
+
 // admission of pending requests in arrival order; returns true if any
 bool admit(fpsz_server *S) {
+  if (S->pending.empty()) return false;
+  const int si = free_stream(S);
+  if (si < 0) return false;
   std::vector<uint64_t> round;
   const double t = now_s(S->t0);
   while (!S->pending.empty() && !S->free_slots.empty()) {
@@ -269,8 +298,7 @@ bool admit(fpsz_server *S) {
     round.push_back(q.id);
   }
   if (round.empty()) return false;
-  const int si = S->next_stream;
-  S->next_stream = (S->next_stream + 1) % (int)S->streams.size();
+  S->next_stream = (si + 1) % (int)S->streams.size();
   S->stats.rounds++;
   hipStream_t s = S->streams[si];
   // compress requests grouped by class; decompress requests read headers
@@ -292,8 +320,10 @@ bool admit(fpsz_server *S) {
       }
       cls[(q.cj.P.dtype * 4 + q.cj.P.ndim) * 2 + q.cj.P.domain].push_back(id);
     } else {
-      hipError_t e = hipMemcpyAsync(slot_header(S, q.slot), q.r.src_dev, kHdr,
-                                    hipMemcpyDeviceToHost, s);
+      hipError_t e = hipSuccess;
+      if (q.r.ready_event) e = hipStreamWaitEvent(s, (hipEvent_t)q.r.ready_event, 0);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(slot_header(S, q.slot), q.r.src_dev, kHdr, hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipEventRecord(S->slot_ev[q.slot], s);
       if (e != hipSuccess) {
         finish(S, q, hip_fail(S->ctx, e, "header read"));

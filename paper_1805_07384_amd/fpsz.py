@@ -66,7 +66,7 @@ class Request(ctypes.Structure):
                 ("domain", ctypes.c_int32), ("dims", ctypes.c_uint64 * 3),
                 ("target_psnr", ctypes.c_double), ("src_dev", ctypes.c_void_p),
                 ("src_bytes", ctypes.c_uint64), ("dst_dev", ctypes.c_void_p),
-                ("dst_capacity", ctypes.c_uint64)]
+                ("dst_capacity", ctypes.c_uint64), ("ready_event", ctypes.c_void_p)]
 
 
 class Result(ctypes.Structure):
@@ -514,6 +514,12 @@ class Server:
         return self._submit(r, (blob, out))
 
     def _submit(self, r, keep) -> int:
+        # the inputs may still be in flight on torch's current stream: the
+        # server's stream waits on an event recorded there after them
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream())
+        r.ready_event = ev.cuda_event
+        keep = keep + (ev,)
         rid = ctypes.c_uint64()
         st = self.lib.fpsz_server_submit(self.handle, ctypes.byref(r), ctypes.byref(rid))
         if st != OK:
