@@ -126,6 +126,26 @@ fpsz_status fpsz_compress(fpsz_ctx *ctx, const void *field_dev, int ndim, const 
                           uint64_t blob_capacity, uint64_t *blob_bytes, fpsz_info *info,
                           void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): fpsz_compress
+ * with the library's own device workspace instead of workspace_dev.  That
+ * workspace is a static array of FPSZ_STATIC_WORKSPACE_BYTES per device (held
+ * from the library's load until the process ends); its address is looked up
+ * once per device in fpsz_create.  The call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine); arguments and results are those of
+ * fpsz_compress.  CAPACITY (nothing launched, *blob_bytes = 0) when
+ * fpsz_compress_workspace_bytes for the shape exceeds
+ * FPSZ_STATIC_WORKSPACE_BYTES; DEVICE when the workspace address could not be
+ * had.  Every call on one device shares that device's array and leaves its
+ * contents behind (each call clears what it needs): calls that overlap in
+ * time on one device, from any contexts or threads, race and corrupt each
+ * other's output. */
+#define FPSZ_STATIC_WORKSPACE_BYTES (64ull << 20)
+fpsz_status fpsz_compress_static(fpsz_ctx *ctx, const void *field_dev, int ndim,
+                                 const uint64_t *dims, fpsz_dtype dtype, double target_psnr,
+                                 fpsz_domain domain, void *blob_dev, uint64_t blob_capacity,
+                                 uint64_t *blob_bytes, fpsz_info *info, void *stream);
+
 /* Parse a blob header held in HOST memory (the first 256 bytes suffice).
  * dims receives 3 entries (unused ones = 1).  CORRUPT on a bad magic or
  * version, INVALID_ARG on NULL pointers or bytes < 256. */

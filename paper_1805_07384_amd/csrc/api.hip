@@ -6,11 +6,45 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "host_common.h"
 
 using namespace fpsz;
+
+// Device workspace of fpsz_compress_static.  In host code `scratch` names a
+// host-side stand-in, not the device address: kernels and copies get the
+// per-device address looked up in fpsz_create (scratch_ptr).
+static __device__ __align__(256) uint8_t scratch[FPSZ_STATIC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+
+// Once per device, with that device current.
+void scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  g_scratch_err[dev] = e;
+  if (e == hipSuccess) g_scratch_ptr[dev] = p;
+}
+
+void *scratch_ptr(int dev, hipError_t *err) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  *err = g_scratch_err[dev];
+  return g_scratch_ptr[dev];
+}
+}  // namespace
 
 extern "C" {
 
@@ -51,6 +85,9 @@ fpsz_status fpsz_create(int hip_device, fpsz_ctx **out) {
     delete c;
     return FPSZ_E_NOMEM;
   }
+  // the static workspace's address on this device (fpsz_compress_static
+  // reports a failure here when it is called)
+  scratch_setup(hip_device);
   *out = c;
   return FPSZ_OK;
 }
@@ -173,6 +210,28 @@ fpsz_status fpsz_compress(fpsz_ctx *ctx, const void *field_dev, int ndim, const 
   const DevParams &D = *ctx->host;
   if (info) fill_compress_info(info, job.P, D);
   return compress_result(ctx, job.P, D, blob_bytes);
+}
+
+fpsz_status fpsz_compress_static(fpsz_ctx *ctx, const void *field_dev, int ndim,
+                                 const uint64_t *dims, fpsz_dtype dtype, double target_psnr,
+                                 fpsz_domain domain, void *blob_dev, uint64_t blob_capacity,
+                                 uint64_t *blob_bytes, fpsz_info *info, void *stream) {
+  if (!ctx) return FPSZ_E_INVALID_ARG;
+  ctx->err[0] = 0;
+  if (blob_bytes) *blob_bytes = 0;
+  Plan P;
+  if (make_plan(ndim, dims, dtype, &P) != FPSZ_OK)
+    return fail(ctx, FPSZ_E_INVALID_ARG, "bad shape or dtype");
+  const uint64_t need = compress_layout(P).total;
+  if (need > FPSZ_STATIC_WORKSPACE_BYTES)
+    return fail(ctx, FPSZ_E_CAPACITY, "field needs %llu workspace bytes; the static workspace holds %llu",
+                (unsigned long long)need, (unsigned long long)FPSZ_STATIC_WORKSPACE_BYTES);
+  hipError_t e = hipSuccess;
+  void *ws = scratch_ptr(ctx->device, &e);
+  if (!ws) return fail(ctx, FPSZ_E_DEVICE, "static workspace address: %s", hipGetErrorString(e));
+  return fpsz_compress(ctx, field_dev, ndim, dims, dtype, target_psnr, domain, ws,
+                       FPSZ_STATIC_WORKSPACE_BYTES, blob_dev, blob_capacity, blob_bytes, info,
+                       stream);
 }
 
 fpsz_status fpsz_blob_header(const void *blob_host, uint64_t bytes, int *ndim, uint64_t *dims,

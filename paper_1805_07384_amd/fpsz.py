@@ -20,6 +20,7 @@ OK, E_INVALID_ARG, E_NONFINITE, E_RANGE, E_CORRUPT, E_CAPACITY, E_NOMEM, E_DEVIC
 F32, F64 = 0, 1
 GLOBAL, TILE = 0, 1
 HDR_BYTES = 256
+STATIC_WORKSPACE_BYTES = 64 << 20  # FPSZ_STATIC_WORKSPACE_BYTES
 
 
 class FpszError(RuntimeError):
@@ -110,6 +111,9 @@ SIGNATURES = {
     "fpsz_compress": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _u64p, ctypes.c_int, ctypes.c_double,
                                      ctypes.c_int, _vp, ctypes.c_uint64, _vp, ctypes.c_uint64,
                                      _u64p, ctypes.POINTER(Info), _vp]),
+    "fpsz_compress_static": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _u64p, ctypes.c_int,
+                                            ctypes.c_double, ctypes.c_int, _vp, ctypes.c_uint64,
+                                            _u64p, ctypes.POINTER(Info), _vp]),
     "fpsz_blob_header": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), _u64p,
                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(Info)]),
     "fpsz_decompress": (ctypes.c_int, [_vp, _vp, ctypes.c_uint64, _vp, ctypes.c_uint64, _vp,
@@ -304,6 +308,20 @@ class Context:
                                     workspace.numel() * workspace.element_size(), blob.data_ptr(),
                                     blob.numel(), ctypes.byref(nb), ctypes.byref(info),
                                     _stream(stream))
+        return st, nb.value, info
+
+    def compress_static(self, x: torch.Tensor, psnr: float, blob: torch.Tensor,
+                        domain: int = GLOBAL, stream=None):
+        """fpsz_compress_static: compress x into ``blob`` using the library's
+        static device workspace (no allocation); returns (status,
+        blob_bytes, Info)."""
+        assert x.is_contiguous() and x.is_cuda
+        nb = ctypes.c_uint64()
+        info = Info()
+        st = self.lib.fpsz_compress_static(self.handle, x.data_ptr(), x.dim(), _dims(x.shape),
+                                           _dtype_code(x), float(psnr), int(domain),
+                                           blob.data_ptr(), blob.numel(), ctypes.byref(nb),
+                                           ctypes.byref(info), _stream(stream))
         return st, nb.value, info
 
     def decompress_into(self, blob: torch.Tensor, nbytes: int, workspace: torch.Tensor,
