@@ -9,7 +9,13 @@ the GPU from a fixed seed and are resident in HBM before timing starts.
 
 value = uncompressed bytes pushed through compress + decompress + verify per
 second, summed over the sweep (GB/s, 1e9 B/s).  Per-target compress and
-decompress rates and |PSNR - target| are reported beside it.
+decompress rates, |PSNR - target| and operation-level roofline fractions
+(algorithmic bytes: compress 2s + b/8, decompress b/8 + s, decompress with
+the check b/8 + 2s per point, over 8 TB/s) are reported beside it, with the
+device-copy bandwidth measured in the same run.  Side legs: the 2D float32
+512x512 field (latency per call), the 3D float64 1024^3 field with spikes at
+100 dB, 120 batched 1800x3600 fields, and a served request trace at two
+arrival rates.
 """
 from __future__ import annotations
 
@@ -44,7 +50,11 @@ def parse():
                     help="skip the 120-field batched-vs-plain leg")
     ap.add_argument("--no-served", action="store_true",
                     help="skip the served-vs-plain request-trace leg")
-    ap.add_argument("--served-requests", type=int, default=400)
+    ap.add_argument("--served-requests", type=int, default=2000)
+    ap.add_argument("--served-rates", default="200,3000,20000",
+                    help="arrival rates (requests/s) the trace is replayed at")
+    ap.add_argument("--no-c1", action="store_true", help="skip the 512x512 latency leg")
+    ap.add_argument("--no-c5", action="store_true", help="skip the 1024^3 float64 leg")
     ap.add_argument("--separate-verify", action="store_true",
                     help="check each reconstruction with its own fpsz_verify call instead of "
                          "in the decompression pass (fpsz_decompress_verify)")
@@ -111,24 +121,158 @@ def algorithmic_bytes(stage: str, n: int, s: int, b: float, fused_check: bool = 
     return None if per is None else per * n
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(x_cpu, psnrs, planes):
-    """The CPU oracle, untuned, on a contiguous slab of the same field."""
+    """The CPU oracle, untuned, single-threaded, on a contiguous slab of the
+    same field; per-stage wall times from the oracle's own timers."""
     import numpy as np
 
     import oracle
 
     sample = np.ascontiguousarray(x_cpu[:planes])
+    stages = {}
     t0 = time.perf_counter()
     for p in psnrs:
         blob, t = oracle.compress(sample, p, trace=False)
         y = oracle.decompress(blob)
         h = oracle.header(blob)
         oracle.stats(sample, y, h["vr"], h["eb"])
+        for k, v in oracle.stage_times().items():
+            stages[k] = stages.get(k, 0.0) + v
     dt = time.perf_counter() - t0
     gbps = sample.nbytes * len(psnrs) / dt / 1e9
+    ne = sample.size * len(psnrs)
     return {"value": round(gbps, 6), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": "float32 slab %s of the benchmark field, compress+decompress+Eq.4 stats at %s dB"
-                      " (%.1f s)" % (list(sample.shape), "/".join("%g" % p for p in psnrs), dt)}
+                      " (%.1f s)" % (list(sample.shape), "/".join("%g" % p for p in psnrs), dt),
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+            "stage_ns_per_point": {k: round(v / ne * 1e9, 2) for k, v in stages.items()}}
+
+
+def op_fracs(n, s, bits, t_c, t_d, t_dc=None):
+    """Operation-level fractions of the 8 TB/s HBM peak on algorithmic bytes:
+    compress 2s + b/8 (the range read, the quantization read, the blob write),
+    decompress b/8 + s (blob read, field write), decompress with the check
+    b/8 + 2s (the original read too)."""
+    b8 = bits / 8.0
+    out = {"compress": round((2 * s + b8) * n / t_c / 1e9 / HBM_PEAK_GBPS, 4)}
+    if t_d:
+        out["decompress"] = round((b8 + s) * n / t_d / 1e9 / HBM_PEAK_GBPS, 4)
+    if t_dc:
+        out["decompress_check"] = round((b8 + 2 * s) * n / t_dc / 1e9 / HBM_PEAK_GBPS, 4)
+    return out
+
+
+def device_copy_gbps(x, reps=10):
+    """Bandwidth of a plain device copy of the field (read + write bytes)."""
+    import numpy as np
+    import torch
+
+    y = torch.empty_like(x)
+    ts = []
+    for _ in range(reps + 2):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        y.copy_(x)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b) * 1e-3)
+    del y
+    return 2.0 * x.numel() * x.element_size() / float(np.median(ts[2:])) / 1e9
+
+
+def timed_calls(fn, reps, warm=3):
+    import numpy as np
+    import torch
+
+    for _ in range(warm):
+        fn()
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)), float(np.percentile(ts, 90))
+
+
+def c1_leg(ctx, dev):
+    """2D float32 512x512 GRF (k^-3) on [-50, 50] at 80 dB: a latency-bound
+    call; median and p90 of 30 calls each after 3 warm-ups."""
+    import torch
+
+    from paper_1805_07384_amd import fpsz, synth
+
+    x = synth.field_2d_grf(512, 512, seed=1, backend="torch", device=dev).contiguous()
+    ws_c = torch.empty(fpsz.compress_workspace_bytes(tuple(x.shape)), dtype=torch.uint8, device=dev)
+    ws_d = torch.empty(fpsz.decompress_workspace_bytes(tuple(x.shape)), dtype=torch.uint8,
+                       device=dev)
+    blob = torch.empty(fpsz.compress_bound(tuple(x.shape)), dtype=torch.uint8, device=dev)
+    out = torch.empty_like(x)
+    st, nb, info = ctx.compress_into(x, 80.0, ws_c, blob)
+    assert st == fpsz.OK
+    c = timed_calls(lambda: ctx.compress_into(x, 80.0, ws_c, blob), 30)
+    d = timed_calls(lambda: ctx.decompress_into(blob, nb, ws_d, out), 30)
+    dv = timed_calls(lambda: ctx.decompress_verify_into(blob, nb, ws_d, out, x), 30)
+    st2, stats = ctx.decompress_verify_into(blob, nb, ws_d, out, x)
+    n, s = x.numel(), 4
+    return {"workload": "2D float32 512x512 GRF k^-3 on [-50, 50], seed 1, 80 dB",
+            "compress_us": round(c[0] * 1e6, 1), "compress_us_p90": round(c[1] * 1e6, 1),
+            "decompress_us": round(d[0] * 1e6, 1), "decompress_us_p90": round(d[1] * 1e6, 1),
+            "decompress_check_us": round(dv[0] * 1e6, 1),
+            "bits_per_value": round(info.bits_per_value, 4),
+            "achieved_psnr": round(stats.psnr, 4), "dpsnr": round(stats.psnr - 80.0, 4),
+            "n_over_eb": stats.n_over_eb,
+            "op_frac": op_fracs(n, s, info.bits_per_value, c[0], d[0], dv[0])}
+
+
+def c5_leg(ctx, dev):
+    """3D float64 1024^3 GRF (k^-3) with 1 % spikes of 1000 sigma at 100 dB:
+    device-resident compress and decompress with the fused Eq. 4 check,
+    median of 3 calls each after one warm-up."""
+    import torch
+
+    from paper_1805_07384_amd import fpsz, synth
+
+    shape = (1024, 1024, 1024)
+    x = synth.field_3d_spiky_f64(shape=shape, seed=5, backend="torch", device=dev).contiguous()
+    torch.cuda.synchronize()
+    n, s = x.numel(), 8
+    ws_c = torch.empty(fpsz.compress_workspace_bytes(shape, x.dtype), dtype=torch.uint8, device=dev)
+    blob = torch.empty(n * 4 + (1 << 20), dtype=torch.uint8, device=dev)
+    st, nb, info = ctx.compress_into(x, 100.0, ws_c, blob)
+    if st != fpsz.OK:
+        raise fpsz.FpszError(st, "C5 compress")
+    c = timed_calls(lambda: ctx.compress_into(x, 100.0, ws_c, blob), 3, warm=1)
+    del ws_c
+    ws_d = torch.empty(fpsz.decompress_workspace_bytes(shape, x.dtype), dtype=torch.uint8,
+                       device=dev)
+    out = torch.empty_like(x)
+    d = timed_calls(lambda: ctx.decompress_into(blob, nb, ws_d, out), 3, warm=1)
+    dv = timed_calls(lambda: ctx.decompress_verify_into(blob, nb, ws_d, out, x), 3, warm=1)
+    st2, stats = ctx.decompress_verify_into(blob, nb, ws_d, out, x)
+    res = {"workload": "3D float64 1024^3 GRF k^-3 plus 1%% spikes of 1000 sigma, seed 5, 100 dB",
+           "bytes": n * s, "compress_ms": round(c[0] * 1e3, 3), "decompress_ms": round(d[0] * 1e3, 3),
+           "decompress_check_ms": round(dv[0] * 1e3, 3),
+           "compress_gbps": round(n * s / c[0] / 1e9, 1), "decompress_gbps": round(n * s / d[0] / 1e9, 1),
+           "bits_per_value": round(info.bits_per_value, 4), "n_outliers": info.n_outliers,
+           "n_patches": info.n_patches, "achieved_psnr": round(stats.psnr, 4),
+           "dpsnr": round(stats.psnr - 100.0, 4), "n_over_eb": stats.n_over_eb,
+           "op_frac": op_fracs(n, s, info.bits_per_value, c[0], d[0], dv[0])}
+    del x, blob, ws_d, out
+    torch.cuda.empty_cache()
+    return res
 
 
 def progress(msg):
@@ -215,38 +359,44 @@ def batched_leg(ctx, dev):
     return res
 
 
-def served_leg(ctx, dev, n_req):
-    """Seeded request trace (Poisson 200/s, 70 % compress / 30 % decompress,
+def served_leg(ctx, dev, n_req, rates):
+    """Seeded request trace (Poisson arrivals, 70 % compress / 30 % decompress,
     lognormal sizes median 16 MiB in [1 MiB, 2 GiB], 1D/2D/3D, targets
     U[40,120] dB) replayed in real time through the server and through
-    one-at-a-time plain calls."""
+    one-at-a-time plain calls, at each arrival rate (the same requests, the
+    arrival times scaled)."""
     import torch
 
     from paper_1805_07384_amd import serving, synth
 
-    trace = synth.serve_trace(n_req=n_req, rate=200.0, seed=4)
+    trace = synth.serve_trace(n_req=n_req, rate=rates[0], seed=4)
     progress("served leg: building %d requests" % n_req)
     work = serving.build_workload(trace, device=dev, pool_size=64, ctx=ctx, log=progress)
-    progress("served leg: plain replay")
-    plain, ps = serving.replay_plain(ctx, work, device=dev)
-    progress("served leg: served replay")
-    served, ss = serving.replay_served(ctx, work, hbm_budget=64 << 30, arena_bytes=24 << 30,
-                                       max_inflight=64, n_streams=4, device=dev)
-    progress("served leg: comparing results")
-    diff = serving.same_results(plain, served)
-    res = {"workload": "%d requests, Poisson 200/s, 70/30 compress/decompress, lognormal size "
+    out = {"workload": "%d requests, Poisson arrivals, 70/30 compress/decompress, lognormal size "
                        "median 16 MiB [1 MiB, 2 GiB], 1D/2D/3D GRF k^-3, target U[40,120] dB, "
-                       "seed 4; budget 64 GiB, 4 streams, 64 slots" % n_req,
-           "plain": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in
-                     {**ps["latency"], "gbps": ps["gbps"], "span_s": ps["span_s"]}.items()},
-           "served": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in
-                      {**ss["latency"], "gbps": ss["gbps"], "span_s": ss["span_s"]}.items()},
-           "results_differing": diff,
-           "server": {k: ss["server"][k] for k in ("rounds", "batched_launches", "peak_inflight",
-                                                   "peak_held_bytes", "failed")}}
-    del work, plain, served
+                       "seed 4; budget 64 GiB, 4 streams, 64 slots" % n_req, "rates": {}}
+    for rate in rates:
+        w_r = [dict(w, t=w["t"] * rates[0] / rate) for w in work]
+        progress("served leg: plain replay at %g/s" % rate)
+        plain, ps = serving.replay_plain(ctx, w_r, device=dev)
+        progress("served leg: served replay at %g/s" % rate)
+        served, ss = serving.replay_served(ctx, w_r, hbm_budget=64 << 30, arena_bytes=24 << 30,
+                                           max_inflight=64, n_streams=4, device=dev)
+        progress("served leg: comparing results")
+        diff = serving.same_results(plain, served)
+        rnd = lambda d: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
+        out["rates"]["%g" % rate] = {
+            "plain": rnd({**ps["latency"], "gbps": ps["gbps"], "span_s": ps["span_s"]}),
+            "served": rnd({**ss["latency"], "gbps": ss["gbps"], "span_s": ss["span_s"]}),
+            "results_differing": diff,
+            "plain_failed": sum(1 for o in plain if o[0] != 0),
+            "server": {k: ss["server"][k] for k in ("rounds", "batched_launches", "peak_inflight",
+                                                    "peak_held_bytes", "failed")}}
+        del plain, served, w_r
+        torch.cuda.empty_cache()
+    del work
     torch.cuda.empty_cache()
-    return res
+    return out
 
 
 def main():
@@ -334,6 +484,15 @@ def main():
         out.copy_(x)
         torch.cuda.synchronize()
     ms_per_step = (t1 - t0) / args.steps * 1e3
+    # decompression alone (no check), per target, outside the timed steps
+    dec_only = {}
+    if not args.separate_verify:
+        progress("decompress-only timing")
+        for p in psnrs:
+            st, nb, _ = ctx.compress_into(x, p, ws_c, blob, domain, stream)
+            dec_only[p] = timed_calls(lambda: ctx.decompress_into(blob, nb, ws_d, out, stream),
+                                      5, warm=1)[0]
+    copy_gbps = device_copy_gbps(x)
     total_bytes = n * s * len(psnrs)
     value = total_bytes / ((t1 - t0) / args.steps) / 1e9
 
@@ -346,6 +505,10 @@ def main():
         v = float(np.median(r["v"]))
         info, stats = r["info"], r["stats"]
         stage_avg = {nm: round(float(np.mean(v)), 4) for nm, v in r["stages"].items()}
+        if args.separate_verify:
+            fr = op_fracs(n, s, info["bits_per_value"], c, d)
+        else:
+            fr = op_fracs(n, s, info["bits_per_value"], c, dec_only[p], d)
         per_target.append({
             "psnr": p, "achieved_psnr": round(stats["psnr"], 4),
             "dpsnr": round(stats["psnr"] - p, 4), "bits_per_value": round(info["bits_per_value"], 4),
@@ -353,6 +516,8 @@ def main():
             "verify_gbps": round(n * s / v / 1e9, 2) if v > 0 else None,
             "n_outliers": info["n_outliers"], "n_patches": info["n_patches"],
             "max_abs_err_over_eb": stats["max_abs_err"] / info["eb"], "n_over_eb": stats["n_over_eb"],
+            "op_frac": fr,
+            "decompress_only_gbps": round(n * s / dec_only[p] / 1e9, 2) if p in dec_only else None,
             "kernel_ms": stage_avg,
         })
         for nm, ms_list in r["stages"].items():
@@ -383,6 +548,21 @@ def main():
         for k, v in tr.items():
             if k in kernels:
                 kernels[k]["traffic"] = v
+    # whole operations against the HBM peak and against the measured copy
+    op_level = {}
+    for key in ("compress", "decompress", "decompress_check"):
+        vals = [t["op_frac"][key] for t in per_target if key in t["op_frac"]]
+        if vals:
+            op_level[key] = {"mean_frac": round(float(np.mean(vals)), 4),
+                             "per_target": vals,
+                             "mean_frac_of_copy": round(float(np.mean(vals)) * HBM_PEAK_GBPS / copy_gbps, 4)}
+    alg_step = 0.0
+    for t in per_target:
+        b8 = t["bits_per_value"] / 8.0
+        alg_step += (2 * s + b8) * n + ((b8 + s) * n if args.separate_verify else (b8 + 2 * s) * n)
+        if args.separate_verify:
+            alg_step += 2 * s * n
+    step_frac = alg_step / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBPS
 
     line = {
         "metric": "compress+decompress+verify GB/s at target PSNR (sweep), |dPSNR| dB",
@@ -405,6 +585,10 @@ def main():
                    "verify": "separate" if args.separate_verify else "in the decompression pass"},
         "mean_abs_dpsnr": round(float(np.mean([abs(t["dpsnr"]) for t in per_target])), 4),
         "per_target": per_target,
+        "op_roofline": {"peak_gbps": HBM_PEAK_GBPS, "device_copy_gbps": round(copy_gbps, 1),
+                        "step_frac": round(step_frac, 4),
+                        "step_frac_of_copy": round(step_frac * HBM_PEAK_GBPS / copy_gbps, 4),
+                        **op_level},
         "kernels": kernels,
         "roofline": roofline,
     }
@@ -413,10 +597,19 @@ def main():
         planes = min(args.cpu_planes, args.edge)
         line["cpu_baseline"] = cpu_baseline(x.cpu().numpy(), psnrs, planes)
     del ws_c, ws_d, blob, out
+    if not args.no_c1:
+        progress("512x512 latency leg")
+        line["c1_512x512"] = c1_leg(ctx, dev)
+    if not args.no_c5:
+        progress("1024^3 float64 leg")
+        del x
+        torch.cuda.empty_cache()
+        line["c5_1024cube_f64"] = c5_leg(ctx, dev)
     if not args.no_batched:
         line["batched"] = batched_leg(ctx, dev)
     if not args.no_served:
-        line["served"] = served_leg(ctx, dev, args.served_requests)
+        rates = [float(r) for r in args.served_rates.split(",")]
+        line["served"] = served_leg(ctx, dev, args.served_requests, rates)
     print(json.dumps(line), flush=True)
 
 

@@ -91,6 +91,8 @@ def lib():
         L.or_stats.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64,
                                ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_uint64)]
+        L.or_stage_times.restype = None
+        L.or_stage_times.argtypes = [ctypes.c_void_p]
         L.or_free.restype = None
         L.or_free.argtypes = [ctypes.c_void_p]
         _lib = L
@@ -259,3 +261,16 @@ def stats(x: np.ndarray, y: np.ndarray, vr: float, eb: float) -> dict:
         raise OracleError(st, "or_stats")
     return {"sse": out[0], "mse": out[1], "psnr": out[2], "max_abs_err": out[3],
             "n_over_eb": int(nov.value)}
+
+
+STAGES = {0: "range", 1: "prequant", 2: "lorenzo", 3: "symbols_hist_exceptions", 4: "codebook",
+          5: "encode", 6: "blob", 8: "parse_tables", 9: "decode", 10: "prefix_sums",
+          11: "reconstruct", 12: "stats"}
+
+
+def stage_times() -> dict:
+    """Wall-clock seconds of each stage of the last compress / decompress /
+    stats calls (for the benchmark's CPU baseline)."""
+    out = (ctypes.c_double * 16)()
+    lib().or_stage_times(out)
+    return {nm: out[k] for k, nm in STAGES.items()}

@@ -46,10 +46,12 @@
  *
  * Built with -O2 -ffp-contract=off, no fast-math, no SIMD intrinsics.
  */
+#define _POSIX_C_SOURCE 199309L
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 
 /* ---- format constants (written out independently of the GPU library) --- */
 #define OR_MAGIC 0x5A535046u /* "FPSZ" little-endian */
@@ -93,6 +95,25 @@ typedef struct {
 /* ------------------------------------------------------------------------ */
 /* small helpers                                                           */
 /* ------------------------------------------------------------------------ */
+/* Wall-clock seconds of the stages of the last call (for the CPU baseline of
+ * the benchmark; no effect on any result).  Slots: 0 range, 1 prequantization,
+ * 2 Lorenzo, 3 symbols + histogram + exception list, 4 Huffman code,
+ * 5 encode, 6 blob assembly; 8 parse + tables, 9 decode, 10 prefix sums,
+ * 11 reconstruction; 12 statistics. */
+static double g_stage[16];
+static double g_mark;
+static double now_s(void) {
+  struct timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+static void stage_begin(void) { g_mark = now_s(); }
+static void stage_end(int k) {
+  const double t = now_s();
+  g_stage[k] += t - g_mark;
+  g_mark = t;
+}
+void or_stage_times(double *out) { memcpy(out, g_stage, sizeof(g_stage)); }
 
 static uint64_t rd_u64(const uint8_t *p) { uint64_t v; memcpy(&v, p, 8); return v; }
 static uint32_t rd_u32(const uint8_t *p) { uint32_t v; memcpy(&v, p, 4); return v; }
@@ -420,6 +441,8 @@ int or_compress(const void *x, int dtype, int ndim, const uint64_t *dims, double
   int st = make_shape(ndim, dims, &S);
   if (st != OR_OK) return st;
   const uint64_t n = S.n;
+  memset(g_stage, 0, sizeof(g_stage));
+  stage_begin();
 
   /* 1. value range of the original data (vr, definition under Eq. 4) */
   double mn = 0, mx = 0;
@@ -432,6 +455,7 @@ int or_compress(const void *x, int dtype, int ndim, const uint64_t *dims, double
   mn = mn + 0.0; /* -0 reads as +0 */
   mx = mx + 0.0;
   double vr = mx - mn;
+  stage_end(0);
 
   /* 2. Eq. 7 and eb_abs = eb_rel * vr (remark after Eq. 6); bin size 2 eb */
   double eb_rel = or_eb_rel(psnr);
@@ -488,6 +512,7 @@ int or_compress(const void *x, int dtype, int ndim, const uint64_t *dims, double
       q[i] = (int32_t)rint(t);
     }
   }
+  stage_end(1);
 
   /* 4. Lorenzo residual: delta = sum over the 8 corners of the unit cube
    *    behind the point of (-1)^(a+b+c) q[z-c][y-b][x-a]; q reads as zero
@@ -508,6 +533,7 @@ int or_compress(const void *x, int dtype, int ndim, const uint64_t *dims, double
             }
         dl[(z * S.ny + y) * S.nx + xx] = (int32_t)acc;
       }
+  stage_end(2);
 
   /* 5. walk the stream: symbols, histogram, exception records */
   uint64_t *perm = (uint64_t *)malloc(sizeof(uint64_t) * n);
@@ -571,12 +597,14 @@ int or_compress(const void *x, int dtype, int ndim, const uint64_t *dims, double
     }
     tile_exc[S.n_tiles] = n_exc;
   }
+  stage_end(3);
 
   /* 6. Huffman code (length-limited, canonical) */
   uint8_t len[OR_NSYM];
   uint32_t code[OR_NSYM];
   or_code_lengths(hist, OR_NSYM, len);
   or_canonical_codes(len, OR_NSYM, code);
+  stage_end(4);
 
   /* 7. encode: per tile, chunks of 128 symbols, bit-contiguous; each tile
    *    padded to a 32-bit word */
@@ -613,6 +641,7 @@ int or_compress(const void *x, int dtype, int ndim, const uint64_t *dims, double
     tile_words[S.n_tiles] = wbase;
   }
   uint64_t n_words = tile_words[S.n_tiles];
+  stage_end(5);
 
   /* 8. assemble the blob */
   or_layout Lo;
@@ -664,6 +693,7 @@ int or_compress(const void *x, int dtype, int ndim, const uint64_t *dims, double
   }
   free(q); free(dl); free(perm); free(sym); free(xtra); free(exc); free(tile_exc);
   free(chunk_bits); free(tile_words); free(words);
+  stage_end(6);
   *blob_out = blob;
   *bytes_out = Lo.total;
   return OR_OK;
@@ -689,6 +719,8 @@ int or_blob_info(const uint8_t *blob, uint64_t bytes, int *dtype, int *ndim, uin
 /* decompression                                                            */
 /* ------------------------------------------------------------------------ */
 int or_decompress(const uint8_t *blob, uint64_t bytes, void *out, uint64_t out_bytes) {
+  memset(g_stage + 8, 0, 4 * sizeof(double));
+  stage_begin();
   if (bytes < OR_HDR_BYTES) return OR_E_CORRUPT;
   if (rd_u32(blob + H_MAGIC) != OR_MAGIC || rd_u16(blob + H_VERSION) != OR_VERSION)
     return OR_E_CORRUPT;
@@ -759,6 +791,7 @@ int or_decompress(const uint8_t *blob, uint64_t bytes, void *out, uint64_t out_b
   stream_order(&S, perm);
   int32_t *dl = (int32_t *)malloc(sizeof(int32_t) * n); /* field order */
   uint8_t *is_out = (uint8_t *)calloc(n, 1);
+  stage_end(8);
   int rc = OR_OK;
   uint64_t p = 0, ci = 0;
   for (uint64_t t = 0; t < n_tiles && rc == OR_OK; t++) {
@@ -836,6 +869,7 @@ int or_decompress(const uint8_t *blob, uint64_t bytes, void *out, uint64_t out_b
     for (uint64_t i = 0; i < n && rc == OR_OK; i++)
       if (is_out[i] == 1) rc = OR_E_CORRUPT; /* outlier symbol without a value */
   }
+  stage_end(9);
   if (rc == OR_OK) {
     /* undo the prediction: inclusive prefix sums along x, y and z, over the
      * whole field (GLOBAL) or restarting at every tile edge (TILE).  Sums are
@@ -858,6 +892,7 @@ int or_decompress(const uint8_t *blob, uint64_t bytes, void *out, uint64_t out_b
         for (uint64_t y = 0; y < S.ny; y++)
           for (uint64_t xx = 0; xx < S.nx; xx++)
             qq[(z * S.ny + y) * S.nx + xx] += qq[((z - 1) * S.ny + y) * S.nx + xx];
+    stage_end(10);
     /* bin midpoints q * 2 eb; patched points take their exact value */
     for (uint64_t i = 0; i < n; i++) {
       int32_t qi = (int32_t)qq[i];
@@ -872,6 +907,7 @@ int or_decompress(const uint8_t *blob, uint64_t bytes, void *out, uint64_t out_b
       }
     }
     free(qq);
+    stage_end(11);
   }
   free(wcopy); free(perm); free(dl); free(is_out); free(patched); free(pbits);
   return rc;
@@ -884,6 +920,8 @@ int or_decompress(const uint8_t *blob, uint64_t bytes, void *out, uint64_t out_b
 int or_stats(const void *x, const void *y, int dtype, uint64_t n, double vr, double eb,
              double *out /* sse, mse, psnr, max_abs_err */, uint64_t *n_over) {
   if (n == 0) return OR_E_INVALID_ARG;
+  g_stage[12] = 0.0;
+  stage_begin();
   double s = 0.0, comp = 0.0, mx = 0.0;
   uint64_t over = 0;
   for (uint64_t i = 0; i < n; i++) {
@@ -904,6 +942,7 @@ int or_stats(const void *x, const void *y, int dtype, uint64_t n, double vr, dou
   out[2] = -20.0 * log10(sqrt(mse) / vr);
   out[3] = mx;
   *n_over = over;
+  stage_end(12);
   return OR_OK;
 }
 

@@ -191,13 +191,33 @@ def test_parity_length_limit(ctx, orc):
     _parity(ctx, orc, x, psnr, 1)
 
 
+@pytest.fixture(scope="module")
+def lognormal512():
+    return synth.field_3d_lognormal(shape=(512, 512, 512), seed=2)
+
+
 @pytest.mark.timeout(400)
-def test_parity_config2_full_size(ctx, orc):
-    # 3D float32 512^3 lognormal field, 80 dB: the benchmark workload, whole
-    # blob and whole reconstruction compared
-    x = synth.field_3d_lognormal(shape=(512, 512, 512), seed=2)
-    info, _ = _parity(ctx, orc, x, 80.0, 0)
+@pytest.mark.parametrize("psnr", [40.0, 60.0, 80.0, 100.0, 120.0])
+def test_parity_config2_full_size(ctx, orc, lognormal512, psnr):
+    # 3D float32 512^3 lognormal field, the benchmark workload at every
+    # target of its sweep: whole blob and whole reconstruction compared (at
+    # 120 dB: escapes, outliers, tiles past their staging slot, patches and
+    # chunks decoded from the global tail)
+    info, _ = _parity(ctx, orc, lognormal512, psnr, 0)
     assert info["bits_per_value"] > 0
+    if psnr == 120.0:
+        assert info["n_outliers"] > 0 and info["n_patches"] > 0
+
+
+@pytest.mark.timeout(400)
+def test_parity_config5_slab(ctx, orc):
+    # one GPU's share of the 1024^3 float64 field when it is split over 8
+    # GPUs along z: a 128 x 1024 x 1024 slab of the same recipe (GRF k^-3
+    # plus 1 % spikes of 1000 sigma) at 100 dB, blob and reconstruction
+    # compared with the oracle
+    x = synth.field_3d_spiky_f64(shape=(128, 1024, 1024), seed=5)
+    info, _ = _parity(ctx, orc, x, 100.0, 0, check_stats=True)
+    assert info["n_outliers"] > 0 or info["n_patches"] > 0
 
 
 def _lorenzo3d_slab(q: "torch.Tensor", qprev: "torch.Tensor") -> "torch.Tensor":
@@ -230,6 +250,13 @@ def test_config5_full_size_f64(ctx, orc):
     st, nb, info = ctx.compress_into(x, psnr, ws, blob, fpsz.GLOBAL)
     assert st == 0, "gpu compress status %d" % st
     info = info.as_dict()
+    # the code lengths in the blob are the oracle's Huffman lengths of the
+    # device histogram
+    o = fpsz.workspace_offset(shape, x.dtype, 1)
+    hist = ws[o:o + 4 * 1036].cpu().numpy().view(np.uint32)
+    assert int(hist.sum()) == x.numel()
+    lens = blob[256:256 + 1036].cpu().numpy()
+    assert np.array_equal(lens, orc.code_lengths(hist))
     del ws
     vr = float(x.max().item()) - float(x.min().item())
     assert info["vr"] == vr

@@ -47,6 +47,20 @@ def test_served_equals_plain(ctx, rate, budget_mib, streams):
     assert st["peak_held_bytes"] <= budget_mib << 20
     if rate > 1e5:  # a burst: requests must have been admitted together
         assert st["peak_inflight"] > 1 and st["batched_launches"] > 0
+    # a sample of the served results against the CPU oracle itself
+    import oracle
+    comp = [i for i, w in enumerate(work) if w["kind"] == "compress"][:3]
+    deco = [i for i, w in enumerate(work) if w["kind"] == "decompress"][:2]
+    for i in comp:
+        w = work[i]
+        _, buf, nb = served[i]
+        ob, _ = oracle.compress(w["x"].cpu().numpy(), w["psnr"])
+        assert buf[:nb].cpu().numpy().tobytes() == ob, "served blob %d differs from the oracle" % i
+    for i in deco:
+        w = work[i]
+        _, buf, _ = served[i]
+        oy = oracle.decompress(w["blob"][:w["nbytes"]].cpu().numpy().tobytes())
+        assert np.array_equal(buf.cpu().numpy().view(np.uint32), oy.view(np.uint32))
 
 
 def test_server_rejects_bad_requests(ctx):
