@@ -91,6 +91,25 @@ def lib():
         L.or_stats.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64,
                                ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_uint64)]
+        L.or_compress_scaled.restype = ctypes.c_int
+        L.or_compress_scaled.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_uint64), ctypes.c_double,
+                                         ctypes.c_int, ctypes.c_double,
+                                         ctypes.POINTER(ctypes.c_void_p),
+                                         ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_Trace)]
+        L.or_compress_closed_loop.restype = ctypes.c_int
+        L.or_compress_closed_loop.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                              ctypes.POINTER(ctypes.c_uint64), ctypes.c_double,
+                                              ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
+                                              ctypes.POINTER(ctypes.c_uint64),
+                                              ctypes.POINTER(_Trace),
+                                              ctypes.POINTER(ctypes.c_double)]
+        L.or_quant_sse.restype = ctypes.c_int
+        L.or_quant_sse.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_double,
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        L.or_closed_loop_scale.restype = ctypes.c_double
+        L.or_closed_loop_scale.argtypes = [ctypes.c_double, ctypes.c_uint64, ctypes.c_double,
+                                           ctypes.c_double]
         L.or_stage_times.restype = None
         L.or_stage_times.argtypes = [ctypes.c_void_p]
         L.or_free.restype = None
@@ -173,6 +192,39 @@ def compress(x: np.ndarray, psnr: float, domain: int = 0, trace: bool = False):
     Returns ``(blob: bytes, trace: dict | None)``.  ``domain`` 0 = GLOBAL
     Lorenzo (zero outside the field), 1 = TILE (zero outside each tile).
     """
+    return _compress(x, psnr, domain, trace, mode=0)
+
+
+def compress_scaled(x: np.ndarray, psnr: float, scale: float, domain: int = 0,
+                    trace: bool = False):
+    """Compression with eb_rel of Eq. 7 multiplied by ``scale``, recorded in
+    the blob (the second pass of the closed loop at a given factor)."""
+    return _compress(x, psnr, domain, trace, mode=1, scale=scale)
+
+
+def compress_closed_loop(x: np.ndarray, psnr: float, domain: int = 0, trace: bool = False):
+    """Closed-loop compression: the quantizer's MSE at the Eq. 7 bound gives
+    one secant step eb' = eb sqrt(MSE_target / MSE_1).  Returns ``(blob,
+    trace, scale)``."""
+    return _compress(x, psnr, domain, trace, mode=2)
+
+
+def quant_sse(x: np.ndarray, psnr: float):
+    """(SSE of the quantizer output at the Eq. 7 bound, patches exact; vr)."""
+    x = np.ascontiguousarray(x)
+    sse, vr = ctypes.c_double(), ctypes.c_double()
+    st = lib().or_quant_sse(x.ctypes.data, _dtype_code(x), x.size, float(psnr), ctypes.byref(sse),
+                            ctypes.byref(vr))
+    if st != OK:
+        raise OracleError(st, "or_quant_sse")
+    return sse.value, vr.value
+
+
+def closed_loop_scale(sse: float, n: int, vr: float, psnr: float) -> float:
+    return float(lib().or_closed_loop_scale(float(sse), int(n), float(vr), float(psnr)))
+
+
+def _compress(x, psnr, domain, trace, mode, scale=1.0):
     x = np.ascontiguousarray(x)
     dt = _dtype_code(x)
     dl = [int(d) for d in x.shape] + [1] * max(0, 3 - x.ndim)
@@ -191,14 +243,24 @@ def compress(x: np.ndarray, psnr: float, domain: int = 0, trace: bool = False):
             setattr(tr, k, v.ctypes.data)
     out = ctypes.c_void_p()
     nb = ctypes.c_uint64(0)
-    st = lib().or_compress(x.ctypes.data, dt, x.ndim, dims, float(psnr), int(domain),
-                           ctypes.byref(out), ctypes.byref(nb), ctypes.byref(tr))
+    sc = ctypes.c_double(1.0)
+    if mode == 0:
+        st = lib().or_compress(x.ctypes.data, dt, x.ndim, dims, float(psnr), int(domain),
+                               ctypes.byref(out), ctypes.byref(nb), ctypes.byref(tr))
+    elif mode == 1:
+        st = lib().or_compress_scaled(x.ctypes.data, dt, x.ndim, dims, float(psnr), int(domain),
+                                      float(scale), ctypes.byref(out), ctypes.byref(nb),
+                                      ctypes.byref(tr))
+    else:
+        st = lib().or_compress_closed_loop(x.ctypes.data, dt, x.ndim, dims, float(psnr),
+                                           int(domain), ctypes.byref(out), ctypes.byref(nb),
+                                           ctypes.byref(tr), ctypes.byref(sc))
     if st != OK:
         raise OracleError(st, "or_compress")
     blob = ctypes.string_at(out.value, nb.value)
     lib().or_free(out)
     if not trace:
-        return blob, None
+        return (blob, None, sc.value) if mode == 2 else (blob, None)
     t = dict(keep)
     t["q"] = t["q"].reshape(x.shape)
     t["delta"] = t["delta"].reshape(x.shape)
@@ -209,7 +271,7 @@ def compress(x: np.ndarray, psnr: float, domain: int = 0, trace: bool = False):
     cn = ["n_tiles", "n_chunks", "n_words", "n_exc", "n_outliers", "n_patches"]
     for i, nm in enumerate(cn):
         t[nm] = int(tr.counts[i])
-    return blob, t
+    return (blob, t, sc.value) if mode == 2 else (blob, t)
 
 
 def header(blob: bytes) -> dict:
@@ -228,6 +290,7 @@ def header(blob: bytes) -> dict:
         "e2": f64(88), "r": f64(96), "min": f64(120), "max": f64(128), "n": u64(136),
         "n_tiles": u64(144), "n_chunks": u64(152), "n_words": u64(160), "n_exc": u64(168),
         "n_outliers": u64(176), "n_patches": u64(184), "bytes": u64(192), "checksum": u64(200),
+        "scale": f64(216),
     }
 
 

@@ -66,6 +66,7 @@
 #define OR_CHUNK 128
 #define OR_FLAG_CONST 1u
 #define OR_FLAG_TILE 2u
+#define OR_FLAG_CLOSED 4u /* bound rescaled by the closed-loop step */
 #define OR_TAG_PATCH 0x80000000u
 
 /* status codes */
@@ -406,7 +407,8 @@ enum {
   H_PSNR = 56, H_EBREL = 64, H_VR = 72, H_EB = 80, H_E2 = 88, H_R = 96,
   H_E2T = 104, H_RT = 112, H_MIN = 120, H_MAX = 128, H_N = 136,
   H_NTILES = 144, H_NCHUNKS = 152, H_NWORDS = 160, H_NEXC = 168,
-  H_NOUT = 176, H_NPATCH = 184, H_BYTES = 192, H_CSUM = 200, H_CONST = 208
+  H_NOUT = 176, H_NPATCH = 184, H_BYTES = 192, H_CSUM = 200, H_CONST = 208,
+  H_SCALE = 216 /* closed loop: the factor applied to eb_rel (raw float64) */
 };
 
 /* section layout after the header */
@@ -430,8 +432,11 @@ static void layout(uint64_t n_tiles, uint64_t n_chunks, uint64_t n_exc, uint64_t
 /* compression                                                              */
 /* ------------------------------------------------------------------------ */
 /* dtype: 0 float32, 1 float64.  domain: 0 GLOBAL, 1 TILE.                  */
-int or_compress(const void *x, int dtype, int ndim, const uint64_t *dims, double psnr,
-                int domain, uint8_t **blob_out, uint64_t *bytes_out, or_trace *tr) {
+/* scale: factor applied to eb_rel; closed: the blob records the factor (flag
+ * CLOSED and the float64 at H_SCALE).  Plain compression is scale 1, closed 0. */
+static int compress_impl(const void *x, int dtype, int ndim, const uint64_t *dims, double psnr,
+                         int domain, double scale, int closed, uint8_t **blob_out,
+                         uint64_t *bytes_out, or_trace *tr) {
   *blob_out = NULL;
   *bytes_out = 0;
   if (dtype != 0 && dtype != 1) return OR_E_INVALID_ARG;
@@ -459,6 +464,7 @@ int or_compress(const void *x, int dtype, int ndim, const uint64_t *dims, double
 
   /* 2. Eq. 7 and eb_abs = eb_rel * vr (remark after Eq. 6); bin size 2 eb */
   double eb_rel = or_eb_rel(psnr);
+  if (closed) eb_rel = eb_rel * scale;
   double eb = vr * eb_rel;
   double e2 = 2.0 * eb;
   double r = 1.0 / e2;
@@ -481,7 +487,9 @@ int or_compress(const void *x, int dtype, int ndim, const uint64_t *dims, double
     blob = (uint8_t *)calloc(1, OR_HDR_BYTES);
     wr_u32(blob + H_MAGIC, OR_MAGIC);
     wr_u16(blob + H_VERSION, OR_VERSION);
-    wr_u16(blob + H_FLAGS, (uint16_t)(OR_FLAG_CONST | (domain ? OR_FLAG_TILE : 0)));
+    wr_u16(blob + H_FLAGS, (uint16_t)(OR_FLAG_CONST | (domain ? OR_FLAG_TILE : 0) |
+                                      (closed ? OR_FLAG_CLOSED : 0)));
+    if (closed) wr_f64(blob + H_SCALE, scale);
     blob[H_DTYPE] = (uint8_t)dtype; blob[H_NDIM] = (uint8_t)ndim;
     blob[H_LOG2D] = 9; blob[H_LOG2R] = 15; blob[H_LMAX] = OR_LMAX;
     for (int i = 0; i < 3; i++) wr_u64(blob + H_DIMS + 8 * i, i < ndim ? dims[i] : 1);
@@ -649,7 +657,8 @@ int or_compress(const void *x, int dtype, int ndim, const uint64_t *dims, double
   blob = (uint8_t *)calloc(1, Lo.total);
   wr_u32(blob + H_MAGIC, OR_MAGIC);
   wr_u16(blob + H_VERSION, OR_VERSION);
-  wr_u16(blob + H_FLAGS, (uint16_t)(domain ? OR_FLAG_TILE : 0));
+  wr_u16(blob + H_FLAGS, (uint16_t)((domain ? OR_FLAG_TILE : 0) | (closed ? OR_FLAG_CLOSED : 0)));
+  if (closed) wr_f64(blob + H_SCALE, scale);
   blob[H_DTYPE] = (uint8_t)dtype; blob[H_NDIM] = (uint8_t)ndim;
   blob[H_LOG2D] = 9; blob[H_LOG2R] = 15; blob[H_LMAX] = OR_LMAX;
   for (int i = 0; i < 3; i++) wr_u64(blob + H_DIMS + 8 * i, i < ndim ? dims[i] : 1);
@@ -697,6 +706,96 @@ int or_compress(const void *x, int dtype, int ndim, const uint64_t *dims, double
   *blob_out = blob;
   *bytes_out = Lo.total;
   return OR_OK;
+}
+
+int or_compress(const void *x, int dtype, int ndim, const uint64_t *dims, double psnr,
+                int domain, uint8_t **blob_out, uint64_t *bytes_out, or_trace *tr) {
+  return compress_impl(x, dtype, ndim, dims, psnr, domain, 1.0, 0, blob_out, bytes_out, tr);
+}
+
+/* Compression with the bound of Eq. 7 multiplied by a given factor, the
+ * factor recorded in the blob (the second pass of the closed loop). */
+int or_compress_scaled(const void *x, int dtype, int ndim, const uint64_t *dims, double psnr,
+                       int domain, double scale, uint8_t **blob_out, uint64_t *bytes_out,
+                       or_trace *tr) {
+  if (!(scale > 0.0) || !isfinite(scale)) return OR_E_INVALID_ARG;
+  return compress_impl(x, dtype, ndim, dims, psnr, domain, scale, 1, blob_out, bytes_out, tr);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Closed-loop correction for low PSNR targets.                             */
+/* Eq. 5 replaces the bin probabilities by a density, which holds only with  */
+/* many bins across the value range; at low PSNR the achieved MSE departs    */
+/* from eb^2 / 3 (Eq. 6).  The measured MSE of the first pass then gives one */
+/* secant step on MSE proportional to eb^2: eb' = eb sqrt(MSE_t / MSE_1),    */
+/* with MSE_t the MSE that Eq. 4 turns into the target,                      */
+/* MSE_t = vr^2 10^(-PSNR/10).  The first pass needs no decompression: the   */
+/* reconstruction is the quantizer's output (Theorem 1), x' = q 2eb, or x at */
+/* a patch.                                                                  */
+/* ------------------------------------------------------------------------ */
+int or_quant_sse(const void *x, int dtype, uint64_t n, double psnr, double *sse_out,
+                 double *vr_out) {
+  if (n == 0 || (dtype != 0 && dtype != 1)) return OR_E_INVALID_ARG;
+  double mn = 0, mx = 0;
+  for (uint64_t i = 0; i < n; i++) {
+    double v = elem(x, dtype, i);
+    if (!isfinite(v)) return OR_E_NONFINITE;
+    if (i == 0 || v < mn) mn = v;
+    if (i == 0 || v > mx) mx = v;
+  }
+  double vr = (mx + 0.0) - (mn + 0.0);
+  *vr_out = vr;
+  *sse_out = 0.0;
+  if (vr == 0.0) return OR_OK;
+  double eb = vr * or_eb_rel(psnr);
+  double e2 = 2.0 * eb, r = 1.0 / e2;
+  float e2_f = (float)e2, r_f = (float)r;
+  double maxabs = fabs(mn + 0.0) > fabs(mx + 0.0) ? fabs(mn + 0.0) : fabs(mx + 0.0);
+  if (!(maxabs * r < (dtype == 0 ? 8388608.0 : 134217728.0))) return OR_E_RANGE;
+  double s = 0.0, comp = 0.0;
+  for (uint64_t i = 0; i < n; i++) {
+    double e;
+    if (dtype == 0) {
+      float xv = ((const float *)x)[i];
+      float xr = (float)(int32_t)rintf(xv * r_f) * e2_f;
+      e = (double)xv - (double)xr;
+    } else {
+      double xv = ((const double *)x)[i];
+      double xr = (double)(int32_t)rint(xv * r) * e2;
+      e = xv - xr;
+    }
+    if (fabs(e) > eb) e = 0.0; /* a patch: stored exactly */
+    double e2v = e * e, t = s + e2v;
+    if (fabs(s) >= fabs(e2v)) comp += (s - t) + e2v;
+    else comp += (e2v - t) + s;
+    s = t;
+  }
+  *sse_out = s + comp;
+  return OR_OK;
+}
+
+/* the secant factor from the first pass (1 when the first pass is exact) */
+double or_closed_loop_scale(double sse, uint64_t n, double vr, double psnr) {
+  if (!(sse > 0.0)) return 1.0;
+  double mse_t = vr * vr * pow(10.0, -psnr / 10.0);
+  return sqrt(mse_t / (sse / (double)n));
+}
+
+int or_compress_closed_loop(const void *x, int dtype, int ndim, const uint64_t *dims,
+                            double psnr, int domain, uint8_t **blob_out, uint64_t *bytes_out,
+                            or_trace *tr, double *scale_out) {
+  *blob_out = NULL;
+  *bytes_out = 0;
+  if (!isfinite(psnr)) return OR_E_INVALID_ARG;
+  or_shape S;
+  int st = make_shape(ndim, dims, &S);
+  if (st != OR_OK) return st;
+  double sse, vr;
+  st = or_quant_sse(x, dtype, S.n, psnr, &sse, &vr);
+  if (st != OR_OK) return st;
+  double scale = or_closed_loop_scale(sse, S.n, vr, psnr);
+  if (scale_out) *scale_out = scale;
+  return compress_impl(x, dtype, ndim, dims, psnr, domain, scale, 1, blob_out, bytes_out, tr);
 }
 
 /* ------------------------------------------------------------------------ */

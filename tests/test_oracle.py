@@ -499,6 +499,84 @@ def test_f64_patch_records_pinned(orc):
     assert np.max(np.abs(x - y)) <= t["eb"]
 
 
+# --------------------------------------------------------------------------
+# closed-loop correction (low PSNR): one secant step on MSE ~ eb^2 (Eq. 6)
+# --------------------------------------------------------------------------
+
+def test_quant_sse_matches_numpy_and_reconstruction(orc):
+    # the first pass measures the quantizer's error, patches exact; by
+    # Theorem 1 that is the error of the decompressed field itself
+    rng = np.random.default_rng(21)
+    for dt, psnr in [(np.float32, 40.0), (np.float32, 120.0), (np.float64, 60.0)]:
+        x = (synth.grf_numpy((40, 50, 30), -3.0, 3) * 5 + rng.standard_normal((40, 50, 30)) * 0.01
+             ).astype(dt)
+        sse, vr = orc.quant_sse(x, psnr)
+        blob, t = orc.compress(x, psnr, trace=True)
+        assert vr == t["vr"]
+        q = _np_prequant(x, t["r_f"], t["r"])
+        if dt == np.float32:
+            xr = (q.astype(np.float32) * np.float32(t["e2_f"])).astype(np.float64)
+        else:
+            xr = q.astype(np.float64) * t["e2"]
+        e = x.astype(np.float64) - xr
+        e[np.abs(e) > t["eb"]] = 0.0
+        ref = math.fsum((e * e).ravel().tolist())
+        assert abs(sse - ref) <= 1e-13 * ref
+        y = orc.decompress(blob)
+        st = orc.stats(x, y, t["vr"], t["eb"])
+        assert abs(st["sse"] - sse) <= 1e-12 * sse
+
+
+def test_closed_loop_scale_against_eq4(orc):
+    # a pair of fields with a known error (see the Eq. 4 test): at the PSNR
+    # Eq. 4 gives for that error the step changes nothing; 20 dB higher it
+    # shrinks the bound tenfold (PSNR is 20 log10 of vr / RMSE)
+    n = 10000
+    x = (np.arange(n) % 65) * 0.125
+    a = 0.0625
+    y = x + np.where(np.arange(n) % 2 == 0, a, -a)
+    st = orc.stats(x, y, 8.0, eb=a)
+    s0 = orc.closed_loop_scale(st["sse"], n, 8.0, st["psnr"])
+    assert abs(s0 - 1.0) < 1e-14
+    s20 = orc.closed_loop_scale(st["sse"], n, 8.0, st["psnr"] + 20.0)
+    assert abs(s20 - 0.1) < 1e-15
+    assert orc.closed_loop_scale(0.0, n, 8.0, 40.0) == 1.0
+
+
+def test_closed_loop_step_is_neutral_when_eq6_holds(orc):
+    # many bins across the range: the error is uniform on [-eb, eb], MSE =
+    # eb^2 / 3 (Eq. 6) up to sampling noise, so the factor is 1 within
+    # 5 sigma of that noise (relative SD of the MSE sqrt(0.8 / N); the factor
+    # is its square root)
+    x = synth.field_2d_grf(512, 512, seed=1).astype(np.float64)
+    n = x.size
+    for psnr in (100.0, 120.0):
+        sse, vr = orc.quant_sse(x, psnr)
+        s = orc.closed_loop_scale(sse, n, vr, psnr)
+        assert abs(s - 1.0) < 2.5 * math.sqrt(0.8 / n)
+
+
+def test_closed_loop_end_to_end(orc):
+    # at 40 dB the lognormal field misses its target by ~0.1 dB (Eq. 5's
+    # density approximation at ~29 bins); one step brings it closer.  The
+    # blob is the scaled compression at that factor, recorded in the header.
+    x = synth.field_3d_lognormal(shape=(64, 64, 64), seed=2)
+    for psnr in (40.0, 60.0):
+        b0, t0 = orc.compress(x, psnr, trace=True)
+        d0 = orc.stats(x, orc.decompress(b0), t0["vr"], t0["eb"])["psnr"] - psnr
+        b1, t1, s = orc.compress_closed_loop(x, psnr, trace=True)
+        y1 = orc.decompress(b1)
+        st = orc.stats(x, y1, t1["vr"], t1["eb"])
+        assert abs(st["psnr"] - psnr) < abs(d0) / 4
+        assert st["n_over_eb"] == 0
+        h = orc.header(b1)
+        assert h["flags"] & 4 and h["scale"] == s and h["eb_rel"] == orc.eb_rel(psnr) * s
+        assert t1["eb"] == t1["vr"] * (orc.eb_rel(psnr) * s)
+        assert orc.compress_scaled(x, psnr, s)[0] == b1
+    # plain blobs carry no factor
+    assert orc.header(b0)["scale"] == 0.0 and not orc.header(b0)["flags"] & 4
+
+
 def test_error_statuses(orc):
     x = np.ones((10, 10), dtype=np.float32)
     blob = orc.compress(x, 80.0)[0]
