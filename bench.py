@@ -344,6 +344,16 @@ def batched_leg(ctx, dev):
         stt = ctx.verify(x, out, info[i]["vr"], info[i]["eb"])
         dps.append(stt["psnr"] - psnrs[i])
         over += stt["n_over_eb"]
+    # the same fields through the closed-loop correction (one call each)
+    progress("batched leg: closed-loop accuracy")
+    dps_c = []
+    for i, x in enumerate(xs):
+        st, nbc, ic = ctx.compress_closed_loop_into(x, psnrs[i], ws, pblob, fpsz.GLOBAL, stream)
+        if st != fpsz.OK or ctx.decompress_into(pblob, nbc, dws, out, stream) != fpsz.OK:
+            raise fpsz.FpszError(st, "closed-loop field %d" % i)
+        stt = ctx.verify(x, out, ic.vr, ic.eb)
+        dps_c.append(stt["psnr"] - psnrs[i])
+        over += stt["n_over_eb"]
     tp_m, tb_m = float(np.median(tp)), float(np.median(tb))
     res = {"workload": "120 2D float32 1800x3600 GRF fields, slope U[-4,-2], range 10^U(-3,4), "
                        "target U[40,120] dB, seed 3",
@@ -353,7 +363,11 @@ def batched_leg(ctx, dev):
            "autotuned_ms": round(tuned_ms, 3), "launch_shape": shape,
            "identical_sizes": psz == list(nb),
            "mean_abs_dpsnr": round(float(np.mean(np.abs(dps))), 4),
-           "meet_rate": round(float(np.mean([d >= 0 for d in dps])), 4), "n_over_eb": int(over)}
+           "meet_rate": round(float(np.mean([d >= 0 for d in dps])), 4), "n_over_eb": int(over),
+           "closed_loop": {"mean_abs_dpsnr": round(float(np.mean(np.abs(dps_c))), 5),
+                           "max_abs_dpsnr": round(float(np.max(np.abs(dps_c))), 5),
+                           "meet_rate": round(float(np.mean([d >= 0 for d in dps_c])), 4)},
+           "plain_max_abs_dpsnr": round(float(np.max(np.abs(dps))), 5)}
     del xs, blobs, ws, pblob, dws, out
     torch.cuda.empty_cache()
     return res
@@ -493,6 +507,19 @@ def main():
             dec_only[p] = timed_calls(lambda: ctx.decompress_into(blob, nb, ws_d, out, stream),
                                       5, warm=1)[0]
     copy_gbps = device_copy_gbps(x)
+    # the closed-loop correction on the benchmark field at each target
+    progress("closed-loop legs")
+    closed = []
+    for p in psnrs:
+        st, nb, ic = ctx.compress_closed_loop_into(x, p, ws_c, blob, domain, stream)
+        if st != fpsz.OK:
+            raise fpsz.FpszError(st, "closed loop at %g dB" % p)
+        tcl = timed_calls(lambda: ctx.compress_closed_loop_into(x, p, ws_c, blob, domain, stream),
+                          3, warm=1)[0]
+        st, stc = ctx.decompress_verify_into(blob, nb, ws_d, out, x, stream)
+        closed.append({"psnr": p, "dpsnr": round(stc.psnr - p, 5), "eb_scale": ic.eb_scale,
+                       "bits_per_value": round(ic.bits_per_value, 4),
+                       "compress_gbps": round(n * s / tcl / 1e9, 2), "n_over_eb": stc.n_over_eb})
     total_bytes = n * s * len(psnrs)
     value = total_bytes / ((t1 - t0) / args.steps) / 1e9
 
@@ -585,6 +612,7 @@ def main():
                    "verify": "separate" if args.separate_verify else "in the decompression pass"},
         "mean_abs_dpsnr": round(float(np.mean([abs(t["dpsnr"]) for t in per_target])), 4),
         "per_target": per_target,
+        "closed_loop": closed,
         "op_roofline": {"peak_gbps": HBM_PEAK_GBPS, "device_copy_gbps": round(copy_gbps, 1),
                         "step_frac": round(step_frac, 4),
                         "step_frac_of_copy": round(step_frac * HBM_PEAK_GBPS / copy_gbps, 4),

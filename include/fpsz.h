@@ -72,6 +72,8 @@ typedef struct {
   double bits_per_value; /* 8 * blob_bytes / n */
   uint32_t is_const;     /* vr == 0: the blob only records the value */
   uint32_t domain;       /* fpsz_domain used */
+  double eb_scale;       /* closed loop: factor applied to Eq. 7's eb_rel (eb_rel above
+                            includes it); 1 for plain compression */
 } fpsz_info;
 
 /* Eq. 4: SSE, MSE = SSE / n, PSNR = -20 log10(sqrt(MSE) / vr), max |x - x'|,
@@ -125,6 +127,24 @@ fpsz_status fpsz_compress(fpsz_ctx *ctx, const void *field_dev, int ndim, const 
                           void *workspace_dev, uint64_t workspace_bytes, void *blob_dev,
                           uint64_t blob_capacity, uint64_t *blob_bytes, fpsz_info *info,
                           void *stream);
+
+/* fpsz_compress with a closed-loop correction for low PSNR targets, where
+ * Eq. 5's density approximation (many bins across the value range) fails and
+ * the achieved PSNR departs from the target.  A first pass over the field
+ * measures the MSE of the quantizer's output at the Eq. 7 bound (by Theorem 1
+ * the reconstruction error; patched points are exact); one secant step on
+ * MSE ~ eb^2 (Eq. 6) then gives eb_rel' = eb_rel * sqrt(MSE_t / MSE_1), with
+ * MSE_t = vr^2 10^(-PSNR/10) the MSE that Eq. 4 maps to the target, and the
+ * field is compressed with eb_rel'.  The factor is recorded in the blob
+ * (header flag 4, float64 at byte 216) and in info->eb_scale; decompression
+ * is unchanged.  Costs one extra read of the field.  Arguments, workspace and
+ * status as fpsz_compress. */
+fpsz_status fpsz_compress_closed_loop(fpsz_ctx *ctx, const void *field_dev, int ndim,
+                                      const uint64_t *dims, fpsz_dtype dtype, double target_psnr,
+                                      fpsz_domain domain, void *workspace_dev,
+                                      uint64_t workspace_bytes, void *blob_dev,
+                                      uint64_t blob_capacity, uint64_t *blob_bytes,
+                                      fpsz_info *info, void *stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): fpsz_compress

@@ -184,11 +184,11 @@ fpsz_status fpsz_compress_workspace_offset(int ndim, const uint64_t *dims, fpsz_
   return FPSZ_OK;
 }
 
-fpsz_status fpsz_compress(fpsz_ctx *ctx, const void *field_dev, int ndim, const uint64_t *dims,
-                          fpsz_dtype dtype, double target_psnr, fpsz_domain domain,
-                          void *workspace_dev, uint64_t workspace_bytes, void *blob_dev,
-                          uint64_t blob_capacity, uint64_t *blob_bytes, fpsz_info *info,
-                          void *stream) {
+static fpsz_status compress_one(fpsz_ctx *ctx, const void *field_dev, int ndim,
+                                const uint64_t *dims, fpsz_dtype dtype, double target_psnr,
+                                fpsz_domain domain, void *workspace_dev, uint64_t workspace_bytes,
+                                void *blob_dev, uint64_t blob_capacity, uint64_t *blob_bytes,
+                                fpsz_info *info, void *stream, int closed) {
   if (!ctx) return FPSZ_E_INVALID_ARG;
   ctx->err[0] = 0;
   CJob job;
@@ -196,6 +196,7 @@ fpsz_status fpsz_compress(fpsz_ctx *ctx, const void *field_dev, int ndim, const 
                                     workspace_dev, workspace_bytes, blob_dev, blob_capacity,
                                     blob_bytes, &job);
   if (st != FPSZ_OK) return st;
+  job.P.closed = closed;
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, FPSZ_E_DEVICE, "hipSetDevice failed");
   hipStream_t s = (hipStream_t)stream;
@@ -210,6 +211,25 @@ fpsz_status fpsz_compress(fpsz_ctx *ctx, const void *field_dev, int ndim, const 
   const DevParams &D = *ctx->host;
   if (info) fill_compress_info(info, job.P, D);
   return compress_result(ctx, job.P, D, blob_bytes);
+}
+
+fpsz_status fpsz_compress(fpsz_ctx *ctx, const void *field_dev, int ndim, const uint64_t *dims,
+                          fpsz_dtype dtype, double target_psnr, fpsz_domain domain,
+                          void *workspace_dev, uint64_t workspace_bytes, void *blob_dev,
+                          uint64_t blob_capacity, uint64_t *blob_bytes, fpsz_info *info,
+                          void *stream) {
+  return compress_one(ctx, field_dev, ndim, dims, dtype, target_psnr, domain, workspace_dev,
+                      workspace_bytes, blob_dev, blob_capacity, blob_bytes, info, stream, 0);
+}
+
+fpsz_status fpsz_compress_closed_loop(fpsz_ctx *ctx, const void *field_dev, int ndim,
+                                      const uint64_t *dims, fpsz_dtype dtype, double target_psnr,
+                                      fpsz_domain domain, void *workspace_dev,
+                                      uint64_t workspace_bytes, void *blob_dev,
+                                      uint64_t blob_capacity, uint64_t *blob_bytes,
+                                      fpsz_info *info, void *stream) {
+  return compress_one(ctx, field_dev, ndim, dims, dtype, target_psnr, domain, workspace_dev,
+                      workspace_bytes, blob_dev, blob_capacity, blob_bytes, info, stream, 1);
 }
 
 fpsz_status fpsz_compress_static(fpsz_ctx *ctx, const void *field_dev, int ndim,
@@ -262,6 +282,7 @@ fpsz_status fpsz_blob_header(const void *blob_host, uint64_t bytes, int *ndim, u
     const uint16_t fl = rd<uint16_t>(h + H_FLAGS);
     info->is_const = (fl & kFlagConst) ? 1 : 0;
     info->domain = (fl & kFlagTile) ? 1 : 0;
+    info->eb_scale = (fl & kFlagClosed) ? rd<double>(h + H_SCALE) : 1.0;
   }
   return FPSZ_OK;
 }

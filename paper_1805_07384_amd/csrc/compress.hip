@@ -156,6 +156,26 @@ __global__ __launch_bounds__(kBlock) void k_range(CJob one, const CJob *__restri
   }
 }
 
+// eb_abs = eb_rel * vr (Eq. 7 and the remark after Eq. 6), the bin size 2 eb,
+// its reciprocal and the range guard
+__device__ inline void derive_bound(const Plan &P, DevParams *dp, double vr, double eb_rel) {
+  const double eb = vr * eb_rel;
+  const double e2 = 2.0 * eb;
+  const double r = 1.0 / e2;
+  dp->vr = vr;
+  dp->eb_rel = eb_rel;
+  dp->eb = eb;
+  dp->e2 = e2;
+  dp->r = r;
+  dp->e2_f = (float)e2;
+  dp->r_f = (float)r;
+  const double maxabs = fabs(dp->mn) > fabs(dp->mx) ? fabs(dp->mn) : fabs(dp->mx);
+  dp->maxabs = maxabs;
+  if (vr == 0.0) { dp->is_const = 1; return; }
+  const double lim = P.dtype == FPSZ_F32 ? 8388608.0 : 134217728.0;
+  if (!(maxabs * r < lim)) dp->status = FPSZ_E_RANGE;
+}
+
 // one block per field: combine the nb partials, derive eb (Eq. 7) and the
 // quantizer constants
 __global__ __launch_bounds__(kBlock) void k_range_final(CJob one, const CJob *__restrict__ jobs,
@@ -194,23 +214,10 @@ __global__ __launch_bounds__(kBlock) void k_range_final(CJob one, const CJob *__
   const double vmn = bmn + 0.0, vmx = bmx + 0.0;  // -0 reads as +0
   dp->mn = vmn;
   dp->mx = vmx;
-  const double vr = vmx - vmn;
-  const double eb = vr * P.eb_rel;
-  const double e2 = 2.0 * eb;
-  const double r = 1.0 / e2;
-  dp->vr = vr;
-  dp->eb_rel = P.eb_rel;
-  dp->eb = eb;
-  dp->e2 = e2;
-  dp->r = r;
-  dp->e2_f = (float)e2;
-  dp->r_f = (float)r;
-  const double maxabs = fabs(vmn) > fabs(vmx) ? fabs(vmn) : fabs(vmx);
-  dp->maxabs = maxabs;
-  if (vr == 0.0) { dp->is_const = 1; return; }
-  const double lim = P.dtype == FPSZ_F32 ? 8388608.0 : 134217728.0;
-  if (!(maxabs * r < lim)) dp->status = FPSZ_E_RANGE;
+  dp->scale = 1.0;
+  derive_bound(P, dp, vmx - vmn, P.eb_rel);
 }
+
 
 // ---------------------------------------------------------------------------
 // a3-a7: prequantization, Lorenzo residual, symbols, histogram, codes and
@@ -382,6 +389,69 @@ typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 template <typename T> struct GVec;
 template <> struct GVec<float> { using V = f32x4_t; };
 template <> struct GVec<double> { using V = f64x2_t; };
+
+// Closed loop, first pass: SSE of the quantizer's output at the Eq. 7 bound
+// (by Theorem 1 the reconstruction error; a patch is stored exactly and adds
+// nothing).  Block b reduces a fixed grid-stride share in a fixed order into
+// part[b] (the range partials are free once k_range_final has run).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_qerr(CJob one, const CJob *__restrict__ jobs) {
+  const CJob J = select_job(one, jobs);
+  const Plan P = J.P;
+  const DevParams *__restrict__ dp = J.W.P;
+  double *__restrict__ part = static_cast<double *>(J.W.range_part);
+  if (!P.closed || dp->status != 0 || dp->is_const) return;
+  const T *__restrict__ x = static_cast<const T *>(J.x);
+  const float rf = dp->r_f, e2f = dp->e2_f;
+  const double r = dp->r, e2 = dp->e2, eb = dp->eb;
+  double sse = 0.0;
+  const uint64_t gsz = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < P.n; i += gsz) {
+    const T v = ((gptr_t<T>)x)[i];
+    const int32_t q = Quant<T>::q(v, rf, r);
+    double e;
+    if constexpr (sizeof(T) == 4) e = (double)v - (double)((float)q * e2f);
+    else e = v - (double)q * e2;
+    e = fabs(e) > eb ? 0.0 : e;
+    sse = __builtin_fma(e, e, sse);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) sse += __shfl_xor(sse, o, 64);
+  __shared__ double s_w[kBlock / 64];
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = sse;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
+}
+
+// Closed loop, the step (one block per field): MSE_1 from the partials in a
+// fixed order, the target MSE that Eq. 4 maps to the target PSNR,
+// MSE_t = vr^2 10^(-PSNR/10), and the secant factor sqrt(MSE_t / MSE_1) on
+// MSE ~ eb^2 (Eq. 6); the bound and quantizer constants are derived again
+// from eb_rel times that factor.
+__global__ __launch_bounds__(kBlock) void k_rescale(CJob one, const CJob *__restrict__ jobs,
+                                                    uint32_t nb) {
+  const CJob J = select_job(one, jobs);
+  const Plan P = J.P;
+  DevParams *__restrict__ dp = J.W.P;
+  const double *__restrict__ part = static_cast<const double *>(J.W.range_part);
+  if (!P.closed || dp->status != 0 || dp->is_const) return;
+  double sse = 0.0;
+  for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) sse += part[b];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) sse += __shfl_xor(sse, o, 64);
+  __shared__ double s_w[kBlock / 64];
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = sse;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  sse = (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
+  dp->q_sse = sse;
+  if (!(sse > 0.0)) return;  // the first pass is exact: factor 1
+  const double vr = dp->vr;
+  const double mse_t = vr * vr * P.mse_factor;
+  const double scale = sqrt(mse_t / (sse / (double)P.n));
+  dp->scale = scale;
+  derive_bound(P, dp, vr, P.eb_rel * scale);
+}
 
 // Full tile, phase 1: quantize this thread's segment (and its left
 // neighbour) into LDS, the halo points with the other threads; patch bits of
@@ -1555,8 +1625,10 @@ __global__ void k_header(CJob one, const CJob *__restrict__ jobs) {
     put32(H_MAGIC, kMagic);
     const uint16_t ver = kVersion;
     __builtin_memcpy(h + H_VERSION, &ver, 2);
-    const uint16_t fl = (uint16_t)((cst ? kFlagConst : 0) | (P.domain ? kFlagTile : 0));
+    const uint16_t fl = (uint16_t)((cst ? kFlagConst : 0) | (P.domain ? kFlagTile : 0) |
+                                   (P.closed ? kFlagClosed : 0));
     __builtin_memcpy(h + H_FLAGS, &fl, 2);
+    if (P.closed) putf(H_SCALE, dp->scale);
     h[H_DTYPE] = (uint8_t)P.dtype;
     h[H_NDIM] = (uint8_t)P.ndim;
     h[H_LOG2D] = 9;
@@ -1742,6 +1814,12 @@ static void launch_compress_t(const CJob &one, const CJob *jobs, int nf, const P
   hipLaunchKernelGGL(k_range<T>, dim3(cfg.range_blocks, nf), dim3(kBlock), 0, s, one, jobs);
   hipLaunchKernelGGL(k_range_final, dim3(1, nf), dim3(kBlock), 0, s, one, jobs, cfg.range_blocks);
   tm->mark(s, "range");
+  if (maxP.closed) {
+    // the partials area holds 3 x kRangeBlocks doubles: one per k_qerr block
+    hipLaunchKernelGGL(k_qerr<T>, dim3(cfg.range_blocks, nf), dim3(kBlock), 0, s, one, jobs);
+    hipLaunchKernelGGL(k_rescale, dim3(1, nf), dim3(kBlock), 0, s, one, jobs, cfg.range_blocks);
+    tm->mark(s, "closed_loop");
+  }
   if (maxP.ndim == 1) launch_quant<T, 1>(one, jobs, nf, maxP, cfg, s, tm);
   else if (maxP.ndim == 2) launch_quant<T, 2>(one, jobs, nf, maxP, cfg, s, tm);
   else launch_quant<T, 3>(one, jobs, nf, maxP, cfg, s, tm);

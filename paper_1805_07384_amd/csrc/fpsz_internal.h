@@ -30,7 +30,7 @@ constexpr int kChunk = 128;
 constexpr int kTilePts = 8192;
 constexpr int kLutBits = 11;
 constexpr uint32_t kTagPatch = 0x80000000u;
-constexpr uint16_t kFlagConst = 1, kFlagTile = 2;
+constexpr uint16_t kFlagConst = 1, kFlagTile = 2, kFlagClosed = 4;
 constexpr int kBlock = 256;
 constexpr int kRangeBlocks = 1024;
 // The compressor's histogram is kept in this many copies (workgroup b adds
@@ -45,7 +45,8 @@ enum : uint32_t {
   H_LOG2R = 11, H_LMAX = 12, H_DIMS = 16, H_TILE = 40, H_CHUNK = 52, H_PSNR = 56,
   H_EBREL = 64, H_VR = 72, H_EB = 80, H_E2 = 88, H_R = 96, H_E2T = 104, H_RT = 112,
   H_MIN = 120, H_MAX = 128, H_N = 136, H_NTILES = 144, H_NCHUNKS = 152, H_NWORDS = 160,
-  H_NEXC = 168, H_NOUT = 176, H_NPATCH = 184, H_BYTES = 192, H_CSUM = 200, H_CONST = 208
+  H_NEXC = 168, H_NOUT = 176, H_NPATCH = 184, H_BYTES = 192, H_CSUM = 200, H_CONST = 208,
+  H_SCALE = 216  // closed loop: factor applied to eb_rel (float64)
 };
 
 __host__ __device__ inline uint64_t align8(uint64_t v) { return (v + 7) & ~uint64_t(7); }
@@ -64,6 +65,10 @@ struct Plan {
   uint64_t off_len, off_two, off_teo, off_cb, off_exc;
   uint64_t capacity;            // blob capacity (compress) or blob bytes (decompress)
   double target_psnr, eb_rel;
+  // closed loop: 10^(-PSNR/10) (host libm), so that the target MSE is
+  // vr^2 * mse_factor; closed = 0 for plain compression
+  double mse_factor;
+  int32_t closed, pad4_;
 };
 
 // Geometry of one tile.
@@ -129,7 +134,9 @@ struct DevParams {
   uint64_t verify_done;
   double v_sse, v_max;
   uint64_t v_over;
-  uint64_t pad_[8];
+  double scale;      // closed loop: factor applied to eb_rel (1 otherwise)
+  double q_sse;      // closed loop: SSE of the first pass
+  uint64_t pad_[6];
 };
 
 // ---- wave primitives (wave64) ----------------------------------------------

@@ -248,6 +248,9 @@ inline fpsz_status prepare_compress(fpsz_ctx *ctx, const void *field_dev, int nd
   P.capacity = blob_capacity;
   P.target_psnr = target_psnr;
   P.eb_rel = sqrt(3.0) * pow(10.0, -target_psnr / 20.0);  // Eq. 7, as fpsz_eb_rel
+  // the MSE that Eq. 4 maps to the target is vr^2 * 10^(-PSNR/10) (closed loop)
+  P.mse_factor = pow(10.0, -target_psnr / 10.0);
+  P.closed = 0;
   uint8_t *ws = (uint8_t *)workspace_dev;
   CompressWs &W = job->W;
   W.P = (DevParams *)ws;
@@ -270,7 +273,7 @@ inline fpsz_status prepare_compress(fpsz_ctx *ctx, const void *field_dev, int nd
 inline void fill_compress_info(fpsz_info *info, const Plan &P, const DevParams &D) {
   memset(info, 0, sizeof(*info));
   info->target_psnr = P.target_psnr;
-  info->eb_rel = P.eb_rel;
+  info->eb_rel = P.closed ? D.eb_rel : P.eb_rel;  // the closed loop's includes its factor
   info->vr = D.vr;
   info->eb = D.eb;
   info->min = D.mn;
@@ -283,6 +286,7 @@ inline void fill_compress_info(fpsz_info *info, const Plan &P, const DevParams &
   info->bits_per_value = 8.0 * (double)D.blob_bytes / (double)P.n;
   info->is_const = D.is_const;
   info->domain = (uint32_t)P.domain;
+  info->eb_scale = P.closed ? D.scale : 1.0;
 }
 
 // Status of a finished compress from its parameter block.

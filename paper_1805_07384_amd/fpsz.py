@@ -36,7 +36,7 @@ class Info(ctypes.Structure):
         ("n", ctypes.c_uint64), ("n_outliers", ctypes.c_uint64), ("n_patches", ctypes.c_uint64),
         ("n_exceptions", ctypes.c_uint64), ("blob_bytes", ctypes.c_uint64),
         ("bits_per_value", ctypes.c_double), ("is_const", ctypes.c_uint32),
-        ("domain", ctypes.c_uint32),
+        ("domain", ctypes.c_uint32), ("eb_scale", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -111,6 +111,10 @@ SIGNATURES = {
     "fpsz_compress": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _u64p, ctypes.c_int, ctypes.c_double,
                                      ctypes.c_int, _vp, ctypes.c_uint64, _vp, ctypes.c_uint64,
                                      _u64p, ctypes.POINTER(Info), _vp]),
+    "fpsz_compress_closed_loop": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _u64p, ctypes.c_int,
+                                                 ctypes.c_double, ctypes.c_int, _vp,
+                                                 ctypes.c_uint64, _vp, ctypes.c_uint64, _u64p,
+                                                 ctypes.POINTER(Info), _vp]),
     "fpsz_compress_static": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _u64p, ctypes.c_int,
                                             ctypes.c_double, ctypes.c_int, _vp, ctypes.c_uint64,
                                             _u64p, ctypes.POINTER(Info), _vp]),
@@ -309,6 +313,33 @@ class Context:
                                     blob.numel(), ctypes.byref(nb), ctypes.byref(info),
                                     _stream(stream))
         return st, nb.value, info
+
+    def compress_closed_loop_into(self, x: torch.Tensor, psnr: float, workspace: torch.Tensor,
+                                  blob: torch.Tensor, domain: int = GLOBAL, stream=None):
+        """fpsz_compress_closed_loop into ``blob``; returns (status,
+        blob_bytes, Info) with Info.eb_scale the factor applied."""
+        assert x.is_contiguous() and x.is_cuda
+        nb = ctypes.c_uint64()
+        info = Info()
+        st = self.lib.fpsz_compress_closed_loop(self.handle, x.data_ptr(), x.dim(),
+                                                _dims(x.shape), _dtype_code(x), float(psnr),
+                                                int(domain), workspace.data_ptr(),
+                                                workspace.numel() * workspace.element_size(),
+                                                blob.data_ptr(), blob.numel(), ctypes.byref(nb),
+                                                ctypes.byref(info), _stream(stream))
+        return st, nb.value, info
+
+    def compress_closed_loop(self, x: torch.Tensor, psnr: float, domain: int = GLOBAL,
+                             stream=None):
+        """Returns (blob tensor of the blob's size, info dict)."""
+        x = x.contiguous()
+        ws = torch.empty(compress_workspace_bytes(x.shape, x.dtype), dtype=torch.uint8,
+                         device=x.device)
+        blob = torch.empty(compress_bound(x.shape, x.dtype), dtype=torch.uint8, device=x.device)
+        st, nb, info = self.compress_closed_loop_into(x, psnr, ws, blob, domain, stream)
+        if st != OK:
+            raise self._err(st, "fpsz_compress_closed_loop")
+        return blob[:nb], info.as_dict()
 
     def compress_static(self, x: torch.Tensor, psnr: float, blob: torch.Tensor,
                         domain: int = GLOBAL, stream=None):

@@ -422,3 +422,45 @@ def test_decompress_verify_constant_and_small_workspace(ctx, orc):
     stt, _ = ctx.decompress_verify_into(blob2, blob2.numel(), small, out,
                                         torch.from_numpy(x2).cuda())
     assert stt == fpsz.E_CAPACITY
+
+
+CLOSED_CASES = [((48, 40, 70), np.float32, 40.0, 0), ((48, 40, 70), np.float32, 60.0, 1),
+                ((300, 200), np.float64, 40.0, 0), ((20000,), np.float32, 30.0, 0),
+                ((64, 64, 64), np.float32, 100.0, 0)]
+
+
+@pytest.mark.parametrize("shape,dt,psnr,domain", CLOSED_CASES)
+def test_parity_closed_loop(ctx, orc, shape, dt, psnr, domain):
+    # closed-loop compression: the factor is a float64 reduction, held to the
+    # oracle's within 1e-9 relative; given the device's factor, the blob is
+    # the oracle's scaled compression byte for byte, and decompression the
+    # oracle's bit for bit
+    from paper_1805_07384_amd import fpsz
+    x = (synth.field_3d_lognormal(shape=shape, seed=2) if len(shape) == 3
+         else synth.grf_numpy(shape, -3.0, 8) * 4.0 + 1.0).astype(dt)
+    print("case closed shape=%s dtype=%s psnr=%s domain=%d" % (shape, x.dtype, psnr, domain),
+          flush=True)
+    xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    ws = torch.full((fpsz.compress_workspace_bytes(x.shape, xt.dtype),), 0xA5, dtype=torch.uint8,
+                    device="cuda")
+    blob = torch.full((fpsz.compress_bound(x.shape, xt.dtype),), 0x5A, dtype=torch.uint8,
+                      device="cuda")
+    st, nb, info = ctx.compress_closed_loop_into(xt, psnr, ws, blob, domain)
+    assert st == 0
+    s_gpu = info.eb_scale
+    _, _, s_or = orc.compress_closed_loop(x, psnr, domain)
+    assert abs(s_gpu - s_or) <= 1e-9 * s_or
+    ob, ot = orc.compress_scaled(x, psnr, s_gpu, domain, trace=True)
+    gb = blob[:nb].cpu().numpy().tobytes()
+    assert gb == ob, "closed-loop blob differs from the oracle's at the device factor"
+    assert info.eb == ot["eb"] and info.eb_rel == orc.eb_rel(psnr) * s_gpu
+    y = ctx.decompress(blob[:nb])
+    oy = orc.decompress(ob)
+    assert np.array_equal(_bits(y.cpu().numpy()), _bits(oy))
+    # closer to the target than plain compression
+    st_c = orc.stats(x, oy, ot["vr"], ot["eb"])
+    b0, t0 = orc.compress(x, psnr, domain, trace=True)
+    st_p = orc.stats(x, orc.decompress(b0), t0["vr"], t0["eb"])
+    assert st_c["n_over_eb"] == 0
+    if abs(st_p["psnr"] - psnr) > 0.01:
+        assert abs(st_c["psnr"] - psnr) < abs(st_p["psnr"] - psnr)
