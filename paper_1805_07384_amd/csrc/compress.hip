@@ -609,10 +609,25 @@ __device__ inline uint32_t symbol_of(int32_t dv, bool &outlier) {
 // layer of the tile grid, 2D: a row of tiles, 1D: 16 consecutive tiles) and
 // unit u goes to XCD u % 8: a tile and its x / y neighbours (whose halo it
 // reads) are handled on the same XCD at about the same time.
+// With 16 or more tile rows along y (2D and 3D), XCD x instead owns a band
+// of tile rows b in [x gy / 8, (x + 1) gy / 8) and walks it z-major, then
+// row, then x: the tile before along z (one band-layer earlier), along y
+// (one row earlier) and along x (just before) were all loaded by the same
+// XCD shortly before, so the halo the tile reads is still in that XCD's L2.
 __device__ inline bool xcd_tile(const Plan &P, int ndim, uint64_t k, uint64_t *t) {
   if ((gridDim.x & 7) != 0) {
     *t = blockIdx.x + k * gridDim.x;
     return *t < P.n_tiles;
+  }
+  if (ndim >= 2 && P.gy >= 16) {
+    const uint32_t x = blockIdx.x & 7;
+    const uint64_t b0 = (uint64_t)x * P.gy / 8, b1 = (uint64_t)(x + 1) * P.gy / 8;
+    const uint64_t row = (b1 - b0) * P.gx;  // tiles of one band-layer
+    const uint64_t L = (blockIdx.x >> 3) + k * (gridDim.x >> 3);
+    const uint64_t a = L / row, rem = L - a * row;
+    if (a >= P.gz) return false;
+    *t = (a * P.gy + b0 + rem / P.gx) * P.gx + rem % P.gx;
+    return true;
   }
   const uint64_t U = ndim == 3 ? (uint64_t)P.gy * P.gx : ndim == 2 ? (uint64_t)P.gx : 16;
   const uint64_t per = gridDim.x >> 3;
@@ -997,8 +1012,8 @@ __device__ inline uint64_t block_seg_scan(const In *__restrict__ v, uint64_t n, 
   return tot;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_exc_scan(CJob one, const CJob *__restrict__ jobs) {
-  const CJob J = select_job(one, jobs);
+// (runs as the second workgroup of the codebook launch, beside the codebook)
+__device__ inline void exc_scan_body(const CJob &J) {
   const Plan P = J.P;
   DevParams *__restrict__ dp = J.W.P;
   const uint32_t *__restrict__ cnt = J.W.exc_cnt;
@@ -1020,33 +1035,6 @@ __global__ __launch_bounds__(kScanThreads) void k_exc_scan(CJob one, const CJob 
     const uint64_t o = P.off_teo + 8 * nt;
     if (o + 8 <= P.capacity) *reinterpret_cast<uint64_t *>(blob + o) = tot;
     else atomicOr(&dp->overflow, 1u);
-  }
-}
-
-// Place staged records (one wave per tile).
-__global__ __launch_bounds__(kBlock) void k_exc_copy(CJob one, const CJob *__restrict__ jobs) {
-  const CJob J = select_job(one, jobs);
-  const Plan P = J.P;
-  DevParams *__restrict__ dp = J.W.P;
-  const uint32_t *__restrict__ cnt = J.W.exc_cnt;
-  const uint32_t *__restrict__ stage = J.W.stage;
-  const uint64_t *__restrict__ off = J.W.exc_off;
-  uint8_t *__restrict__ blob = J.blob;
-  if (dp->status != 0 || dp->is_const) return;
-  const uint64_t t = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (t >= P.n_tiles) return;
-  const uint32_t c = cnt[t];
-  if (c == 0 || c > (uint32_t)kStage) return;
-  const uint64_t o0 = P.off_exc + 8 * off[t];
-  for (uint32_t e = lane; e < c; e += 64) {
-    const uint64_t o = o0 + 8 * e;
-    if (o + 8 <= P.capacity) {
-      const uint2 v = *reinterpret_cast<const uint2 *>(stage + (t * kStage + e) * 2);
-      *reinterpret_cast<uint2 *>(blob + o) = v;
-    } else {
-      atomicOr(&dp->overflow, 1u);
-    }
   }
 }
 
@@ -1079,8 +1067,14 @@ __device__ inline int count_leq(const uint32_t *a, int n, uint32_t w) {
   return lo;
 }
 
+// Workgroup 0 of the launch builds the code; workgroup 1 scans the tiles'
+// exception counts (the two are independent).
 __global__ __launch_bounds__(kCbThreads) void k_codebook(CJob one, const CJob *__restrict__ jobs) {
   const CJob J = select_job(one, jobs);
+  if (blockIdx.x == 1) {  // uniform over the block
+    exc_scan_body(J);
+    return;
+  }
   const Plan P = J.P;
   DevParams *__restrict__ dp = J.W.P;
   uint32_t *__restrict__ hist_g = J.W.hist;
@@ -1447,6 +1441,22 @@ __global__ __launch_bounds__(kBlock) void k_enc_count(CJob one, const CJob *__re
     const TileGeo g = tile_geo(P, t);
     EncCodes E = enc_codes(P, J.W.codes, g, tid);
     E.prefetch();
+    // the tile's staged exception records to their place in the blob; the
+    // tile's bit counts below reuse the same staging bytes, so the records
+    // are read first (tiles with more records were written in place)
+    {
+      const uint32_t c = J.W.exc_cnt[t];  // uniform over the block
+      if (c && c <= (uint32_t)kStage) {
+        const uint64_t o0 = P.off_exc + 8 * J.W.exc_off[t];
+        for (uint32_t e = tid; e < c; e += kBlock) {
+          const uint64_t o = o0 + 8 * e;
+          const uint2 v = *reinterpret_cast<const uint2 *>(J.W.stage + (t * kStage + e) * 2);
+          if (o + 8 <= P.capacity) *reinterpret_cast<uint2 *>(blob + o) = v;
+          else atomicOr(&dp->overflow, 1u);
+        }
+        __syncthreads();
+      }
+    }
     uint32_t bits = 0;
     bool direct = false;
     if (E.fast) bits = direct_bits(E, len8, &direct);
@@ -1686,65 +1696,10 @@ __global__ void k_header(CJob one, const CJob *__restrict__ jobs) {
   }
 }
 
-// Checksum workgroups for a blob: about 128 KiB per workgroup (32 rounds of
-// 16-byte loads per thread), at most 1024.  Small blobs want few workgroups
-// (each ends with a block reduction and an atomic), large ones more than one
-// per CU to hide the hashing's latency.
-__host__ __device__ inline uint32_t checksum_grid(uint64_t bytes) {
-  const uint64_t cw = bytes / (16ull * kBlock * 32) + 1;
-  return (uint32_t)(cw < 1024 ? cw : 1024);
-}
-
-// checksum over the blob's 32-bit words; the checksum field reads as zero.
-// Accumulates into dp->checksum; use_dp_bytes: the blob size is dp->blob_bytes
-// (compress, after k_header), else bytes_limit (decompress).
-__device__ inline void checksum_body(const uint8_t *__restrict__ blob, uint64_t bytes_limit,
-                                     DevParams *__restrict__ dp, int use_dp_bytes) {
-  if (use_dp_bytes && (dp->status != 0 || dp->overflow)) return;
-  const uint64_t bytes = use_dp_bytes ? dp->blob_bytes : bytes_limit;
-  // a grid sized for the capacity uses only the workgroups this blob needs
-  const uint32_t nblk = gridDim.x < checksum_grid(bytes) ? gridDim.x : checksum_grid(bytes);
-  if (blockIdx.x >= nblk) return;  // uniform over the block, before any barrier
-  const uint64_t nw = bytes / 4;  // a multiple of 2 (blobs are 8-byte sized)
-  const uint32_t *w = reinterpret_cast<const uint32_t *>(blob);
-  const uint4 *w4 = reinterpret_cast<const uint4 *>(blob);
-  uint64_t s = 0;
-  // 16-byte loads when the blob allows them (it is only required to be 8-aligned)
-  const uint64_t n4 = (uintptr_t)blob % 16 == 0 ? nw / 4 : 0;
-  const uint64_t gsz = (uint64_t)nblk * blockDim.x;
-  auto quad = [&](const uint4 v, uint64_t q) {
-    const uint64_t j = 4 * q;
-    s += mix64(v.x, j) + mix64(v.y, j + 1);
-    s += mix64((j + 2 == 50) ? 0u : v.z, j + 2) + mix64((j + 3 == 51) ? 0u : v.w, j + 3);
-  };
-  uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  for (; q + 3 * gsz < n4; q += 4 * gsz) {  // four loads in flight per thread
-    const uint4 a = w4[q], b = w4[q + gsz], c = w4[q + 2 * gsz], d = w4[q + 3 * gsz];
-    quad(a, q);
-    quad(b, q + gsz);
-    quad(c, q + 2 * gsz);
-    quad(d, q + 3 * gsz);
-  }
-  for (; q < n4; q += gsz) quad(w4[q], q);
-  for (uint64_t j = n4 * 4 + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < nw; j += gsz)
-    s += mix64((j == 50 || j == 51) ? 0u : w[j], j);
-  // one atomic per block: atomics on one address are serialized, so their
-  // count, not the memory traffic, would set the kernel's time
-  __shared__ uint64_t part[kBlock / 64];
-  s = wave_sum_u64(s);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint64_t b = 0;
-    for (int i = 0; i < kBlock / 64; i++) b += part[i];
-    if (b) atomicAdd((unsigned long long *)&dp->checksum, (unsigned long long)b);
-  }
-}
-
 __global__ __launch_bounds__(kBlock) void k_checksum(const uint8_t *__restrict__ blob,
                                                      uint64_t bytes_limit,
                                                      DevParams *__restrict__ dp) {
-  checksum_body(blob, bytes_limit, dp, 0);
+  checksum_body(blob, bytes_limit, dp, 0, blockIdx.x, gridDim.x);
 }
 
 hipError_t launch_checksum(const uint8_t *blob, uint64_t bytes, DevParams *dp, hipStream_t s) {
@@ -1756,7 +1711,7 @@ hipError_t launch_checksum(const uint8_t *blob, uint64_t bytes, DevParams *dp, h
 // compress: checksum of each field's finished blob (its size from dp)
 __global__ __launch_bounds__(kBlock) void k_checksum_jobs(CJob one, const CJob *__restrict__ jobs) {
   const CJob J = select_job(one, jobs);
-  checksum_body(J.blob, 0, J.W.P, 1);
+  checksum_body(J.blob, 0, J.W.P, 1, blockIdx.x, gridDim.x);
 }
 
 __global__ void k_checksum_store(CJob one, const CJob *__restrict__ jobs) {
@@ -1790,10 +1745,11 @@ static void launch_quant_d(const CJob &one, const CJob *jobs, int nf, const Plan
   if (ragged)
     hipLaunchKernelGGL((k_quant<T, NDIM, GLOBAL, false, false>), grid, dim3(kBlock), 0, s, one, jobs);
   tm->mark(s, "quant");
-  hipLaunchKernelGGL(k_exc_scan, dim3(1, nf), dim3(kScanThreads), 0, s, one, jobs);
-  const uint32_t cgrid = (uint32_t)ceil_div(maxP.n_tiles, kBlock / 64);
-  hipLaunchKernelGGL(k_exc_copy, dim3(cgrid, nf), dim3(kBlock), 0, s, one, jobs);
-  // tiles with more than kStage records recompute them in place
+  // the code and the exception offsets (one launch, two workgroups per field)
+  hipLaunchKernelGGL(k_codebook, dim3(2, nf), dim3(kCbThreads), 0, s, one, jobs);
+  tm->mark(s, "codebook");
+  // tiles with more than kStage records recompute them in place (the others'
+  // staged records are placed by the encoder's count pass)
   hipLaunchKernelGGL((k_quant<T, NDIM, GLOBAL, true, true>), grid, dim3(kBlock), 0, s, one, jobs);
   if (ragged)
     hipLaunchKernelGGL((k_quant<T, NDIM, GLOBAL, true, false>), grid, dim3(kBlock), 0, s, one, jobs);
@@ -1824,8 +1780,6 @@ static void launch_compress_t(const CJob &one, const CJob *jobs, int nf, const P
   else if (maxP.ndim == 2) launch_quant<T, 2>(one, jobs, nf, maxP, cfg, s, tm);
   else launch_quant<T, 3>(one, jobs, nf, maxP, cfg, s, tm);
   tm->mark(s, "exceptions");
-  hipLaunchKernelGGL(k_codebook, dim3(1, nf), dim3(kCbThreads), 0, s, one, jobs);
-  tm->mark(s, "codebook");
   hipLaunchKernelGGL(k_enc_count, dim3(cfg.encode_grid, nf), dim3(kBlock), 0, s, one, jobs);
   hipLaunchKernelGGL(k_enc_scan, dim3(1, nf), dim3(kScanThreads), 0, s, one, jobs);
   tm->mark(s, "encode_count");

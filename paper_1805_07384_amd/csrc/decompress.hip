@@ -96,6 +96,70 @@ struct VStat {
   }
 };
 
+// The check's per-tile partials combined in a fixed order: thread i takes
+// tiles i, i + blockDim.x, ..., then a fixed tree over lanes and waves; one
+// workgroup of 1024 threads with sixteen rows each in flight.  (Folding this
+// into the last reconstruction workgroup needs a device-scope fence in every
+// workgroup, which writes back the XCD's L2 each time: measured 0.31 ->
+// 1.15 ms for the 512^3 reconstruction.)
+constexpr int kVstatThreads = 1024;
+__global__ __launch_bounds__(kVstatThreads) void k_vstat_final(const double *__restrict__ vpart,
+                                                               uint64_t nt,
+                                                               DevParams *__restrict__ dp) {
+  double sse = 0.0, mx = 0.0;
+  uint64_t over = 0;
+  constexpr int kU = 16;
+  const uint64_t nthr = blockDim.x;
+  const uint64_t *vp = reinterpret_cast<const uint64_t *>(vpart);
+  auto ld = [&](uint64_t i) { return vp[i]; };
+  for (uint64_t b0 = threadIdx.x; b0 < nt; b0 += nthr * kU) {
+    uint64_t s[kU], m[kU], c[kU];
+    // clamped indexes, so that the loads are issued together without
+    // branches; rows past nt are masked afterwards
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      const uint64_t b = b0 + (uint64_t)u * nthr;
+      const uint64_t bc = b < nt ? b : nt - 1;
+      s[u] = ld(3 * bc);
+      m[u] = ld(3 * bc + 1);
+      c[u] = ld(3 * bc + 2);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      const bool in = b0 + (uint64_t)u * nthr < nt;
+      const double su = __longlong_as_double((long long)s[u]);
+      const double mu = __longlong_as_double((long long)m[u]);
+      sse += in ? su : 0.0;
+      mx = in && mu > mx ? mu : mx;
+      over += in ? c[u] : 0ull;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    sse += __shfl_xor(sse, o, 64);
+    const double m2 = __shfl_xor(mx, o, 64);
+    mx = m2 > mx ? m2 : mx;
+    over += __shfl_xor(over, o, 64);
+  }
+  __shared__ double s_sse[16], s_mx[16];
+  __shared__ uint64_t s_over[16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) { s_sse[wv] = sse; s_mx[wv] = mx; s_over[wv] = over; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, mm = 0.0;
+    uint64_t cc = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); w++) {
+      a += s_sse[w];
+      mm = s_mx[w] > mm ? s_mx[w] : mm;
+      cc += s_over[w];
+    }
+    dp->v_sse = a;
+    dp->v_max = mm;
+    dp->v_over = cc;
+  }
+}
+
 // Tile of a one-tile-per-workgroup grid, XCD-aware: workgroups are
 // dispatched round-robin over the 8 XCDs (block b on XCD b % 8), so XCD k is
 // given the k-th eighth of the tiles in order.  Tiles that neighbour in x
@@ -115,11 +179,10 @@ typedef double df64x2_t __attribute__((ext_vector_type(2)));
 
 // ---------------------------------------------------------------------------
 // decoder tables from the code lengths in the blob (one workgroup)
-__global__ __launch_bounds__(1024) void k_dec_tables(Plan P, const uint8_t *__restrict__ blob,
-                                                     DevParams *__restrict__ dp,
-                                                     uint16_t *__restrict__ lut,
-                                                     uint32_t *__restrict__ ltab,
-                                                     uint16_t *__restrict__ sorted) {
+__device__ inline void dec_tables_body(const Plan &P, const uint8_t *__restrict__ blob,
+                                       DevParams *__restrict__ dp, uint16_t *__restrict__ lut,
+                                       uint32_t *__restrict__ ltab,
+                                       uint16_t *__restrict__ sorted) {
   __shared__ uint8_t lens[kNSym];
   __shared__ uint32_t lcount[kLMax + 2], lfirst[kLMax + 2], lbase[kLMax + 2];
   __shared__ unsigned long long kraft;
@@ -182,11 +245,27 @@ __global__ __launch_bounds__(1024) void k_dec_tables(Plan P, const uint8_t *__re
   }
 }
 
+// The blob checksum and the decoder tables in one launch: block 0 builds the
+// tables while the others hash the blob (the decoder compares the sum with
+// the stored one before it reads anything).
+__global__ __launch_bounds__(1024) void k_front(Plan P, const uint8_t *__restrict__ blob,
+                                                uint64_t bytes, DevParams *__restrict__ dp,
+                                                uint16_t *__restrict__ lut,
+                                                uint32_t *__restrict__ ltab,
+                                                uint16_t *__restrict__ sorted) {
+  if (blockIdx.x == 0) {  // uniform over the block
+    dec_tables_body(P, blob, dp, lut, ltab, sorted);
+    return;
+  }
+  checksum_body(blob, bytes, dp, 0, blockIdx.x - 1, gridDim.x - 1);
+}
+
 // ---------------------------------------------------------------------------
 // Decode: one wave per tile, lane k decodes chunk k (128 symbols) in one
-// pass.  The first `stage_words` words of the tile are staged in LDS; lanes
-// whose chunk ends inside that window read from LDS, the others (the tail of
-// tiles larger than the window) read the blob directly.  Each lane holds two
+// pass.  The tile's words are staged in LDS (the whole tile, or a window of
+// it when the workgroup's tiles do not fit its pool together); lanes whose
+// chunk ends inside the staged words read from LDS, the others read the blob
+// directly.  Each lane holds two
 // words of its chunk in registers and one read ahead, so a symbol step is a
 // funnel shift, a table lookup and a pack, with no LDS read on the path from
 // one symbol to the next but the table's.  Table entries with bit 15 set
@@ -195,7 +274,7 @@ __global__ __launch_bounds__(1024) void k_dec_tables(Plan P, const uint8_t *__re
 // Residual codes are written in stream order, eight per 16-byte store
 // (outliers as -32768; their residual is in the exception list, whose outlier
 // count is checked).
-constexpr int kDecWaves = 8;
+constexpr int kDecWaves = 8;  // waves (tiles) per workgroup
 constexpr int kDecBlock = 64 * kDecWaves;
 
 typedef __attribute__((address_space(3))) const uint32_t lds_cu32;
@@ -371,24 +450,36 @@ __device__ inline uint32_t decode_run(Reader &R, int cnt, uint32_t lut_lds, uint
   return nout;
 }
 
+// Words of a workgroup's tiles in LDS: the waves' tiles are placed one after
+// another in one pool (each followed by two zero words), so a tile of any
+// size is read from LDS as long as the workgroup's tiles fit together; the
+// launch picks the number of waves per workgroup from the average tile size
+// so that they nearly always do.  Otherwise each wave gets an equal share of
+// the pool as its window, and lanes whose chunk ends past it read the blob.
 template <int NDIM>
 __global__ __launch_bounds__(kDecBlock) void k_decode(Plan P, const uint8_t *__restrict__ blob,
                                                       DecodeArgs A, DevParams *__restrict__ dp,
-                                                      int16_t *__restrict__ codes, uint32_t stage_words) {
+                                                      int16_t *__restrict__ codes, uint32_t pool_words) {
   __shared__ __attribute__((aligned(16))) uint16_t lut[1 << kLut];
   __shared__ uint32_t lim[kLMax + 1];
   __shared__ int32_t off[kLMax + 1];
   __shared__ uint16_t sorted[kNSym];
-  extern __shared__ uint32_t wstage[];  // kDecWaves windows of stage_words + 2
+  __shared__ uint32_t s_words[kDecWaves];
+  extern __shared__ uint32_t wstage[];  // pool of pool_words
 
-  if (dp->corrupt) return;
+  if (dp->corrupt) return;  // uniform over the grid
+  if (*reinterpret_cast<const uint64_t *>(blob + H_CSUM) != dp->checksum) {
+    if (threadIdx.x == 0) atomicOr(&dp->corrupt, 1u);
+    return;
+  }
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nwv = (int)(blockDim.x >> 6);
   {
     const du32x4_t *src = reinterpret_cast<const du32x4_t *>(A.lut);
     du32x4_t *d = reinterpret_cast<du32x4_t *>(lut);
-    for (int i = tid; i < (1 << kLut) / 8; i += kDecBlock) d[i] = src[i];
+    for (int i = tid; i < (1 << kLut) / 8; i += (int)blockDim.x) d[i] = src[i];
   }
-  for (int i = tid; i < kNSym; i += kDecBlock) {
+  for (int i = tid; i < kNSym; i += (int)blockDim.x) {
     const uint16_t v = A.sorted[i];
     sorted[i] = v == 0 ? (uint16_t)kSymOutlierTag : v;
   }
@@ -397,21 +488,43 @@ __global__ __launch_bounds__(kDecBlock) void k_decode(Plan P, const uint8_t *__r
     lim[tid] = tid ? (first + cnt) << (kLMax - tid) : 0u;
     off[tid] = (int32_t)base - (int32_t)first;
   }
-  __syncthreads();
   // the tile is wave-uniform: its values live in scalar registers
-  const uint64_t t = (uint64_t)blockIdx.x * kDecWaves + __builtin_amdgcn_readfirstlane(wv);
-  if (t >= P.n_tiles) return;  // no barrier follows
-  const TileGeo g = tile_geo(P, t);
-  const int nt = (int)g.nt;
+  const uint64_t t = (uint64_t)blockIdx.x * (uint64_t)nwv + __builtin_amdgcn_readfirstlane(wv);
+  const bool valid = t < P.n_tiles;
   const uint64_t *two = reinterpret_cast<const uint64_t *>(blob + P.off_two);
   const uint64_t *teo = reinterpret_cast<const uint64_t *>(blob + P.off_teo);
-  const uint64_t w0 = two[t], w1 = two[t + 1];
-  const uint64_t e0 = teo[t], e1 = teo[t + 1];
-  if (w0 > w1 || w1 > A.n_words || e0 > e1 || e1 > A.n_exc || w1 - w0 > (uint64_t)kTilePts) {
-    if (lane == 0) atomicOr(&dp->corrupt, 1u);
-    return;
+  uint64_t w0 = 0, w1 = 0, e0 = 0, e1 = 0;
+  if (valid) {
+    w0 = two[t];
+    w1 = two[t + 1];
+    e0 = teo[t];
+    e1 = teo[t + 1];
   }
-  const uint32_t nw = (uint32_t)(w1 - w0);
+  const bool sane =
+      valid && !(w0 > w1 || w1 > A.n_words || e0 > e1 || e1 > A.n_exc || w1 - w0 > (uint64_t)kTilePts);
+  if (valid && !sane && lane == 0) atomicOr(&dp->corrupt, 1u);
+  const uint32_t nw = sane ? (uint32_t)(w1 - w0) : 0u;
+  if (lane == 0) s_words[wv] = nw + 2;
+  __syncthreads();  // the last barrier of the kernel
+  uint32_t pos = 0, tot = 0;
+  for (int w = 0; w < nwv; w++) {
+    const uint32_t v = s_words[w];
+    pos += w < wv ? v : 0u;
+    tot += v;
+  }
+  if (!sane) return;
+  uint32_t *mine;
+  uint32_t wn;
+  if (tot <= pool_words) {  // uniform over the workgroup: every tile whole
+    mine = wstage + pos;
+    wn = nw;
+  } else {
+    const uint32_t share = pool_words / (uint32_t)nwv;
+    mine = wstage + (uint32_t)wv * share;
+    wn = nw < share - 2 ? nw : share - 2;
+  }
+  const TileGeo g = tile_geo(P, t);
+  const int nt = (int)g.nt;
   const uint32_t *gw = reinterpret_cast<const uint32_t *>(blob + A.off_words) + w0;
   const uint16_t *cbits = reinterpret_cast<const uint16_t *>(blob + P.off_cb);
   const uint32_t cb = lane < (int)g.nck ? cbits[g.chunk_base + lane] : 0u;
@@ -428,8 +541,6 @@ __global__ __launch_bounds__(kDecBlock) void k_decode(Plan P, const uint8_t *__r
     LT.off[m] = __builtin_amdgcn_readfirstlane(off[kLut + m]);
   }
   // stage the window: its words and two zero words after them
-  uint32_t *mine = wstage + (size_t)wv * (stage_words + 2);
-  const uint32_t wn = nw < stage_words ? nw : stage_words;
   for (uint32_t i = lane; i < wn + 2; i += 64) mine[i] = i < wn ? gw[i] : 0u;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -1409,77 +1520,20 @@ static void excl_set(std::initializer_list<ScanJob> jobs, uint32_t *tmp, hipStre
   hipLaunchKernelGGL(k_excl_set, dim3((uint32_t)(b < 65536 ? b : 65536)), dim3(kBlock), 0, s, S);
 }
 
-// ---------------------------------------------------------------------------
-__global__ void k_csum_check(const uint8_t *__restrict__ blob, DevParams *__restrict__ dp) {
-  const uint64_t stored = *reinterpret_cast<const uint64_t *>(blob + H_CSUM);
-  if (stored != dp->checksum) dp->corrupt = 1;
-}
-
-// The check's per-tile partials combined in a fixed order: thread i takes
-// tiles i, i + kVstatThreads, ..., then a fixed tree over lanes and waves.
-// 1024 threads with 16 rows each have the partials of 16384 tiles in flight
-// at once.
-constexpr int kVstatThreads = 1024;
-__global__ __launch_bounds__(kVstatThreads) void k_vstat_final(const double *__restrict__ vpart,
-                                                               uint64_t nt,
-                                                               DevParams *__restrict__ dp) {
-  double sse = 0.0, mx = 0.0;
-  uint64_t over = 0;
-  constexpr int kU = 16;
-  for (uint64_t b0 = threadIdx.x; b0 < nt; b0 += (uint64_t)kVstatThreads * kU) {
-    double s[kU], m[kU], c[kU];
-    // clamped indexes, so that the loads are issued together without
-    // branches; rows past nt are masked afterwards
-#pragma unroll
-    for (int u = 0; u < kU; u++) {
-      const uint64_t b = b0 + (uint64_t)u * kVstatThreads;
-      const uint64_t bc = b < nt ? b : nt - 1;
-      s[u] = vpart[3 * bc];
-      m[u] = vpart[3 * bc + 1];
-      c[u] = vpart[3 * bc + 2];
-    }
-#pragma unroll
-    for (int u = 0; u < kU; u++) {
-      const bool in = b0 + (uint64_t)u * kVstatThreads < nt;
-      sse += in ? s[u] : 0.0;
-      mx = in && m[u] > mx ? m[u] : mx;
-      over += in ? (uint64_t)__double_as_longlong(c[u]) : 0ull;
-    }
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    sse += __shfl_xor(sse, o, 64);
-    const double m2 = __shfl_xor(mx, o, 64);
-    mx = m2 > mx ? m2 : mx;
-    over += __shfl_xor(over, o, 64);
-  }
-  __shared__ double s_sse[kVstatThreads / 64], s_mx[kVstatThreads / 64];
-  __shared__ uint64_t s_over[kVstatThreads / 64];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) { s_sse[wv] = sse; s_mx[wv] = mx; s_over[wv] = over; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double a = 0.0, m = 0.0;
-    uint64_t c = 0;
-    for (int w = 0; w < kVstatThreads / 64; w++) {
-      a += s_sse[w];
-      m = s_mx[w] > m ? s_mx[w] : m;
-      c += s_over[w];
-    }
-    dp->v_sse = a;
-    dp->v_max = m;
-    dp->v_over = c;
-  }
-}
+struct DecShape {
+  uint32_t waves;       // waves (tiles) per decode workgroup
+  uint32_t pool_words;  // LDS pool of the workgroup
+};
 
 template <typename T, int NDIM>
 static void launch_dec_t(const Plan &P, const uint8_t *blob, const DecodeArgs &A, DevParams *dp,
-                         int16_t *codes, uint32_t *tmp, uint32_t stage_words, T *out,
-                         hipStream_t s, Timer *tm) {
+                         int16_t *codes, uint32_t *tmp, DecShape ds, T *out, hipStream_t s,
+                         Timer *tm) {
   using G = DGeo<NDIM>;
-  const dim3 dgrid((uint32_t)ceil_div(P.n_tiles, kDecWaves)), grid((uint32_t)P.n_tiles), blk(kBlock);
-  const size_t dyn = (size_t)kDecWaves * (stage_words + 2) * 4;
-  hipLaunchKernelGGL((k_decode<NDIM>), dgrid, dim3(kDecBlock), dyn, s, P, blob, A, dp, codes, stage_words);
+  const dim3 dgrid((uint32_t)ceil_div(P.n_tiles, ds.waves)), grid((uint32_t)P.n_tiles), blk(kBlock);
+  const size_t dyn = (size_t)ds.pool_words * 4;
+  hipLaunchKernelGGL((k_decode<NDIM>), dgrid, dim3(64 * ds.waves), dyn, s, P, blob, A, dp, codes,
+                     ds.pool_words);
   tm->mark(s, "decode");
   const bool ragged = P.pad_ != 0;
   if (P.domain == FPSZ_DOMAIN_GLOBAL) {
@@ -1530,11 +1584,9 @@ static void launch_dec_t(const Plan &P, const uint8_t *blob, const DecodeArgs &A
   }
 }
 
-// Largest decode window (words per wave) that keeps two decode workgroups
-// resident per CU next to their decoder tables (at most 20 KB each): one
-// workgroup per CU leaves too few waves to hide the LDS latency of the symbol
-// loop, and the chunks past the window are read from global memory instead.
-static uint64_t decode_window_limit() {
+// LDS pool (words) of a decode workgroup when two are resident per CU next to
+// their decoder tables (at most 20 KB each).
+static uint64_t decode_pool_limit() {
   static int cached[64][2];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
@@ -1553,8 +1605,20 @@ static uint64_t decode_window_limit() {
   int64_t lds = cached[dev][1] / 2;
   if (lds > cached[dev][0]) lds = cached[dev][0];
   const int64_t words = (lds - 20480) / 4;
-  const int64_t per_wave = words / kDecWaves - 2;
-  return per_wave < 512 ? 512 : (uint64_t)(per_wave & ~(int64_t)63);
+  return words < 8 * 514 ? 8 * 514 : (uint64_t)words;
+}
+
+// Waves per decode workgroup.  The symbol loop is bound by latency, so the
+// number of waves resident matters most: eight per workgroup, two workgroups
+// per CU (four waves per SIMD).  Measured on the 512^3 sweep: fewer waves with
+// whole tiles in LDS (2-4 per workgroup at 100-120 dB) were slower than eight
+// whose large tiles partly read the blob, and ten per workgroup were slower
+// than eight at 40-60 dB.
+static DecShape decode_shape(const Plan &, uint64_t) {
+  DecShape d;
+  d.waves = (uint32_t)kDecWaves;
+  d.pool_words = (uint32_t)decode_pool_limit();
+  return d;
 }
 
 hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const DecompressWs &W,
@@ -1564,13 +1628,10 @@ hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const Deco
   tm->mark(s, "begin");
   hipError_t e = launch_fill_zero(W.P, W.zero_bytes, s);
   if (e != hipSuccess) return e;
-  e = launch_checksum(blob, P.capacity, W.P, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_csum_check, dim3(1), dim3(1), 0, s, blob, W.P);
-  tm->mark(s, "checksum_check");
-  hipLaunchKernelGGL(k_dec_tables, dim3(1), dim3(1024), 0, s, P, blob, W.P, W.lut, W.ltab,
-                     W.sorted);
-  tm->mark(s, "tables");
+  const uint32_t cblk = (checksum_grid(P.capacity) * kBlock + 1023) / 1024;
+  hipLaunchKernelGGL(k_front, dim3(1 + cblk), dim3(1024), 0, s, P, blob, P.capacity, W.P, W.lut,
+                     W.ltab, W.sorted);
+  tm->mark(s, "checksum_tables");
   DecodeArgs A;
   A.off_words = off_words;
   A.n_words = n_words;
@@ -1590,21 +1651,15 @@ hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const Deco
   A.ref = ref;
   A.eb = eb;
   A.vpart = W.vpart;
-  // LDS window per wave: a quarter above the average words per tile, so that
-  // most chunks are read from LDS; the rest are read from global memory.
-  const uint64_t avg = P.n_tiles ? n_words / P.n_tiles : 0;
-  uint64_t sw = (avg + avg / 4 + 64 + 63) & ~(uint64_t)63;
-  const uint64_t sw_max = decode_window_limit();
-  sw = sw < 512 ? 512 : (sw > sw_max ? sw_max : sw);
-  const uint32_t stage_words = (uint32_t)sw;
+  const DecShape ds = decode_shape(P, n_words);
   if (P.dtype == FPSZ_F32) {
-    if (P.ndim == 1) launch_dec_t<float, 1>(P, blob, A, W.P, W.codes, W.tmp, stage_words, (float *)out, s, tm);
-    else if (P.ndim == 2) launch_dec_t<float, 2>(P, blob, A, W.P, W.codes, W.tmp, stage_words, (float *)out, s, tm);
-    else launch_dec_t<float, 3>(P, blob, A, W.P, W.codes, W.tmp, stage_words, (float *)out, s, tm);
+    if (P.ndim == 1) launch_dec_t<float, 1>(P, blob, A, W.P, W.codes, W.tmp, ds, (float *)out, s, tm);
+    else if (P.ndim == 2) launch_dec_t<float, 2>(P, blob, A, W.P, W.codes, W.tmp, ds, (float *)out, s, tm);
+    else launch_dec_t<float, 3>(P, blob, A, W.P, W.codes, W.tmp, ds, (float *)out, s, tm);
   } else {
-    if (P.ndim == 1) launch_dec_t<double, 1>(P, blob, A, W.P, W.codes, W.tmp, stage_words, (double *)out, s, tm);
-    else if (P.ndim == 2) launch_dec_t<double, 2>(P, blob, A, W.P, W.codes, W.tmp, stage_words, (double *)out, s, tm);
-    else launch_dec_t<double, 3>(P, blob, A, W.P, W.codes, W.tmp, stage_words, (double *)out, s, tm);
+    if (P.ndim == 1) launch_dec_t<double, 1>(P, blob, A, W.P, W.codes, W.tmp, ds, (double *)out, s, tm);
+    else if (P.ndim == 2) launch_dec_t<double, 2>(P, blob, A, W.P, W.codes, W.tmp, ds, (double *)out, s, tm);
+    else launch_dec_t<double, 3>(P, blob, A, W.P, W.codes, W.tmp, ds, (double *)out, s, tm);
   }
   return hipGetLastError();
 }

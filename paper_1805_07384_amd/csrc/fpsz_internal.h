@@ -271,6 +271,64 @@ __device__ inline void canonical_from_lengths(const uint8_t *lens, uint32_t *cod
   __syncthreads();
 }
 
+// Checksum workgroups for a blob: about 128 KiB per workgroup (32 rounds of
+// 16-byte loads per thread), at most 1024.  Small blobs want few workgroups
+// (each ends with a block reduction and an atomic), large ones more than one
+// per CU to hide the hashing's latency.
+__host__ __device__ inline uint32_t checksum_grid(uint64_t bytes) {
+  const uint64_t cw = bytes / (16ull * kBlock * 32) + 1;
+  return (uint32_t)(cw < 1024 ? cw : 1024);
+}
+
+// checksum over the blob's 32-bit words; the checksum field reads as zero.
+// Accumulates into dp->checksum; use_dp_bytes: the blob size is dp->blob_bytes
+// (compress, after k_header), else bytes_limit (decompress).
+// Block bi of nb (blocks of any multiple of 64 threads up to 1024).
+__device__ inline void checksum_body(const uint8_t *__restrict__ blob, uint64_t bytes_limit,
+                                     DevParams *__restrict__ dp, int use_dp_bytes, uint32_t bi,
+                                     uint32_t nb) {
+  if (use_dp_bytes && (dp->status != 0 || dp->overflow)) return;
+  const uint64_t bytes = use_dp_bytes ? dp->blob_bytes : bytes_limit;
+  // a grid sized for the capacity uses only the workgroups this blob needs
+  const uint32_t want = (checksum_grid(bytes) * kBlock + blockDim.x - 1) / blockDim.x;
+  const uint32_t nblk = nb < want ? nb : want;
+  if (bi >= nblk) return;  // uniform over the block, before any barrier
+  const uint64_t nw = bytes / 4;  // a multiple of 2 (blobs are 8-byte sized)
+  const uint32_t *w = reinterpret_cast<const uint32_t *>(blob);
+  const uint4 *w4 = reinterpret_cast<const uint4 *>(blob);
+  uint64_t s = 0;
+  // 16-byte loads when the blob allows them (it is only required to be 8-aligned)
+  const uint64_t n4 = (uintptr_t)blob % 16 == 0 ? nw / 4 : 0;
+  const uint64_t gsz = (uint64_t)nblk * blockDim.x;
+  auto quad = [&](const uint4 v, uint64_t q) {
+    const uint64_t j = 4 * q;
+    s += mix64(v.x, j) + mix64(v.y, j + 1);
+    s += mix64((j + 2 == 50) ? 0u : v.z, j + 2) + mix64((j + 3 == 51) ? 0u : v.w, j + 3);
+  };
+  uint64_t q = bi * (uint64_t)blockDim.x + threadIdx.x;
+  for (; q + 3 * gsz < n4; q += 4 * gsz) {  // four loads in flight per thread
+    const uint4 a = w4[q], b = w4[q + gsz], c = w4[q + 2 * gsz], d = w4[q + 3 * gsz];
+    quad(a, q);
+    quad(b, q + gsz);
+    quad(c, q + 2 * gsz);
+    quad(d, q + 3 * gsz);
+  }
+  for (; q < n4; q += gsz) quad(w4[q], q);
+  for (uint64_t j = n4 * 4 + bi * (uint64_t)blockDim.x + threadIdx.x; j < nw; j += gsz)
+    s += mix64((j == 50 || j == 51) ? 0u : w[j], j);
+  // one atomic per block: atomics on one address are serialized, so their
+  // count, not the memory traffic, would set the kernel's time
+  __shared__ uint64_t part[16];
+  s = wave_sum_u64(s);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t b = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); i++) b += part[i];
+    if (b) atomicAdd((unsigned long long *)&dp->checksum, (unsigned long long)b);
+  }
+}
+
 // Optional per-stage timing with HIP events recorded on the launch stream.
 struct Timer {
   static constexpr int kMax = 48;
