@@ -392,28 +392,32 @@ __device__ inline void slow_step(uint32_t top, uint32_t e, const LongTabs &LT,
 }
 
 // One symbol: returns residual + 512 (mod 2^16) and consumes its bits.
+// (Escapes decoded inline by every lane, with only outliers and long codes
+// in the slow step, measured no faster at 100-120 dB: long codes still send
+// most waves there.)
 template <class Reader>
 __device__ inline uint32_t decode_sym(Reader &R, uint32_t lut_lds, uint32_t sorted_lds,
-                                      const LongTabs &LT, uint32_t *tot, uint32_t *nout,
-                                      bool &badv) {
+                                      const LongTabs &LT, uint32_t *nout, bool &badv) {
   const uint32_t top = R.top();
   const uint32_t e = *(lds_cu16 *)(uintptr_t)(lut_lds + ((top >> (32 - kLut)) << 1));
   uint32_t v = e >> 5, n = e & 31u;
   if (__builtin_amdgcn_ballot_w64(e >= 0x8000u)) slow_step(top, e, LT, sorted_lds, &v, &n, nout, badv);
   R.consume(n);
-  *tot += n;
   return v;
 }
 
 // Decode one chunk of cnt symbols into dst.  FULL (128 symbols, 16-byte
 // aligned destination): the codes of 32 symbols are held in registers and
 // stored as four 16-byte pieces of one lane, so the cache sees whole 64-byte
-// pieces rather than scattered ones.
+// pieces rather than scattered ones.  *end receives the word-relative bit
+// position after the last symbol: the reader's next 32 bits start
+// 32 (idx - 1) - s bits into the tile (a and b are words idx - 2 and
+// idx - 1, the window's top bit is bit 31 + s of a:b).
 template <bool FULL, class Reader>
 __device__ inline uint32_t decode_run(Reader &R, int cnt, uint32_t lut_lds, uint32_t sorted_lds,
-                                      const LongTabs &LT, int16_t *dst, uint32_t *used,
+                                      const LongTabs &LT, int16_t *dst, uint32_t *end,
                                       bool *bad) {
-  uint32_t nout = 0, tot = 0;
+  uint32_t nout = 0;
   bool badv = false;
   if (FULL) {
     typedef __attribute__((address_space(1))) du32x4_t gq;
@@ -422,8 +426,8 @@ __device__ inline uint32_t decode_run(Reader &R, int cnt, uint32_t lut_lds, uint
       uint32_t pk[16];
 #pragma unroll
       for (int h = 0; h < 32; h += 2) {
-        const uint32_t a = decode_sym(R, lut_lds, sorted_lds, LT, &tot, &nout, badv);
-        const uint32_t b = decode_sym(R, lut_lds, sorted_lds, LT, &tot, &nout, badv);
+        const uint32_t a = decode_sym(R, lut_lds, sorted_lds, LT, &nout, badv);
+        const uint32_t b = decode_sym(R, lut_lds, sorted_lds, LT, &nout, badv);
         du16x2_t p2 = __builtin_bit_cast(du16x2_t, a | (b << 16));
         p2 -= (du16x2_t)(512);
         pk[h >> 1] = __builtin_bit_cast(uint32_t, p2);
@@ -441,11 +445,11 @@ __device__ inline uint32_t decode_run(Reader &R, int cnt, uint32_t lut_lds, uint
     }
   } else {
     for (int k = 0; k < cnt; k++) {
-      const uint32_t a = decode_sym(R, lut_lds, sorted_lds, LT, &tot, &nout, badv);
+      const uint32_t a = decode_sym(R, lut_lds, sorted_lds, LT, &nout, badv);
       dst[k] = (int16_t)(uint16_t)(a - 512u);
     }
   }
-  *used = tot;
+  *end = 32u * (R.idx - 1u) - R.s;
   *bad = badv;
   return nout;
 }
@@ -554,7 +558,7 @@ __global__ __launch_bounds__(kDecBlock) void k_decode(Plan P, const uint8_t *__r
   // full chunks with a 16-byte aligned destination (k0 is a multiple of 128)
   const bool full = cnt == kChunk && (g.start & 7) == 0;
   bool bad = false;
-  uint32_t used = cb, nout = 0;
+  uint32_t endpos = incl, nout = 0;  // bit position after the chunk
   const bool lds = clw < wn;
   const uint32_t lut_lds = lds_addr(lut), sorted_lds = lds_addr(sorted);
   if (__builtin_amdgcn_ballot_w64(cnt > 0 && !lds)) {
@@ -566,8 +570,8 @@ __global__ __launch_bounds__(kDecBlock) void k_decode(Plan P, const uint8_t *__r
       R.wlim = wn + 1;
       R.glim = nw - 1;
       R.init(cstart);
-      if (full) nout = decode_run<true>(R, cnt, lut_lds, sorted_lds, LT, dst, &used, &bad);
-      else nout = decode_run<false>(R, cnt, lut_lds, sorted_lds, LT, dst, &used, &bad);
+      if (full) nout = decode_run<true>(R, cnt, lut_lds, sorted_lds, LT, dst, &endpos, &bad);
+      else nout = decode_run<false>(R, cnt, lut_lds, sorted_lds, LT, dst, &endpos, &bad);
     }
   } else if (cnt > 0) {
     BitReader<false> R;
@@ -577,8 +581,8 @@ __global__ __launch_bounds__(kDecBlock) void k_decode(Plan P, const uint8_t *__r
     R.wlim = wn + 1;
     R.glim = 0;
     R.init(cstart);
-    if (full) nout = decode_run<true>(R, cnt, lut_lds, sorted_lds, LT, dst, &used, &bad);
-    else nout = decode_run<false>(R, cnt, lut_lds, sorted_lds, LT, dst, &used, &bad);
+    if (full) nout = decode_run<true>(R, cnt, lut_lds, sorted_lds, LT, dst, &endpos, &bad);
+    else nout = decode_run<false>(R, cnt, lut_lds, sorted_lds, LT, dst, &endpos, &bad);
   }
   // every outlier symbol must have its record
   uint32_t nrec = 0;
@@ -586,7 +590,7 @@ __global__ __launch_bounds__(kDecBlock) void k_decode(Plan P, const uint8_t *__r
   for (uint64_t e = e0 + lane; e < e1; e += 64) nrec += (exc[2 * e] & kTagPatch) ? 0u : 1u;
   nrec = wave_sum_u32(nrec);
   nout = wave_sum_u32(nout);
-  if (bad || used != cb || nrec != nout) atomicOr(&dp->corrupt, 1u);
+  if (bad || endpos != incl || nrec != nout) atomicOr(&dp->corrupt, 1u);
 }
 
 // ---------------------------------------------------------------------------
@@ -1614,7 +1618,7 @@ static uint64_t decode_pool_limit() {
 // whole tiles in LDS (2-4 per workgroup at 100-120 dB) were slower than eight
 // whose large tiles partly read the blob, and ten per workgroup were slower
 // than eight at 40-60 dB.
-static DecShape decode_shape(const Plan &, uint64_t) {
+static DecShape decode_shape() {
   DecShape d;
   d.waves = (uint32_t)kDecWaves;
   d.pool_words = (uint32_t)decode_pool_limit();
@@ -1651,7 +1655,7 @@ hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const Deco
   A.ref = ref;
   A.eb = eb;
   A.vpart = W.vpart;
-  const DecShape ds = decode_shape(P, n_words);
+  const DecShape ds = decode_shape();
   if (P.dtype == FPSZ_F32) {
     if (P.ndim == 1) launch_dec_t<float, 1>(P, blob, A, W.P, W.codes, W.tmp, ds, (float *)out, s, tm);
     else if (P.ndim == 2) launch_dec_t<float, 2>(P, blob, A, W.P, W.codes, W.tmp, ds, (float *)out, s, tm);
