@@ -104,6 +104,11 @@ def lib():
                                               ctypes.POINTER(ctypes.c_uint64),
                                               ctypes.POINTER(_Trace),
                                               ctypes.POINTER(ctypes.c_double)]
+        L.or_compress_inloop.restype = ctypes.c_int
+        L.or_compress_inloop.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_uint64), ctypes.c_double,
+                                         ctypes.POINTER(ctypes.c_void_p),
+                                         ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_Trace)]
         L.or_quant_sse.restype = ctypes.c_int
         L.or_quant_sse.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_double,
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
@@ -209,6 +214,14 @@ def compress_closed_loop(x: np.ndarray, psnr: float, domain: int = 0, trace: boo
     return _compress(x, psnr, domain, trace, mode=2)
 
 
+def compress_inloop(x: np.ndarray, psnr: float, trace: bool = False):
+    """SZ 1.4-style in-loop compression (tile domain): each point is predicted
+    from the reconstructed values of its preceding neighbours in its tile and
+    the prediction error quantized; points whose code leaves the radius or
+    whose reconstruction misses the bound are stored exactly."""
+    return _compress(x, psnr, 1, trace, mode=3)
+
+
 def quant_sse(x: np.ndarray, psnr: float):
     """(SSE of the quantizer output at the Eq. 7 bound, patches exact; vr)."""
     x = np.ascontiguousarray(x)
@@ -251,6 +264,9 @@ def _compress(x, psnr, domain, trace, mode, scale=1.0):
         st = lib().or_compress_scaled(x.ctypes.data, dt, x.ndim, dims, float(psnr), int(domain),
                                       float(scale), ctypes.byref(out), ctypes.byref(nb),
                                       ctypes.byref(tr))
+    elif mode == 3:
+        st = lib().or_compress_inloop(x.ctypes.data, dt, x.ndim, dims, float(psnr),
+                                      ctypes.byref(out), ctypes.byref(nb), ctypes.byref(tr))
     else:
         st = lib().or_compress_closed_loop(x.ctypes.data, dt, x.ndim, dims, float(psnr),
                                            int(domain), ctypes.byref(out), ctypes.byref(nb),

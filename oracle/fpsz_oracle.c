@@ -67,6 +67,7 @@
 #define OR_FLAG_CONST 1u
 #define OR_FLAG_TILE 2u
 #define OR_FLAG_CLOSED 4u /* bound rescaled by the closed-loop step */
+#define OR_FLAG_INLOOP 8u /* in-loop prediction from reconstructed values (TILE) */
 #define OR_TAG_PATCH 0x80000000u
 
 /* status codes */
@@ -186,6 +187,46 @@ static void stream_order(const or_shape *s, uint64_t *perm) {
           for (uint64_t y = y0; y < y1; y++)
             for (uint64_t x = x0; x < x1; x++) perm[p++] = (z * s->ny + y) * s->nx + x;
       }
+}
+
+/* ------------------------------------------------------------------------ */
+/* In-loop prediction (SZ 1.4's scheme, Sec. II-A step (1) and Sec. III,     */
+/* Eq. 1): the Lorenzo predictor of a point reads the RECONSTRUCTED values   */
+/* of its preceding neighbours, as the decompressor will see them; outside   */
+/* the point's tile it reads zero.  The seven terms are summed in the field's */
+/* precision in this fixed order (zero for a neighbour outside the tile):     */
+/*   (z,y,x-1) + (z,y-1,x) + (z-1,y,x) - (z,y-1,x-1) - (z-1,y,x-1)            */
+/*   - (z-1,y-1,x) + (z-1,y-1,x-1)                                            */
+/* ------------------------------------------------------------------------ */
+static double il_nb(const void *xr, int dtype, const or_shape *S, uint64_t z, uint64_t y,
+                    uint64_t x, uint64_t z0, uint64_t y0, uint64_t x0, int dz, int dy, int dx) {
+  if ((dz && z == z0) || (dy && y == y0) || (dx && x == x0)) return 0.0;
+  uint64_t i = ((z - dz) * S->ny + (y - dy)) * S->nx + (x - dx);
+  return dtype == 0 ? (double)((const float *)xr)[i] : ((const double *)xr)[i];
+}
+
+static float il_pred_f(const float *xr, const or_shape *S, uint64_t z, uint64_t y, uint64_t x,
+                       uint64_t z0, uint64_t y0, uint64_t x0) {
+  float p = (float)il_nb(xr, 0, S, z, y, x, z0, y0, x0, 0, 0, 1);
+  p = p + (float)il_nb(xr, 0, S, z, y, x, z0, y0, x0, 0, 1, 0);
+  p = p + (float)il_nb(xr, 0, S, z, y, x, z0, y0, x0, 1, 0, 0);
+  p = p - (float)il_nb(xr, 0, S, z, y, x, z0, y0, x0, 0, 1, 1);
+  p = p - (float)il_nb(xr, 0, S, z, y, x, z0, y0, x0, 1, 0, 1);
+  p = p - (float)il_nb(xr, 0, S, z, y, x, z0, y0, x0, 1, 1, 0);
+  p = p + (float)il_nb(xr, 0, S, z, y, x, z0, y0, x0, 1, 1, 1);
+  return p;
+}
+
+static double il_pred_d(const double *xr, const or_shape *S, uint64_t z, uint64_t y, uint64_t x,
+                        uint64_t z0, uint64_t y0, uint64_t x0) {
+  double p = il_nb(xr, 1, S, z, y, x, z0, y0, x0, 0, 0, 1);
+  p = p + il_nb(xr, 1, S, z, y, x, z0, y0, x0, 0, 1, 0);
+  p = p + il_nb(xr, 1, S, z, y, x, z0, y0, x0, 1, 0, 0);
+  p = p - il_nb(xr, 1, S, z, y, x, z0, y0, x0, 0, 1, 1);
+  p = p - il_nb(xr, 1, S, z, y, x, z0, y0, x0, 1, 0, 1);
+  p = p - il_nb(xr, 1, S, z, y, x, z0, y0, x0, 1, 1, 0);
+  p = p + il_nb(xr, 1, S, z, y, x, z0, y0, x0, 1, 1, 1);
+  return p;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -435,8 +476,9 @@ static void layout(uint64_t n_tiles, uint64_t n_chunks, uint64_t n_exc, uint64_t
 /* scale: factor applied to eb_rel; closed: the blob records the factor (flag
  * CLOSED and the float64 at H_SCALE).  Plain compression is scale 1, closed 0. */
 static int compress_impl(const void *x, int dtype, int ndim, const uint64_t *dims, double psnr,
-                         int domain, double scale, int closed, uint8_t **blob_out,
+                         int domain, double scale, int closed, int inloop, uint8_t **blob_out,
                          uint64_t *bytes_out, or_trace *tr) {
+  if (inloop) domain = 1; /* in-loop prediction runs per tile */
   *blob_out = NULL;
   *bytes_out = 0;
   if (dtype != 0 && dtype != 1) return OR_E_INVALID_ARG;
@@ -488,7 +530,8 @@ static int compress_impl(const void *x, int dtype, int ndim, const uint64_t *dim
     wr_u32(blob + H_MAGIC, OR_MAGIC);
     wr_u16(blob + H_VERSION, OR_VERSION);
     wr_u16(blob + H_FLAGS, (uint16_t)(OR_FLAG_CONST | (domain ? OR_FLAG_TILE : 0) |
-                                      (closed ? OR_FLAG_CLOSED : 0)));
+                                      (closed ? OR_FLAG_CLOSED : 0) |
+                                      (inloop ? OR_FLAG_INLOOP : 0)));
     if (closed) wr_f64(blob + H_SCALE, scale);
     blob[H_DTYPE] = (uint8_t)dtype; blob[H_NDIM] = (uint8_t)ndim;
     blob[H_LOG2D] = 9; blob[H_LOG2R] = 15; blob[H_LMAX] = OR_LMAX;
@@ -509,9 +552,13 @@ static int compress_impl(const void *x, int dtype, int ndim, const uint64_t *dim
   }
 
   /* 3. prequantization: bin index q = rint(x / (2 eb)) (uniform bins,
-   *    midpoint reconstruction q * 2 eb) */
+   *    midpoint reconstruction q * 2 eb).  In-loop mode quantizes the
+   *    prediction errors in the stream walk instead (step 5). */
   int32_t *q = (int32_t *)malloc(sizeof(int32_t) * n);
-  for (uint64_t i = 0; i < n; i++) {
+  int32_t *dl = (int32_t *)malloc(sizeof(int32_t) * n);
+  float *xrf = inloop && dtype == 0 ? (float *)malloc(4 * n) : NULL;
+  double *xrd = inloop && dtype == 1 ? (double *)malloc(8 * n) : NULL;
+  for (uint64_t i = 0; i < n && !inloop; i++) {
     if (dtype == 0) {
       float t = ((const float *)x)[i] * r_f;
       q[i] = (int32_t)rintf(t);
@@ -525,8 +572,7 @@ static int compress_impl(const void *x, int dtype, int ndim, const uint64_t *dim
   /* 4. Lorenzo residual: delta = sum over the 8 corners of the unit cube
    *    behind the point of (-1)^(a+b+c) q[z-c][y-b][x-a]; q reads as zero
    *    outside the field (GLOBAL) or outside the point's tile (TILE). */
-  int32_t *dl = (int32_t *)malloc(sizeof(int32_t) * n);
-  for (uint64_t z = 0; z < S.nz; z++)
+  for (uint64_t z = 0; z < S.nz && !inloop; z++)
     for (uint64_t y = 0; y < S.ny; y++)
       for (uint64_t xx = 0; xx < S.nx; xx++) {
         uint64_t z0 = 0, y0 = 0, x0 = 0;
@@ -566,6 +612,35 @@ static int compress_impl(const void *x, int dtype, int ndim, const uint64_t *dim
         uint64_t i = perm[p];
         int ne;
         uint32_t ev;
+        if (inloop) {
+          /* prediction from reconstructed neighbours, quantized error; a
+           * point whose code leaves the radius or whose reconstruction
+           * misses the bound in floating point is stored exactly */
+          uint64_t xz = i / (S.ny * S.nx), xy = (i / S.nx) % S.ny, xx = i % S.nx;
+          uint64_t z0 = a * S.tz, y0 = b * S.ty, x0 = c * S.tx;
+          int keep;
+          int32_t qi;
+          if (dtype == 0) {
+            float xv = ((const float *)x)[i];
+            float pr = il_pred_f(xrf, &S, xz, xy, xx, z0, y0, x0);
+            float dd = xv - pr;
+            qi = (int32_t)rintf(dd * r_f);
+            float rec = pr + (float)qi * e2_f;
+            keep = qi > -OR_OUTLIER_MIN && qi < OR_OUTLIER_MIN &&
+                   !(fabs((double)xv - (double)rec) > eb);
+            xrf[i] = keep ? rec : xv;
+          } else {
+            double xv = ((const double *)x)[i];
+            double pr = il_pred_d(xrd, &S, xz, xy, xx, z0, y0, x0);
+            double dd = xv - pr;
+            qi = (int32_t)rint(dd * r);
+            double rec = pr + (double)qi * e2;
+            keep = qi > -OR_OUTLIER_MIN && qi < OR_OUTLIER_MIN && !(fabs(xv - rec) > eb);
+            xrd[i] = keep ? rec : xv;
+          }
+          q[i] = qi;
+          dl[i] = keep ? qi : -OR_OUTLIER_MIN; /* the outlier symbol marks an exact point */
+        }
         int s = or_symbol(dl[i], &ne, &ev);
         sym[p] = s;
         xtra[p] = ev;
@@ -573,12 +648,13 @@ static int compress_impl(const void *x, int dtype, int ndim, const uint64_t *dim
         if (tr && tr->code16) tr->code16[p] = (int16_t)(s == 0 ? -32768 : dl[i]);
         int npush = 0;
         uint32_t rec[6];
-        if (s == 0) { rec[0] = (uint32_t)p; rec[1] = (uint32_t)dl[i]; npush = 1; n_out++; }
-        /* patch test: the float reconstruction must lie within eb of x */
+        if (s == 0 && !inloop) { rec[0] = (uint32_t)p; rec[1] = (uint32_t)dl[i]; npush = 1; n_out++; }
+        /* patch test: the float reconstruction must lie within eb of x (in
+         * in-loop mode: the points marked by the outlier symbol) */
         int patch;
         if (dtype == 0) {
           float xr = (float)q[i] * e2_f;
-          patch = fabs((double)((const float *)x)[i] - (double)xr) > eb;
+          patch = inloop ? s == 0 : fabs((double)((const float *)x)[i] - (double)xr) > eb;
           if (patch) {
             uint32_t bits;
             memcpy(&bits, &((const float *)x)[i], 4);
@@ -586,7 +662,7 @@ static int compress_impl(const void *x, int dtype, int ndim, const uint64_t *dim
           }
         } else {
           double xr = (double)q[i] * e2;
-          patch = fabs(((const double *)x)[i] - xr) > eb;
+          patch = inloop ? s == 0 : fabs(((const double *)x)[i] - xr) > eb;
           if (patch) {
             uint64_t bits;
             memcpy(&bits, &((const double *)x)[i], 8);
@@ -657,7 +733,8 @@ static int compress_impl(const void *x, int dtype, int ndim, const uint64_t *dim
   blob = (uint8_t *)calloc(1, Lo.total);
   wr_u32(blob + H_MAGIC, OR_MAGIC);
   wr_u16(blob + H_VERSION, OR_VERSION);
-  wr_u16(blob + H_FLAGS, (uint16_t)((domain ? OR_FLAG_TILE : 0) | (closed ? OR_FLAG_CLOSED : 0)));
+  wr_u16(blob + H_FLAGS, (uint16_t)((domain ? OR_FLAG_TILE : 0) | (closed ? OR_FLAG_CLOSED : 0) |
+                                     (inloop ? OR_FLAG_INLOOP : 0)));
   if (closed) wr_f64(blob + H_SCALE, scale);
   blob[H_DTYPE] = (uint8_t)dtype; blob[H_NDIM] = (uint8_t)ndim;
   blob[H_LOG2D] = 9; blob[H_LOG2R] = 15; blob[H_LMAX] = OR_LMAX;
@@ -701,6 +778,7 @@ static int compress_impl(const void *x, int dtype, int ndim, const uint64_t *dim
     tr->counts[3] = n_exc; tr->counts[4] = n_out; tr->counts[5] = n_pat;
   }
   free(q); free(dl); free(perm); free(sym); free(xtra); free(exc); free(tile_exc);
+  free(xrf); free(xrd);
   free(chunk_bits); free(tile_words); free(words);
   stage_end(6);
   *blob_out = blob;
@@ -710,7 +788,13 @@ static int compress_impl(const void *x, int dtype, int ndim, const uint64_t *dim
 
 int or_compress(const void *x, int dtype, int ndim, const uint64_t *dims, double psnr,
                 int domain, uint8_t **blob_out, uint64_t *bytes_out, or_trace *tr) {
-  return compress_impl(x, dtype, ndim, dims, psnr, domain, 1.0, 0, blob_out, bytes_out, tr);
+  return compress_impl(x, dtype, ndim, dims, psnr, domain, 1.0, 0, 0, blob_out, bytes_out, tr);
+}
+
+/* SZ 1.4-style in-loop compression (tile domain): see il_pred_f. */
+int or_compress_inloop(const void *x, int dtype, int ndim, const uint64_t *dims, double psnr,
+                       uint8_t **blob_out, uint64_t *bytes_out, or_trace *tr) {
+  return compress_impl(x, dtype, ndim, dims, psnr, 1, 1.0, 0, 1, blob_out, bytes_out, tr);
 }
 
 /* Compression with the bound of Eq. 7 multiplied by a given factor, the
@@ -719,7 +803,7 @@ int or_compress_scaled(const void *x, int dtype, int ndim, const uint64_t *dims,
                        int domain, double scale, uint8_t **blob_out, uint64_t *bytes_out,
                        or_trace *tr) {
   if (!(scale > 0.0) || !isfinite(scale)) return OR_E_INVALID_ARG;
-  return compress_impl(x, dtype, ndim, dims, psnr, domain, scale, 1, blob_out, bytes_out, tr);
+  return compress_impl(x, dtype, ndim, dims, psnr, domain, scale, 1, 0, blob_out, bytes_out, tr);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -795,7 +879,7 @@ int or_compress_closed_loop(const void *x, int dtype, int ndim, const uint64_t *
   if (st != OR_OK) return st;
   double scale = or_closed_loop_scale(sse, S.n, vr, psnr);
   if (scale_out) *scale_out = scale;
-  return compress_impl(x, dtype, ndim, dims, psnr, domain, scale, 1, blob_out, bytes_out, tr);
+  return compress_impl(x, dtype, ndim, dims, psnr, domain, scale, 1, 0, blob_out, bytes_out, tr);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -844,6 +928,8 @@ int or_decompress(const uint8_t *blob, uint64_t bytes, void *out, uint64_t out_b
     return OR_OK;
   }
   int domain = (flags & OR_FLAG_TILE) ? 1 : 0;
+  int inloop = (flags & OR_FLAG_INLOOP) ? 1 : 0;
+  if (inloop && !domain) return OR_E_CORRUPT;
   uint64_t n_tiles = rd_u64(blob + H_NTILES), n_chunks = rd_u64(blob + H_NCHUNKS);
   uint64_t n_words = rd_u64(blob + H_NWORDS), n_exc = rd_u64(blob + H_NEXC);
   if (n_tiles != S.n_tiles || n_chunks != S.n_chunks) return OR_E_CORRUPT;
@@ -960,16 +1046,52 @@ int or_decompress(const uint8_t *blob, uint64_t bytes, void *out, uint64_t out_b
         }
         patched[i] = 1;
       } else {
-        if (!is_out[i]) { rc = OR_E_CORRUPT; break; }
+        if (!is_out[i] || inloop) { rc = OR_E_CORRUPT; break; }
         dl[i] = (int32_t)val;
         is_out[i] = 2;
       }
     }
-    for (uint64_t i = 0; i < n && rc == OR_OK; i++)
-      if (is_out[i] == 1) rc = OR_E_CORRUPT; /* outlier symbol without a value */
+    for (uint64_t i = 0; i < n && rc == OR_OK; i++) {
+      if (inloop) {
+        /* in-loop blobs: the outlier symbol marks exactly the stored points */
+        if ((is_out[i] == 1) != (patched[i] != 0)) rc = OR_E_CORRUPT;
+      } else if (is_out[i] == 1) {
+        rc = OR_E_CORRUPT; /* outlier symbol without a value */
+      }
+    }
   }
-  stage_end(9);
-  if (rc == OR_OK) {
+  if (rc == OR_OK && inloop) {
+    /* repeat the compressor's in-loop prediction point by point, tile by
+     * tile, in stream order (each point's neighbours come before it) */
+    stage_end(9);
+    uint64_t p2 = 0;
+    for (uint64_t t = 0; t < n_tiles; t++) {
+      uint64_t a = t / (S.gy * S.gx), b = (t / S.gx) % S.gy, c = t % S.gx;
+      uint64_t ez = (a + 1) * S.tz <= S.nz ? S.tz : S.nz - a * S.tz;
+      uint64_t ey = (b + 1) * S.ty <= S.ny ? S.ty : S.ny - b * S.ty;
+      uint64_t ex = (c + 1) * S.tx <= S.nx ? S.tx : S.nx - c * S.tx;
+      uint64_t nt = ez * ey * ex;
+      uint64_t z0 = a * S.tz, y0 = b * S.ty, x0 = c * S.tx;
+      for (uint64_t k = 0; k < nt; k++, p2++) {
+        uint64_t i = perm[p2];
+        uint64_t xz = i / (S.ny * S.nx), xy = (i / S.nx) % S.ny, xx = i % S.nx;
+        if (dtype == 0) {
+          float v;
+          if (patched[i]) { uint32_t bb = (uint32_t)pbits[i]; memcpy(&v, &bb, 4); }
+          else v = il_pred_f((const float *)out, &S, xz, xy, xx, z0, y0, x0) + (float)dl[i] * e2_f;
+          ((float *)out)[i] = v;
+        } else {
+          double v;
+          if (patched[i]) memcpy(&v, &pbits[i], 8);
+          else v = il_pred_d((const double *)out, &S, xz, xy, xx, z0, y0, x0) + (double)dl[i] * e2;
+          ((double *)out)[i] = v;
+        }
+      }
+    }
+    stage_end(11);
+  }
+  if (!inloop) stage_end(9);
+  if (rc == OR_OK && !inloop) {
     /* undo the prediction: inclusive prefix sums along x, y and z, over the
      * whole field (GLOBAL) or restarting at every tile edge (TILE).  Sums are
      * taken modulo 2^32; the true bin indexes fit in 32 bits, so the

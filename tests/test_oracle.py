@@ -577,6 +577,67 @@ def test_closed_loop_end_to_end(orc):
     assert orc.header(b0)["scale"] == 0.0 and not orc.header(b0)["flags"] & 4
 
 
+# --------------------------------------------------------------------------
+# in-loop (SZ 1.4-style) prediction, tile domain
+# --------------------------------------------------------------------------
+
+def _np_lorenzo_tiles(q: np.ndarray) -> np.ndarray:
+    """Lorenzo residual with zero outside each tile (np.diff per tile)."""
+    t = TILE[q.ndim]
+    d = np.zeros(q.shape, dtype=np.int64)
+    for idx in itertools.product(*[range(0, n, tt) for n, tt in zip(q.shape, t)]):
+        sl = tuple(slice(i, i + tt) for i, tt in zip(idx, t))
+        d[sl] = _np_lorenzo(q[sl])
+    return d
+
+
+@pytest.mark.parametrize("shape", [(20000,), (70, 300), (20, 37, 70)])
+def test_inloop_integer_field_is_lossless_with_lorenzo_codes(orc, shape):
+    # an integer-valued field at the PSNR where the bin 2 eb is 1 (up to the
+    # last place): the in-loop predictor sees the exact values, every code is
+    # the field's own Lorenzo residual per tile (numpy np.diff), and the
+    # reconstruction is the field itself
+    rng = np.random.default_rng(31)
+    x = np.cumsum(rng.integers(-3, 4, size=shape), axis=-1).astype(np.float32)
+    x.flat[0] = x.min() - 1.0
+    vr = float(x.max() - x.min())
+    psnr = 20.0 * math.log10(2.0 * math.sqrt(3.0) * vr)
+    blob, t = orc.compress_inloop(x, psnr, trace=True)
+    assert t["e2_f"] == 1.0 and t["n_patches"] == 0
+    assert np.array_equal(t["q"].astype(np.int64), _np_lorenzo_tiles(x.astype(np.int64)))
+    assert np.array_equal(orc.decompress(blob), x)
+    h = orc.header(blob)
+    assert h["flags"] & 8 and h["flags"] & 2
+
+
+@pytest.mark.parametrize("shape", [(70001,), (129, 257), (33, 17, 65), (16, 16, 32)])
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+@pytest.mark.parametrize("psnr", [30.0, 80.0, 120.0])
+def test_inloop_round_trip_bound(orc, shape, dt, psnr):
+    # every point within eb; stored points exact
+    x = (synth.grf_numpy(shape, -3.0, 11) * 3.0 + 1.0).astype(dt)
+    blob, t = orc.compress_inloop(x, psnr, trace=True)
+    y = orc.decompress(blob)
+    err = np.abs(x.astype(np.float64) - y.astype(np.float64))
+    assert np.all(err <= t["eb"])
+    stored = t["code16"] == -32768
+    assert int(stored.sum()) == t["n_patches"] and t["n_outliers"] == 0
+
+
+def test_inloop_matches_prequantization_in_statistics(orc):
+    # in exact arithmetic a Lorenzo prediction of multiples of 2 eb is a
+    # multiple of 2 eb, so in-loop quantization lands on the same lattice as
+    # prequantization: the PSNR agrees within the statistical band of Eq. 6
+    x = synth.field_2d_grf(512, 512, seed=1).astype(np.float64)
+    band = 4.343 * 5 * math.sqrt(0.8 / x.size)
+    for psnr in (60.0, 80.0, 100.0):
+        b1, t1 = orc.compress_inloop(x, psnr, trace=True)
+        s1 = orc.stats(x, orc.decompress(b1), t1["vr"], t1["eb"])["psnr"]
+        b0, t0 = orc.compress(x, psnr, domain=1, trace=True)
+        s0 = orc.stats(x, orc.decompress(b0), t0["vr"], t0["eb"])["psnr"]
+        assert abs(s1 - s0) < band and abs(s1 - psnr) < band
+
+
 def test_error_statuses(orc):
     x = np.ones((10, 10), dtype=np.float32)
     blob = orc.compress(x, 80.0)[0]
