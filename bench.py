@@ -520,6 +520,21 @@ def main():
         closed.append({"psnr": p, "dpsnr": round(stc.psnr - p, 5), "eb_scale": ic.eb_scale,
                        "bits_per_value": round(ic.bits_per_value, 4),
                        "compress_gbps": round(n * s / tcl / 1e9, 2), "n_over_eb": stc.n_over_eb})
+    # the SZ 1.4-style in-loop variant (tile domain) on the same field
+    progress("in-loop legs")
+    inloop = []
+    for p in psnrs:
+        st, nb, ii = ctx.compress_inloop_into(x, p, ws_c, blob, stream)
+        if st != fpsz.OK:
+            raise fpsz.FpszError(st, "in-loop at %g dB" % p)
+        til = timed_calls(lambda: ctx.compress_inloop_into(x, p, ws_c, blob, stream), 3, warm=1)[0]
+        tdl = timed_calls(lambda: ctx.decompress_into(blob, nb, ws_d, out, stream), 3, warm=1)[0]
+        st, sti = ctx.decompress_verify_into(blob, nb, ws_d, out, x, stream)
+        inloop.append({"psnr": p, "dpsnr": round(sti.psnr - p, 5),
+                       "bits_per_value": round(ii.bits_per_value, 4), "n_stored": ii.n_patches,
+                       "compress_gbps": round(n * s / til / 1e9, 2),
+                       "decompress_gbps": round(n * s / tdl / 1e9, 2), "n_over_eb": sti.n_over_eb,
+                       "op_frac": op_fracs(n, s, ii.bits_per_value, til, tdl)})
     total_bytes = n * s * len(psnrs)
     value = total_bytes / ((t1 - t0) / args.steps) / 1e9
 
@@ -613,6 +628,7 @@ def main():
         "mean_abs_dpsnr": round(float(np.mean([abs(t["dpsnr"]) for t in per_target])), 4),
         "per_target": per_target,
         "closed_loop": closed,
+        "inloop": inloop,
         "op_roofline": {"peak_gbps": HBM_PEAK_GBPS, "device_copy_gbps": round(copy_gbps, 1),
                         "step_frac": round(step_frac, 4),
                         "step_frac_of_copy": round(step_frac * HBM_PEAK_GBPS / copy_gbps, 4),

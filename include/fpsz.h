@@ -74,6 +74,8 @@ typedef struct {
   uint32_t domain;       /* fpsz_domain used */
   double eb_scale;       /* closed loop: factor applied to Eq. 7's eb_rel (eb_rel above
                             includes it); 1 for plain compression */
+  uint32_t inloop;       /* 1: in-loop prediction (fpsz_compress_inloop) */
+  uint32_t reserved;
 } fpsz_info;
 
 /* Eq. 4: SSE, MSE = SSE / n, PSNR = -20 log10(sqrt(MSE) / vr), max |x - x'|,
@@ -145,6 +147,22 @@ fpsz_status fpsz_compress_closed_loop(fpsz_ctx *ctx, const void *field_dev, int 
                                       uint64_t workspace_bytes, void *blob_dev,
                                       uint64_t blob_capacity, uint64_t *blob_bytes,
                                       fpsz_info *info, void *stream);
+
+/* The SZ 1.4-style in-loop variant (Sec. II-A step (1), Sec. III Eq. 1): each
+ * point's Lorenzo prediction reads the reconstructed values of its preceding
+ * neighbours, the prediction error is quantized with bin 2 eb (Eq. 7's bound
+ * as in fpsz_compress), and the point is reconstructed at once.  Points whose
+ * code leaves the radius 2^15 or whose reconstruction misses eb in floating
+ * point are stored exactly.  Prediction runs inside each 8192-point tile
+ * (zero outside it; a whole-field in-loop predictor would serialize the
+ * field), each tile swept by diagonals on the device.  The blob (header flag
+ * 8, tile domain) decompresses with fpsz_decompress; |x - x'| <= eb at every
+ * point.  Arguments, workspace and status as fpsz_compress. */
+fpsz_status fpsz_compress_inloop(fpsz_ctx *ctx, const void *field_dev, int ndim,
+                                 const uint64_t *dims, fpsz_dtype dtype, double target_psnr,
+                                 void *workspace_dev, uint64_t workspace_bytes, void *blob_dev,
+                                 uint64_t blob_capacity, uint64_t *blob_bytes, fpsz_info *info,
+                                 void *stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): fpsz_compress

@@ -188,7 +188,7 @@ static fpsz_status compress_one(fpsz_ctx *ctx, const void *field_dev, int ndim,
                                 const uint64_t *dims, fpsz_dtype dtype, double target_psnr,
                                 fpsz_domain domain, void *workspace_dev, uint64_t workspace_bytes,
                                 void *blob_dev, uint64_t blob_capacity, uint64_t *blob_bytes,
-                                fpsz_info *info, void *stream, int closed) {
+                                fpsz_info *info, void *stream, int closed, int inloop = 0) {
   if (!ctx) return FPSZ_E_INVALID_ARG;
   ctx->err[0] = 0;
   CJob job;
@@ -197,6 +197,7 @@ static fpsz_status compress_one(fpsz_ctx *ctx, const void *field_dev, int ndim,
                                     blob_bytes, &job);
   if (st != FPSZ_OK) return st;
   job.P.closed = closed;
+  job.P.inloop = inloop;
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, FPSZ_E_DEVICE, "hipSetDevice failed");
   hipStream_t s = (hipStream_t)stream;
@@ -220,6 +221,16 @@ fpsz_status fpsz_compress(fpsz_ctx *ctx, const void *field_dev, int ndim, const 
                           void *stream) {
   return compress_one(ctx, field_dev, ndim, dims, dtype, target_psnr, domain, workspace_dev,
                       workspace_bytes, blob_dev, blob_capacity, blob_bytes, info, stream, 0);
+}
+
+fpsz_status fpsz_compress_inloop(fpsz_ctx *ctx, const void *field_dev, int ndim,
+                                 const uint64_t *dims, fpsz_dtype dtype, double target_psnr,
+                                 void *workspace_dev, uint64_t workspace_bytes, void *blob_dev,
+                                 uint64_t blob_capacity, uint64_t *blob_bytes, fpsz_info *info,
+                                 void *stream) {
+  return compress_one(ctx, field_dev, ndim, dims, dtype, target_psnr, FPSZ_DOMAIN_TILE,
+                      workspace_dev, workspace_bytes, blob_dev, blob_capacity, blob_bytes, info,
+                      stream, 0, 1);
 }
 
 fpsz_status fpsz_compress_closed_loop(fpsz_ctx *ctx, const void *field_dev, int ndim,
@@ -283,6 +294,7 @@ fpsz_status fpsz_blob_header(const void *blob_host, uint64_t bytes, int *ndim, u
     info->is_const = (fl & kFlagConst) ? 1 : 0;
     info->domain = (fl & kFlagTile) ? 1 : 0;
     info->eb_scale = (fl & kFlagClosed) ? rd<double>(h + H_SCALE) : 1.0;
+    info->inloop = (fl & kFlagInloop) ? 1 : 0;
   }
   return FPSZ_OK;
 }

@@ -929,6 +929,170 @@ __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restri
   }
 }
 
+// ---------------------------------------------------------------------------
+// SZ 1.4-style in-loop variant (tile domain; Sec. II-A step (1), Sec. III
+// Eq. 1): a point's Lorenzo prediction reads the RECONSTRUCTED values of its
+// preceding neighbours in the tile (zero outside it), the prediction error is
+// quantized with bin 2 eb, and the point is reconstructed at once, so the
+// next points see it.  A point whose code leaves the radius 2^15 or whose
+// reconstruction misses the bound in floating point is stored exactly (the
+// outlier symbol plus a patch record).  The seven prediction terms are
+// summed in the field's precision in a fixed order, so that compression and
+// decompression (and any other implementation that keeps the order) agree to
+// the bit.  A tile is swept by diagonals: every point of diagonal
+// z + y + x = d depends only on diagonals d - 1 .. d - 3, so a diagonal's
+// points run in parallel, one barrier per diagonal (3D: thread (z, y) takes
+// x = d - z - y; 2D: thread y takes x = d - y; 1D: one thread walks the tile).
+template <typename T, int NDIM>
+__device__ inline T il_pred(const T *xl, int z, int y, int x) {
+  using G = Geo<NDIM>;
+  auto nb = [&](int dz, int dy, int dx) -> T {
+    return (z >= dz && y >= dy && x >= dx) ? xl[((z - dz) * G::TY + (y - dy)) * G::TX + (x - dx)]
+                                           : (T)0;
+  };
+  T p = nb(0, 0, 1);
+  p = p + nb(0, 1, 0);
+  p = p + nb(1, 0, 0);
+  p = p - nb(0, 1, 1);
+  p = p - nb(1, 0, 1);
+  p = p - nb(1, 1, 0);
+  p = p + nb(1, 1, 1);
+  return p;
+}
+
+// Runs fn(z, y, x) over the clipped tile in dependency order (all threads
+// call it; it ends with a barrier).
+template <int NDIM, typename Fn>
+__device__ inline void il_sweep(int ez, int ey, int ex, Fn fn) {
+  const int tid = threadIdx.x;
+  if (NDIM == 1) {
+    if (tid == 0)
+      for (int x = 0; x < ex; x++) fn(0, 0, x);
+    __syncthreads();
+    return;
+  }
+  const int z = NDIM == 3 ? tid >> 4 : 0;
+  const int y = NDIM == 3 ? tid & 15 : tid;
+  const int nd = ez + ey + ex - 2;
+  for (int d = 0; d < nd; d++) {
+    const int x = d - z - y;
+    if (z < ez && y < ey && x >= 0 && x < ex) fn(z, y, x);
+    __syncthreads();
+  }
+}
+
+template <typename T, int NDIM, bool RECORDS>
+__global__ __launch_bounds__(kBlock) void k_quant_il(CJob one, const CJob *__restrict__ jobs) {
+  const CJob J = select_job(one, jobs);
+  const T *__restrict__ x = static_cast<const T *>(J.x);
+  const Plan P = J.P;
+  DevParams *__restrict__ dp = J.W.P;
+  using G = Geo<NDIM>;
+  __shared__ __align__(16) T xl[kTilePts];
+  __shared__ int32_t cq[kTilePts];
+  __shared__ uint32_t hist[RECORDS ? 1 : kNSym];
+  __shared__ uint32_t scr[8];
+  if (dp->status != 0 || dp->is_const) return;
+  if (RECORDS && !dp->big_tiles) return;
+  const int tid = threadIdx.x;
+  const float rf = dp->r_f, e2f = dp->e2_f;
+  const double r = dp->r, e2 = dp->e2, eb = dp->eb;
+  constexpr int RW = sizeof(T) / 4;
+  if (!RECORDS)
+    for (int s = tid; s < kNSym; s += kBlock) hist[s] = 0;
+  uint64_t my_pat = 0;
+  uint64_t t;
+  for (uint64_t it_k = 0; xcd_tile(P, NDIM, it_k, &t); it_k++) {
+    if (RECORDS && J.W.exc_cnt[t] <= (uint32_t)kStage) continue;  // uniform
+    const TileGeo g = tile_geo(P, t);
+    const int ez = (int)g.ez, ey = (int)g.ey, ex = (int)g.ex, nt = (int)g.nt;
+    __syncthreads();  // the previous tile's LDS is read
+    for (int s = tid; s < nt; s += kBlock) {
+      const int z = s / (ey * ex), rem = s - z * ey * ex, y = rem / ex, xx = rem - y * ex;
+      xl[(z * G::TY + y) * G::TX + xx] =
+          x[((g.z0 + z) * P.ny + (g.y0 + y)) * P.nx + (g.x0 + xx)];
+    }
+    __syncthreads();
+    il_sweep<NDIM>(ez, ey, ex, [&](int z, int y, int xx) {
+      const int i = (z * G::TY + y) * G::TX + xx;
+      const T xv = xl[i];
+      const T p = il_pred<T, NDIM>(xl, z, y, xx);
+      const T dd = xv - p;
+      int32_t q;
+      T rec;
+      if constexpr (sizeof(T) == 4) {
+        q = (int32_t)__builtin_rintf(dd * rf);
+        rec = p + (float)q * e2f;
+      } else {
+        q = (int32_t)__builtin_rint(dd * r);
+        rec = p + (double)q * e2;
+      }
+      const bool keep = q > -32768 && q < 32768 && !(fabs((double)xv - (double)rec) > eb);
+      xl[i] = keep ? rec : xv;
+      cq[i] = keep ? q : -32768;
+    });
+    // this thread's 32 stream points: codes, symbols, stored points
+    const int i0 = 32 * tid;
+    const int cnt = nt - i0 < 0 ? 0 : (nt - i0 > 32 ? 32 : nt - i0);
+    uint32_t pflags = 0;
+    for (int j = 0; j < cnt; j++) {
+      const int sidx = i0 + j;
+      const int z = sidx / (ey * ex), rem = sidx - z * ey * ex, y = rem / ex, xx = rem - y * ex;
+      const int32_t c = cq[(z * G::TY + y) * G::TX + xx];
+      if (!RECORDS) {
+        J.W.codes[g.start + (uint64_t)sidx] = (int16_t)c;
+        bool outl;
+        atomicAdd(&hist[symbol_of(c, outl)], 1u);
+      }
+      pflags |= (c == -32768 ? 1u : 0u) << j;
+    }
+    const uint32_t nexc = RW * __popc(pflags);
+    if (!RECORDS) my_pat += __popc(pflags);
+    uint32_t tile_total;
+    const uint32_t my_off = block_excl_scan_u32(nexc, scr, &tile_total);
+    if (!RECORDS && tid == 0) {
+      J.W.exc_cnt[t] = tile_total;
+      if (tile_total > (uint32_t)kStage) atomicOr(&dp->big_tiles, 1u);
+    }
+    if (nexc && (RECORDS || tile_total <= (uint32_t)kStage)) {
+      uint32_t e = my_off;
+      const uint64_t base_off = RECORDS ? J.W.exc_off[t] : 0;
+      for (int j = 0; j < cnt; j++) {
+        if (!((pflags >> j) & 1u)) continue;
+        const int sidx = i0 + j;
+        const int z = sidx / (ey * ex), rem = sidx - z * ey * ex, y = rem / ex, xx = rem - y * ex;
+        const T v = xl[(z * G::TY + y) * G::TX + xx];  // the stored point holds x itself
+        uint32_t bits[2];
+        __builtin_memcpy(bits, &v, sizeof(T));
+        const uint32_t key = (uint32_t)(g.start + (uint64_t)sidx) | kTagPatch;
+        for (int k = 0; k < RW; k++, e++) {
+          if (RECORDS) {
+            const uint64_t o = P.off_exc + 8 * (base_off + e);
+            if (o + 8 <= P.capacity) {
+              uint32_t *rec = reinterpret_cast<uint32_t *>(J.blob + o);
+              rec[0] = key;
+              rec[1] = bits[k];
+            } else {
+              atomicOr(&dp->overflow, 1u);
+            }
+          } else {
+            uint32_t *rec = J.W.stage + (t * kStage + e) * 2;
+            rec[0] = key;
+            rec[1] = bits[k];
+          }
+        }
+      }
+    }
+  }
+  if (RECORDS) return;
+  __syncthreads();
+  for (int s = tid; s < kNSym; s += kBlock)
+    if (hist[s]) atomicAdd(&J.W.hist[(blockIdx.x % kHistCopies) * kNSym + s], hist[s]);
+  my_pat = wave_sum_u64(my_pat);
+  if ((tid & 63) == 0 && my_pat)
+    atomicAdd((unsigned long long *)&dp->n_pat, (unsigned long long)my_pat);
+}
+
 // Exclusive scan of the per-tile record counts (one workgroup): tile offsets
 // into the blob's tile_exc_offset section and the workspace, the total.
 constexpr int kScanThreads = 1024;
@@ -1636,7 +1800,7 @@ __global__ void k_header(CJob one, const CJob *__restrict__ jobs) {
     const uint16_t ver = kVersion;
     __builtin_memcpy(h + H_VERSION, &ver, 2);
     const uint16_t fl = (uint16_t)((cst ? kFlagConst : 0) | (P.domain ? kFlagTile : 0) |
-                                   (P.closed ? kFlagClosed : 0));
+                                   (P.closed ? kFlagClosed : 0) | (P.inloop ? kFlagInloop : 0));
     __builtin_memcpy(h + H_FLAGS, &fl, 2);
     if (P.closed) putf(H_SCALE, dp->scale);
     h[H_DTYPE] = (uint8_t)P.dtype;
@@ -1739,6 +1903,15 @@ template <typename T, int NDIM, bool GLOBAL>
 static void launch_quant_d(const CJob &one, const CJob *jobs, int nf, const Plan &maxP,
                            const LaunchCfg &cfg, hipStream_t s, Timer *tm) {
   const dim3 grid(cfg.quant_grid, nf);
+  if (maxP.inloop) {
+    // in-loop prediction (every field of the launch; tile domain)
+    hipLaunchKernelGGL((k_quant_il<T, NDIM, false>), grid, dim3(kBlock), 0, s, one, jobs);
+    tm->mark(s, "quant");
+    hipLaunchKernelGGL(k_codebook, dim3(2, nf), dim3(kCbThreads), 0, s, one, jobs);
+    tm->mark(s, "codebook");
+    hipLaunchKernelGGL((k_quant_il<T, NDIM, true>), grid, dim3(kBlock), 0, s, one, jobs);
+    return;
+  }
   // maxP.pad_ carries "some field of the launch has ragged tiles"
   const bool ragged = maxP.pad_ != 0;
   hipLaunchKernelGGL((k_quant<T, NDIM, GLOBAL, false, true>), grid, dim3(kBlock), 0, s, one, jobs);

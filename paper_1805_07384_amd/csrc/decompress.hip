@@ -51,6 +51,9 @@ struct DecodeArgs {
   const void *ref;
   double eb;
   double *vpart;
+  // in-loop blobs: records per stored point (1 float32, 2 float64); 0 for
+  // plain blobs, whose untagged records are the outliers' residuals
+  uint32_t il_rw;
 };
 
 // Eq. 4 statistics of one tile of the reconstruction against the original,
@@ -585,12 +588,20 @@ __global__ __launch_bounds__(kDecBlock) void k_decode(Plan P, const uint8_t *__r
     else nout = decode_run<false>(R, cnt, lut_lds, sorted_lds, LT, dst, &endpos, &bad);
   }
   // every outlier symbol must have its record
-  uint32_t nrec = 0;
+  // (in-loop blobs: every outlier symbol is a stored point with A.il_rw
+  // patch records, and there are no others)
+  uint32_t nrec = 0, ntag = 0;
   const uint32_t *exc = reinterpret_cast<const uint32_t *>(blob + P.off_exc);
-  for (uint64_t e = e0 + lane; e < e1; e += 64) nrec += (exc[2 * e] & kTagPatch) ? 0u : 1u;
+  for (uint64_t e = e0 + lane; e < e1; e += 64) {
+    const bool tag = (exc[2 * e] & kTagPatch) != 0;
+    nrec += tag ? 0u : 1u;
+    ntag += tag ? 1u : 0u;
+  }
   nrec = wave_sum_u32(nrec);
+  ntag = wave_sum_u32(ntag);
   nout = wave_sum_u32(nout);
-  if (bad || endpos != incl || nrec != nout) atomicOr(&dp->corrupt, 1u);
+  const bool recs_ok = A.il_rw ? (nrec == 0 && ntag == A.il_rw * nout) : nrec == nout;
+  if (bad || endpos != incl || !recs_ok) atomicOr(&dp->corrupt, 1u);
 }
 
 // ---------------------------------------------------------------------------
@@ -1405,6 +1416,127 @@ __global__ __launch_bounds__(kBlock, 3) void k_rec_full(Plan P, const uint8_t *_
 }
 
 // ---------------------------------------------------------------------------
+// In-loop blobs (SZ 1.4-style, tile domain): the compressor's sweep repeated
+// with the decoded codes (one workgroup per tile): stored points take their
+// record's value, every other point its prediction from the reconstructed
+// neighbours plus code * 2 eb, diagonal by diagonal.
+template <typename T, int NDIM>
+__device__ inline T il_pred_d(const T *xl, int z, int y, int x) {
+  using G = DGeo<NDIM>;
+  auto nb = [&](int dz, int dy, int dx) -> T {
+    return (z >= dz && y >= dy && x >= dx) ? xl[((z - dz) * G::TY + (y - dy)) * G::TX + (x - dx)]
+                                           : (T)0;
+  };
+  T p = nb(0, 0, 1);
+  p = p + nb(0, 1, 0);
+  p = p + nb(1, 0, 0);
+  p = p - nb(0, 1, 1);
+  p = p - nb(1, 0, 1);
+  p = p - nb(1, 1, 0);
+  p = p + nb(1, 1, 1);
+  return p;
+}
+
+template <typename T, int NDIM>
+__global__ __launch_bounds__(kBlock) void k_rec_il(Plan P, const uint8_t *__restrict__ blob,
+                                                   DecodeArgs A, DevParams *__restrict__ dp,
+                                                   const int16_t *__restrict__ codes,
+                                                   T *__restrict__ out) {
+  using G = DGeo<NDIM>;
+  constexpr int RW = sizeof(T) / 4;
+  __shared__ __align__(16) T xl[kTilePts];
+  __shared__ int32_t cq[kTilePts];
+  __shared__ uint32_t stored[kTilePts / 32];
+  __shared__ uint32_t s_bad;
+  if (dp->corrupt) return;
+  const int tid = threadIdx.x;
+  const uint64_t t = xcd_block_tile(P.n_tiles);
+  const TileGeo g = tile_geo(P, t);
+  const int ez = (int)g.ez, ey = (int)g.ey, ex = (int)g.ex, nt = (int)g.nt;
+  const uint64_t *teo = reinterpret_cast<const uint64_t *>(blob + P.off_teo);
+  const uint64_t e0 = teo[t], e1 = teo[t + 1];
+  if (e0 > e1 || e1 > A.n_exc) return;  // reported by the decode kernel
+  const uint32_t *exc = reinterpret_cast<const uint32_t *>(blob + P.off_exc);
+  if (tid == 0) s_bad = 0;
+  for (int i = tid; i < kTilePts / 32; i += kBlock) stored[i] = 0;
+  auto lidx = [&](int sidx) {
+    const int z = sidx / (ey * ex), rem = sidx - z * ey * ex, y = rem / ex, xx = rem - y * ex;
+    return (z * G::TY + y) * G::TX + xx;
+  };
+  for (int sidx = tid; sidx < nt; sidx += kBlock) cq[lidx(sidx)] = codes[g.start + (uint64_t)sidx];
+  __syncthreads();
+  // stored points: their exact value, one patch record each (two for float64)
+  for (uint64_t e = e0 + tid; e < e1; e += kBlock) {
+    const uint32_t key = exc[2 * e];
+    const uint64_t pos = key & ~kTagPatch;
+    if (!(key & kTagPatch) || pos < g.start || pos >= g.start + (uint64_t)nt) {
+      atomicOr(&s_bad, 1u);
+      continue;
+    }
+    if (RW == 2 && e > e0 && exc[2 * (e - 1)] == key) continue;  // high half of a pair
+    const int i = lidx((int)(pos - g.start));
+    if (cq[i] != -32768 || (atomicOr(&stored[i >> 5], 1u << (i & 31)) & (1u << (i & 31)))) {
+      atomicOr(&s_bad, 1u);
+      continue;
+    }
+    T v;
+    if constexpr (sizeof(T) == 4) {
+      const uint32_t b = exc[2 * e + 1];
+      __builtin_memcpy(&v, &b, 4);
+    } else {
+      if (e + 1 >= e1 || exc[2 * (e + 1)] != key) { atomicOr(&s_bad, 1u); continue; }
+      const uint64_t b = (uint64_t)exc[2 * e + 1] | ((uint64_t)exc[2 * e + 3] << 32);
+      __builtin_memcpy(&v, &b, 8);
+    }
+    xl[i] = v;
+  }
+  __syncthreads();
+  // every outlier symbol is a stored point
+  for (int sidx = tid; sidx < nt; sidx += kBlock) {
+    const int i = lidx(sidx);
+    if ((cq[i] == -32768) != (((stored[i >> 5] >> (i & 31)) & 1u) != 0)) atomicOr(&s_bad, 1u);
+  }
+  __syncthreads();
+  if (s_bad) {
+    if (tid == 0) atomicOr(&dp->corrupt, 1u);
+    return;
+  }
+  const double e2 = A.e2;
+  const float e2f = A.e2_f;
+  // the sweep (3D: thread (z, y) takes x = d - z - y; 2D: thread y; 1D: one thread)
+  auto step = [&](int z, int y, int xx) {
+    const int i = (z * G::TY + y) * G::TX + xx;
+    if ((stored[i >> 5] >> (i & 31)) & 1u) return;
+    const T p = il_pred_d<T, NDIM>(xl, z, y, xx);
+    if constexpr (sizeof(T) == 4) xl[i] = p + (float)cq[i] * e2f;
+    else xl[i] = p + (double)cq[i] * e2;
+  };
+  if (NDIM == 1) {
+    if (tid == 0)
+      for (int xx = 0; xx < ex; xx++) step(0, 0, xx);
+    __syncthreads();
+  } else {
+    const int z = NDIM == 3 ? tid >> 4 : 0;
+    const int y = NDIM == 3 ? tid & 15 : tid;
+    const int nd = ez + ey + ex - 2;
+    for (int d = 0; d < nd; d++) {
+      const int xx = d - z - y;
+      if (z < ez && y < ey && xx >= 0 && xx < ex) step(z, y, xx);
+      __syncthreads();
+    }
+  }
+  VStat vs;
+  for (int sidx = tid; sidx < nt; sidx += kBlock) {
+    const int z = sidx / (ey * ex), rem = sidx - z * ey * ex, y = rem / ex, xx = rem - y * ex;
+    const T v = xl[(z * G::TY + y) * G::TX + xx];
+    const uint64_t oi = ((g.z0 + z) * P.ny + g.y0 + y) * P.nx + g.x0 + xx;
+    out[oi] = v;
+    if (A.ref) vs.add(static_cast<const T *>(A.ref)[oi], v, A.eb);
+  }
+  if (A.ref) vs.store(A.vpart, t);
+}
+
+// ---------------------------------------------------------------------------
 // Exclusive scans (modulo 2^32) of a row-major u32 array along one axis.
 // Element (o, k, i) sits at (o * len + k) * inner + i.  The axis is cut into
 // segments of 32; each thread scans one segment of one column after adding
@@ -1540,7 +1672,9 @@ static void launch_dec_t(const Plan &P, const uint8_t *blob, const DecodeArgs &A
                      ds.pool_words);
   tm->mark(s, "decode");
   const bool ragged = P.pad_ != 0;
-  if (P.domain == FPSZ_DOMAIN_GLOBAL) {
+  if (P.inloop) {
+    hipLaunchKernelGGL((k_rec_il<T, NDIM>), grid, blk, 0, s, P, blob, A, dp, codes, out);
+  } else if (P.domain == FPSZ_DOMAIN_GLOBAL) {
     hipLaunchKernelGGL((k_proj_full<NDIM, (int)(sizeof(T) / 4)>), grid, blk, 0, s, P, blob, A, dp,
                        codes);
     if (ragged) hipLaunchKernelGGL((k_proj<NDIM>), grid, blk, 0, s, P, blob, A, dp, codes);
@@ -1655,6 +1789,7 @@ hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const Deco
   A.ref = ref;
   A.eb = eb;
   A.vpart = W.vpart;
+  A.il_rw = P.inloop ? (P.dtype == FPSZ_F32 ? 1u : 2u) : 0u;
   const DecShape ds = decode_shape();
   if (P.dtype == FPSZ_F32) {
     if (P.ndim == 1) launch_dec_t<float, 1>(P, blob, A, W.P, W.codes, W.tmp, ds, (float *)out, s, tm);

@@ -30,7 +30,7 @@ constexpr int kChunk = 128;
 constexpr int kTilePts = 8192;
 constexpr int kLutBits = 11;
 constexpr uint32_t kTagPatch = 0x80000000u;
-constexpr uint16_t kFlagConst = 1, kFlagTile = 2, kFlagClosed = 4;
+constexpr uint16_t kFlagConst = 1, kFlagTile = 2, kFlagClosed = 4, kFlagInloop = 8;
 constexpr int kBlock = 256;
 constexpr int kRangeBlocks = 1024;
 // The compressor's histogram is kept in this many copies (workgroup b adds
@@ -68,7 +68,8 @@ struct Plan {
   // closed loop: 10^(-PSNR/10) (host libm), so that the target MSE is
   // vr^2 * mse_factor; closed = 0 for plain compression
   double mse_factor;
-  int32_t closed, pad4_;
+  int32_t closed;
+  int32_t inloop;  // SZ 1.4-style in-loop prediction (tile domain)
 };
 
 // Geometry of one tile.

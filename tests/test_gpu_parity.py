@@ -464,3 +464,62 @@ def test_parity_closed_loop(ctx, orc, shape, dt, psnr, domain):
     assert st_c["n_over_eb"] == 0
     if abs(st_p["psnr"] - psnr) > 0.01:
         assert abs(st_c["psnr"] - psnr) < abs(st_p["psnr"] - psnr)
+
+
+INLOOP_CASES = [((20000,), np.float32, 80.0), ((8193,), np.float64, 120.0),
+                ((150, 300), np.float32, 30.0), ((65, 129), np.float64, 100.0),
+                ((40, 37, 70), np.float32, 120.0), ((16, 16, 32), np.float32, 60.0),
+                ((33, 17, 65), np.float64, 80.0), ((64, 64, 64), np.float32, 100.0)]
+
+
+@pytest.mark.parametrize("shape,dt,psnr", INLOOP_CASES)
+def test_parity_inloop(ctx, orc, shape, dt, psnr):
+    # the SZ 1.4-style in-loop variant: blob and reconstruction bit-exact
+    # with the oracle's sequential loop; the fused check agrees
+    from paper_1805_07384_amd import fpsz
+    x = (synth.grf_numpy(shape, -3.0, 13) * 3.0 + 1.0).astype(dt)
+    print("case inloop shape=%s dtype=%s psnr=%s" % (shape, x.dtype, psnr), flush=True)
+    ob, ot = orc.compress_inloop(x, psnr, trace=True)
+    xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    ws = torch.full((fpsz.compress_workspace_bytes(x.shape, xt.dtype),), 0xA5, dtype=torch.uint8,
+                    device="cuda")
+    blob = torch.full((fpsz.compress_bound(x.shape, xt.dtype),), 0x5A, dtype=torch.uint8,
+                      device="cuda")
+    st, nb, info = ctx.compress_inloop_into(xt, psnr, ws, blob)
+    assert st == 0
+    gb = blob[:nb].cpu().numpy().tobytes()
+    if gb != ob:
+        o = fpsz.workspace_offset(x.shape, xt.dtype, 4)
+        c16 = ws[o:o + 2 * x.size].cpu().numpy().view(np.int16)
+        d = np.nonzero(c16 != ot["code16"])[0]
+        pytest.fail("in-loop blob differs: %d of %d codes differ, first %s gpu %s oracle %s"
+                    % (len(d), x.size, d[:5], c16[d[:5]], ot["code16"][d[:5]]))
+    assert info.inloop == 1 and info.n_patches == ot["n_patches"] and info.n_outliers == 0
+    y = ctx.decompress(blob[:nb])
+    oy = orc.decompress(ob)
+    assert np.array_equal(_bits(y.cpu().numpy()), _bits(oy))
+    y2, stv = ctx.decompress_verify(blob[:nb], xt)
+    assert np.array_equal(_bits(y2.cpu().numpy()), _bits(oy))
+    os_ = orc.stats(x, oy, ot["vr"], ot["eb"])
+    assert stv["n_over_eb"] == 0 == os_["n_over_eb"]
+    assert stv["max_abs_err"] == os_["max_abs_err"]
+    assert abs(stv["sse"] - os_["sse"]) <= 1e-9 * os_["sse"]
+
+
+def test_parity_inloop_stored_points(ctx, orc):
+    # the float64 bin-edge field: many points whose reconstruction misses
+    # the bound in floating point are stored exactly (two records each)
+    import patchfield as pf
+    from paper_1805_07384_amd import fpsz
+    x = pf.f64_patch_field()
+    print("case inloop stored points", flush=True)
+    ob, ot = orc.compress_inloop(x, pf.PSNR, trace=True)
+    assert ot["n_patches"] > 0
+    xt = torch.from_numpy(x).cuda()
+    ws = torch.empty(fpsz.compress_workspace_bytes(x.shape, xt.dtype), dtype=torch.uint8,
+                     device="cuda")
+    blob = torch.empty(fpsz.compress_bound(x.shape, xt.dtype), dtype=torch.uint8, device="cuda")
+    st, nb, info = ctx.compress_inloop_into(xt, pf.PSNR, ws, blob)
+    assert st == 0 and blob[:nb].cpu().numpy().tobytes() == ob
+    y = ctx.decompress(blob[:nb])
+    assert np.array_equal(_bits(y.cpu().numpy()), _bits(orc.decompress(ob)))
