@@ -109,6 +109,11 @@ def lib():
                                          ctypes.POINTER(ctypes.c_uint64), ctypes.c_double,
                                          ctypes.POINTER(ctypes.c_void_p),
                                          ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_Trace)]
+        L.or_compress_xform.restype = ctypes.c_int
+        L.or_compress_xform.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_uint64), ctypes.c_double,
+                                        ctypes.POINTER(ctypes.c_void_p),
+                                        ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_Trace)]
         L.or_quant_sse.restype = ctypes.c_int
         L.or_quant_sse.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_double,
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
@@ -222,6 +227,14 @@ def compress_inloop(x: np.ndarray, psnr: float, trace: bool = False):
     return _compress(x, psnr, 1, trace, mode=3)
 
 
+def compress_xform(x: np.ndarray, psnr: float, trace: bool = False):
+    """Orthogonal-transform compression: 4^ndim blocks, orthonormal
+    Walsh-Hadamard transform, coefficients quantized with bin 2 eb (Eq. 7),
+    DC bins coded as differences within a tile.  Dimensions must be multiples
+    of 4.  The trace's "q" holds the codes in stream order."""
+    return _compress(x, psnr, 1, trace, mode=4)
+
+
 def quant_sse(x: np.ndarray, psnr: float):
     """(SSE of the quantizer output at the Eq. 7 bound, patches exact; vr)."""
     x = np.ascontiguousarray(x)
@@ -264,6 +277,9 @@ def _compress(x, psnr, domain, trace, mode, scale=1.0):
         st = lib().or_compress_scaled(x.ctypes.data, dt, x.ndim, dims, float(psnr), int(domain),
                                       float(scale), ctypes.byref(out), ctypes.byref(nb),
                                       ctypes.byref(tr))
+    elif mode == 4:
+        st = lib().or_compress_xform(x.ctypes.data, dt, x.ndim, dims, float(psnr),
+                                     ctypes.byref(out), ctypes.byref(nb), ctypes.byref(tr))
     elif mode == 3:
         st = lib().or_compress_inloop(x.ctypes.data, dt, x.ndim, dims, float(psnr),
                                       ctypes.byref(out), ctypes.byref(nb), ctypes.byref(tr))

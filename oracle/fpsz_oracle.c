@@ -68,6 +68,7 @@
 #define OR_FLAG_TILE 2u
 #define OR_FLAG_CLOSED 4u /* bound rescaled by the closed-loop step */
 #define OR_FLAG_INLOOP 8u /* in-loop prediction from reconstructed values (TILE) */
+#define OR_FLAG_XFORM 16u /* orthonormal block transform of the coefficients (TILE) */
 #define OR_TAG_PATCH 0x80000000u
 
 /* status codes */
@@ -227,6 +228,93 @@ static double il_pred_d(const double *xr, const or_shape *S, uint64_t z, uint64_
   p = p - il_nb(xr, 1, S, z, y, x, z0, y0, x0, 1, 1, 0);
   p = p + il_nb(xr, 1, S, z, y, x, z0, y0, x0, 1, 1, 1);
   return p;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Orthogonal-transform variant (Sec. III Theorem 2, Sec. IV Theorem 3): the */
+/* field is cut into blocks of 4 (1D), 4 x 4 (2D) or 4 x 4 x 4 (3D) points,   */
+/* each block transformed by the orthonormal 4-point Walsh-Hadamard matrix    */
+/*   H = 1/2 [[1,1,1,1], [1,1,-1,-1], [1,-1,-1,1], [1,-1,1,-1]]               */
+/* along x, then y, then z, and the coefficients quantized with bin 2 eb.     */
+/* H is symmetric and H H = I, so the inverse applies H along the same axes.  */
+/* An orthonormal transform keeps the squared error, so the MSE of the data   */
+/* is that of the coefficients (Theorem 2) and Eq. 7 sets the PSNR as for     */
+/* the prediction-based scheme (Theorem 3); there is no pointwise bound.      */
+/* The sums run in the field's precision in the order written below.          */
+/* ------------------------------------------------------------------------ */
+static void wht4_f(float *v, int st) {
+  float a = v[0], b = v[st], c = v[2 * st], d = v[3 * st];
+  float w0 = ((a + b) + c) + d, w1 = ((a + b) - c) - d;
+  float w2 = ((a - b) - c) + d, w3 = ((a - b) + c) - d;
+  v[0] = 0.5f * w0; v[st] = 0.5f * w1; v[2 * st] = 0.5f * w2; v[3 * st] = 0.5f * w3;
+}
+static void wht4_d(double *v, int st) {
+  double a = v[0], b = v[st], c = v[2 * st], d = v[3 * st];
+  double w0 = ((a + b) + c) + d, w1 = ((a + b) - c) - d;
+  double w2 = ((a - b) - c) + d, w3 = ((a - b) + c) - d;
+  v[0] = 0.5 * w0; v[st] = 0.5 * w1; v[2 * st] = 0.5 * w2; v[3 * st] = 0.5 * w3;
+}
+/* a block of 4^ndim values laid out [kz][ky][kx] (strides 16, 4, 1) */
+static void wht_block_f(float *blk, int ndim) {
+  for (int r = 0; r < (ndim == 3 ? 16 : ndim == 2 ? 4 : 1); r++) wht4_f(blk + 4 * r, 1);
+  if (ndim >= 2)
+    for (int kz = 0; kz < (ndim == 3 ? 4 : 1); kz++)
+      for (int kx = 0; kx < 4; kx++) wht4_f(blk + 16 * kz + kx, 4);
+  if (ndim == 3)
+    for (int r = 0; r < 16; r++) wht4_f(blk + r, 16);
+}
+static void wht_block_d(double *blk, int ndim) {
+  for (int r = 0; r < (ndim == 3 ? 16 : ndim == 2 ? 4 : 1); r++) wht4_d(blk + 4 * r, 1);
+  if (ndim >= 2)
+    for (int kz = 0; kz < (ndim == 3 ? 4 : 1); kz++)
+      for (int kx = 0; kx < 4; kx++) wht4_d(blk + 16 * kz + kx, 4);
+  if (ndim == 3)
+    for (int r = 0; r < 16; r++) wht4_d(blk + r, 16);
+}
+
+/* Codes of the transform variant in stream order: tile by tile, blocks in
+ * row-major order over the tile's block grid, a block's 4^ndim coefficient
+ * codes row-major; a block's first (DC) code is its difference from the
+ * previous block's DC bin in the tile (the first block's from zero). */
+static void xform_codes(const void *x, int dtype, int ndim, const or_shape *S, double r,
+                        float r_f, int32_t *code) {
+  const int bs = ndim == 3 ? 64 : ndim == 2 ? 16 : 4;
+  const int bz = ndim == 3 ? 4 : 1, by = ndim >= 2 ? 4 : 1;
+  uint64_t p = 0;
+  for (uint64_t t = 0; t < S->n_tiles; t++) {
+    uint64_t a = t / (S->gy * S->gx), b = (t / S->gx) % S->gy, c = t % S->gx;
+    uint64_t z0 = a * S->tz, y0 = b * S->ty, x0 = c * S->tx;
+    uint64_t ez = z0 + S->tz <= S->nz ? S->tz : S->nz - z0;
+    uint64_t ey = y0 + S->ty <= S->ny ? S->ty : S->ny - y0;
+    uint64_t ex = x0 + S->tx <= S->nx ? S->tx : S->nx - x0;
+    int32_t prev_dc = 0;
+    for (uint64_t kz = 0; kz < ez; kz += bz)
+      for (uint64_t ky = 0; ky < ey; ky += by)
+        for (uint64_t kx = 0; kx < ex; kx += 4) {
+          float bf[64];
+          double bd[64];
+          for (int u = 0; u < bs; u++) {
+            int uz = u / 16, uy = (u / 4) % 4, ux = u % 4;
+            if (ndim == 2) { uz = 0; uy = u / 4; }
+            if (ndim == 1) { uz = 0; uy = 0; }
+            uint64_t i = ((z0 + kz + uz) * S->ny + (y0 + ky + uy)) * S->nx + (x0 + kx + ux);
+            if (dtype == 0) bf[u] = ((const float *)x)[i];
+            else bd[u] = ((const double *)x)[i];
+          }
+          if (dtype == 0) wht_block_f(bf, ndim);
+          else wht_block_d(bd, ndim);
+          for (int u = 0; u < bs; u++) {
+            int32_t q = dtype == 0 ? (int32_t)rintf(bf[u] * r_f) : (int32_t)rint(bd[u] * r);
+            if (u == 0) {
+              code[p + u] = q - prev_dc;
+              prev_dc = q;
+            } else {
+              code[p + u] = q;
+            }
+          }
+          p += (uint64_t)bs;
+        }
+  }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -476,9 +564,10 @@ static void layout(uint64_t n_tiles, uint64_t n_chunks, uint64_t n_exc, uint64_t
 /* scale: factor applied to eb_rel; closed: the blob records the factor (flag
  * CLOSED and the float64 at H_SCALE).  Plain compression is scale 1, closed 0. */
 static int compress_impl(const void *x, int dtype, int ndim, const uint64_t *dims, double psnr,
-                         int domain, double scale, int closed, int inloop, uint8_t **blob_out,
-                         uint64_t *bytes_out, or_trace *tr) {
-  if (inloop) domain = 1; /* in-loop prediction runs per tile */
+                         int domain, double scale, int closed, int variant,
+                         uint8_t **blob_out, uint64_t *bytes_out, or_trace *tr) {
+  const int inloop = variant == 1, xform = variant == 2;
+  if (variant) domain = 1; /* in-loop prediction and block transforms run per tile */
   *blob_out = NULL;
   *bytes_out = 0;
   if (dtype != 0 && dtype != 1) return OR_E_INVALID_ARG;
@@ -531,7 +620,7 @@ static int compress_impl(const void *x, int dtype, int ndim, const uint64_t *dim
     wr_u16(blob + H_VERSION, OR_VERSION);
     wr_u16(blob + H_FLAGS, (uint16_t)(OR_FLAG_CONST | (domain ? OR_FLAG_TILE : 0) |
                                       (closed ? OR_FLAG_CLOSED : 0) |
-                                      (inloop ? OR_FLAG_INLOOP : 0)));
+                                      (inloop ? OR_FLAG_INLOOP : 0) | (xform ? OR_FLAG_XFORM : 0)));
     if (closed) wr_f64(blob + H_SCALE, scale);
     blob[H_DTYPE] = (uint8_t)dtype; blob[H_NDIM] = (uint8_t)ndim;
     blob[H_LOG2D] = 9; blob[H_LOG2R] = 15; blob[H_LMAX] = OR_LMAX;
@@ -558,7 +647,7 @@ static int compress_impl(const void *x, int dtype, int ndim, const uint64_t *dim
   int32_t *dl = (int32_t *)malloc(sizeof(int32_t) * n);
   float *xrf = inloop && dtype == 0 ? (float *)malloc(4 * n) : NULL;
   double *xrd = inloop && dtype == 1 ? (double *)malloc(8 * n) : NULL;
-  for (uint64_t i = 0; i < n && !inloop; i++) {
+  for (uint64_t i = 0; i < n && !inloop && !xform; i++) {
     if (dtype == 0) {
       float t = ((const float *)x)[i] * r_f;
       q[i] = (int32_t)rintf(t);
@@ -572,7 +661,11 @@ static int compress_impl(const void *x, int dtype, int ndim, const uint64_t *dim
   /* 4. Lorenzo residual: delta = sum over the 8 corners of the unit cube
    *    behind the point of (-1)^(a+b+c) q[z-c][y-b][x-a]; q reads as zero
    *    outside the field (GLOBAL) or outside the point's tile (TILE). */
-  for (uint64_t z = 0; z < S.nz && !inloop; z++)
+  if (xform) {
+    xform_codes(x, dtype, ndim, &S, r, r_f, dl); /* stream order */
+    memcpy(q, dl, 4 * n);
+  }
+  for (uint64_t z = 0; z < S.nz && !inloop && !xform; z++)
     for (uint64_t y = 0; y < S.ny; y++)
       for (uint64_t xx = 0; xx < S.nx; xx++) {
         uint64_t z0 = 0, y0 = 0, x0 = 0;
@@ -591,7 +684,10 @@ static int compress_impl(const void *x, int dtype, int ndim, const uint64_t *dim
 
   /* 5. walk the stream: symbols, histogram, exception records */
   uint64_t *perm = (uint64_t *)malloc(sizeof(uint64_t) * n);
-  stream_order(&S, perm);
+  if (xform)
+    for (uint64_t i = 0; i < n; i++) perm[i] = i; /* codes are already in stream order */
+  else
+    stream_order(&S, perm);
   int32_t *sym = (int32_t *)malloc(sizeof(int32_t) * n);
   uint32_t *xtra = (uint32_t *)malloc(sizeof(uint32_t) * n);
   uint32_t hist[OR_NSYM];
@@ -649,12 +745,13 @@ static int compress_impl(const void *x, int dtype, int ndim, const uint64_t *dim
         int npush = 0;
         uint32_t rec[6];
         if (s == 0 && !inloop) { rec[0] = (uint32_t)p; rec[1] = (uint32_t)dl[i]; npush = 1; n_out++; }
+        /* (transform codes: no exact points; q below is unused) */
         /* patch test: the float reconstruction must lie within eb of x (in
          * in-loop mode: the points marked by the outlier symbol) */
         int patch;
         if (dtype == 0) {
           float xr = (float)q[i] * e2_f;
-          patch = inloop ? s == 0 : fabs((double)((const float *)x)[i] - (double)xr) > eb;
+          patch = xform ? 0 : inloop ? s == 0 : fabs((double)((const float *)x)[i] - (double)xr) > eb;
           if (patch) {
             uint32_t bits;
             memcpy(&bits, &((const float *)x)[i], 4);
@@ -662,7 +759,7 @@ static int compress_impl(const void *x, int dtype, int ndim, const uint64_t *dim
           }
         } else {
           double xr = (double)q[i] * e2;
-          patch = inloop ? s == 0 : fabs(((const double *)x)[i] - xr) > eb;
+          patch = xform ? 0 : inloop ? s == 0 : fabs(((const double *)x)[i] - xr) > eb;
           if (patch) {
             uint64_t bits;
             memcpy(&bits, &((const double *)x)[i], 8);
@@ -734,7 +831,7 @@ static int compress_impl(const void *x, int dtype, int ndim, const uint64_t *dim
   wr_u32(blob + H_MAGIC, OR_MAGIC);
   wr_u16(blob + H_VERSION, OR_VERSION);
   wr_u16(blob + H_FLAGS, (uint16_t)((domain ? OR_FLAG_TILE : 0) | (closed ? OR_FLAG_CLOSED : 0) |
-                                     (inloop ? OR_FLAG_INLOOP : 0)));
+                                     (inloop ? OR_FLAG_INLOOP : 0) | (xform ? OR_FLAG_XFORM : 0)));
   if (closed) wr_f64(blob + H_SCALE, scale);
   blob[H_DTYPE] = (uint8_t)dtype; blob[H_NDIM] = (uint8_t)ndim;
   blob[H_LOG2D] = 9; blob[H_LOG2R] = 15; blob[H_LMAX] = OR_LMAX;
@@ -795,6 +892,18 @@ int or_compress(const void *x, int dtype, int ndim, const uint64_t *dims, double
 int or_compress_inloop(const void *x, int dtype, int ndim, const uint64_t *dims, double psnr,
                        uint8_t **blob_out, uint64_t *bytes_out, or_trace *tr) {
   return compress_impl(x, dtype, ndim, dims, psnr, 1, 1.0, 0, 1, blob_out, bytes_out, tr);
+}
+
+/* Orthogonal-transform compression (see wht4_f); every dimension of the
+ * field must be a multiple of 4. */
+int or_compress_xform(const void *x, int dtype, int ndim, const uint64_t *dims, double psnr,
+                      uint8_t **blob_out, uint64_t *bytes_out, or_trace *tr) {
+  *blob_out = NULL;
+  *bytes_out = 0;
+  if (ndim < 1 || ndim > 3 || !dims) return OR_E_INVALID_ARG;
+  for (int i = 0; i < ndim; i++)
+    if (dims[i] % 4) return OR_E_INVALID_ARG;
+  return compress_impl(x, dtype, ndim, dims, psnr, 1, 1.0, 0, 2, blob_out, bytes_out, tr);
 }
 
 /* Compression with the bound of Eq. 7 multiplied by a given factor, the
@@ -929,7 +1038,12 @@ int or_decompress(const uint8_t *blob, uint64_t bytes, void *out, uint64_t out_b
   }
   int domain = (flags & OR_FLAG_TILE) ? 1 : 0;
   int inloop = (flags & OR_FLAG_INLOOP) ? 1 : 0;
-  if (inloop && !domain) return OR_E_CORRUPT;
+  int xform = (flags & OR_FLAG_XFORM) ? 1 : 0;
+  if ((inloop || xform) && !domain) return OR_E_CORRUPT;
+  if (inloop && xform) return OR_E_CORRUPT;
+  if (xform)
+    for (int i = 0; i < ndim; i++)
+      if (dims[i] % 4) return OR_E_CORRUPT;
   uint64_t n_tiles = rd_u64(blob + H_NTILES), n_chunks = rd_u64(blob + H_NCHUNKS);
   uint64_t n_words = rd_u64(blob + H_NWORDS), n_exc = rd_u64(blob + H_NEXC);
   if (n_tiles != S.n_tiles || n_chunks != S.n_chunks) return OR_E_CORRUPT;
@@ -973,8 +1087,11 @@ int or_decompress(const uint8_t *blob, uint64_t bytes, void *out, uint64_t out_b
   (void)words;
 
   uint64_t *perm = (uint64_t *)malloc(sizeof(uint64_t) * n);
-  stream_order(&S, perm);
-  int32_t *dl = (int32_t *)malloc(sizeof(int32_t) * n); /* field order */
+  if (xform)
+    for (uint64_t i = 0; i < n; i++) perm[i] = i; /* coefficient codes stay in stream order */
+  else
+    stream_order(&S, perm);
+  int32_t *dl = (int32_t *)malloc(sizeof(int32_t) * n); /* field order (stream order: xform) */
   uint8_t *is_out = (uint8_t *)calloc(n, 1);
   stage_end(8);
   int rc = OR_OK;
@@ -1090,8 +1207,47 @@ int or_decompress(const uint8_t *blob, uint64_t bytes, void *out, uint64_t out_b
     }
     stage_end(11);
   }
-  if (!inloop) stage_end(9);
-  if (rc == OR_OK && !inloop) {
+  if (rc == OR_OK && xform) {
+    /* undo the DC differences, dequantize, inverse transform (H again) */
+    stage_end(9);
+    const int bs = ndim == 3 ? 64 : ndim == 2 ? 16 : 4;
+    const int bz = ndim == 3 ? 4 : 1, by = ndim >= 2 ? 4 : 1;
+    uint64_t p2 = 0;
+    for (uint64_t t = 0; t < n_tiles; t++) {
+      uint64_t a = t / (S.gy * S.gx), b = (t / S.gx) % S.gy, c = t % S.gx;
+      uint64_t z0 = a * S.tz, y0 = b * S.ty, x0 = c * S.tx;
+      uint64_t ez = z0 + S.tz <= S.nz ? S.tz : S.nz - z0;
+      uint64_t ey = y0 + S.ty <= S.ny ? S.ty : S.ny - y0;
+      uint64_t ex = x0 + S.tx <= S.nx ? S.tx : S.nx - x0;
+      uint32_t dc = 0;
+      for (uint64_t kz = 0; kz < ez; kz += bz)
+        for (uint64_t ky = 0; ky < ey; ky += by)
+          for (uint64_t kx = 0; kx < ex; kx += 4) {
+            float bf[64];
+            double bd[64];
+            for (int u = 0; u < bs; u++) {
+              int32_t qv = dl[p2 + u];
+              if (u == 0) { dc += (uint32_t)qv; qv = (int32_t)dc; }
+              if (dtype == 0) bf[u] = (float)qv * e2_f;
+              else bd[u] = (double)qv * e2;
+            }
+            if (dtype == 0) wht_block_f(bf, ndim);
+            else wht_block_d(bd, ndim);
+            for (int u = 0; u < bs; u++) {
+              int uz = u / 16, uy = (u / 4) % 4, ux = u % 4;
+              if (ndim == 2) { uz = 0; uy = u / 4; }
+              if (ndim == 1) { uz = 0; uy = 0; }
+              uint64_t i = ((z0 + kz + uz) * S.ny + (y0 + ky + uy)) * S.nx + (x0 + kx + ux);
+              if (dtype == 0) ((float *)out)[i] = bf[u];
+              else ((double *)out)[i] = bd[u];
+            }
+            p2 += (uint64_t)bs;
+          }
+    }
+    stage_end(11);
+  }
+  if (!inloop && !xform) stage_end(9);
+  if (rc == OR_OK && !inloop && !xform) {
     /* undo the prediction: inclusive prefix sums along x, y and z, over the
      * whole field (GLOBAL) or restarting at every tile edge (TILE).  Sums are
      * taken modulo 2^32; the true bin indexes fit in 32 bits, so the

@@ -638,6 +638,81 @@ def test_inloop_matches_prequantization_in_statistics(orc):
         assert abs(s1 - s0) < band and abs(s1 - psnr) < band
 
 
+# --------------------------------------------------------------------------
+# orthogonal-transform variant (Theorem 2 / Theorem 3)
+# --------------------------------------------------------------------------
+
+_H4 = 0.5 * np.array([[1, 1, 1, 1], [1, 1, -1, -1], [1, -1, -1, 1], [1, -1, 1, -1]], dtype=np.float64)
+
+
+def _np_blocks(x):
+    """The field's 4^ndim blocks in stream order (tiles row-major, blocks
+    row-major inside a tile), each as an array of shape (4,)*ndim."""
+    t = TILE[x.ndim]
+    out = []
+    for idx in itertools.product(*[range(0, n, tt) for n, tt in zip(x.shape, t)]):
+        tile = x[tuple(slice(i, i + tt) for i, tt in zip(idx, t))]
+        for b in itertools.product(*[range(0, n, 4) for n in tile.shape]):
+            out.append(tile[tuple(slice(i, i + 4) for i in b)])
+    return out
+
+
+def _np_wht(blk):
+    c = blk.astype(np.float64)
+    for ax in range(c.ndim):
+        c = np.moveaxis(np.tensordot(_H4, np.moveaxis(c, ax, 0), axes=(1, 0)), 0, ax)
+    return c
+
+
+@pytest.mark.parametrize("shape", [(4096,), (68, 132), (20, 36, 68)])
+def test_xform_coefficients_and_parseval(orc, shape):
+    # coefficients against numpy's Walsh-Hadamard transform of each block
+    # (different summation order: codes may differ only where c / 2eb sits
+    # within rounding of a half), and Theorem 2: the data-domain SSE of the
+    # reconstruction equals the SSE of the coefficient quantization
+    x = (synth.grf_numpy(shape, -3.0, 17) * 5.0).astype(np.float64)
+    psnr = 90.0
+    blob, t = orc.compress_xform(x, psnr, trace=True)
+    codes = t["q"].ravel().astype(np.int64)
+    bs = 4 ** x.ndim
+    blocks = _np_blocks(x)
+    assert len(blocks) * bs == x.size
+    c = np.concatenate([_np_wht(b).ravel() for b in blocks])
+    # undo the DC differences (they restart at each tile)
+    q = codes.copy()
+    per_tile = int(np.prod(TILE[x.ndim])) // bs
+    tiles_dc = []
+    k = 0
+    for idx in itertools.product(*[range(0, n, tt) for n, tt in zip(x.shape, TILE[x.ndim])]):
+        nb = int(np.prod([min(tt, n - i) for n, i, tt in zip(x.shape, idx, TILE[x.ndim])])) // bs
+        q[(k + np.arange(nb)) * bs] = np.cumsum(codes[(k + np.arange(nb)) * bs])
+        k += nb
+    qn = np.rint(c * t["r"]).astype(np.int64)
+    diff = np.nonzero(qn != q)[0]
+    assert len(diff) <= 1e-4 * q.size
+    assert np.all(np.abs(np.abs(c[diff] * t["r"] - np.floor(c[diff] * t["r"])) - 0.5) < 1e-9)
+    y = orc.decompress(blob)
+    st = orc.stats(x, y, t["vr"], t["eb"])
+    sse_coef = math.fsum(((c - q * t["e2"]) ** 2).tolist())
+    assert abs(st["sse"] - sse_coef) <= 1e-9 * sse_coef
+
+
+def test_xform_psnr_and_statuses(orc):
+    # Theorem 3: uniform quantization of orthonormal coefficients with bin
+    # 2 eb gives MSE eb^2 / 3, so Eq. 7 reaches the target (within the
+    # statistical band of Eq. 6 where the bins are many)
+    x = synth.field_2d_grf(512, 512, seed=1).astype(np.float64)
+    band = 4.343 * 5 * math.sqrt(0.8 / x.size)
+    for psnr in (80.0, 100.0, 120.0):
+        blob, t = orc.compress_xform(x, psnr, trace=True)
+        st = orc.stats(x, orc.decompress(blob), t["vr"], t["eb"])
+        assert abs(st["psnr"] - psnr) < band
+        assert orc.header(blob)["flags"] & 16
+    with pytest.raises(orc.OracleError) as e:
+        orc.compress_xform(np.zeros((10, 12), dtype=np.float32), 80.0)
+    assert e.value.status == orc.E_INVALID_ARG
+
+
 def test_error_statuses(orc):
     x = np.ones((10, 10), dtype=np.float32)
     blob = orc.compress(x, 80.0)[0]
