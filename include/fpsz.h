@@ -74,7 +74,8 @@ typedef struct {
   uint32_t domain;       /* fpsz_domain used */
   double eb_scale;       /* closed loop: factor applied to Eq. 7's eb_rel (eb_rel above
                             includes it); 1 for plain compression */
-  uint32_t inloop;       /* 1: in-loop prediction (fpsz_compress_inloop) */
+  uint32_t variant;      /* 0 plain, 1 in-loop prediction (fpsz_compress_inloop),
+                            2 block transform (fpsz_compress_xform) */
   uint32_t reserved;
 } fpsz_info;
 
@@ -163,6 +164,23 @@ fpsz_status fpsz_compress_inloop(fpsz_ctx *ctx, const void *field_dev, int ndim,
                                  void *workspace_dev, uint64_t workspace_bytes, void *blob_dev,
                                  uint64_t blob_capacity, uint64_t *blob_bytes, fpsz_info *info,
                                  void *stream);
+
+/* The orthogonal-transform variant (Sec. III Theorem 2, Sec. IV Theorem 3):
+ * blocks of 4 (1D), 4x4 (2D) or 4x4x4 (3D) points are transformed by the
+ * orthonormal 4-point Walsh-Hadamard matrix H = 1/2 [[1,1,1,1], [1,1,-1,-1],
+ * [1,-1,-1,1], [1,-1,1,-1]] along x, y, z, and the coefficients quantized with
+ * bin 2 eb (Eq. 7's bound).  An orthonormal transform keeps the squared error,
+ * so the PSNR follows Eq. 7 as for prediction, but there is no pointwise
+ * bound.  A block's first (DC) bin is coded as its difference from the
+ * previous block's in the tile.  Every dimension must be a multiple of 4
+ * (INVALID_ARG otherwise).  The blob (header flag 16, tile domain)
+ * decompresses with fpsz_decompress.  Arguments, workspace and status as
+ * fpsz_compress. */
+fpsz_status fpsz_compress_xform(fpsz_ctx *ctx, const void *field_dev, int ndim,
+                                const uint64_t *dims, fpsz_dtype dtype, double target_psnr,
+                                void *workspace_dev, uint64_t workspace_bytes, void *blob_dev,
+                                uint64_t blob_capacity, uint64_t *blob_bytes, fpsz_info *info,
+                                void *stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): fpsz_compress

@@ -306,7 +306,7 @@ static void xform_codes(const void *x, int dtype, int ndim, const or_shape *S, d
           for (int u = 0; u < bs; u++) {
             int32_t q = dtype == 0 ? (int32_t)rintf(bf[u] * r_f) : (int32_t)rint(bd[u] * r);
             if (u == 0) {
-              code[p + u] = q - prev_dc;
+              code[p + u] = (int32_t)((uint32_t)q - (uint32_t)prev_dc); /* modulo 2^32 */
               prev_dc = q;
             } else {
               code[p + u] = q;

@@ -188,7 +188,8 @@ static fpsz_status compress_one(fpsz_ctx *ctx, const void *field_dev, int ndim,
                                 const uint64_t *dims, fpsz_dtype dtype, double target_psnr,
                                 fpsz_domain domain, void *workspace_dev, uint64_t workspace_bytes,
                                 void *blob_dev, uint64_t blob_capacity, uint64_t *blob_bytes,
-                                fpsz_info *info, void *stream, int closed, int inloop = 0) {
+                                fpsz_info *info, void *stream, int closed,
+                                int variant = kVarPlain) {
   if (!ctx) return FPSZ_E_INVALID_ARG;
   ctx->err[0] = 0;
   CJob job;
@@ -197,7 +198,7 @@ static fpsz_status compress_one(fpsz_ctx *ctx, const void *field_dev, int ndim,
                                     blob_bytes, &job);
   if (st != FPSZ_OK) return st;
   job.P.closed = closed;
-  job.P.inloop = inloop;
+  job.P.variant = variant;
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, FPSZ_E_DEVICE, "hipSetDevice failed");
   hipStream_t s = (hipStream_t)stream;
@@ -230,7 +231,21 @@ fpsz_status fpsz_compress_inloop(fpsz_ctx *ctx, const void *field_dev, int ndim,
                                  void *stream) {
   return compress_one(ctx, field_dev, ndim, dims, dtype, target_psnr, FPSZ_DOMAIN_TILE,
                       workspace_dev, workspace_bytes, blob_dev, blob_capacity, blob_bytes, info,
-                      stream, 0, 1);
+                      stream, 0, kVarInloop);
+}
+
+fpsz_status fpsz_compress_xform(fpsz_ctx *ctx, const void *field_dev, int ndim,
+                                const uint64_t *dims, fpsz_dtype dtype, double target_psnr,
+                                void *workspace_dev, uint64_t workspace_bytes, void *blob_dev,
+                                uint64_t blob_capacity, uint64_t *blob_bytes, fpsz_info *info,
+                                void *stream) {
+  if (ctx) ctx->err[0] = 0;
+  if (!ctx || !dims || ndim < 1 || ndim > 3) return FPSZ_E_INVALID_ARG;
+  for (int i = 0; i < ndim; i++)
+    if (dims[i] % 4) return fail(ctx, FPSZ_E_INVALID_ARG, "dims must be multiples of 4");
+  return compress_one(ctx, field_dev, ndim, dims, dtype, target_psnr, FPSZ_DOMAIN_TILE,
+                      workspace_dev, workspace_bytes, blob_dev, blob_capacity, blob_bytes, info,
+                      stream, 0, kVarXform);
 }
 
 fpsz_status fpsz_compress_closed_loop(fpsz_ctx *ctx, const void *field_dev, int ndim,
@@ -294,7 +309,7 @@ fpsz_status fpsz_blob_header(const void *blob_host, uint64_t bytes, int *ndim, u
     info->is_const = (fl & kFlagConst) ? 1 : 0;
     info->domain = (fl & kFlagTile) ? 1 : 0;
     info->eb_scale = (fl & kFlagClosed) ? rd<double>(h + H_SCALE) : 1.0;
-    info->inloop = (fl & kFlagInloop) ? 1 : 0;
+    info->variant = (fl & kFlagInloop) ? kVarInloop : (fl & kFlagXform) ? kVarXform : kVarPlain;
   }
   return FPSZ_OK;
 }

@@ -1093,6 +1093,165 @@ __global__ __launch_bounds__(kBlock) void k_quant_il(CJob one, const CJob *__res
     atomicAdd((unsigned long long *)&dp->n_pat, (unsigned long long)my_pat);
 }
 
+// ---------------------------------------------------------------------------
+// Orthogonal-transform variant (Sec. III Theorem 2, Sec. IV Theorem 3):
+// blocks of 4 / 4x4 / 4x4x4 points, the orthonormal 4-point Walsh-Hadamard
+// matrix H = 1/2 [[1,1,1,1], [1,1,-1,-1], [1,-1,-1,1], [1,-1,1,-1]] along x,
+// then y, then z, coefficients quantized with bin 2 eb.  H is symmetric and
+// H H = I, so decompression applies H again.  The sums run in the field's
+// precision in the order written here (the same order wherever the scheme
+// is implemented, so results agree to the bit).  Codes are in stream order:
+// blocks row-major over the tile's block grid, a block's coefficients
+// row-major; a block's DC bin is coded as its difference from the previous
+// block's in the tile.  Each thread takes BPT consecutive blocks.
+template <int NDIM> struct XfGeo;
+template <> struct XfGeo<1> { static constexpr int BZ = 1, BY = 1, BS = 4, BPT = 8; };
+template <> struct XfGeo<2> { static constexpr int BZ = 1, BY = 4, BS = 16, BPT = 2; };
+template <> struct XfGeo<3> { static constexpr int BZ = 4, BY = 4, BS = 64, BPT = 1; };
+
+template <typename T> __device__ inline void wht4(T &a, T &b, T &c, T &d) {
+  const T w0 = ((a + b) + c) + d, w1 = ((a + b) - c) - d;
+  const T w2 = ((a - b) - c) + d, w3 = ((a - b) + c) - d;
+  a = (T)0.5 * w0;
+  b = (T)0.5 * w1;
+  c = (T)0.5 * w2;
+  d = (T)0.5 * w3;
+}
+
+// a block of 4^NDIM values laid out [kz][ky][kx]
+template <typename T, int NDIM> __device__ inline void wht_block(T *v) {
+  constexpr int R = NDIM == 3 ? 16 : NDIM == 2 ? 4 : 1;
+#pragma unroll
+  for (int r = 0; r < R; r++) wht4(v[4 * r], v[4 * r + 1], v[4 * r + 2], v[4 * r + 3]);
+  if (NDIM >= 2) {
+#pragma unroll
+    for (int kz = 0; kz < (NDIM == 3 ? 4 : 1); kz++)
+#pragma unroll
+      for (int kx = 0; kx < 4; kx++)
+        wht4(v[16 * kz + kx], v[16 * kz + 4 + kx], v[16 * kz + 8 + kx], v[16 * kz + 12 + kx]);
+  }
+  if (NDIM == 3) {
+#pragma unroll
+    for (int r = 0; r < 16; r++) wht4(v[r], v[r + 16], v[r + 32], v[r + 48]);
+  }
+}
+
+// point u of a block in the field (block origin bz0, by0, bx0 inside the tile)
+template <int NDIM> __device__ inline void xf_point(int u, int &uz, int &uy, int &ux) {
+  uz = NDIM == 3 ? u >> 4 : 0;
+  uy = NDIM == 3 ? (u >> 2) & 3 : NDIM == 2 ? u >> 2 : 0;
+  ux = u & 3;
+}
+
+template <typename T, int NDIM, bool RECORDS>
+__global__ __launch_bounds__(kBlock) void k_quant_xf(CJob one, const CJob *__restrict__ jobs) {
+  const CJob J = select_job(one, jobs);
+  const T *__restrict__ x = static_cast<const T *>(J.x);
+  const Plan P = J.P;
+  DevParams *__restrict__ dp = J.W.P;
+  using X = XfGeo<NDIM>;
+  __shared__ int32_t dcs[kTilePts / 4];
+  __shared__ uint32_t hist[RECORDS ? 1 : kNSym];
+  __shared__ uint32_t scr[8];
+  if (dp->status != 0 || dp->is_const) return;
+  if (RECORDS && !dp->big_tiles) return;
+  const int tid = threadIdx.x;
+  const float rf = dp->r_f;
+  const double r = dp->r;
+  if (!RECORDS)
+    for (int s = tid; s < kNSym; s += kBlock) hist[s] = 0;
+  uint64_t my_out = 0;
+  uint64_t t;
+  for (uint64_t it_k = 0; xcd_tile(P, NDIM, it_k, &t); it_k++) {
+    if (RECORDS && J.W.exc_cnt[t] <= (uint32_t)kStage) continue;  // uniform
+    const TileGeo g = tile_geo(P, t);
+    const int nbx = (int)g.ex / 4, nby = (int)g.ey / X::BY, nbz = (int)g.ez / X::BZ;
+    const int nb = nbz * nby * nbx;
+    __syncthreads();  // the previous tile's DC bins are read
+    int32_t cq[X::BPT * X::BS];
+#pragma unroll
+    for (int k = 0; k < X::BPT; k++) {
+      const int b = tid * X::BPT + k;
+      if (b < nb) {
+        const int kz = b / (nby * nbx), rem = b - kz * nby * nbx, ky = rem / nbx, kx = rem - ky * nbx;
+        T v[X::BS];
+#pragma unroll
+        for (int u = 0; u < X::BS; u++) {
+          int uz, uy, ux;
+          xf_point<NDIM>(u, uz, uy, ux);
+          v[u] = x[((g.z0 + (uint64_t)(kz * X::BZ + uz)) * P.ny + (g.y0 + (uint64_t)(ky * X::BY + uy))) *
+                       P.nx + (g.x0 + (uint64_t)(kx * 4 + ux))];
+        }
+        wht_block<T, NDIM>(v);
+#pragma unroll
+        for (int u = 0; u < X::BS; u++) {
+          if constexpr (sizeof(T) == 4) cq[k * X::BS + u] = (int32_t)__builtin_rintf(v[u] * rf);
+          else cq[k * X::BS + u] = (int32_t)__builtin_rint(v[u] * r);
+        }
+        dcs[b] = cq[k * X::BS];
+      }
+    }
+    __syncthreads();
+    uint64_t oflags = 0;  // bit k * BS + u: outlier
+#pragma unroll
+    for (int k = 0; k < X::BPT; k++) {
+      const int b = tid * X::BPT + k;
+      if (b >= nb) continue;
+      cq[k * X::BS] = (int32_t)((uint32_t)cq[k * X::BS] - (uint32_t)(b > 0 ? dcs[b - 1] : 0));
+#pragma unroll
+      for (int u = 0; u < X::BS; u++) {
+        const int32_t c = cq[k * X::BS + u];
+        bool outl;
+        const uint32_t sy = symbol_of(c, outl);
+        if (!RECORDS) {
+          J.W.codes[g.start + (uint64_t)(b * X::BS + u)] = outl ? (int16_t)-32768 : (int16_t)c;
+          atomicAdd(&hist[sy], 1u);
+        }
+        oflags |= (outl ? 1ull : 0ull) << (k * X::BS + u);
+      }
+    }
+    const uint32_t nexc = (uint32_t)__popcll(oflags);
+    if (!RECORDS) my_out += nexc;
+    uint32_t tile_total;
+    const uint32_t my_off = block_excl_scan_u32(nexc, scr, &tile_total);
+    if (!RECORDS && tid == 0) {
+      J.W.exc_cnt[t] = tile_total;
+      if (tile_total > (uint32_t)kStage) atomicOr(&dp->big_tiles, 1u);
+    }
+    if (nexc && (RECORDS || tile_total <= (uint32_t)kStage)) {
+      uint32_t e = my_off;
+      const uint64_t base_off = RECORDS ? J.W.exc_off[t] : 0;
+#pragma unroll
+      for (int j = 0; j < X::BPT * X::BS; j++) {
+        if (!((oflags >> j) & 1ull)) continue;
+        const uint32_t pos = (uint32_t)(g.start + (uint64_t)(tid * X::BPT * X::BS + j));
+        if (RECORDS) {
+          const uint64_t o = P.off_exc + 8 * (base_off + e);
+          if (o + 8 <= P.capacity) {
+            uint32_t *rec = reinterpret_cast<uint32_t *>(J.blob + o);
+            rec[0] = pos;
+            rec[1] = (uint32_t)cq[j];
+          } else {
+            atomicOr(&dp->overflow, 1u);
+          }
+        } else {
+          uint32_t *rec = J.W.stage + (t * kStage + e) * 2;
+          rec[0] = pos;
+          rec[1] = (uint32_t)cq[j];
+        }
+        e++;
+      }
+    }
+  }
+  if (RECORDS) return;
+  __syncthreads();
+  for (int s = tid; s < kNSym; s += kBlock)
+    if (hist[s]) atomicAdd(&J.W.hist[(blockIdx.x % kHistCopies) * kNSym + s], hist[s]);
+  my_out = wave_sum_u64(my_out);
+  if ((tid & 63) == 0 && my_out)
+    atomicAdd((unsigned long long *)&dp->n_out, (unsigned long long)my_out);
+}
+
 // Exclusive scan of the per-tile record counts (one workgroup): tile offsets
 // into the blob's tile_exc_offset section and the workspace, the total.
 constexpr int kScanThreads = 1024;
@@ -1800,7 +1959,9 @@ __global__ void k_header(CJob one, const CJob *__restrict__ jobs) {
     const uint16_t ver = kVersion;
     __builtin_memcpy(h + H_VERSION, &ver, 2);
     const uint16_t fl = (uint16_t)((cst ? kFlagConst : 0) | (P.domain ? kFlagTile : 0) |
-                                   (P.closed ? kFlagClosed : 0) | (P.inloop ? kFlagInloop : 0));
+                                   (P.closed ? kFlagClosed : 0) |
+                                   (P.variant == kVarInloop ? kFlagInloop : 0) |
+                                   (P.variant == kVarXform ? kFlagXform : 0));
     __builtin_memcpy(h + H_FLAGS, &fl, 2);
     if (P.closed) putf(H_SCALE, dp->scale);
     h[H_DTYPE] = (uint8_t)P.dtype;
@@ -1903,7 +2064,15 @@ template <typename T, int NDIM, bool GLOBAL>
 static void launch_quant_d(const CJob &one, const CJob *jobs, int nf, const Plan &maxP,
                            const LaunchCfg &cfg, hipStream_t s, Timer *tm) {
   const dim3 grid(cfg.quant_grid, nf);
-  if (maxP.inloop) {
+  if (maxP.variant == kVarXform) {
+    hipLaunchKernelGGL((k_quant_xf<T, NDIM, false>), grid, dim3(kBlock), 0, s, one, jobs);
+    tm->mark(s, "quant");
+    hipLaunchKernelGGL(k_codebook, dim3(2, nf), dim3(kCbThreads), 0, s, one, jobs);
+    tm->mark(s, "codebook");
+    hipLaunchKernelGGL((k_quant_xf<T, NDIM, true>), grid, dim3(kBlock), 0, s, one, jobs);
+    return;
+  }
+  if (maxP.variant == kVarInloop) {
     // in-loop prediction (every field of the launch; tile domain)
     hipLaunchKernelGGL((k_quant_il<T, NDIM, false>), grid, dim3(kBlock), 0, s, one, jobs);
     tm->mark(s, "quant");

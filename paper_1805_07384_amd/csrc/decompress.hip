@@ -1537,6 +1537,136 @@ __global__ __launch_bounds__(kBlock) void k_rec_il(Plan P, const uint8_t *__rest
 }
 
 // ---------------------------------------------------------------------------
+// Orthogonal-transform variant: inverse (Sec. III Theorem 2, Sec. IV Theorem 3):
+// blocks of 4 / 4x4 / 4x4x4 points, the orthonormal 4-point Walsh-Hadamard
+// matrix H = 1/2 [[1,1,1,1], [1,1,-1,-1], [1,-1,-1,1], [1,-1,1,-1]] along x,
+// then y, then z, coefficients quantized with bin 2 eb (the compressor's
+// description).  H is symmetric and
+// H H = I, so decompression applies H again.  The sums run in the field's
+// precision in the order written here (the same order wherever the scheme
+// is implemented, so results agree to the bit).  Codes are in stream order:
+// blocks row-major over the tile's block grid, a block's coefficients
+// row-major; a block's DC bin is coded as its difference from the previous
+// block's in the tile.  Each thread takes BPT consecutive blocks.
+template <int NDIM> struct XfGeo;
+template <> struct XfGeo<1> { static constexpr int BZ = 1, BY = 1, BS = 4, BPT = 8; };
+template <> struct XfGeo<2> { static constexpr int BZ = 1, BY = 4, BS = 16, BPT = 2; };
+template <> struct XfGeo<3> { static constexpr int BZ = 4, BY = 4, BS = 64, BPT = 1; };
+
+template <typename T> __device__ inline void wht4(T &a, T &b, T &c, T &d) {
+  const T w0 = ((a + b) + c) + d, w1 = ((a + b) - c) - d;
+  const T w2 = ((a - b) - c) + d, w3 = ((a - b) + c) - d;
+  a = (T)0.5 * w0;
+  b = (T)0.5 * w1;
+  c = (T)0.5 * w2;
+  d = (T)0.5 * w3;
+}
+
+// a block of 4^NDIM values laid out [kz][ky][kx]
+template <typename T, int NDIM> __device__ inline void wht_block(T *v) {
+  constexpr int R = NDIM == 3 ? 16 : NDIM == 2 ? 4 : 1;
+#pragma unroll
+  for (int r = 0; r < R; r++) wht4(v[4 * r], v[4 * r + 1], v[4 * r + 2], v[4 * r + 3]);
+  if (NDIM >= 2) {
+#pragma unroll
+    for (int kz = 0; kz < (NDIM == 3 ? 4 : 1); kz++)
+#pragma unroll
+      for (int kx = 0; kx < 4; kx++)
+        wht4(v[16 * kz + kx], v[16 * kz + 4 + kx], v[16 * kz + 8 + kx], v[16 * kz + 12 + kx]);
+  }
+  if (NDIM == 3) {
+#pragma unroll
+    for (int r = 0; r < 16; r++) wht4(v[r], v[r + 16], v[r + 32], v[r + 48]);
+  }
+}
+
+// point u of a block in the field (block origin bz0, by0, bx0 inside the tile)
+template <int NDIM> __device__ inline void xf_point(int u, int &uz, int &uy, int &ux) {
+  uz = NDIM == 3 ? u >> 4 : 0;
+  uy = NDIM == 3 ? (u >> 2) & 3 : NDIM == 2 ? u >> 2 : 0;
+  ux = u & 3;
+}
+
+template <typename T, int NDIM>
+__global__ __launch_bounds__(kBlock) void k_rec_xf(Plan P, const uint8_t *__restrict__ blob,
+                                                   DecodeArgs A, DevParams *__restrict__ dp,
+                                                   const int16_t *__restrict__ codes,
+                                                   T *__restrict__ out) {
+  using X = XfGeo<NDIM>;
+  __shared__ int32_t cq[kTilePts];
+  __shared__ uint32_t scr[8];
+  __shared__ uint32_t s_bad;
+  if (dp->corrupt) return;
+  const int tid = threadIdx.x;
+  const uint64_t t = xcd_block_tile(P.n_tiles);
+  const TileGeo g = tile_geo(P, t);
+  const int nt = (int)g.nt;
+  const int nbx = (int)g.ex / 4, nby = (int)g.ey / X::BY, nbz = (int)g.ez / X::BZ;
+  const int nb = nbz * nby * nbx;
+  const uint64_t *teo = reinterpret_cast<const uint64_t *>(blob + P.off_teo);
+  const uint64_t e0 = teo[t], e1 = teo[t + 1];
+  if (e0 > e1 || e1 > A.n_exc) return;  // reported by the decode kernel
+  const uint32_t *exc = reinterpret_cast<const uint32_t *>(blob + P.off_exc);
+  if (tid == 0) s_bad = 0;
+  for (int i = tid; i < nt; i += kBlock) cq[i] = codes[g.start + (uint64_t)i];
+  __syncthreads();
+  // outlier codes from the exception list (no other records in these blobs)
+  for (uint64_t e = e0 + tid; e < e1; e += kBlock) {
+    const uint32_t key = exc[2 * e];
+    const uint64_t pos = key;
+    if ((key & kTagPatch) || pos < g.start || pos >= g.start + (uint64_t)nt ||
+        cq[pos - g.start] != -32768) {
+      atomicOr(&s_bad, 1u);
+      continue;
+    }
+    cq[pos - g.start] = (int32_t)exc[2 * e + 1];
+  }
+  __syncthreads();
+  if (s_bad) {
+    if (tid == 0) atomicOr(&dp->corrupt, 1u);
+    return;
+  }
+  // DC bins: a running sum of the differences over the tile's blocks
+  uint32_t mine = 0;
+#pragma unroll
+  for (int k = 0; k < X::BPT; k++) {
+    const int b = tid * X::BPT + k;
+    if (b < nb) mine += (uint32_t)cq[b * X::BS];
+  }
+  uint32_t tot;
+  uint32_t dc = block_excl_scan_u32(mine, scr, &tot);
+  VStat vs;
+#pragma unroll
+  for (int k = 0; k < X::BPT; k++) {
+    const int b = tid * X::BPT + k;
+    if (b >= nb) continue;
+    const int kz = b / (nby * nbx), rem = b - kz * nby * nbx, ky = rem / nbx, kx = rem - ky * nbx;
+    T v[X::BS];
+#pragma unroll
+    for (int u = 0; u < X::BS; u++) {
+      int32_t q = cq[b * X::BS + u];
+      if (u == 0) {
+        dc += (uint32_t)q;
+        q = (int32_t)dc;
+      }
+      if constexpr (sizeof(T) == 4) v[u] = (float)q * A.e2_f;
+      else v[u] = (double)q * A.e2;
+    }
+    wht_block<T, NDIM>(v);
+#pragma unroll
+    for (int u = 0; u < X::BS; u++) {
+      int uz, uy, ux;
+      xf_point<NDIM>(u, uz, uy, ux);
+      const uint64_t oi = ((g.z0 + (uint64_t)(kz * X::BZ + uz)) * P.ny + (g.y0 + (uint64_t)(ky * X::BY + uy))) *
+                              P.nx + (g.x0 + (uint64_t)(kx * 4 + ux));
+      out[oi] = v[u];
+      if (A.ref) vs.add(static_cast<const T *>(A.ref)[oi], v[u], A.eb);
+    }
+  }
+  if (A.ref) vs.store(A.vpart, t);
+}
+
+// ---------------------------------------------------------------------------
 // Exclusive scans (modulo 2^32) of a row-major u32 array along one axis.
 // Element (o, k, i) sits at (o * len + k) * inner + i.  The axis is cut into
 // segments of 32; each thread scans one segment of one column after adding
@@ -1672,7 +1802,9 @@ static void launch_dec_t(const Plan &P, const uint8_t *blob, const DecodeArgs &A
                      ds.pool_words);
   tm->mark(s, "decode");
   const bool ragged = P.pad_ != 0;
-  if (P.inloop) {
+  if (P.variant == kVarXform) {
+    hipLaunchKernelGGL((k_rec_xf<T, NDIM>), grid, blk, 0, s, P, blob, A, dp, codes, out);
+  } else if (P.variant == kVarInloop) {
     hipLaunchKernelGGL((k_rec_il<T, NDIM>), grid, blk, 0, s, P, blob, A, dp, codes, out);
   } else if (P.domain == FPSZ_DOMAIN_GLOBAL) {
     hipLaunchKernelGGL((k_proj_full<NDIM, (int)(sizeof(T) / 4)>), grid, blk, 0, s, P, blob, A, dp,
@@ -1789,7 +1921,7 @@ hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const Deco
   A.ref = ref;
   A.eb = eb;
   A.vpart = W.vpart;
-  A.il_rw = P.inloop ? (P.dtype == FPSZ_F32 ? 1u : 2u) : 0u;
+  A.il_rw = P.variant == kVarInloop ? (P.dtype == FPSZ_F32 ? 1u : 2u) : 0u;
   const DecShape ds = decode_shape();
   if (P.dtype == FPSZ_F32) {
     if (P.ndim == 1) launch_dec_t<float, 1>(P, blob, A, W.P, W.codes, W.tmp, ds, (float *)out, s, tm);

@@ -30,7 +30,11 @@ constexpr int kChunk = 128;
 constexpr int kTilePts = 8192;
 constexpr int kLutBits = 11;
 constexpr uint32_t kTagPatch = 0x80000000u;
-constexpr uint16_t kFlagConst = 1, kFlagTile = 2, kFlagClosed = 4, kFlagInloop = 8;
+constexpr uint16_t kFlagConst = 1, kFlagTile = 2, kFlagClosed = 4, kFlagInloop = 8,
+                   kFlagXform = 16;
+// Plan::variant: plain Lorenzo on prequantized bins, SZ 1.4-style in-loop
+// prediction, or the orthogonal block transform (the last two tile domain)
+enum : int32_t { kVarPlain = 0, kVarInloop = 1, kVarXform = 2 };
 constexpr int kBlock = 256;
 constexpr int kRangeBlocks = 1024;
 // The compressor's histogram is kept in this many copies (workgroup b adds
@@ -69,7 +73,7 @@ struct Plan {
   // vr^2 * mse_factor; closed = 0 for plain compression
   double mse_factor;
   int32_t closed;
-  int32_t inloop;  // SZ 1.4-style in-loop prediction (tile domain)
+  int32_t variant;  // kVarPlain, kVarInloop or kVarXform
 };
 
 // Geometry of one tile.

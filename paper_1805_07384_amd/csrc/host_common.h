@@ -251,7 +251,7 @@ inline fpsz_status prepare_compress(fpsz_ctx *ctx, const void *field_dev, int nd
   // the MSE that Eq. 4 maps to the target is vr^2 * 10^(-PSNR/10) (closed loop)
   P.mse_factor = pow(10.0, -target_psnr / 10.0);
   P.closed = 0;
-  P.inloop = 0;
+  P.variant = kVarPlain;
   uint8_t *ws = (uint8_t *)workspace_dev;
   CompressWs &W = job->W;
   W.P = (DevParams *)ws;
@@ -288,7 +288,7 @@ inline void fill_compress_info(fpsz_info *info, const Plan &P, const DevParams &
   info->is_const = D.is_const;
   info->domain = (uint32_t)P.domain;
   info->eb_scale = P.closed ? D.scale : 1.0;
-  info->inloop = (uint32_t)P.inloop;
+  info->variant = (uint32_t)P.variant;
 }
 
 // Status of a finished compress from its parameter block.
@@ -352,9 +352,14 @@ inline fpsz_status prepare_decompress(fpsz_ctx *ctx, const uint8_t *h, const voi
   if ((uintptr_t)field_out_dev % esz) return fail(ctx, FPSZ_E_INVALID_ARG, "output not element-aligned");
   const uint16_t flags = rd<uint16_t>(h + H_FLAGS);
   P.domain = (flags & kFlagTile) ? FPSZ_DOMAIN_TILE : FPSZ_DOMAIN_GLOBAL;
-  P.inloop = (flags & kFlagInloop) ? 1 : 0;
-  if (P.inloop && P.domain != FPSZ_DOMAIN_TILE)
-    return fail(ctx, FPSZ_E_CORRUPT, "in-loop blob outside the tile domain");
+  P.variant = (flags & kFlagInloop) ? kVarInloop : (flags & kFlagXform) ? kVarXform : kVarPlain;
+  if (P.variant != kVarPlain && P.domain != FPSZ_DOMAIN_TILE)
+    return fail(ctx, FPSZ_E_CORRUPT, "variant blob outside the tile domain");
+  if ((flags & kFlagInloop) && (flags & kFlagXform))
+    return fail(ctx, FPSZ_E_CORRUPT, "two variants in one blob");
+  if (P.variant == kVarXform)
+    for (int i = 0; i < nd; i++)
+      if (dims[i] % 4) return fail(ctx, FPSZ_E_CORRUPT, "transform blob dims not multiples of 4");
   P.capacity = blob_bytes;
   J->blob = (const uint8_t *)blob_dev;
   J->out = field_out_dev;

@@ -37,7 +37,7 @@ class Info(ctypes.Structure):
         ("n_exceptions", ctypes.c_uint64), ("blob_bytes", ctypes.c_uint64),
         ("bits_per_value", ctypes.c_double), ("is_const", ctypes.c_uint32),
         ("domain", ctypes.c_uint32), ("eb_scale", ctypes.c_double),
-        ("inloop", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+        ("variant", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
     ]
 
     def as_dict(self):
@@ -112,6 +112,9 @@ SIGNATURES = {
     "fpsz_compress": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _u64p, ctypes.c_int, ctypes.c_double,
                                      ctypes.c_int, _vp, ctypes.c_uint64, _vp, ctypes.c_uint64,
                                      _u64p, ctypes.POINTER(Info), _vp]),
+    "fpsz_compress_xform": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _u64p, ctypes.c_int,
+                                           ctypes.c_double, _vp, ctypes.c_uint64, _vp,
+                                           ctypes.c_uint64, _u64p, ctypes.POINTER(Info), _vp]),
     "fpsz_compress_inloop": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _u64p, ctypes.c_int,
                                             ctypes.c_double, _vp, ctypes.c_uint64, _vp,
                                             ctypes.c_uint64, _u64p, ctypes.POINTER(Info), _vp]),
@@ -329,6 +332,19 @@ class Context:
                                            workspace.numel() * workspace.element_size(),
                                            blob.data_ptr(), blob.numel(), ctypes.byref(nb),
                                            ctypes.byref(info), _stream(stream))
+        return st, nb.value, info
+
+    def compress_xform_into(self, x: torch.Tensor, psnr: float, workspace: torch.Tensor,
+                            blob: torch.Tensor, stream=None):
+        """fpsz_compress_xform into ``blob``; returns (status, blob_bytes, Info)."""
+        assert x.is_contiguous() and x.is_cuda
+        nb = ctypes.c_uint64()
+        info = Info()
+        st = self.lib.fpsz_compress_xform(self.handle, x.data_ptr(), x.dim(), _dims(x.shape),
+                                          _dtype_code(x), float(psnr), workspace.data_ptr(),
+                                          workspace.numel() * workspace.element_size(),
+                                          blob.data_ptr(), blob.numel(), ctypes.byref(nb),
+                                          ctypes.byref(info), _stream(stream))
         return st, nb.value, info
 
     def compress_closed_loop_into(self, x: torch.Tensor, psnr: float, workspace: torch.Tensor,

@@ -494,7 +494,7 @@ def test_parity_inloop(ctx, orc, shape, dt, psnr):
         d = np.nonzero(c16 != ot["code16"])[0]
         pytest.fail("in-loop blob differs: %d of %d codes differ, first %s gpu %s oracle %s"
                     % (len(d), x.size, d[:5], c16[d[:5]], ot["code16"][d[:5]]))
-    assert info.inloop == 1 and info.n_patches == ot["n_patches"] and info.n_outliers == 0
+    assert info.variant == 1 and info.n_patches == ot["n_patches"] and info.n_outliers == 0
     y = ctx.decompress(blob[:nb])
     oy = orc.decompress(ob)
     assert np.array_equal(_bits(y.cpu().numpy()), _bits(oy))
@@ -523,3 +523,73 @@ def test_parity_inloop_stored_points(ctx, orc):
     assert st == 0 and blob[:nb].cpu().numpy().tobytes() == ob
     y = ctx.decompress(blob[:nb])
     assert np.array_equal(_bits(y.cpu().numpy()), _bits(orc.decompress(ob)))
+
+
+XFORM_CASES = [((4096,), np.float32, 80.0), ((8196,), np.float64, 120.0),
+               ((68, 132), np.float32, 40.0), ((68, 132), np.float64, 100.0),
+               ((20, 36, 68), np.float32, 120.0), ((20, 36, 68), np.float64, 60.0),
+               ((64, 64, 64), np.float32, 80.0)]
+
+
+def _xform_run(ctx, x, psnr):
+    from paper_1805_07384_amd import fpsz
+    xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    ws = torch.full((fpsz.compress_workspace_bytes(x.shape, xt.dtype),), 0xA5, dtype=torch.uint8,
+                    device="cuda")
+    blob = torch.full((fpsz.compress_bound(x.shape, xt.dtype),), 0x5A, dtype=torch.uint8,
+                      device="cuda")
+    st, nb, info = ctx.compress_xform_into(xt, psnr, ws, blob)
+    return xt, ws, blob, st, nb, info
+
+
+@pytest.mark.parametrize("shape,dt,psnr", XFORM_CASES)
+def test_parity_xform(ctx, orc, shape, dt, psnr):
+    # the orthogonal-transform variant: blob and reconstruction bit-exact
+    # with the oracle; the fused check agrees with the oracle's statistics
+    from paper_1805_07384_amd import fpsz
+    x = (synth.grf_numpy(shape, -3.0, 21) * 4.0 - 2.0).astype(dt)
+    print("case xform shape=%s dtype=%s psnr=%s" % (shape, x.dtype, psnr), flush=True)
+    ob, ot = orc.compress_xform(x, psnr, trace=True)
+    xt, ws, blob, st, nb, info = _xform_run(ctx, x, psnr)
+    assert st == 0
+    gb = blob[:nb].cpu().numpy().tobytes()
+    if gb != ob:
+        o = fpsz.workspace_offset(x.shape, xt.dtype, 4)
+        c16 = ws[o:o + 2 * x.size].cpu().numpy().view(np.int16)
+        d = np.nonzero(c16 != ot["code16"])[0]
+        pytest.fail("transform blob differs: %d of %d codes differ, first %s gpu %s oracle %s"
+                    % (len(d), x.size, d[:5], c16[d[:5]], ot["code16"][d[:5]]))
+    assert info.variant == 2 and info.n_patches == 0
+    assert info.n_outliers == ot["n_outliers"]
+    y = ctx.decompress(blob[:nb])
+    oy = orc.decompress(ob)
+    assert np.array_equal(_bits(y.cpu().numpy()), _bits(oy))
+    y2, stv = ctx.decompress_verify(blob[:nb], xt)
+    assert np.array_equal(_bits(y2.cpu().numpy()), _bits(oy))
+    os_ = orc.stats(x, oy, ot["vr"], ot["eb"])
+    assert stv["n_over_eb"] == os_["n_over_eb"]
+    assert stv["max_abs_err"] == os_["max_abs_err"]
+    assert abs(stv["sse"] - os_["sse"]) <= 1e-9 * os_["sse"]
+
+
+def test_parity_xform_outliers_and_constant(ctx, orc):
+    # white noise at 120 dB: coefficient bins beyond 2^15 are stored as
+    # outlier records; a constant field gives the constant blob
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-1.0, 1.0, size=(36, 40, 44)).astype(np.float64)
+    print("case xform outliers", flush=True)
+    ob, ot = orc.compress_xform(x, 120.0, trace=True)
+    assert ot["n_outliers"] > 0
+    xt, ws, blob, st, nb, info = _xform_run(ctx, x, 120.0)
+    assert st == 0 and info.n_outliers == ot["n_outliers"]
+    assert blob[:nb].cpu().numpy().tobytes() == ob
+    y = ctx.decompress(blob[:nb])
+    assert np.array_equal(_bits(y.cpu().numpy()), _bits(orc.decompress(ob)))
+    c = np.full((8, 12), 3.25, dtype=np.float32)
+    print("case xform constant", flush=True)
+    ob, _ = orc.compress_xform(c, 80.0, trace=True)
+    xt, ws, blob, st, nb, info = _xform_run(ctx, c, 80.0)
+    assert st == 0 and blob[:nb].cpu().numpy().tobytes() == ob
+    assert np.array_equal(ctx.decompress(blob[:nb]).cpu().numpy(), c)
+    xt, ws, blob, st, nb, info = _xform_run(ctx, np.zeros((10, 12), np.float32), 80.0)
+    assert st != 0
