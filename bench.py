@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--served-requests", type=int, default=2000)
     ap.add_argument("--served-rates", default="200,3000,20000",
                     help="arrival rates (requests/s) the trace is replayed at")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the closed-loop, in-loop and transform legs")
     ap.add_argument("--no-c1", action="store_true", help="skip the 512x512 latency leg")
     ap.add_argument("--no-c5", action="store_true", help="skip the 1024^3 float64 leg")
     ap.add_argument("--separate-verify", action="store_true",
@@ -508,9 +510,10 @@ def main():
                                       5, warm=1)[0]
     copy_gbps = device_copy_gbps(x)
     # the closed-loop correction on the benchmark field at each target
-    progress("closed-loop legs")
-    closed = []
-    for p in psnrs:
+    closed, inloop, xform = [], [], []
+    for p in ([] if args.no_variants else psnrs):
+        if p == psnrs[0]:
+            progress("closed-loop legs")
         st, nb, ic = ctx.compress_closed_loop_into(x, p, ws_c, blob, domain, stream)
         if st != fpsz.OK:
             raise fpsz.FpszError(st, "closed loop at %g dB" % p)
@@ -521,9 +524,9 @@ def main():
                        "bits_per_value": round(ic.bits_per_value, 4),
                        "compress_gbps": round(n * s / tcl / 1e9, 2), "n_over_eb": stc.n_over_eb})
     # the SZ 1.4-style in-loop variant (tile domain) on the same field
-    progress("in-loop legs")
-    inloop = []
-    for p in psnrs:
+    for p in ([] if args.no_variants else psnrs):
+        if p == psnrs[0]:
+            progress("in-loop legs")
         st, nb, ii = ctx.compress_inloop_into(x, p, ws_c, blob, stream)
         if st != fpsz.OK:
             raise fpsz.FpszError(st, "in-loop at %g dB" % p)
@@ -535,6 +538,21 @@ def main():
                        "compress_gbps": round(n * s / til / 1e9, 2),
                        "decompress_gbps": round(n * s / tdl / 1e9, 2), "n_over_eb": sti.n_over_eb,
                        "op_frac": op_fracs(n, s, ii.bits_per_value, til, tdl)})
+    # the orthogonal-transform variant (Theorem 3) on the same field
+    for p in ([] if args.no_variants else psnrs):
+        if p == psnrs[0]:
+            progress("transform legs")
+        st, nb, ix = ctx.compress_xform_into(x, p, ws_c, blob, stream)
+        if st != fpsz.OK:
+            raise fpsz.FpszError(st, "transform at %g dB" % p)
+        txf = timed_calls(lambda: ctx.compress_xform_into(x, p, ws_c, blob, stream), 3, warm=1)[0]
+        tdx = timed_calls(lambda: ctx.decompress_into(blob, nb, ws_d, out, stream), 3, warm=1)[0]
+        st, stx = ctx.decompress_verify_into(blob, nb, ws_d, out, x, stream)
+        xform.append({"psnr": p, "dpsnr": round(stx.psnr - p, 5),
+                      "bits_per_value": round(ix.bits_per_value, 4), "n_outliers": ix.n_outliers,
+                      "compress_gbps": round(n * s / txf / 1e9, 2),
+                      "decompress_gbps": round(n * s / tdx / 1e9, 2),
+                      "op_frac": op_fracs(n, s, ix.bits_per_value, txf, tdx)})
     total_bytes = n * s * len(psnrs)
     value = total_bytes / ((t1 - t0) / args.steps) / 1e9
 
@@ -629,6 +647,7 @@ def main():
         "per_target": per_target,
         "closed_loop": closed,
         "inloop": inloop,
+        "xform": xform,
         "op_roofline": {"peak_gbps": HBM_PEAK_GBPS, "device_copy_gbps": round(copy_gbps, 1),
                         "step_frac": round(step_frac, 4),
                         "step_frac_of_copy": round(step_frac * HBM_PEAK_GBPS / copy_gbps, 4),
