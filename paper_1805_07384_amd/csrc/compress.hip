@@ -1378,6 +1378,42 @@ __device__ inline void exc_scan_body(const CJob &J) {
 constexpr int kCbThreads = 1024;
 
 // number of entries of sorted a[0..n) that are < w (lower bound)
+// Ascending sort of a[0..n) (distinct keys, n <= kSortSlots) in LDS by a
+// bitonic network over the next power of two, padded with all-ones keys.
+// Pair p of a stage compares slots i and i + j, i = p with a zero bit
+// inserted at j; with j <= 64 a wave's pairs stay inside its own 128 slots,
+// so those stages need only the wave's own LDS ordering, and a workgroup
+// barrier is needed only around the stages with j >= 128.
+constexpr int kSortSlots = 2048;
+__device__ inline void bitonic_sort_u64(uint64_t *a, int n) {
+  const int tid = threadIdx.x;
+  int np2 = 2;
+  while (np2 < n) np2 <<= 1;
+  for (int i = n + tid; i < np2; i += (int)blockDim.x) a[i] = ~0ull;
+  __syncthreads();
+  for (int k = 2; k <= np2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int p = tid; p < (np2 >> 1); p += (int)blockDim.x) {
+        const int i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
+        const uint64_t x = a[i], y = a[i + j];
+        const bool up = (i & k) == 0;
+        if ((x > y) == up) {
+          a[i] = y;
+          a[i + j] = x;
+        }
+      }
+      if (j >= 128 || (j == 1 && k >= 128)) {
+        __syncthreads();
+      } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
+  }
+  __syncthreads();
+}
+
 __device__ inline int count_less(const uint32_t *a, int n, uint32_t w) {
   int lo = 0, hi = n;
   while (lo < hi) { const int mid = (lo + hi) >> 1; if (a[mid] < w) lo = mid + 1; else hi = mid; }
@@ -1404,55 +1440,46 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CJob one, const CJob *_
   uint8_t *__restrict__ len_out = J.W.code_len;
   uint32_t *__restrict__ code_out = J.W.code;
   uint8_t *__restrict__ blob = J.blob;
-  __shared__ uint64_t keyu[kNSym];  // the nonzero keys, unsorted
-  __shared__ uint64_t key[kNSym];   // the same, ascending
+  __shared__ uint64_t key[kSortSlots];  // the nonzero keys; ascending after the sort
   __shared__ uint32_t Lw[kNSym];
   __shared__ uint16_t Ls[kNSym];
   __shared__ uint32_t Iw[kNSym];
   __shared__ uint16_t parL[kNSym], parI[kNSym];
-  __shared__ uint32_t tmpw[2 * kNSym];
   __shared__ uint16_t dA[kNSym], pA[kNSym], dB[kNSym], pB[kNSym];
   __shared__ uint8_t lens[kNSym];
   __shared__ uint32_t lcount[kLMax + 2], lfirst[kLMax + 2], lbase[kLMax + 2];
   __shared__ uint32_t wcnt[17 * 20];
-  __shared__ uint32_t bits[64], lstart[64];
+  __shared__ uint32_t bits[64];
   __shared__ int s_n, s_maxl;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
   if (dp->status != 0 || dp->is_const) return;
 
-  // nonzero bins (weight << 11 | symbol: distinct keys) in any order, then
-  // each key's rank = number of smaller keys (reads of one key by all
-  // threads are LDS broadcasts; no barrier inside)
+  // nonzero bins (weight << 11 | symbol: distinct keys) in any order (one
+  // slot reservation per wave), then ascending by a bitonic network
   if (tid == 0) { s_n = 0; s_maxl = 0; }
-  for (int s = tid; s < kNSym; s += kCbThreads) lens[s] = 0;
+  for (int s = tid; s < kNSym; s += kCbThreads) {
+    lens[s] = 0;
+    Iw[s] = 0;  // merged weights are summed into place
+  }
   if (tid < 64) bits[tid] = 0;
   __syncthreads();
-  for (int i = tid; i < kNSym; i += kCbThreads) {
+  for (int i0 = 0; i0 < kNSym; i0 += kCbThreads) {  // uniform trip count
+    const int i = i0 + tid;
     uint32_t c = 0;
+    if (i < kNSym) {
 #pragma unroll
-    for (int k = 0; k < kHistCopies; k++) c += hist_g[k * kNSym + i];
-    hist_g[i] = c;  // copy 0 keeps the total
-    if (c) keyu[atomicAdd(&s_n, 1)] = ((uint64_t)c << 11) | (uint64_t)i;
-  }
-  __syncthreads();
-  {
-    const int nk = s_n;
-    for (int i = tid; i < nk; i += kCbThreads) {
-      const uint64_t me = keyu[i];
-      int r = 0;
-      int j = 0;
-      for (; j + 8 <= nk; j += 8) {  // eight independent reads in flight
-        int c = 0;
-#pragma unroll
-        for (int u = 0; u < 8; u++) c += keyu[j + u] < me ? 1 : 0;
-        r += c;
-      }
-      for (; j < nk; j++) r += keyu[j] < me ? 1 : 0;
-      key[r] = me;
+      for (int k = 0; k < kHistCopies; k++) c += hist_g[k * kNSym + i];
+      hist_g[i] = c;  // copy 0 keeps the total
     }
+    const uint64_t m = __ballot(c != 0);
+    int base = 0;
+    if (lane == 0 && m) base = atomicAdd(&s_n, __popcll(m));
+    base = __shfl(base, 0, 64);
+    if (c) key[base + __popcll(m & ((1ull << lane) - 1))] = ((uint64_t)c << 11) | (uint64_t)i;
   }
   __syncthreads();
   const int n = s_n;
+  bitonic_sort_u64(key, n);
   if (n <= 1) {
     if (tid == 0 && n == 1) lens[key[0] & 2047] = 1;
     __syncthreads();
@@ -1501,27 +1528,30 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CJob one, const CJob *_
         if (tid == 0) atomicOr(&dp->spin_fail, 2u);
         break;
       }
+      // the items of merged rank 2p and 2p + 1 form node ni + p: each adds
+      // its weight there (the slots are zero until now; integer sums do not
+      // depend on the order)
       for (int k = tid; k < m; k += kCbThreads) {
         if (k < ml) {
           const uint32_t w = Lw[li + k];
           const int rank = k + count_less(Iw + ii, nI, w);
           parL[li + k] = (uint16_t)(ni + rank / 2);
-          tmpw[rank] = w;
+          atomicAdd(&Iw[ni + rank / 2], w);
         } else {
           const int i = k - ml;
           const uint32_t w = Iw[ii + i];
           const int rank = i + count_leq(Lw + li, ml, w);
           parI[ii + i] = (uint16_t)(ni + rank / 2);
-          tmpw[rank] = w;
+          atomicAdd(&Iw[ni + rank / 2], w);
         }
       }
       __syncthreads();
       const int half = m / 2;
-      for (int p = tid; p < half; p += kCbThreads) Iw[ni + p] = tmpw[2 * p] + tmpw[2 * p + 1];
-      __syncthreads();
       if (m & 1) {
+        // the odd item (rank m - 1, already in node ni + half) pairs with
+        // the lightest new node, ni
         if (tid == 0) {
-          Iw[ni + half] = tmpw[m - 1] + Iw[ni];
+          Iw[ni + half] += Iw[ni];
           parI[ni] = (uint16_t)(ni + half);
         }
         __syncthreads();
@@ -1550,11 +1580,27 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CJob one, const CJob *_
       uint16_t *t0 = dc; dc = dn; dn = t0;
       uint16_t *t1 = pc; pc = pn; pn = t1;
     }
-    for (int j = tid; j < n; j += kCbThreads) {
-      const int l = dc[parL[j]] + 1;
-      lens[Ls[j]] = (uint8_t)(l < 63 ? l : 63);
-      atomicMax(&s_maxl, l);
-      atomicAdd(&bits[l < 63 ? l : 63], 1u);
+    // lengths, their maximum and their counts (one atomic per wave and
+    // distinct length, not one per symbol on a handful of addresses)
+    for (int j0 = 0; j0 < n; j0 += kCbThreads) {  // uniform trip count
+      const int j = j0 + tid;
+      int l = 0;
+      if (j < n) {
+        l = dc[parL[j]] + 1;
+        l = l < 63 ? l : 63;
+        lens[Ls[j]] = (uint8_t)l;
+      }
+      int mx = l;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+      if (lane == 0 && mx) atomicMax(&s_maxl, mx);
+      uint64_t rem = __ballot(l != 0);
+      while (rem) {  // uniform
+        const int lv = __shfl(l, __ffsll((unsigned long long)rem) - 1, 64);
+        const uint64_t mm = __ballot(l == lv);
+        if (lane == 0) atomicAdd(&bits[lv], (uint32_t)__popcll(mm));
+        rem &= ~mm;
+      }
     }
     __syncthreads();
     if (s_maxl > kLMax) {
@@ -1629,16 +1675,23 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CJob one, const CJob *_
         if (broken && lane == 0) atomicOr(&dp->spin_fail, 4u);
       }
       __syncthreads();
-      if (tid == 0) {
-        // sorted position ranges per length, longest first
+      // lengths re-dealt along the sorted order, longest first: position j
+      // gets the longest l whose range (the counts of lengths l .. kLMax)
+      // reaches past j.  The range ends are the same for every thread.
+      uint32_t end[kLMax + 1];
+      {
         uint32_t st = 0;
-        for (int l = kLMax; l >= 1; l--) { lstart[l] = st; st += bits[l]; }
+#pragma unroll
+        for (int l = kLMax; l >= 1; l--) {
+          st += bits[l];
+          end[l] = st;
+        }
       }
-      __syncthreads();
       for (int j = tid; j < n; j += kCbThreads) {
-        int l = kLMax;
-        while (l > 1 && !(j >= (int)lstart[l] && j < (int)(lstart[l] + bits[l]))) l--;
-        lens[Ls[j]] = (uint8_t)l;
+        int k = 0;
+#pragma unroll
+        for (int l = 2; l <= kLMax; l++) k += (uint32_t)j >= end[l] ? 1 : 0;
+        lens[Ls[j]] = (uint8_t)(kLMax - k > 1 ? kLMax - k : 1);
       }
       __syncthreads();
     }

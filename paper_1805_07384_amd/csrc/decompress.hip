@@ -547,8 +547,27 @@ __global__ __launch_bounds__(kDecBlock) void k_decode(Plan P, const uint8_t *__r
     LT.lim[m] = __builtin_amdgcn_readfirstlane(lim[kLut + m]);
     LT.off[m] = __builtin_amdgcn_readfirstlane(off[kLut + m]);
   }
-  // stage the window: its words and two zero words after them
-  for (uint32_t i = lane; i < wn + 2; i += 64) mine[i] = i < wn ? gw[i] : 0u;
+  // stage the window: its words and two zero words after them.  Eight loads
+  // per lane are issued before any is waited for (clamped indexes, masked
+  // afterwards): a load per loop step with its wait took one memory round
+  // trip per 64 words.
+  {
+    const dgptr_t<uint32_t> g1 = (dgptr_t<uint32_t>)gw;
+    const uint32_t last = wn ? wn - 1u : 0u;
+    for (uint32_t i0 = 0; i0 < wn + 2; i0 += 512) {
+      uint32_t v[8];
+#pragma unroll
+      for (int k = 0; k < 8; k++) {
+        const uint32_t i = i0 + (uint32_t)lane + 64u * (uint32_t)k;
+        v[k] = wn ? g1[i < last ? i : last] : 0u;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; k++) {
+        const uint32_t i = i0 + (uint32_t)lane + 64u * (uint32_t)k;
+        if (i < wn + 2) mine[i] = i < wn ? v[k] : 0u;
+      }
+    }
+  }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
