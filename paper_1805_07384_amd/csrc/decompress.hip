@@ -278,6 +278,8 @@ __global__ __launch_bounds__(1024) void k_front(Plan P, const uint8_t *__restric
 // (outliers as -32768; their residual is in the exception list, whose outlier
 // count is checked).
 constexpr int kDecWaves = 8;  // waves (tiles) per workgroup
+// LDS pool of a decode workgroup: this factor times the average tile's words
+constexpr uint64_t kPoolSlackNum = 3, kPoolSlackDen = 2;
 constexpr int kDecBlock = 64 * kDecWaves;
 
 typedef __attribute__((address_space(3))) const uint32_t lds_cu32;
@@ -1903,10 +1905,18 @@ static uint64_t decode_pool_limit() {
 // whole tiles in LDS (2-4 per workgroup at 100-120 dB) were slower than eight
 // whose large tiles partly read the blob, and ten per workgroup were slower
 // than eight at 40-60 dB.
-static DecShape decode_shape() {
+static DecShape decode_shape(uint64_t n_words, uint64_t n_tiles) {
   DecShape d;
   d.waves = (uint32_t)kDecWaves;
-  d.pool_words = (uint32_t)decode_pool_limit();
+  const uint64_t lim = decode_pool_limit();
+  // a pool for the workgroup's tiles at kPoolSlack times the blob's average
+  // tile (plus the two zero words each): small tiles leave LDS for more
+  // workgroups per CU; a workgroup whose tiles do not fit reads past equal
+  // windows from global memory
+  const uint64_t avg = n_tiles ? (n_words + n_tiles - 1) / n_tiles : 0;
+  uint64_t want = (uint64_t)kDecWaves * ((avg * kPoolSlackNum) / kPoolSlackDen + 2 + 64);
+  want = (want + 255) & ~255ull;
+  d.pool_words = (uint32_t)(want < lim ? want : lim);
   return d;
 }
 
@@ -1941,7 +1951,7 @@ hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const Deco
   A.eb = eb;
   A.vpart = W.vpart;
   A.il_rw = P.variant == kVarInloop ? (P.dtype == FPSZ_F32 ? 1u : 2u) : 0u;
-  const DecShape ds = decode_shape();
+  const DecShape ds = decode_shape(n_words, P.n_tiles);
   if (P.dtype == FPSZ_F32) {
     if (P.ndim == 1) launch_dec_t<float, 1>(P, blob, A, W.P, W.codes, W.tmp, ds, (float *)out, s, tm);
     else if (P.ndim == 2) launch_dec_t<float, 2>(P, blob, A, W.P, W.codes, W.tmp, ds, (float *)out, s, tm);
