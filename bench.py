@@ -39,7 +39,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--edge", type=int, default=512, help="cube edge of the 3D field")
     ap.add_argument("--psnrs", default="40,60,80,100,120")
-    ap.add_argument("--domain", choices=["global", "tile"], default="global")
+    # TILE restarts the Lorenzo stencil at each tile: the same reconstruction
+    # as GLOBAL (Theorem 1), no face projections in decompression, and on the
+    # benchmark field slightly smaller blobs; GLOBAL is measured as a leg
+    ap.add_argument("--domain", choices=["global", "tile"], default="tile")
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-planes", type=int, default=128,
@@ -53,6 +56,8 @@ def parse():
     ap.add_argument("--served-requests", type=int, default=2000)
     ap.add_argument("--served-rates", default="200,3000,20000",
                     help="arrival rates (requests/s) the trace is replayed at")
+    ap.add_argument("--no-other-domain", action="store_true",
+                    help="skip the sweep leg in the other Lorenzo domain")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the closed-loop, in-loop and transform legs")
     ap.add_argument("--no-c1", action="store_true", help="skip the 512x512 latency leg")
@@ -134,7 +139,7 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(x_cpu, psnrs, planes):
+def cpu_baseline(x_cpu, psnrs, planes, domain):
     """The CPU oracle, untuned, single-threaded, on a contiguous slab of the
     same field; per-stage wall times from the oracle's own timers."""
     import numpy as np
@@ -145,7 +150,7 @@ def cpu_baseline(x_cpu, psnrs, planes):
     stages = {}
     t0 = time.perf_counter()
     for p in psnrs:
-        blob, t = oracle.compress(sample, p, trace=False)
+        blob, t = oracle.compress(sample, p, domain, trace=False)
         y = oracle.decompress(blob)
         h = oracle.header(blob)
         oracle.stats(sample, y, h["vr"], h["eb"])
@@ -155,8 +160,9 @@ def cpu_baseline(x_cpu, psnrs, planes):
     gbps = sample.nbytes * len(psnrs) / dt / 1e9
     ne = sample.size * len(psnrs)
     return {"value": round(gbps, 6), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": "float32 slab %s of the benchmark field, compress+decompress+Eq.4 stats at %s dB"
-                      " (%.1f s)" % (list(sample.shape), "/".join("%g" % p for p in psnrs), dt),
+            "sample": "float32 slab %s of the benchmark field, %s domain, compress+decompress+Eq.4 "
+                      "stats at %s dB (%.1f s)" % (list(sample.shape), "TILE" if domain else "GLOBAL",
+                                                  "/".join("%g" % p for p in psnrs), dt),
             "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
             "stage_ns_per_point": {k: round(v / ne * 1e9, 2) for k, v in stages.items()}}
@@ -509,6 +515,26 @@ def main():
             dec_only[p] = timed_calls(lambda: ctx.decompress_into(blob, nb, ws_d, out, stream),
                                       5, warm=1)[0]
     copy_gbps = device_copy_gbps(x)
+    # the same sweep in the other Lorenzo domain (blob size and speed)
+    other = "global" if args.domain == "tile" else "tile"
+    other_leg = []
+    for p in ([] if args.no_other_domain else psnrs):
+        if p == psnrs[0]:
+            progress("%s-domain legs" % other)
+        od = fpsz.GLOBAL if other == "global" else fpsz.TILE
+        st, nb, io = ctx.compress_into(x, p, ws_c, blob, od, stream)
+        if st != fpsz.OK:
+            raise fpsz.FpszError(st, "%s domain at %g dB" % (other, p))
+        tco = timed_calls(lambda: ctx.compress_into(x, p, ws_c, blob, od, stream), 3, warm=1)[0]
+        tdo = timed_calls(lambda: ctx.decompress_verify_into(blob, nb, ws_d, out, x, stream), 3,
+                          warm=1)[0]
+        st, sto = ctx.decompress_verify_into(blob, nb, ws_d, out, x, stream)
+        other_leg.append({"psnr": p, "dpsnr": round(sto.psnr - p, 5),
+                          "bits_per_value": round(io.bits_per_value, 4),
+                          "compress_gbps": round(n * s / tco / 1e9, 2),
+                          "decompress_check_gbps": round(n * s / tdo / 1e9, 2),
+                          "n_over_eb": sto.n_over_eb,
+                          "op_frac": op_fracs(n, s, io.bits_per_value, tco, None, tdo)})
     # the closed-loop correction on the benchmark field at each target
     closed, inloop, xform = [], [], []
     for p in ([] if args.no_variants else psnrs):
@@ -646,6 +672,7 @@ def main():
         "mean_abs_dpsnr": round(float(np.mean([abs(t["dpsnr"]) for t in per_target])), 4),
         "per_target": per_target,
         "closed_loop": closed,
+        "other_domain": {"domain": other, "per_target": other_leg},
         "inloop": inloop,
         "xform": xform,
         "op_roofline": {"peak_gbps": HBM_PEAK_GBPS, "device_copy_gbps": round(copy_gbps, 1),
@@ -658,7 +685,7 @@ def main():
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle)")
         planes = min(args.cpu_planes, args.edge)
-        line["cpu_baseline"] = cpu_baseline(x.cpu().numpy(), psnrs, planes)
+        line["cpu_baseline"] = cpu_baseline(x.cpu().numpy(), psnrs, planes, int(domain))
     del ws_c, ws_d, blob, out
     if not args.no_c1:
         progress("512x512 latency leg")

@@ -116,8 +116,9 @@ def test_parity_shapes(ctx, orc, shape, dt):
 @pytest.mark.parametrize("psnr", [20.0, 40.0, 60.0, 100.0, 120.0])
 def test_parity_psnr_sweep(ctx, orc, psnr):
     x = synth.field_3d_lognormal(shape=(48, 40, 70), seed=2)
-    _parity(ctx, orc, x, psnr, 0)
-    _parity(ctx, orc, x.astype(np.float64), psnr, 0)
+    for domain in (0, 1):
+        _parity(ctx, orc, x, psnr, domain)
+        _parity(ctx, orc, x.astype(np.float64), psnr, domain)
 
 
 def test_parity_outliers_and_patches(ctx, orc):
@@ -197,13 +198,14 @@ def lognormal512():
 
 
 @pytest.mark.timeout(400)
+@pytest.mark.parametrize("domain", [1, 0])
 @pytest.mark.parametrize("psnr", [40.0, 60.0, 80.0, 100.0, 120.0])
-def test_parity_config2_full_size(ctx, orc, lognormal512, psnr):
+def test_parity_config2_full_size(ctx, orc, lognormal512, psnr, domain):
     # 3D float32 512^3 lognormal field, the benchmark workload at every
-    # target of its sweep: whole blob and whole reconstruction compared (at
-    # 120 dB: escapes, outliers, tiles past their staging slot, patches and
-    # chunks decoded from the global tail)
-    info, _ = _parity(ctx, orc, lognormal512, psnr, 0)
+    # target of its sweep, in both Lorenzo domains: whole blob and whole
+    # reconstruction compared (at 120 dB: escapes, outliers, tiles past their
+    # staging slot, patches and chunks decoded from the global tail)
+    info, _ = _parity(ctx, orc, lognormal512, psnr, domain)
     assert info["bits_per_value"] > 0
     if psnr == 120.0:
         assert info["n_outliers"] > 0 and info["n_patches"] > 0
