@@ -202,6 +202,36 @@ fpsz_status fpsz_compress_static(fpsz_ctx *ctx, const void *field_dev, int ndim,
                                  fpsz_domain domain, void *blob_dev, uint64_t blob_capacity,
                                  uint64_t *blob_bytes, fpsz_info *info, void *stream);
 
+/* Outcome of fpsz_compress_async, written to device memory by the call's last
+ * kernel (48 bytes, 8-byte aligned).  status is an fpsz_status as
+ * fpsz_compress would return it for the device-side part (NONFINITE, RANGE,
+ * CAPACITY when the blob did not fit blob_capacity, DEVICE); blob_bytes is
+ * valid when status is OK (and, with CAPACITY, is the size needed). */
+typedef struct {
+  uint32_t status;
+  uint32_t is_const;
+  uint64_t blob_bytes;
+  uint64_t n_outliers;
+  uint64_t n_patches;
+  double vr;
+  double eb;
+} fpsz_async_result;
+
+/* fpsz_compress (Sec. IV workflow after Eq. 7: range, bound, prediction,
+ * quantization, Huffman coding) without any synchronization or host read:
+ * every step is enqueued on `stream` and the outcome is written to
+ * result_dev (device memory, one fpsz_async_result).  The call allocates
+ * nothing and makes no memset or copy, so a stream capture of it replays as
+ * a graph.  Arguments as fpsz_compress.  The return value covers only what
+ * the host checks before enqueueing (INVALID_ARG, CAPACITY for a small
+ * workspace); blob and result are defined once the stream reaches the end of
+ * the call.  No stage times are recorded. */
+fpsz_status fpsz_compress_async(fpsz_ctx *ctx, const void *field_dev, int ndim,
+                                const uint64_t *dims, fpsz_dtype dtype, double target_psnr,
+                                fpsz_domain domain, void *workspace_dev, uint64_t workspace_bytes,
+                                void *blob_dev, uint64_t blob_capacity,
+                                fpsz_async_result *result_dev, void *stream);
+
 /* Parse a blob header held in HOST memory (the first 256 bytes suffice).
  * dims receives 3 entries (unused ones = 1).  CORRUPT on a bad magic or
  * version, INVALID_ARG on NULL pointers or bytes < 256. */

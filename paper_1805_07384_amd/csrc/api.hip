@@ -215,6 +215,31 @@ static fpsz_status compress_one(fpsz_ctx *ctx, const void *field_dev, int ndim,
   return compress_result(ctx, job.P, D, blob_bytes);
 }
 
+fpsz_status fpsz_compress_async(fpsz_ctx *ctx, const void *field_dev, int ndim,
+                                const uint64_t *dims, fpsz_dtype dtype, double target_psnr,
+                                fpsz_domain domain, void *workspace_dev, uint64_t workspace_bytes,
+                                void *blob_dev, uint64_t blob_capacity,
+                                fpsz_async_result *result_dev, void *stream) {
+  if (!ctx) return FPSZ_E_INVALID_ARG;
+  ctx->err[0] = 0;
+  if (!result_dev || (uintptr_t)result_dev % 8)
+    return fail(ctx, FPSZ_E_INVALID_ARG, "result must be a non-null 8-aligned device pointer");
+  CJob job;
+  uint64_t nb = 0;
+  fpsz_status st = prepare_compress(ctx, field_dev, ndim, dims, dtype, target_psnr, domain,
+                                    workspace_dev, workspace_bytes, blob_dev, blob_capacity, &nb,
+                                    &job);
+  if (st != FPSZ_OK) return st;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, FPSZ_E_DEVICE, "hipSetDevice failed");
+  hipStream_t s = (hipStream_t)stream;
+  Timer off;  // no events: nothing to collect without a synchronization
+  hipError_t e = launch_compress_jobs(job, nullptr, 1, job.P, default_launch_cfg(job.P), s, &off);
+  if (e == hipSuccess) e = launch_async_result(job, result_dev, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "compress launch");
+  return FPSZ_OK;
+}
+
 fpsz_status fpsz_compress(fpsz_ctx *ctx, const void *field_dev, int ndim, const uint64_t *dims,
                           fpsz_dtype dtype, double target_psnr, fpsz_domain domain,
                           void *workspace_dev, uint64_t workspace_bytes, void *blob_dev,

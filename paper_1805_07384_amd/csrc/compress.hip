@@ -2187,6 +2187,30 @@ static void launch_compress_t(const CJob &one, const CJob *jobs, int nf, const P
   tm->mark(s, "checksum");
 }
 
+// fpsz_compress_async's outcome from the field's parameter block, with the
+// status rules of the synchronous call
+__global__ void k_async_result(CJob one, fpsz_async_result *out) {
+  if (threadIdx.x != 0) return;
+  const DevParams *dp = one.W.P;
+  uint32_t st = dp->status;
+  if (st == 0 && dp->spin_fail) st = FPSZ_E_DEVICE;
+  if (st == 0 && (dp->overflow || dp->blob_bytes > one.P.capacity)) st = FPSZ_E_CAPACITY;
+  fpsz_async_result r;
+  r.status = st;
+  r.is_const = dp->is_const;
+  r.blob_bytes = dp->blob_bytes;
+  r.n_outliers = dp->n_out;
+  r.n_patches = dp->n_pat;
+  r.vr = dp->vr;
+  r.eb = dp->eb;
+  *out = r;
+}
+
+hipError_t launch_async_result(const CJob &one, fpsz_async_result *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_async_result, dim3(1), dim3(64), 0, s, one, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_compress_jobs(const CJob &one, const CJob *jobs_dev, int nf, const Plan &maxP,
                                 const LaunchCfg &cfg, hipStream_t s, Timer *tm) {
   if (nf < 1 || nf > 65535 || (nf > 1 && !jobs_dev)) return hipErrorInvalidValue;

@@ -408,6 +408,8 @@ hipError_t launch_compress_jobs(const CJob &one, const CJob *jobs_dev, int nf, c
                                 const LaunchCfg &cfg, hipStream_t s, Timer *tm);
 
 hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t s);
+// the outcome of a compression into a device-side fpsz_async_result
+hipError_t launch_async_result(const CJob &one, fpsz_async_result *out, hipStream_t s);
 hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const DecompressWs &W,
                                   uint64_t off_words, uint64_t n_words, uint64_t n_exc, double e2,
                                   float e2_f, void *out, const void *ref, double eb, hipStream_t s,

@@ -29,6 +29,22 @@ class FpszError(RuntimeError):
         self.status = status
 
 
+class AsyncResult(ctypes.Structure):
+    """fpsz_async_result: the device-side outcome of fpsz_compress_async."""
+    _fields_ = [("status", ctypes.c_uint32), ("is_const", ctypes.c_uint32),
+                ("blob_bytes", ctypes.c_uint64), ("n_outliers", ctypes.c_uint64),
+                ("n_patches", ctypes.c_uint64), ("vr", ctypes.c_double), ("eb", ctypes.c_double)]
+
+
+ASYNC_RESULT_BYTES = ctypes.sizeof(AsyncResult)
+
+
+def async_result(result: torch.Tensor) -> AsyncResult:
+    """Copy a device-side fpsz_async_result to the host (synchronizes)."""
+    raw = bytes(result[:ASYNC_RESULT_BYTES].cpu().numpy().tobytes())
+    return AsyncResult.from_buffer_copy(raw)
+
+
 class Info(ctypes.Structure):
     _fields_ = [
         ("target_psnr", ctypes.c_double), ("eb_rel", ctypes.c_double), ("vr", ctypes.c_double),
@@ -125,6 +141,9 @@ SIGNATURES = {
     "fpsz_compress_static": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _u64p, ctypes.c_int,
                                             ctypes.c_double, ctypes.c_int, _vp, ctypes.c_uint64,
                                             _u64p, ctypes.POINTER(Info), _vp]),
+    "fpsz_compress_async": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _u64p, ctypes.c_int,
+                                           ctypes.c_double, ctypes.c_int, _vp, ctypes.c_uint64,
+                                           _vp, ctypes.c_uint64, _vp, _vp]),
     "fpsz_blob_header": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), _u64p,
                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(Info)]),
     "fpsz_decompress": (ctypes.c_int, [_vp, _vp, ctypes.c_uint64, _vp, ctypes.c_uint64, _vp,
@@ -387,6 +406,22 @@ class Context:
                                            blob.data_ptr(), blob.numel(), ctypes.byref(nb),
                                            ctypes.byref(info), _stream(stream))
         return st, nb.value, info
+
+    def compress_async_into(self, x: torch.Tensor, psnr: float, workspace: torch.Tensor,
+                            blob: torch.Tensor, result: torch.Tensor, domain: int = GLOBAL,
+                            stream=None) -> int:
+        """fpsz_compress_async: enqueue the compression of x into ``blob``;
+        the outcome goes to ``result`` (a device uint8 tensor of
+        ASYNC_RESULT_BYTES, read it with async_result()).  Returns the host
+        status only; nothing is synchronized."""
+        assert x.is_contiguous() and x.is_cuda
+        assert result.is_cuda and result.numel() * result.element_size() >= ASYNC_RESULT_BYTES
+        return self.lib.fpsz_compress_async(self.handle, x.data_ptr(), x.dim(), _dims(x.shape),
+                                            _dtype_code(x), float(psnr), int(domain),
+                                            workspace.data_ptr(),
+                                            workspace.numel() * workspace.element_size(),
+                                            blob.data_ptr(), blob.numel(), result.data_ptr(),
+                                            _stream(stream))
 
     def decompress_into(self, blob: torch.Tensor, nbytes: int, workspace: torch.Tensor,
                         out: torch.Tensor, stream=None) -> int:
