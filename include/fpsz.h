@@ -351,6 +351,17 @@ fpsz_status fpsz_batch_autotune(fpsz_batch *b, void *stream, int reps, double *b
  * blocks} per field. */
 fpsz_status fpsz_batch_launch_shape(const fpsz_batch *b, int cls, uint32_t *shape4);
 
+/* Number of field groups of the batch (the cls range of the shape calls). */
+fpsz_status fpsz_batch_class_count(const fpsz_batch *b, int *count);
+
+/* Set the launch shape of field group `cls` (shape4 as above), e.g. one that
+ * fpsz_batch_autotune found for the same fields earlier and a cache kept:
+ * every entry must lie in 1..the bound that fpsz_batch_autotune uses (the
+ * group's tile count for the two grids, 1024 for the range and checksum
+ * blocks), else INVALID_ARG and nothing changes.  Re-captures the graph.
+ * Shapes do not change any output bit. */
+fpsz_status fpsz_batch_set_launch_shape(fpsz_batch *b, int cls, const uint32_t *shape4);
+
 void fpsz_batch_destroy(fpsz_batch *b);
 
 /* One-shot convenience: create (no graph), run, destroy. */

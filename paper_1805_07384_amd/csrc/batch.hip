@@ -358,6 +358,33 @@ fpsz_status fpsz_batch_launch_shape(const fpsz_batch *b, int cls, uint32_t *shap
   return FPSZ_OK;
 }
 
+fpsz_status fpsz_batch_class_count(const fpsz_batch *b, int *count) {
+  if (!b || !count) return FPSZ_E_INVALID_ARG;
+  *count = (int)b->classes.size();
+  return FPSZ_OK;
+}
+
+fpsz_status fpsz_batch_set_launch_shape(fpsz_batch *b, int cls, const uint32_t *shape4) {
+  if (!b || !shape4 || cls < 0 || cls >= (int)b->classes.size()) return FPSZ_E_INVALID_ARG;
+  fpsz_ctx *ctx = b->ctx;
+  ctx->err[0] = 0;
+  BatchClass &c = b->classes[cls];
+  const uint64_t lim[4] = {(uint64_t)kRangeBlocks, c.maxP.n_tiles, c.maxP.n_tiles, 1024};
+  for (int k = 0; k < 4; k++)
+    if (shape4[k] < 1 || shape4[k] > lim[k])
+      return fail(ctx, FPSZ_E_INVALID_ARG, "shape entry %d = %u outside 1..%llu", k,
+                  (unsigned)shape4[k], (unsigned long long)lim[k]);
+  c.cfg.range_blocks = shape4[0];
+  c.cfg.quant_grid = shape4[1];
+  c.cfg.encode_grid = shape4[2];
+  c.cfg.csum_blocks = shape4[3];
+  if (b->use_graph) {
+    DeviceGuard g(ctx->device);
+    return capture(b);
+  }
+  return FPSZ_OK;
+}
+
 fpsz_status fpsz_compress_batch(fpsz_ctx *ctx, int n, const fpsz_field_desc *fields,
                                 void *workspace_dev, uint64_t workspace_bytes,
                                 uint64_t *blob_bytes, fpsz_info *info, fpsz_status *status,

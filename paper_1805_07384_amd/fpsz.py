@@ -164,6 +164,9 @@ SIGNATURES = {
                                       ctypes.POINTER(ctypes.c_int)]),
     "fpsz_batch_autotune": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
     "fpsz_batch_launch_shape": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint32)]),
+    "fpsz_batch_class_count": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
+    "fpsz_batch_set_launch_shape": (ctypes.c_int, [_vp, ctypes.c_int,
+                                                   ctypes.POINTER(ctypes.c_uint32)]),
     "fpsz_batch_destroy": (None, [_vp]),
     "fpsz_compress_batch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(FieldDesc), _vp,
                                            ctypes.c_uint64, _u64p, ctypes.POINTER(Info),
@@ -518,6 +521,67 @@ def field_descs(fields, psnrs, blobs, domains=None):
     return arr
 
 
+# -- persistent autotune cache (JSON) ------------------------------------------
+# {"version": 1, "entries": {key: {"shapes": [[range, quant, encode, checksum]
+# per field group], "best_ms": t, "fields": n}}}.  The key covers what the
+# launch shapes depend on: the device, the library build and every field's
+# (dtype, ndim, dims, domain) as a multiset; targets do not enter (shapes are
+# bit-neutral and the timing barely depends on them).
+
+def _device_name(device) -> str:
+    try:
+        p = torch.cuda.get_device_properties(device)
+        return "%s/%s/%d" % (p.name, getattr(p, "gcnArchName", ""), p.multi_processor_count)
+    except Exception:  # noqa: BLE001 - a name is only part of a cache key
+        return "unknown"
+
+
+def autotune_key(descs, device_name: str) -> str:
+    import hashlib
+    import json
+    fields = sorted((int(d.dtype), int(d.ndim), [int(v) for v in d.dims], int(d.domain))
+                    for d in descs)
+    ver = load_library().fpsz_version().decode()
+    blob = json.dumps({"device": device_name, "version": ver, "fields": fields},
+                      sort_keys=True)
+    return hashlib.sha256(blob.encode()).hexdigest()
+
+
+def load_autotune_cache(path: str) -> dict:
+    """Entries of a cache file; {} for a missing, unreadable or foreign file."""
+    import json
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return {}
+    if not isinstance(d, dict) or d.get("version") != 1 or not isinstance(d.get("entries"), dict):
+        return {}
+    out = {}
+    for k, v in d["entries"].items():
+        ok = (isinstance(v, dict) and isinstance(v.get("shapes"), list)
+              and all(isinstance(s, list) and len(s) == 4 and all(isinstance(x, int) and x > 0
+                                                                 for x in s)
+                      for s in v["shapes"]) and isinstance(v.get("best_ms"), (int, float)))
+        if ok:
+            out[k] = v
+    return out
+
+
+def store_autotune_cache(path: str, key: str, shapes, best_ms: float):
+    """Add (or replace) one entry; the file is replaced atomically."""
+    import json
+    import tempfile
+    entries = load_autotune_cache(path)
+    entries[key] = {"shapes": [[int(x) for x in s] for s in shapes], "best_ms": float(best_ms)}
+    d = os.path.dirname(os.path.abspath(path))
+    os.makedirs(d, exist_ok=True)
+    fd, tmp = tempfile.mkstemp(prefix=".fpsz_autotune.", dir=d)
+    with os.fdopen(fd, "w") as fh:
+        json.dump({"version": 1, "entries": entries}, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
 def batch_workspace_bytes(descs) -> int:
     out = ctypes.c_uint64()
     st = load_library().fpsz_batch_workspace_bytes(len(descs), descs, ctypes.byref(out))
@@ -558,12 +622,45 @@ class Batch:
             raise self.ctx._err(st, "fpsz_batch_run")
         return st, list(nb), [i.as_dict() for i in info], list(sts)
 
-    def autotune(self, reps: int = 3, stream=None) -> float:
+    def autotune(self, reps: int = 3, stream=None, cache: str | None = None) -> float:
+        """Time launch shapes and keep the fastest (fpsz_batch_autotune).  With
+        a cache file (``cache``, else $FPSZ_AUTOTUNE_CACHE when set), shapes
+        found earlier for the same fields on the same device are applied
+        without timing, and new ones are added to the file.  Sets
+        ``self.autotune_source`` to "cache" or "timed"; returns the best batch
+        time in ms (the one recorded with the shapes on a cache hit)."""
+        if cache is None:
+            cache = os.environ.get("FPSZ_AUTOTUNE_CACHE") or None
+        key = autotune_key(self.descs, _device_name(self.fields[0].device)) if cache else None
+        if key is not None:
+            hit = load_autotune_cache(cache).get(key)
+            if hit is not None and len(hit["shapes"]) == self.class_count():
+                for c, sh in enumerate(hit["shapes"]):
+                    self.set_launch_shape(c, sh)
+                self.autotune_source = "cache"
+                return float(hit["best_ms"])
         best = ctypes.c_double()
         st = self.lib.fpsz_batch_autotune(self.handle, _stream(stream), int(reps), ctypes.byref(best))
         if st != OK:
             raise self.ctx._err(st, "fpsz_batch_autotune")
+        self.autotune_source = "timed"
+        if key is not None:
+            store_autotune_cache(cache, key, [self.launch_shape(c) for c in range(self.class_count())],
+                                 best.value)
         return best.value
+
+    def class_count(self) -> int:
+        n = ctypes.c_int()
+        st = self.lib.fpsz_batch_class_count(self.handle, ctypes.byref(n))
+        if st != OK:
+            raise FpszError(st, "class count")
+        return n.value
+
+    def set_launch_shape(self, cls: int, shape4):
+        arr = (ctypes.c_uint32 * 4)(*[int(v) for v in shape4])
+        st = self.lib.fpsz_batch_set_launch_shape(self.handle, int(cls), arr)
+        if st != OK:
+            raise self.ctx._err(st, "fpsz_batch_set_launch_shape")
 
     def launch_shape(self, cls: int = 0):
         out = (ctypes.c_uint32 * 4)()

@@ -113,6 +113,36 @@ def test_batch_autotune_is_bit_neutral(ctx):
     b.close()
 
 
+def test_batch_autotune_cache(ctx, tmp_path):
+    # shapes timed once are stored in a JSON cache; a new batch of the same
+    # fields (other targets) on the same device takes them without timing,
+    # and its blobs equal the plain calls'
+    from paper_1805_07384_amd import fpsz
+    print("case autotune cache", flush=True)
+    path = str(tmp_path / "tune.json")
+    items = _mixed_fields()
+    b, xs, blobs = _make_batch(ctx, items, True)
+    b.autotune(reps=1, cache=path)
+    assert b.autotune_source == "timed"
+    shapes = [b.launch_shape(c) for c in range(b.class_count())]
+    b.close()
+    entries = fpsz.load_autotune_cache(path)
+    assert len(entries) == 1 and list(entries.values())[0]["shapes"] == shapes
+    items2 = [(x, min(p + 7.0, 120.0), d) for x, p, d in items]
+    b2, xs2, blobs2 = _make_batch(ctx, items2, True)
+    b2.autotune(reps=1, cache=path)
+    assert b2.autotune_source == "cache"
+    assert [b2.launch_shape(c) for c in range(b2.class_count())] == shapes
+    st, nb, _, sts = b2.run()
+    assert st == 0
+    for i, (x, p, d) in enumerate(items2):
+        pb, _ = _plain(ctx, xs2[i], p, d)
+        assert blobs2[i][:nb[i]].cpu().numpy().tobytes() == pb, "field %d" % i
+    with pytest.raises(fpsz.FpszError):
+        b2.set_launch_shape(0, [0, 1, 1, 1])
+    b2.close()
+
+
 def test_batch_per_field_status(ctx):
     from paper_1805_07384_amd import fpsz
     print("case batch statuses", flush=True)
