@@ -306,9 +306,25 @@ __device__ inline void load_row(const T *__restrict__ x, const Plan &P, const Ti
 #pragma unroll
       for (int h = 0; h < VW; h++) v[k * VW + h] = pa[h];
     }
+  } else if (load_row_pts && nx_seg > 0) {
+    // Inside the field buffer the segment is read whole (points past the
+    // tile's edge are the next row's, masked below): 32 loads from one
+    // address, issued before any is waited for.  Written as
+    // j < nx_seg ? x[..] : 0 each load got its own branch and wait, which is
+    // left to the segments that end the buffer.
+    const T *src = x + rowbase + x0l;
+    if (rowbase + x0l + 32 <= P.n) {
+#pragma unroll
+      for (int j = 0; j < 32; j++) v[j] = src[j];
+#pragma unroll
+      for (int j = 0; j < 32; j++) v[j] = j < nx_seg ? v[j] : (T)0;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 32; j++) v[j] = j < nx_seg ? src[j] : (T)0;
+    }
   } else {
 #pragma unroll
-    for (int j = 0; j < 32; j++) v[j] = (load_row_pts && j < nx_seg) ? x[rowbase + x0l + j] : (T)0;
+    for (int j = 0; j < 32; j++) v[j] = (T)0;
   }
   uint32_t pbits = 0;
 #pragma unroll
@@ -603,38 +619,30 @@ __device__ inline uint32_t symbol_of(int32_t dv, bool &outlier) {
   return a <= 511 ? (uint32_t)(dv + 512) : (outlier ? 0u : esc);
 }
 
-// XCD-aware tile order for persistent grids whose size is a multiple of 8:
-// workgroups are dispatched round-robin over the 8 XCDs (each with its own
-// L2), so block b runs on XCD b % 8.  Tiles are grouped in units (3D: a
-// layer of the tile grid, 2D: a row of tiles, 1D: 16 consecutive tiles) and
-// unit u goes to XCD u % 8: a tile and its x / y neighbours (whose halo it
-// reads) are handled on the same XCD at about the same time.
-// With 16 or more tile rows along y (2D and 3D), XCD x instead owns a band
-// of tile rows b in [x gy / 8, (x + 1) gy / 8) and walks it z-major, then
-// row, then x: the tile before along z (one band-layer earlier), along y
-// (one row earlier) and along x (just before) were all loaded by the same
-// XCD shortly before, so the halo the tile reads is still in that XCD's L2.
-__device__ inline bool xcd_tile(const Plan &P, int ndim, uint64_t k, uint64_t *t) {
-  if ((gridDim.x & 7) != 0) {
+// Tile order of the persistent quantization grids.  Workgroups are
+// dispatched round-robin over the 8 XCDs (each with its own L2), so block b
+// runs on XCD b % 8.  With halos to read (GLOBAL domain) and a tile-row count
+// along y that splits evenly over the XCDs (16 or more rows, a multiple of
+// 8), XCD x owns the band of tile rows b in [x gy / 8, (x + 1) gy / 8) and
+// walks it z-major, then row, then x: the tile before along z (one
+// band-layer earlier), along y (one row earlier) and along x (just before)
+// were all loaded by the same XCD shortly before, so the halo the tile
+// reads is still in that XCD's L2.  Otherwise tiles go round-robin over the
+// workgroups (bands of unequal size would leave XCDs idle: 29 tile rows give
+// bands of 3 and 4).
+__device__ inline bool xcd_tile(const Plan &P, int ndim, uint64_t k, uint64_t *t, bool halo) {
+  if (!halo || (gridDim.x & 7) != 0 || ndim < 2 || P.gy < 16 || (P.gy & 7) != 0) {
     *t = blockIdx.x + k * gridDim.x;
     return *t < P.n_tiles;
   }
-  if (ndim >= 2 && P.gy >= 16) {
-    const uint32_t x = blockIdx.x & 7;
-    const uint64_t b0 = (uint64_t)x * P.gy / 8, b1 = (uint64_t)(x + 1) * P.gy / 8;
-    const uint64_t row = (b1 - b0) * P.gx;  // tiles of one band-layer
-    const uint64_t L = (blockIdx.x >> 3) + k * (gridDim.x >> 3);
-    const uint64_t a = L / row, rem = L - a * row;
-    if (a >= P.gz) return false;
-    *t = (a * P.gy + b0 + rem / P.gx) * P.gx + rem % P.gx;
-    return true;
-  }
-  const uint64_t U = ndim == 3 ? (uint64_t)P.gy * P.gx : ndim == 2 ? (uint64_t)P.gx : 16;
-  const uint64_t per = gridDim.x >> 3;
-  const uint64_t L = (blockIdx.x >> 3) + k * per;
-  const uint64_t u = (blockIdx.x & 7) + 8 * (L / U);
-  *t = u * U + L % U;
-  return *t < P.n_tiles;
+  const uint32_t x = blockIdx.x & 7;
+  const uint64_t b0 = (uint64_t)x * P.gy / 8, b1 = (uint64_t)(x + 1) * P.gy / 8;
+  const uint64_t row = (b1 - b0) * P.gx;  // tiles of one band-layer
+  const uint64_t L = (blockIdx.x >> 3) + k * (gridDim.x >> 3);
+  const uint64_t a = L / row, rem = L - a * row;
+  if (a >= P.gz) return false;
+  *t = (a * P.gy + b0 + rem / P.gx) * P.gx + rem % P.gx;
+  return true;
 }
 
 template <typename T, int NDIM, bool GLOBAL, bool RECORDS, bool FULL>
@@ -674,7 +682,15 @@ __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restri
   uint64_t my_out = 0, my_pat = 0;
 
   uint64_t t;
-  for (uint64_t it_k = 0; xcd_tile(P, NDIM, it_k, &t); it_k++) {
+  // full tiles in the XCD-aware order; clipped tiles (the last tile row,
+  // column or layer) round-robin over the workgroups, since the band order
+  // would give a whole clipped tile row to one XCD
+  auto next_tile = [&](uint64_t k, uint64_t *tt) -> bool {
+    if (FULL) return xcd_tile(P, NDIM, k, tt, GLOBAL);
+    *tt = blockIdx.x + k * gridDim.x;
+    return *tt < P.n_tiles;
+  };
+  for (uint64_t it_k = 0; next_tile(it_k, &t); it_k++) {
     if (RECORDS && exc_cnt[t] <= (uint32_t)kStage) continue;  // uniform
     const TileGeo g = tile_geo(P, t);
     const int ez = (int)g.ez, ey = (int)g.ey, ex = (int)g.ex, nt = (int)g.nt;
@@ -1002,7 +1018,7 @@ __global__ __launch_bounds__(kBlock) void k_quant_il(CJob one, const CJob *__res
     for (int s = tid; s < kNSym; s += kBlock) hist[s] = 0;
   uint64_t my_pat = 0;
   uint64_t t;
-  for (uint64_t it_k = 0; xcd_tile(P, NDIM, it_k, &t); it_k++) {
+  for (uint64_t it_k = 0; xcd_tile(P, NDIM, it_k, &t, false); it_k++) {
     if (RECORDS && J.W.exc_cnt[t] <= (uint32_t)kStage) continue;  // uniform
     const TileGeo g = tile_geo(P, t);
     const int ez = (int)g.ez, ey = (int)g.ey, ex = (int)g.ex, nt = (int)g.nt;
@@ -1162,7 +1178,7 @@ __global__ __launch_bounds__(kBlock) void k_quant_xf(CJob one, const CJob *__res
     for (int s = tid; s < kNSym; s += kBlock) hist[s] = 0;
   uint64_t my_out = 0;
   uint64_t t;
-  for (uint64_t it_k = 0; xcd_tile(P, NDIM, it_k, &t); it_k++) {
+  for (uint64_t it_k = 0; xcd_tile(P, NDIM, it_k, &t, false); it_k++) {
     if (RECORDS && J.W.exc_cnt[t] <= (uint32_t)kStage) continue;  // uniform
     const TileGeo g = tile_geo(P, t);
     const int nbx = (int)g.ex / 4, nby = (int)g.ey / X::BY, nbz = (int)g.ez / X::BZ;
