@@ -238,6 +238,34 @@ fpsz_status fpsz_compress_async(fpsz_ctx *ctx, const void *field_dev, int ndim,
 fpsz_status fpsz_blob_header(const void *blob_host, uint64_t bytes, int *ndim, uint64_t *dims,
                              fpsz_dtype *dtype, fpsz_info *info);
 
+/* Outcome of fpsz_decompress_async, written to device memory by the call's
+ * last kernel (48 bytes, 8-byte aligned).  status: OK or CORRUPT.  checked:
+ * 1 when an original was given, and then stats holds Eq. 4 against it (the
+ * PSNR with the blob's value range). */
+typedef struct {
+  uint32_t status;
+  uint32_t checked;
+  fpsz_stats stats;
+} fpsz_decompress_result;
+
+/* fpsz_decompress / fpsz_decompress_verify (Sec. III reconstruction, Eq. 4
+ * check) without any synchronization or host read: the blob's header comes
+ * from the caller in HOST memory (header_host, its first 256 bytes, e.g.
+ * kept when the blob was stored), so the call needs no device-to-host copy
+ * of it; the device checks that the blob in device memory carries the same
+ * header (else CORRUPT) besides its checksum.  orig_dev may be NULL (no
+ * check).  The outcome goes to result_dev (device memory).  The call
+ * allocates nothing and makes no memset or copy, so a stream capture of it
+ * replays as a graph (for the same blob header).  Other arguments as
+ * fpsz_decompress_verify.  The return value covers only what the host
+ * checks before enqueueing (INVALID_ARG, CORRUPT for a malformed host
+ * header, CAPACITY for a small workspace or output). */
+fpsz_status fpsz_decompress_async(fpsz_ctx *ctx, const void *blob_dev, uint64_t blob_bytes,
+                                  const void *header_host, void *workspace_dev,
+                                  uint64_t workspace_bytes, void *field_out_dev,
+                                  uint64_t out_bytes, const void *orig_dev,
+                                  fpsz_decompress_result *result_dev, void *stream);
+
 /* Decompress a blob produced by fpsz_compress (Sec. III: decode, repeat the
  * prediction by inclusive prefix sums, reconstruct bin midpoints q * 2 eb).
  *   blob_dev       device, blob_bytes long; read only

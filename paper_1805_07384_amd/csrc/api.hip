@@ -373,6 +373,47 @@ fpsz_status fpsz_decompress(fpsz_ctx *ctx, const void *blob_dev, uint64_t blob_b
   return decompress_result(ctx, J, *ctx->host);
 }
 
+fpsz_status fpsz_decompress_async(fpsz_ctx *ctx, const void *blob_dev, uint64_t blob_bytes,
+                                  const void *header_host, void *workspace_dev,
+                                  uint64_t workspace_bytes, void *field_out_dev,
+                                  uint64_t out_bytes, const void *orig_dev,
+                                  fpsz_decompress_result *result_dev, void *stream) {
+  if (!ctx) return FPSZ_E_INVALID_ARG;
+  ctx->err[0] = 0;
+  if (!blob_dev || !header_host || !workspace_dev || !field_out_dev || !result_dev)
+    return fail(ctx, FPSZ_E_INVALID_ARG, "null pointer argument");
+  if ((uintptr_t)result_dev % 8) return fail(ctx, FPSZ_E_INVALID_ARG, "result must be 8-aligned");
+  if (blob_bytes < kHdr || blob_bytes % 8)
+    return fail(ctx, FPSZ_E_CORRUPT, "blob size %llu", (unsigned long long)blob_bytes);
+  if ((uintptr_t)blob_dev % 8) return fail(ctx, FPSZ_E_INVALID_ARG, "blob must be 8-aligned");
+  HdrBytes hb;
+  memcpy(hb.w, header_host, kHdr);
+  DJob J;
+  fpsz_status st = prepare_decompress(ctx, reinterpret_cast<const uint8_t *>(hb.w), blob_dev,
+                                      blob_bytes, workspace_dev, workspace_bytes, field_out_dev,
+                                      out_bytes, &J);
+  if (st != FPSZ_OK) return st;
+  if (orig_dev) {
+    if (!J.W.vpart)
+      return fail(ctx, FPSZ_E_CAPACITY, "workspace needs %llu bytes",
+                  (unsigned long long)decompress_layout(J.P).total);
+    const size_t esz = J.P.dtype == FPSZ_F32 ? 4 : 8;
+    if ((uintptr_t)orig_dev % esz)
+      return fail(ctx, FPSZ_E_INVALID_ARG, "original not element-aligned");
+    J.ref = orig_dev;
+  }
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, FPSZ_E_DEVICE, "hipSetDevice failed");
+  hipStream_t s = (hipStream_t)stream;
+  Timer off;  // no events: nothing to collect without a synchronization
+  hipError_t e = launch_decompress_job(J, s, &off, &hb);
+  if (e == hipSuccess)
+    e = launch_dasync_result(J.W.P, result_dev, J.is_const ? 1 : 0, J.csum, orig_dev ? 1 : 0,
+                             J.P.n, J.vr, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "decompress launch");
+  return FPSZ_OK;
+}
+
 fpsz_status fpsz_decompress_verify(fpsz_ctx *ctx, const void *blob_dev, uint64_t blob_bytes,
                                    void *workspace_dev, uint64_t workspace_bytes,
                                    void *field_out_dev, uint64_t out_bytes, const void *orig_dev,

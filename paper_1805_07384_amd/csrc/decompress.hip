@@ -1923,9 +1923,10 @@ static DecShape decode_shape(uint64_t n_words, uint64_t n_tiles) {
 hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const DecompressWs &W,
                                   uint64_t off_words, uint64_t n_words, uint64_t n_exc, double e2,
                                   float e2_f, void *out, const void *ref, double eb, hipStream_t s,
-                                  Timer *tm) {
+                                  Timer *tm, const HdrBytes *hdr) {
   tm->mark(s, "begin");
   hipError_t e = launch_fill_zero(W.P, W.zero_bytes, s);
+  if (e == hipSuccess && hdr) e = launch_hdr_check(blob, *hdr, W.P, s);
   if (e != hipSuccess) return e;
   const uint32_t cblk = (checksum_grid(P.capacity) * kBlock + 1023) / 1024;
   hipLaunchKernelGGL(k_front, dim3(1 + cblk), dim3(1024), 0, s, P, blob, P.capacity, W.P, W.lut,
@@ -1961,6 +1962,49 @@ hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const Deco
     else if (P.ndim == 2) launch_dec_t<double, 2>(P, blob, A, W.P, W.codes, W.tmp, ds, (double *)out, s, tm);
     else launch_dec_t<double, 3>(P, blob, A, W.P, W.codes, W.tmp, ds, (double *)out, s, tm);
   }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// fpsz_decompress_async: the blob in device memory must carry the header the
+// host planned from (checked before any other kernel reads the blob)
+__global__ void k_hdr_check(const uint8_t *__restrict__ blob, HdrBytes h,
+                            DevParams *__restrict__ dp) {
+  const int i = threadIdx.x;  // 64 threads, one header word each
+  const uint32_t w = reinterpret_cast<const uint32_t *>(blob)[i];
+  if (__builtin_amdgcn_ballot_w64(w != h.w[i]) && i == 0) atomicOr(&dp->corrupt, 1u);
+}
+
+hipError_t launch_hdr_check(const uint8_t *blob, const HdrBytes &h, DevParams *dp, hipStream_t s) {
+  hipLaunchKernelGGL(k_hdr_check, dim3(1), dim3(64), 0, s, blob, h, dp);
+  return hipGetLastError();
+}
+
+// the outcome with the status rules and the Eq. 4 statistics of the
+// synchronous calls (PSNR = -20 log10(sqrt(MSE) / vr))
+__global__ void k_dasync_result(DevParams *__restrict__ dp, fpsz_decompress_result *out,
+                                int is_const, uint64_t csum, int checked, uint64_t n, double vr) {
+  if (threadIdx.x != 0) return;
+  fpsz_decompress_result r;
+  const bool bad = dp->corrupt || (is_const && dp->checksum != csum);
+  r.status = bad ? FPSZ_E_CORRUPT : FPSZ_OK;
+  r.checked = checked && !bad ? 1u : 0u;
+  r.stats.sse = r.stats.mse = r.stats.psnr = r.stats.max_abs_err = 0.0;
+  r.stats.n_over_eb = 0;
+  if (r.checked) {
+    r.stats.sse = dp->v_sse;
+    r.stats.mse = dp->v_sse / (double)n;
+    r.stats.psnr = -20.0 * log10(sqrt(r.stats.mse) / vr);
+    r.stats.max_abs_err = dp->v_max;
+    r.stats.n_over_eb = dp->v_over;
+  }
+  *out = r;
+}
+
+hipError_t launch_dasync_result(DevParams *dp, fpsz_decompress_result *out, int is_const,
+                                uint64_t csum, int checked, uint64_t n, double vr, hipStream_t s) {
+  hipLaunchKernelGGL(k_dasync_result, dim3(1), dim3(64), 0, s, dp, out, is_const, csum, checked, n,
+                     vr);
   return hipGetLastError();
 }
 

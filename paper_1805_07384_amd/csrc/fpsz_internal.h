@@ -408,12 +408,20 @@ hipError_t launch_compress_jobs(const CJob &one, const CJob *jobs_dev, int nf, c
                                 const LaunchCfg &cfg, hipStream_t s, Timer *tm);
 
 hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t s);
+// a blob header expected in device memory (the caller's host copy)
+struct HdrBytes {
+  uint32_t w[64];
+};
+hipError_t launch_hdr_check(const uint8_t *blob, const HdrBytes &h, DevParams *dp, hipStream_t s);
+// fpsz_decompress_async's outcome
+hipError_t launch_dasync_result(DevParams *dp, fpsz_decompress_result *out, int is_const,
+                                uint64_t csum, int checked, uint64_t n, double vr, hipStream_t s);
 // the outcome of a compression into a device-side fpsz_async_result
 hipError_t launch_async_result(const CJob &one, fpsz_async_result *out, hipStream_t s);
 hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const DecompressWs &W,
                                   uint64_t off_words, uint64_t n_words, uint64_t n_exc, double e2,
                                   float e2_f, void *out, const void *ref, double eb, hipStream_t s,
-                                  Timer *tm);
+                                  Timer *tm, const HdrBytes *hdr = nullptr);
 hipError_t launch_const_fill_bits(const Plan &P, uint64_t bits, void *out, hipStream_t s);
 hipError_t launch_checksum(const uint8_t *blob, uint64_t bytes, DevParams *dp, hipStream_t s);
 hipError_t launch_verify(const void *x, const void *y, uint64_t n, int dtype, double eb,

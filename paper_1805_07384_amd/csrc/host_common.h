@@ -421,9 +421,11 @@ inline fpsz_status prepare_decompress(fpsz_ctx *ctx, const uint8_t *h, const voi
 }
 
 // Enqueues the decompression (no synchronization).
-inline hipError_t launch_decompress_job(const DJob &J, hipStream_t s, Timer *tm) {
+inline hipError_t launch_decompress_job(const DJob &J, hipStream_t s, Timer *tm,
+                                        const HdrBytes *hdr = nullptr) {
   if (J.is_const) {
     hipError_t e = launch_fill_zero(J.W.P, sizeof(DevParams), s);
+    if (e == hipSuccess && hdr) e = launch_hdr_check(J.blob, *hdr, J.W.P, s);
     if (e == hipSuccess) e = launch_checksum(J.blob, kHdr, J.W.P, s);
     if (e == hipSuccess) e = launch_const_fill_bits(J.P, J.const_bits, J.out, s);
     // a constant field is checked by the plain verify kernels
@@ -432,7 +434,7 @@ inline hipError_t launch_decompress_job(const DJob &J, hipStream_t s, Timer *tm)
     return e;
   }
   return launch_decompress_args(J.P, J.blob, J.W, J.off_words, J.n_words, J.n_exc, J.e2, J.e2_f,
-                                J.out, J.ref, J.eb, s, tm);
+                                J.out, J.ref, J.eb, s, tm, hdr);
 }
 
 // Status of a finished decompression from its parameter block.

@@ -39,6 +39,22 @@ class AsyncResult(ctypes.Structure):
 ASYNC_RESULT_BYTES = ctypes.sizeof(AsyncResult)
 
 
+class DecompressResult(ctypes.Structure):
+    """fpsz_decompress_result: the device-side outcome of fpsz_decompress_async."""
+    _fields_ = [("status", ctypes.c_uint32), ("checked", ctypes.c_uint32),
+                ("sse", ctypes.c_double), ("mse", ctypes.c_double), ("psnr", ctypes.c_double),
+                ("max_abs_err", ctypes.c_double), ("n_over_eb", ctypes.c_uint64)]
+
+
+DECOMPRESS_RESULT_BYTES = ctypes.sizeof(DecompressResult)
+
+
+def decompress_result(result: torch.Tensor) -> DecompressResult:
+    """Copy a device-side fpsz_decompress_result to the host (synchronizes)."""
+    raw = bytes(result[:DECOMPRESS_RESULT_BYTES].cpu().numpy().tobytes())
+    return DecompressResult.from_buffer_copy(raw)
+
+
 def async_result(result: torch.Tensor) -> AsyncResult:
     """Copy a device-side fpsz_async_result to the host (synchronizes)."""
     raw = bytes(result[:ASYNC_RESULT_BYTES].cpu().numpy().tobytes())
@@ -144,6 +160,8 @@ SIGNATURES = {
     "fpsz_compress_async": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _u64p, ctypes.c_int,
                                            ctypes.c_double, ctypes.c_int, _vp, ctypes.c_uint64,
                                            _vp, ctypes.c_uint64, _vp, _vp]),
+    "fpsz_decompress_async": (ctypes.c_int, [_vp, _vp, ctypes.c_uint64, _vp, _vp, ctypes.c_uint64,
+                                             _vp, ctypes.c_uint64, _vp, _vp, _vp]),
     "fpsz_blob_header": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), _u64p,
                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(Info)]),
     "fpsz_decompress": (ctypes.c_int, [_vp, _vp, ctypes.c_uint64, _vp, ctypes.c_uint64, _vp,
@@ -425,6 +443,23 @@ class Context:
                                             workspace.numel() * workspace.element_size(),
                                             blob.data_ptr(), blob.numel(), result.data_ptr(),
                                             _stream(stream))
+
+    def decompress_async_into(self, blob: torch.Tensor, nbytes: int, header: bytes,
+                              workspace: torch.Tensor, out: torch.Tensor, result: torch.Tensor,
+                              orig: torch.Tensor | None = None, stream=None) -> int:
+        """fpsz_decompress_async: enqueue the decompression of ``blob`` whose
+        header (its first 256 bytes) the caller holds on the host; the
+        outcome (and Eq. 4 against ``orig`` when given) goes to ``result`` (a
+        device uint8 tensor of DECOMPRESS_RESULT_BYTES, read it with
+        decompress_result()).  Returns the host status only."""
+        assert len(header) >= 256
+        assert result.is_cuda and result.numel() * result.element_size() >= DECOMPRESS_RESULT_BYTES
+        hb = ctypes.create_string_buffer(bytes(header[:256]), 256)
+        return self.lib.fpsz_decompress_async(
+            self.handle, blob.data_ptr(), int(nbytes), hb, workspace.data_ptr(),
+            workspace.numel() * workspace.element_size(), out.data_ptr(),
+            out.numel() * out.element_size(), orig.data_ptr() if orig is not None else None,
+            result.data_ptr(), _stream(stream))
 
     def decompress_into(self, blob: torch.Tensor, nbytes: int, workspace: torch.Tensor,
                         out: torch.Tensor, stream=None) -> int:

@@ -1,8 +1,10 @@
-"""fpsz_compress_async (the compress entry point that writes its outcome to
-device memory and never synchronizes) against fpsz_compress: identical blobs
-and reports when called directly, when captured in a graph and replayed on
-new data (each replay checked against the direct call, with eager work and
-synchronizations between replays), and device-side statuses."""
+"""fpsz_compress_async and fpsz_decompress_async (the entry points that write
+their outcome to device memory and never synchronize) against the
+synchronous calls: identical blobs, reconstructions and reports when called
+directly and when captured in a graph and replayed (each replay checked,
+with eager work and synchronizations between replays), and device-side
+statuses (non-finite input, capacity, a header that does not match the
+blob)."""
 import numpy as np
 import pytest
 
@@ -114,3 +116,109 @@ def test_async_device_statuses(ctx):
     assert ctx.compress_async_into(yt, 120.0, ws, small, res_t) == 0
     r = fpsz.async_result(res_t)
     assert r.status == fpsz.E_CAPACITY and r.blob_bytes == pblob.numel()
+
+
+def _blob(ctx, x, psnr, domain):
+    from paper_1805_07384_amd import fpsz
+    xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    pblob, pinfo = _plain(ctx, xt, psnr, domain)
+    return xt, pblob
+
+
+def _dasync(ctx, blob, header, shape, dtype, orig=None, stream=None):
+    from paper_1805_07384_amd import fpsz
+    wd = torch.full((fpsz.decompress_workspace_bytes(shape, dtype),), 0xA5, dtype=torch.uint8,
+                    device="cuda")
+    out = torch.full(shape, 7.0, dtype=dtype, device="cuda")
+    res = torch.zeros(fpsz.DECOMPRESS_RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    st = ctx.decompress_async_into(blob, blob.numel(), header, wd, out, res, orig, stream)
+    return st, out, res, wd
+
+
+@pytest.mark.parametrize("shape,dt,psnr,domain", [((40, 37, 70), np.float32, 80.0, 1),
+                                                  ((300, 200), np.float64, 120.0, 0),
+                                                  ((20000,), np.float32, 40.0, 0)])
+def test_decompress_async_matches_sync(ctx, shape, dt, psnr, domain):
+    from paper_1805_07384_amd import fpsz
+    x = (synth.grf_numpy(shape, -3.0, 9) * 5.0 + 1.0).astype(dt)
+    print("case decompress async shape=%s dtype=%s psnr=%s" % (shape, x.dtype, psnr), flush=True)
+    xt, blob = _blob(ctx, x, psnr, domain)
+    header = blob[:256].cpu().numpy().tobytes()
+    y_sync, st_sync = ctx.decompress_verify(blob, xt)
+    st, out, res_t, _ = _dasync(ctx, blob, header, xt.shape, xt.dtype, xt)
+    assert st == 0
+    r = fpsz.decompress_result(res_t)
+    assert r.status == 0 and r.checked == 1
+    assert torch.equal(out.cpu(), y_sync.cpu())
+    assert r.sse == st_sync["sse"] and r.max_abs_err == st_sync["max_abs_err"]
+    assert r.n_over_eb == st_sync["n_over_eb"]
+    assert abs(r.psnr - st_sync["psnr"]) <= 1e-12 * abs(st_sync["psnr"])
+    # without an original: the reconstruction only
+    st, out2, res_t, _ = _dasync(ctx, blob, header, xt.shape, xt.dtype, None)
+    r = fpsz.decompress_result(res_t)
+    assert st == 0 and r.status == 0 and r.checked == 0 and torch.equal(out2, out)
+
+
+def test_decompress_async_header_mismatch_and_constant(ctx):
+    from paper_1805_07384_amd import fpsz
+    shape = (64, 96)
+    xa = synth.grf_numpy(shape, -3.0, 3).astype(np.float32)
+    xb = (synth.grf_numpy(shape, -3.0, 4) * 2.0).astype(np.float32)
+    _, ba = _blob(ctx, xa, 80.0, 0)
+    _, bb = _blob(ctx, xb, 80.0, 0)
+    print("case decompress async header mismatch", flush=True)
+    # blob b (zero-padded to blob a's size) with the header of blob a: the
+    # host plan is valid, the device finds the blob's own header differs and
+    # reports CORRUPT, never a fault
+    m = max(ba.numel(), bb.numel())
+    bbuf = torch.zeros(m, dtype=torch.uint8, device="cuda")
+    bbuf[:bb.numel()] = bb
+    st, _, res_t, _ = _dasync(ctx, bbuf[:ba.numel()], ba[:256].cpu().numpy().tobytes(), shape,
+                              torch.float32)
+    assert st == 0
+    assert fpsz.decompress_result(res_t).status == fpsz.E_CORRUPT
+    print("case decompress async constant", flush=True)
+    c = np.full(shape, -1.5, dtype=np.float32)
+    ct, cb = _blob(ctx, c, 80.0, 1)
+    st, out, res_t, _ = _dasync(ctx, cb, cb[:256].cpu().numpy().tobytes(), shape, torch.float32,
+                                ct)
+    r = fpsz.decompress_result(res_t)
+    assert st == 0 and r.status == 0 and r.checked == 1 and r.sse == 0.0
+    assert torch.equal(out, ct)
+
+
+def test_decompress_async_in_a_graph(ctx):
+    # captured once, replayed three times (the output cleared by eager work
+    # in between): every replay equals the synchronous call
+    from paper_1805_07384_amd import fpsz
+    x = synth.field_3d_lognormal(shape=(48, 64, 96), seed=21)
+    xt, blob = _blob(ctx, x, 80.0, 1)
+    header = blob[:256].cpu().numpy().tobytes()
+    y_sync, st_sync = ctx.decompress_verify(blob, xt)
+    wd = torch.empty(fpsz.decompress_workspace_bytes(xt.shape, xt.dtype), dtype=torch.uint8,
+                     device="cuda")
+    out = torch.empty_like(xt)
+    res_t = torch.zeros(fpsz.DECOMPRESS_RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        assert ctx.decompress_async_into(blob, blob.numel(), header, wd, out, res_t, xt, side) == 0
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    print("case decompress async graph capture", flush=True)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        st = ctx.decompress_async_into(blob, blob.numel(), header, wd, out, res_t, xt,
+                                       torch.cuda.current_stream())
+    assert st == 0
+    for k in range(3):
+        print("case decompress async graph replay %d" % k, flush=True)
+        out.fill_(0.0)
+        res_t.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        r = fpsz.decompress_result(res_t)
+        assert r.status == 0 and r.checked == 1
+        assert torch.equal(out, y_sync)
+        assert r.sse == st_sync["sse"] and r.n_over_eb == st_sync["n_over_eb"]
