@@ -635,13 +635,15 @@ __device__ inline bool xcd_tile(const Plan &P, int ndim, uint64_t k, uint64_t *t
     *t = blockIdx.x + k * gridDim.x;
     return *t < P.n_tiles;
   }
+  // tile counts are below 2^31: 32-bit divisions
   const uint32_t x = blockIdx.x & 7;
-  const uint64_t b0 = (uint64_t)x * P.gy / 8, b1 = (uint64_t)(x + 1) * P.gy / 8;
-  const uint64_t row = (b1 - b0) * P.gx;  // tiles of one band-layer
-  const uint64_t L = (blockIdx.x >> 3) + k * (gridDim.x >> 3);
-  const uint64_t a = L / row, rem = L - a * row;
-  if (a >= P.gz) return false;
-  *t = (a * P.gy + b0 + rem / P.gx) * P.gx + rem % P.gx;
+  const uint32_t b0 = x * P.gy / 8, b1 = (x + 1) * P.gy / 8;
+  const uint32_t row = (b1 - b0) * P.gx;  // tiles of one band-layer
+  const uint64_t L64 = (blockIdx.x >> 3) + k * (gridDim.x >> 3);
+  if (L64 >= (uint64_t)row * P.gz) return false;
+  const uint32_t L = (uint32_t)L64, a = L / row, rem = L - a * row;
+  const uint32_t rr = rem / P.gx;
+  *t = ((uint64_t)a * P.gy + b0 + rr) * P.gx + (rem - rr * P.gx);
   return true;
 }
 

@@ -98,9 +98,12 @@ __host__ __device__ inline uint64_t chunks_of(uint64_t ez, uint64_t ey, uint64_t
 // it precedes.
 __host__ __device__ inline TileGeo tile_geo(const Plan &P, uint64_t t) {
   TileGeo g;
-  g.c = (uint32_t)(t % P.gx);
-  g.b = (uint32_t)((t / P.gx) % P.gy);
-  g.a = (uint32_t)(t / ((uint64_t)P.gx * P.gy));
+  // tile counts are below 2^31 (fields hold fewer points): 32-bit divisions,
+  // a fraction of the 64-bit sequence on the scalar unit
+  const uint32_t t32 = (uint32_t)t, q = t32 / P.gx;
+  g.c = t32 - q * P.gx;
+  g.a = q / P.gy;
+  g.b = q - g.a * P.gy;
   g.z0 = (uint64_t)g.a * P.tz;
   g.y0 = (uint64_t)g.b * P.ty;
   g.x0 = (uint64_t)g.c * P.tx;
