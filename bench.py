@@ -123,6 +123,7 @@ def algorithmic_bytes(stage: str, n: int, s: int, b: float, fused_check: bool = 
         "encode": b / 8.0,
         "decode": b / 8.0,
         "rec": 2.0 * s if fused_check else s,
+        "decode_rec": b / 8.0 + (2.0 * s if fused_check else s),
         "verify": 2.0 * s,
     }.get(stage)
     return None if per is None else per * n

@@ -459,28 +459,41 @@ __device__ inline uint32_t decode_run(Reader &R, int cnt, uint32_t lut_lds, uint
   return nout;
 }
 
+// LDS of a decode workgroup: the decoder tables, the waves' word counts and
+// the pool of tile words (lut 16-byte aligned)
+struct DecLds {
+  uint16_t *lut;      // 1 << kLut entries
+  uint32_t *lim;      // kLMax + 1
+  int32_t *off;       // kLMax + 1
+  uint16_t *sorted;   // kNSym
+  uint32_t *s_words;  // one per wave
+  uint32_t *pool;     // pool_words
+};
+
 // Words of a workgroup's tiles in LDS: the waves' tiles are placed one after
 // another in one pool (each followed by two zero words), so a tile of any
 // size is read from LDS as long as the workgroup's tiles fit together; the
-// launch picks the number of waves per workgroup from the average tile size
-// so that they nearly always do.  Otherwise each wave gets an equal share of
-// the pool as its window, and lanes whose chunk ends past it read the blob.
+// launch sizes the pool from the average tile so that they nearly always
+// do.  Otherwise each wave gets an equal share of the pool as its window,
+// and lanes whose chunk ends past it read the blob.
+// Wave w decodes tile t0 + w.  Every thread reaches the one workgroup
+// barrier; an inconsistent tile sets the device's corrupt flag and, if
+// `flag` is given, that LDS word.
 template <int NDIM>
-__global__ __launch_bounds__(kDecBlock) void k_decode(Plan P, const uint8_t *__restrict__ blob,
-                                                      DecodeArgs A, DevParams *__restrict__ dp,
-                                                      int16_t *__restrict__ codes, uint32_t pool_words) {
-  __shared__ __attribute__((aligned(16))) uint16_t lut[1 << kLut];
-  __shared__ uint32_t lim[kLMax + 1];
-  __shared__ int32_t off[kLMax + 1];
-  __shared__ uint16_t sorted[kNSym];
-  __shared__ uint32_t s_words[kDecWaves];
-  extern __shared__ uint32_t wstage[];  // pool of pool_words
-
-  if (dp->corrupt) return;  // uniform over the grid
-  if (*reinterpret_cast<const uint64_t *>(blob + H_CSUM) != dp->checksum) {
-    if (threadIdx.x == 0) atomicOr(&dp->corrupt, 1u);
-    return;
-  }
+__device__ inline void decode_group(const Plan &P, const uint8_t *__restrict__ blob,
+                                    const DecodeArgs &A, DevParams *__restrict__ dp,
+                                    int16_t *__restrict__ codes, uint32_t pool_words, uint64_t t0,
+                                    const DecLds &L, uint32_t *flag) {
+  uint16_t *const lut = L.lut;
+  uint32_t *const lim = L.lim;
+  int32_t *const off = L.off;
+  uint16_t *const sorted = L.sorted;
+  uint32_t *const s_words = L.s_words;
+  uint32_t *const wstage = L.pool;
+  auto mark_bad = [&]() {
+    atomicOr(&dp->corrupt, 1u);
+    if (flag) *flag = 1u;
+  };
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nwv = (int)(blockDim.x >> 6);
   {
@@ -498,7 +511,7 @@ __global__ __launch_bounds__(kDecBlock) void k_decode(Plan P, const uint8_t *__r
     off[tid] = (int32_t)base - (int32_t)first;
   }
   // the tile is wave-uniform: its values live in scalar registers
-  const uint64_t t = (uint64_t)blockIdx.x * (uint64_t)nwv + __builtin_amdgcn_readfirstlane(wv);
+  const uint64_t t = t0 + __builtin_amdgcn_readfirstlane(wv);
   const bool valid = t < P.n_tiles;
   const uint64_t *two = reinterpret_cast<const uint64_t *>(blob + P.off_two);
   const uint64_t *teo = reinterpret_cast<const uint64_t *>(blob + P.off_teo);
@@ -511,10 +524,10 @@ __global__ __launch_bounds__(kDecBlock) void k_decode(Plan P, const uint8_t *__r
   }
   const bool sane =
       valid && !(w0 > w1 || w1 > A.n_words || e0 > e1 || e1 > A.n_exc || w1 - w0 > (uint64_t)kTilePts);
-  if (valid && !sane && lane == 0) atomicOr(&dp->corrupt, 1u);
+  if (valid && !sane && lane == 0) mark_bad();
   const uint32_t nw = sane ? (uint32_t)(w1 - w0) : 0u;
   if (lane == 0) s_words[wv] = nw + 2;
-  __syncthreads();  // the last barrier of the kernel
+  __syncthreads();  // the function's one barrier
   uint32_t pos = 0, tot = 0;
   for (int w = 0; w < nwv; w++) {
     const uint32_t v = s_words[w];
@@ -540,7 +553,7 @@ __global__ __launch_bounds__(kDecBlock) void k_decode(Plan P, const uint8_t *__r
   const uint32_t incl = wave_incl_scan_u32(cb);
   const uint32_t total = __shfl(incl, 63, 64);
   if (total > nw * 32u) {
-    if (lane == 0) atomicOr(&dp->corrupt, 1u);
+    if (lane == 0) mark_bad();
     return;
   }
   LongTabs LT;
@@ -622,7 +635,28 @@ __global__ __launch_bounds__(kDecBlock) void k_decode(Plan P, const uint8_t *__r
   ntag = wave_sum_u32(ntag);
   nout = wave_sum_u32(nout);
   const bool recs_ok = A.il_rw ? (nrec == 0 && ntag == A.il_rw * nout) : nrec == nout;
-  if (bad || endpos != incl || !recs_ok) atomicOr(&dp->corrupt, 1u);
+  if (bad || endpos != incl || !recs_ok) mark_bad();
+}
+
+template <int NDIM>
+__global__ __launch_bounds__(kDecBlock) void k_decode(Plan P, const uint8_t *__restrict__ blob,
+                                                      DecodeArgs A, DevParams *__restrict__ dp,
+                                                      int16_t *__restrict__ codes, uint32_t pool_words) {
+  __shared__ __attribute__((aligned(16))) uint16_t lut[1 << kLut];
+  __shared__ uint32_t lim[kLMax + 1];
+  __shared__ int32_t off[kLMax + 1];
+  __shared__ uint16_t sorted[kNSym];
+  __shared__ uint32_t s_words[kDecWaves];
+  extern __shared__ uint32_t wstage[];  // pool of pool_words
+
+  if (dp->corrupt) return;  // uniform over the grid
+  if (*reinterpret_cast<const uint64_t *>(blob + H_CSUM) != dp->checksum) {
+    if (threadIdx.x == 0) atomicOr(&dp->corrupt, 1u);
+    return;
+  }
+  const DecLds L = {lut, lim, off, sorted, s_words, wstage};
+  decode_group<NDIM>(P, blob, A, dp, codes, pool_words, (uint64_t)blockIdx.x * (blockDim.x >> 6), L,
+                     nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1183,28 +1217,35 @@ __global__ __launch_bounds__(kBlock) void k_proj_full(Plan P, const uint8_t *__r
   }
 }
 
+// LDS of the full-tile reconstruction (16-byte aligned arrays)
+struct RecLds {
+  uint32_t *lds_m;   // 2 * kBlock
+  uint32_t *lds_t;   // 4 * 16 * kSegWD
+  uint32_t *s_face;  // 2 * 16 * kSegWD (GLOBAL domain only)
+  uint32_t *s_out;   // (kBlock / 64) * 32 * kSegWD
+  uint32_t *scr;     // 8
+  uint32_t *s_bad;   // 1
+};
+constexpr int kRecLdsWords = 2 * kBlock + 4 * 16 * kSegWD + (kBlock / 64) * 32 * kSegWD + 8 + 4;
+
+// Reconstruction of full tile t by the whole workgroup (it has barriers;
+// every thread calls it with the same t).  Returns false, uniformly, when the
+// tile's exception list is inconsistent (the corrupt flag is then set).
 template <typename T, int NDIM, bool GLOBAL>
-__global__ __launch_bounds__(kBlock, 3) void k_rec_full(Plan P, const uint8_t *__restrict__ blob,
-                                                     DecodeArgs A, DevParams *__restrict__ dp,
-                                                     const int16_t *__restrict__ codes,
-                                                     T *__restrict__ out) {
+__device__ inline bool rec_full_tile(const Plan &P, const uint8_t *__restrict__ blob,
+                                     const DecodeArgs &A, DevParams *__restrict__ dp,
+                                     const int16_t *__restrict__ codes, T *__restrict__ out,
+                                     uint64_t t, const RecLds &L) {
   using G = DGeo<NDIM>;
   constexpr int TZ = G::TZ, TY = G::TY, TX = G::TX;
   constexpr int FZ = NDIM == 3 ? TY * TX : 1, FY = TZ * TX, FX = TZ * TY;
   constexpr int RW = sizeof(T) / 4;
-  __shared__ uint32_t lds_m[2 * kBlock];
-  __shared__ __align__(16) uint32_t lds_t[4 * 16 * kSegWD];
-  // halo rows of the tile (3D: Fz rows by y, then Fy + Gx rows by z; 2D: the
-  // Fy row), 36-word row stride so that 16 lanes reading 16 rows hit
-  // distinct banks
-  __shared__ __align__(16) uint32_t s_face[2 * 16 * kSegWD];
-  __shared__ uint32_t scr[8];
-  __shared__ uint32_t s_bad;
-  if (dp->corrupt) return;
+  uint32_t *const lds_m = L.lds_m, *const lds_t = L.lds_t, *const s_face = L.s_face;
+  uint32_t *const scr = L.scr, *const s_bad_p = L.s_bad;
+  uint32_t &s_bad = *s_bad_p;
   const int tid = threadIdx.x;
-  const uint64_t t = xcd_block_tile(P.n_tiles);
   const TileGeo g = tile_geo(P, t);
-  if (g.nt != (uint32_t)kTilePts) return;  // uniform: ragged tiles elsewhere
+  if (g.nt != (uint32_t)kTilePts) return true;  // uniform: ragged tiles elsewhere
   const RowMap<NDIM> m(tid);
   typedef dgptr_t<du32x4_t> g4;
   // the tile's halo data is read first, so that its latency overlaps the
@@ -1287,7 +1328,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_rec_full(Plan P, const uint8_t *_
   }
   const uint64_t *teo = reinterpret_cast<const uint64_t *>(blob + P.off_teo);
   const uint64_t e0 = teo[t], e1 = teo[t + 1];
-  if (e0 > e1 || e1 > A.n_exc) return;  // reported by the decode kernel
+  if (e0 > e1 || e1 > A.n_exc) return true;  // reported by the decode kernel
   const uint32_t *exc = reinterpret_cast<const uint32_t *>(blob + P.off_exc);
   if (tid == 0) s_bad = 0;
   __syncthreads();
@@ -1348,7 +1389,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_rec_full(Plan P, const uint8_t *_
   __syncthreads();
   if (s_bad) {
     if (tid == 0) atomicOr(&dp->corrupt, 1u);
-    return;
+    return false;
   }
   // the check against the original: per-thread sums in a fixed order (row
   // order, or piece order in the transposed layout), then the block's
@@ -1363,8 +1404,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_rec_full(Plan P, const uint8_t *_
       // rows transposed through LDS: two rounds of 32 rows per wave; in
       // round h lane l stores piece l % 8 of rows l / 8 + 8 j (j = 0..3) of
       // that half, i.e. eight whole rows per store instruction
-      __shared__ __align__(16) uint32_t s_out[(kBlock / 64) * 32 * kSegWD];
-      uint32_t *wb = s_out + wv * 32 * kSegWD;
+      uint32_t *wb = L.s_out + wv * 32 * kSegWD;
 #pragma unroll
       for (int h = 0; h < 2; h++) {
         if ((lane >> 5) == h) {
@@ -1434,6 +1474,80 @@ __global__ __launch_bounds__(kBlock, 3) void k_rec_full(Plan P, const uint8_t *_
     }
   }
   if (A.ref) vs.store(A.vpart, t);  // uniform over the block (it has barriers)
+  return true;
+}
+
+template <typename T, int NDIM, bool GLOBAL>
+__global__ __launch_bounds__(kBlock, 3) void k_rec_full(Plan P, const uint8_t *__restrict__ blob,
+                                                     DecodeArgs A, DevParams *__restrict__ dp,
+                                                     const int16_t *__restrict__ codes,
+                                                     T *__restrict__ out) {
+  __shared__ __align__(16) uint32_t lds_m[2 * kBlock];
+  __shared__ __align__(16) uint32_t lds_t[4 * 16 * kSegWD];
+  // halo rows of the tile (3D: Fz rows by y, then Fy + Gx rows by z; 2D: the
+  // Fy row), 36-word row stride so that 16 lanes reading 16 rows hit
+  // distinct banks
+  __shared__ __align__(16) uint32_t s_face[GLOBAL ? 2 * 16 * kSegWD : 4];
+  __shared__ __align__(16) uint32_t s_out[(kBlock / 64) * 32 * kSegWD];
+  __shared__ uint32_t scr[8];
+  __shared__ uint32_t s_bad;
+  if (dp->corrupt) return;
+  const RecLds L = {lds_m, lds_t, s_face, s_out, scr, &s_bad};
+  (void)rec_full_tile<T, NDIM, GLOBAL>(P, blob, A, dp, codes, out, xcd_block_tile(P.n_tiles), L);
+}
+
+// ---------------------------------------------------------------------------
+// Plain TILE-domain blobs: decoding and the full tiles' reconstruction in one
+// launch.  Workgroup b decodes a group of four tiles, one per wave (the
+// decoder above), into the residual buffer, then reconstructs them one after
+// the other with all four waves (the full-tile reconstruction above), while
+// their residuals are still in the XCD's L2.  Workgroups resident on one CU
+// are at different phases, so the decoder's dependent table lookups and the
+// reconstruction's streaming overlap instead of running one launch after the
+// other.  The phases share one dynamic LDS region: first the decoder's tables
+// and tile words, then the reconstruction's buffers.  Ragged tiles are
+// decoded here and reconstructed by the general kernel afterwards.
+constexpr int kDrWaves = 4;
+// word offsets in the region: decoder tables (lut 16-byte aligned), word
+// counts, pool (16-byte aligned); the reconstruction's buffers from word 0
+constexpr uint32_t kDrLim = (1u << kLut) / 2, kDrOff = kDrLim + 20, kDrSorted = kDrOff + 20,
+                   kDrWords = kDrSorted + 520, kDrPool = kDrWords + 4;
+static_assert(kLMax + 1 <= 20 && (kNSym + 1) / 2 <= 520 && kDrPool % 4 == 0, "decode LDS layout");
+static_assert(kDrWaves * 64 == kBlock, "one reconstruction workgroup per tile group");
+
+template <typename T, int NDIM>
+__global__ __launch_bounds__(kBlock, 3) void k_decrec(Plan P, const uint8_t *__restrict__ blob,
+                                                   DecodeArgs A, DevParams *__restrict__ dp,
+                                                   int16_t *__restrict__ codes, T *__restrict__ out,
+                                                   uint32_t pool_words) {
+  extern __shared__ __align__(16) uint32_t dr_lds[];
+  __shared__ uint32_t s_flag;
+  if (dp->corrupt) return;  // uniform over the grid
+  if (*reinterpret_cast<const uint64_t *>(blob + H_CSUM) != dp->checksum) {
+    if (threadIdx.x == 0) atomicOr(&dp->corrupt, 1u);
+    return;
+  }
+  if (threadIdx.x == 0) s_flag = 0;  // published by the decoder's barrier
+  const uint64_t t0 = xcd_block_tile(ceil_div(P.n_tiles, kDrWaves)) * kDrWaves;
+  const DecLds D = {reinterpret_cast<uint16_t *>(dr_lds), dr_lds + kDrLim,
+                    reinterpret_cast<int32_t *>(dr_lds + kDrOff),
+                    reinterpret_cast<uint16_t *>(dr_lds + kDrSorted), dr_lds + kDrWords,
+                    dr_lds + kDrPool};
+  decode_group<NDIM>(P, blob, A, dp, codes, pool_words, t0, D, &s_flag);
+  // the group's residuals are visible to the whole workgroup and the
+  // decoder's LDS is free
+  __syncthreads();
+  if (s_flag) return;  // uniform: a tile of the group is inconsistent
+  const RecLds R = {dr_lds, dr_lds + 2 * kBlock, nullptr,
+                    dr_lds + 2 * kBlock + 4 * 16 * kSegWD,
+                    dr_lds + kRecLdsWords - 12, dr_lds + kRecLdsWords - 4};
+#pragma unroll 1
+  for (int w = 0; w < kDrWaves; w++) {
+    const uint64_t t = t0 + (uint64_t)w;
+    if (t >= P.n_tiles) break;  // uniform
+    if (w) __syncthreads();  // every thread is done with the previous tile's LDS
+    if (!rec_full_tile<T, NDIM, false>(P, blob, A, dp, codes, out, t, R)) break;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1810,6 +1924,8 @@ static void excl_set(std::initializer_list<ScanJob> jobs, uint32_t *tmp, hipStre
 struct DecShape {
   uint32_t waves;       // waves (tiles) per decode workgroup
   uint32_t pool_words;  // LDS pool of the workgroup
+  uint32_t fused_pool_words;  // LDS pool of a decode + reconstruction workgroup
+  bool fused;                 // plain TILE blobs: decode and reconstruct in one launch
 };
 
 template <typename T, int NDIM>
@@ -1818,11 +1934,27 @@ static void launch_dec_t(const Plan &P, const uint8_t *blob, const DecodeArgs &A
                          Timer *tm) {
   using G = DGeo<NDIM>;
   const dim3 dgrid((uint32_t)ceil_div(P.n_tiles, ds.waves)), grid((uint32_t)P.n_tiles), blk(kBlock);
+  const bool ragged = P.pad_ != 0;
+  if (P.variant == kVarPlain && P.domain == FPSZ_DOMAIN_TILE && ds.fused) {
+    const uint32_t lw = kDrPool + ds.fused_pool_words;
+    const size_t dyn = 4 * (size_t)(lw > (uint32_t)kRecLdsWords ? lw : (uint32_t)kRecLdsWords);
+    hipLaunchKernelGGL((k_decrec<T, NDIM>), dim3((uint32_t)ceil_div(P.n_tiles, kDrWaves)), blk,
+                       dyn, s, P, blob, A, dp, codes, out, ds.fused_pool_words);
+    tm->mark(s, "decode_rec");
+    if (ragged) {
+      hipLaunchKernelGGL((k_rec<T, NDIM, false>), grid, blk, 0, s, P, blob, A, dp, codes, out);
+      tm->mark(s, "rec");
+    }
+    if (A.ref) {
+      hipLaunchKernelGGL(k_vstat_final, dim3(1), dim3(kVstatThreads), 0, s, A.vpart, P.n_tiles, dp);
+      tm->mark(s, "check_final");
+    }
+    return;
+  }
   const size_t dyn = (size_t)ds.pool_words * 4;
   hipLaunchKernelGGL((k_decode<NDIM>), dgrid, dim3(64 * ds.waves), dyn, s, P, blob, A, dp, codes,
                      ds.pool_words);
   tm->mark(s, "decode");
-  const bool ragged = P.pad_ != 0;
   if (P.variant == kVarXform) {
     hipLaunchKernelGGL((k_rec_xf<T, NDIM>), grid, blk, 0, s, P, blob, A, dp, codes, out);
   } else if (P.variant == kVarInloop) {
@@ -1875,9 +2007,8 @@ static void launch_dec_t(const Plan &P, const uint8_t *blob, const DecodeArgs &A
   }
 }
 
-// LDS pool (words) of a decode workgroup when two are resident per CU next to
-// their decoder tables (at most 20 KB each).
-static uint64_t decode_pool_limit() {
+// LDS bytes per workgroup (at most) and per CU of the current device
+static void lds_limits(int64_t *per_block, int64_t *per_cu) {
   static int cached[64][2];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
@@ -1893,10 +2024,31 @@ static uint64_t decode_pool_limit() {
     cached[dev][1] = cu;
     cached[dev][0] = blk;
   }
-  int64_t lds = cached[dev][1] / 2;
-  if (lds > cached[dev][0]) lds = cached[dev][0];
+  *per_block = cached[dev][0];
+  *per_cu = cached[dev][1];
+}
+
+// LDS pool (words) of a decode workgroup when two are resident per CU next to
+// their decoder tables (at most 20 KB each).
+static uint64_t decode_pool_limit() {
+  int64_t blk, cu;
+  lds_limits(&blk, &cu);
+  int64_t lds = cu / 2;
+  if (lds > blk) lds = blk;
   const int64_t words = (lds - 20480) / 4;
   return words < 8 * 514 ? 8 * 514 : (uint64_t)words;
+}
+
+// LDS pool (words) of a fused decode + reconstruction workgroup when three
+// are resident per CU (the decoder's tables take kDrPool words before it).
+static uint64_t fused_pool_limit() {
+  int64_t blk, cu;
+  lds_limits(&blk, &cu);
+  int64_t lds = cu / 3;
+  if (lds > blk) lds = blk;
+  const int64_t words = (lds - 512) / 4 - (int64_t)kDrPool;
+  const int64_t w = (words / 256) * 256;
+  return w < kDrWaves * 514 ? kDrWaves * 514 : (uint64_t)w;
 }
 
 // Waves per decode workgroup.  The symbol loop is bound by latency, so the
@@ -1917,6 +2069,18 @@ static DecShape decode_shape(uint64_t n_words, uint64_t n_tiles) {
   uint64_t want = (uint64_t)kDecWaves * ((avg * kPoolSlackNum) / kPoolSlackDen + 2 + 64);
   want = (want + 255) & ~255ull;
   d.pool_words = (uint32_t)(want < lim ? want : lim);
+  // the fused kernel's four tiles, within a pool that keeps three of its
+  // workgroups resident per CU.  It is used when four tiles of the average
+  // size fit that pool whole.  Measured on the 512^3 sweep (decode +
+  // reconstruction with the check): 0.442 -> 0.396, 0.475 -> 0.416 and
+  // 0.516 -> 0.457 ms at 40, 60 and 80 dB (1.4-5.6 bits per value); at 100
+  // and 120 dB (8.9-12.3 bits) its windows hold a smaller part of each tile
+  // and it was 5-9 % slower than the two kernels, which stay in use there.
+  uint64_t fw = (uint64_t)kDrWaves * ((avg * kPoolSlackNum) / kPoolSlackDen + 2 + 64);
+  fw = (fw + 255) & ~255ull;
+  const uint64_t flim = fused_pool_limit();
+  d.fused_pool_words = (uint32_t)(fw < flim ? fw : flim);
+  d.fused = (uint64_t)kDrWaves * (avg + 2) <= flim;
   return d;
 }
 

@@ -134,6 +134,34 @@ def test_parity_outliers_and_patches(ctx, orc):
     _parity(ctx, orc, xf.astype(np.float64) * 1.0001, 150.0, 0)
 
 
+@pytest.mark.parametrize("case", ["outliers_f32", "patches_f64"])
+def test_parity_tile_fused_exceptions(ctx, orc, case):
+    # TILE-domain blobs whose tiles average at most ~2000 code words are
+    # decoded and reconstructed in one launch (four average tiles fit its
+    # LDS pool); exception records in that path, next to ragged tiles.
+    # outliers: a smooth field of tiny amplitude with sparse spikes of the
+    # full range at 120 dB (spike residuals beyond 2^15 bins); patches:
+    # float64 values within ulps of bin edges at 60 dB
+    import patchfield as pf
+    shape = (33, 48, 96)
+    if case == "outliers_f32":
+        rng = np.random.default_rng(21)
+        x = synth.grf_numpy(shape, -3.0, 21) * 1e-5
+        spikes = rng.random(shape) < 0.002
+        x = np.where(spikes, rng.choice([-1.0, 1.0], size=shape), x).astype(np.float32)
+        psnr = 120.0
+    else:
+        x = pf.f64_patch_field(shape=shape, psnr=60.0)
+        psnr = 60.0
+    h = orc.header(orc.compress(x, psnr, domain=1)[0])
+    assert h["n_words"] / h["n_tiles"] <= 2048  # the one-launch path
+    info, _ = _parity(ctx, orc, x, psnr, 1)
+    if case == "outliers_f32":
+        assert info["n_outliers"] > 0
+    else:
+        assert info["n_patches"] > 0
+
+
 @pytest.mark.parametrize("shape", [(17, 33, 70), (33, 48, 96)])
 def test_parity_f64_patches(ctx, orc, shape):
     # float64 values within three ulps of bin edges: two-record patches in a
