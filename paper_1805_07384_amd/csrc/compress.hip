@@ -894,11 +894,15 @@ __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restri
     if (nexc && (RECORDS || staged)) {
       uint32_t e = my_off;
       const uint64_t base_off = RECORDS ? exc_off[t] : 0;
-      int z = i0 / (ey * ex);
-      const int rem = i0 - z * ey * ex;
-      int y = rem / ex, xx = rem - (rem / ex) * ex;
-      for (int j = 0; j < cnt; j++) {
-        const uint32_t pos = (uint32_t)(g.start + (uint64_t)(i0 + j));
+      // only the points with an outlier or a patch, in stream order
+      uint32_t todo = flags | pflags;
+      while (todo) {
+        const int j = __ffs(todo) - 1;
+        todo &= todo - 1;
+        const int i = i0 + j;  // stream index inside the tile
+        const int z = i / (ey * ex), rem = i - z * ey * ex;
+        const int y = rem / ex, xx = rem - y * ex;
+        const uint32_t pos = (uint32_t)(g.start + (uint64_t)i);
         uint32_t recs[6];
         int nr = 0;
         if ((flags >> j) & 1u) {
@@ -930,7 +934,6 @@ __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restri
             rec[1] = recs[2 * k + 1];
           }
         }
-        if (++xx == ex) { xx = 0; if (++y == ey) { y = 0; z++; } }
       }
     }
   }
