@@ -1,17 +1,21 @@
 // compress.hip -- gfx950 kernels of fixed-PSNR SZ-style compression.
 //
 // Pipeline (one stream, no host round trip until the end):
-//   k_range     value range of the original data (definition under Eq. 4),
-//               then eb_abs = eb_rel * vr (Eq. 7, remark after Eq. 6),
-//               bin size 2 eb and its reciprocal, in a last-block epilogue
+//   k_range, k_range_final  value range of the original data (definition
+//               under Eq. 4) from per-block partials, then eb_abs =
+//               eb_rel * vr (Eq. 7, remark after Eq. 6), the bin size 2 eb
+//               and its reciprocal; the range blocks also clear the call's
+//               parameter block and counters
 //   k_quant     prequantization q = rint(x / 2eb) (uniform bins with
 //               midpoint reconstruction, Eq. 5-6), Lorenzo residual on q
 //               from an LDS tile with a one-point halo (Sec. II-A step (1),
-//               Sec. III), symbol histogram, residual codes, and the
-//               exception list compacted in stream order by look-back
-//   k_codebook  Huffman code lengths (Sec. II-A step (2)) and canonical codes
-//   k_encode    bit packing per tile, tile offsets by look-back
-//   k_header / k_checksum  header fields and the blob checksum
+//               Sec. III), symbol histogram, residual codes, and the tile's
+//               exception records staged in stream order
+//   k_codebook  Huffman code lengths (Sec. II-A step (2)) and canonical
+//               codes; a second workgroup scans the tiles' record counts
+//   k_enc_count, k_enc_scan, k_enc_pack  bits per chunk and tile, the
+//               tiles' word offsets (and the header), the bit packing
+//   k_checksum_jobs, k_checksum_store  the blob checksum
 #include <float.h>
 #include <math.h>
 
@@ -43,16 +47,6 @@ __global__ void k_fill_zero(uint32_t *p, uint64_t nwords) {
     p[i] = 0;
 }
 
-// clears each field's parameter block and counters
-__global__ void k_zero_jobs(CJob one, const CJob *__restrict__ jobs) {
-  const CJob J = select_job(one, jobs);
-  uint32_t *p = reinterpret_cast<uint32_t *>(J.W.P);
-  const uint64_t nwords = J.W.zero_bytes / 4;
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nwords;
-       i += (uint64_t)gridDim.x * blockDim.x)
-    p[i] = 0;
-}
-
 hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t s) {
   const uint64_t nw = bytes / 4;
   if (nw == 0) return hipSuccess;
@@ -65,7 +59,10 @@ hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t s) {
 // a1: range reduction.  Each block reduces a grid-stride share into a
 // partial; one block per field combines the partials and derives the error
 // bound.  (No block waits on another and no atomics: a counter on one
-// address serializes every block that reaches it.)
+// address serializes every block that reaches it.)  The range blocks also
+// clear the field's parameter block, histograms, code tables and tile word
+// counts for the rest of the call (the first launch of a compression; no
+// kernel of it reads them, and the partials they write are not cleared).
 typedef float rf32x4_t __attribute__((ext_vector_type(4)));
 typedef double rf64x2_t __attribute__((ext_vector_type(2)));
 template <typename T> struct VecOf;
@@ -109,6 +106,16 @@ __global__ __launch_bounds__(kBlock) void k_range(CJob one, const CJob *__restri
   const uint64_t nvec = (n - head) / W;
   const uint64_t gtid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   const uint64_t gsz = (uint64_t)gridDim.x * blockDim.x;
+  {
+    uint32_t *z = reinterpret_cast<uint32_t *>(J.W.P);
+    const uint64_t a = (uint64_t)(reinterpret_cast<const uint8_t *>(J.W.range_part) -
+                                  reinterpret_cast<const uint8_t *>(J.W.P)) / 4;
+    const uint64_t b = (uint64_t)(reinterpret_cast<const uint8_t *>(J.W.hist) -
+                                  reinterpret_cast<const uint8_t *>(J.W.P)) / 4;
+    const uint64_t nw = J.W.zero_bytes / 4;
+    for (uint64_t i = gtid; i < a; i += gsz) z[i] = 0;
+    for (uint64_t i = b + gtid; i < nw; i += gsz) z[i] = 0;
+  }
   gV *xv = (gV *)(x + head);
   uint64_t i = gtid;
   for (; i + 7 * gsz < nvec; i += 8 * gsz) {  // eight 16-byte loads in flight
@@ -1890,30 +1897,37 @@ __global__ __launch_bounds__(kBlock) void k_enc_count(CJob one, const CJob *__re
   }
 }
 
+__device__ inline void write_header(const CJob &J);
+
 // exclusive scan of the tile word counts: word offsets in place, the blob's
-// tile_word_offset section and the total
+// tile_word_offset section and the total, then the header (constant fields:
+// the header only)
 __global__ __launch_bounds__(kScanThreads) void k_enc_scan(CJob one, const CJob *__restrict__ jobs) {
   const CJob J = select_job(one, jobs);
   const Plan P = J.P;
   DevParams *__restrict__ dp = J.W.P;
   uint64_t *__restrict__ tw = J.W.word_state;
   uint8_t *__restrict__ blob = J.blob;
-  if (dp->status != 0 || dp->is_const) return;
-  const uint64_t nt = P.n_tiles;
-  uint32_t ovf = 0;
-  const uint64_t tot = block_seg_scan(tw, nt, [&](uint64_t t, uint64_t ex) {
-    tw[t] = ex;
-    const uint64_t o = P.off_two + 8 * t;
-    if (o + 8 <= P.capacity) *reinterpret_cast<uint64_t *>(blob + o) = ex;
-    else ovf = 1;
-  });
-  if (ovf) atomicOr(&dp->overflow, 1u);
-  if (threadIdx.x == 0) {
-    dp->n_words = tot;
-    const uint64_t o = P.off_two + 8 * nt;
-    if (o + 8 <= P.capacity) *reinterpret_cast<uint64_t *>(blob + o) = tot;
-    else atomicOr(&dp->overflow, 1u);
+  if (dp->status != 0) return;  // uniform
+  if (!dp->is_const) {
+    const uint64_t nt = P.n_tiles;
+    uint32_t ovf = 0;
+    const uint64_t tot = block_seg_scan(tw, nt, [&](uint64_t t, uint64_t ex) {
+      tw[t] = ex;
+      const uint64_t o = P.off_two + 8 * t;
+      if (o + 8 <= P.capacity) *reinterpret_cast<uint64_t *>(blob + o) = ex;
+      else ovf = 1;
+    });
+    if (ovf) atomicOr(&dp->overflow, 1u);
+    if (threadIdx.x == 0) {
+      dp->n_words = tot;
+      const uint64_t o = P.off_two + 8 * nt;
+      if (o + 8 <= P.capacity) *reinterpret_cast<uint64_t *>(blob + o) = tot;
+      else atomicOr(&dp->overflow, 1u);
+    }
   }
+  __syncthreads();  // dp->n_words is visible to the workgroup
+  write_header(J);
 }
 
 __global__ __launch_bounds__(kBlock) void k_enc_pack(CJob one, const CJob *__restrict__ jobs) {
@@ -2011,14 +2025,13 @@ __global__ __launch_bounds__(kBlock) void k_enc_pack(CJob one, const CJob *__res
 }
 
 // ---------------------------------------------------------------------------
-// header, padding and total size (one workgroup)
-__global__ void k_header(CJob one, const CJob *__restrict__ jobs) {
-  const CJob J = select_job(one, jobs);
-  const Plan P = J.P;
+// header, padding and total size (by the whole workgroup, after the word
+// counts are scanned; dp->n_words written by the same workgroup)
+__device__ inline void write_header(const CJob &J) {
+  const Plan &P = J.P;
   DevParams *__restrict__ dp = J.W.P;
   uint8_t *__restrict__ blob = J.blob;
   const int tid = threadIdx.x;
-  if (dp->status != 0) return;
   __shared__ uint8_t h[kHdr];
   for (int i = tid; i < (int)kHdr; i += blockDim.x) h[i] = 0;
   __syncthreads();
@@ -2201,8 +2214,6 @@ static void launch_compress_t(const CJob &one, const CJob *jobs, int nf, const P
   tm->mark(s, "encode_count");
   hipLaunchKernelGGL(k_enc_pack, dim3(cfg.encode_grid, nf), dim3(kBlock), 0, s, one, jobs);
   tm->mark(s, "encode");
-  hipLaunchKernelGGL(k_header, dim3(1, nf), dim3(kBlock), 0, s, one, jobs);
-  tm->mark(s, "header");
   hipLaunchKernelGGL(k_checksum_jobs, dim3(cfg.csum_blocks, nf), dim3(kBlock), 0, s, one, jobs);
   hipLaunchKernelGGL(k_checksum_store, dim3(1, nf), dim3(1), 0, s, one, jobs);
   tm->mark(s, "checksum");
@@ -2238,8 +2249,6 @@ hipError_t launch_compress_jobs(const CJob &one, const CJob *jobs_dev, int nf, c
   if (!cfg.range_blocks || !cfg.quant_grid || !cfg.encode_grid || !cfg.csum_blocks)
     return hipErrorInvalidValue;
   tm->mark(s, "begin");
-  hipLaunchKernelGGL(k_zero_jobs, dim3(8, nf), dim3(kBlock), 0, s, one, jobs_dev);
-  tm->mark(s, "init");
   if (maxP.dtype == FPSZ_F32) launch_compress_t<float>(one, jobs_dev, nf, maxP, cfg, s, tm);
   else launch_compress_t<double>(one, jobs_dev, nf, maxP, cfg, s, tm);
   return hipGetLastError();

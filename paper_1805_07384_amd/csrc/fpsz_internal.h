@@ -290,7 +290,7 @@ __host__ __device__ inline uint32_t checksum_grid(uint64_t bytes) {
 
 // checksum over the blob's 32-bit words; the checksum field reads as zero.
 // Accumulates into dp->checksum; use_dp_bytes: the blob size is dp->blob_bytes
-// (compress, after k_header), else bytes_limit (decompress).
+// (compress, after the header is written), else bytes_limit (decompress).
 // Block bi of nb (blocks of any multiple of 64 threads up to 1024).
 __device__ inline void checksum_body(const uint8_t *__restrict__ blob, uint64_t bytes_limit,
                                      DevParams *__restrict__ dp, int use_dp_bytes, uint32_t bi,
