@@ -1231,7 +1231,10 @@ constexpr int kRecLdsWords = 2 * kBlock + 4 * 16 * kSegWD + (kBlock / 64) * 32 *
 // Reconstruction of full tile t by the whole workgroup (it has barriers;
 // every thread calls it with the same t).  Returns false, uniformly, when the
 // tile's exception list is inconsistent (the corrupt flag is then set).
-template <typename T, int NDIM, bool GLOBAL>
+// STREAM: the original is read and the float32 field written with
+// non-temporal accesses (in the one-launch decompression, so that the L2
+// keeps the residuals the workgroup has just decoded).
+template <typename T, int NDIM, bool GLOBAL, bool STREAM = false>
 __device__ inline bool rec_full_tile(const Plan &P, const uint8_t *__restrict__ blob,
                                      const DecodeArgs &A, DevParams *__restrict__ dp,
                                      const int16_t *__restrict__ codes, T *__restrict__ out,
@@ -1297,7 +1300,8 @@ __device__ inline bool rec_full_tile(const Plan &P, const uint8_t *__restrict__ 
     typedef __attribute__((address_space(1))) const df32x4_t gcf4;
 #pragma unroll
     for (int J = 0; J < 8; J++) {
-      const df32x4_t a = ((gcf4 *)(static_cast<const T *>(A.ref) + row_at((lane >> 3) + 8 * J)))[lane & 7];
+      gcf4 *src = (gcf4 *)(static_cast<const T *>(A.ref) + row_at((lane >> 3) + 8 * J)) + (lane & 7);
+      const df32x4_t a = STREAM ? __builtin_nontemporal_load(src) : *src;
       xr[4 * J] = a.x; xr[4 * J + 1] = a.y; xr[4 * J + 2] = a.z; xr[4 * J + 3] = a.w;
     }
   } else if (A.ref) {
@@ -1431,7 +1435,9 @@ __device__ inline bool rec_full_tile(const Plan &P, const uint8_t *__restrict__ 
           f.y = __uint_as_float(a.y);
           f.z = __uint_as_float(a.z);
           f.w = __uint_as_float(a.w);
-          ((gf4 *)(out + row_at(32 * h + rr)))[lane & 7] = f;
+          gf4 *dst = (gf4 *)(out + row_at(32 * h + rr)) + (lane & 7);
+          if (STREAM) __builtin_nontemporal_store(f, dst);
+          else *dst = f;
           if (A.ref) {
             const int J = 4 * h + j;  // the same rows' piece of the original
             vs.add(xr[4 * J], f.x, A.eb);
@@ -1546,7 +1552,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_decrec(Plan P, const uint8_t *__r
     const uint64_t t = t0 + (uint64_t)w;
     if (t >= P.n_tiles) break;  // uniform
     if (w) __syncthreads();  // every thread is done with the previous tile's LDS
-    if (!rec_full_tile<T, NDIM, false>(P, blob, A, dp, codes, out, t, R)) break;
+    if (!rec_full_tile<T, NDIM, false, true>(P, blob, A, dp, codes, out, t, R)) break;
   }
 }
 
