@@ -216,9 +216,10 @@ def timed_calls(fn, reps, warm=3):
     return float(np.median(ts)), float(np.percentile(ts, 90))
 
 
-def c1_leg(ctx, dev):
+def c1_leg(ctx, dev, domain):
     """2D float32 512x512 GRF (k^-3) on [-50, 50] at 80 dB: a latency-bound
-    call; median and p90 of 30 calls each after 3 warm-ups."""
+    call; median and p90 of 30 calls each after 3 warm-ups, in the sweep's
+    Lorenzo domain, and the same calls in the other domain."""
     import torch
 
     from paper_1805_07384_amd import fpsz, synth
@@ -229,21 +230,28 @@ def c1_leg(ctx, dev):
                        device=dev)
     blob = torch.empty(fpsz.compress_bound(tuple(x.shape)), dtype=torch.uint8, device=dev)
     out = torch.empty_like(x)
-    st, nb, info = ctx.compress_into(x, 80.0, ws_c, blob)
-    assert st == fpsz.OK
-    c = timed_calls(lambda: ctx.compress_into(x, 80.0, ws_c, blob), 30)
-    d = timed_calls(lambda: ctx.decompress_into(blob, nb, ws_d, out), 30)
-    dv = timed_calls(lambda: ctx.decompress_verify_into(blob, nb, ws_d, out, x), 30)
-    st2, stats = ctx.decompress_verify_into(blob, nb, ws_d, out, x)
     n, s = x.numel(), 4
-    return {"workload": "2D float32 512x512 GRF k^-3 on [-50, 50], seed 1, 80 dB",
-            "compress_us": round(c[0] * 1e6, 1), "compress_us_p90": round(c[1] * 1e6, 1),
-            "decompress_us": round(d[0] * 1e6, 1), "decompress_us_p90": round(d[1] * 1e6, 1),
-            "decompress_check_us": round(dv[0] * 1e6, 1),
-            "bits_per_value": round(info.bits_per_value, 4),
-            "achieved_psnr": round(stats.psnr, 4), "dpsnr": round(stats.psnr - 80.0, 4),
-            "n_over_eb": stats.n_over_eb,
-            "op_frac": op_fracs(n, s, info.bits_per_value, c[0], d[0], dv[0])}
+
+    def one(dom):
+        st, nb, info = ctx.compress_into(x, 80.0, ws_c, blob, dom)
+        assert st == fpsz.OK
+        c = timed_calls(lambda: ctx.compress_into(x, 80.0, ws_c, blob, dom), 30)
+        d = timed_calls(lambda: ctx.decompress_into(blob, nb, ws_d, out), 30)
+        dv = timed_calls(lambda: ctx.decompress_verify_into(blob, nb, ws_d, out, x), 30)
+        st2, stats = ctx.decompress_verify_into(blob, nb, ws_d, out, x)
+        return {"domain": "tile" if dom == fpsz.TILE else "global",
+                "compress_us": round(c[0] * 1e6, 1), "compress_us_p90": round(c[1] * 1e6, 1),
+                "decompress_us": round(d[0] * 1e6, 1), "decompress_us_p90": round(d[1] * 1e6, 1),
+                "decompress_check_us": round(dv[0] * 1e6, 1),
+                "bits_per_value": round(info.bits_per_value, 4),
+                "achieved_psnr": round(stats.psnr, 4), "dpsnr": round(stats.psnr - 80.0, 4),
+                "n_over_eb": stats.n_over_eb,
+                "op_frac": op_fracs(n, s, info.bits_per_value, c[0], d[0], dv[0])}
+
+    r = {"workload": "2D float32 512x512 GRF k^-3 on [-50, 50], seed 1, 80 dB"}
+    r.update(one(domain))
+    r["other_domain"] = one(fpsz.GLOBAL if domain == fpsz.TILE else fpsz.TILE)
+    return r
 
 
 def c5_leg(ctx, dev):
@@ -690,7 +698,7 @@ def main():
     del ws_c, ws_d, blob, out
     if not args.no_c1:
         progress("512x512 latency leg")
-        line["c1_512x512"] = c1_leg(ctx, dev)
+        line["c1_512x512"] = c1_leg(ctx, dev, domain)
     if not args.no_c5:
         progress("1024^3 float64 leg")
         del x

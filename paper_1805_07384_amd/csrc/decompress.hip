@@ -2013,13 +2013,14 @@ static void launch_dec_t(const Plan &P, const uint8_t *blob, const DecodeArgs &A
   }
 }
 
-// LDS bytes per workgroup (at most) and per CU of the current device
-static void lds_limits(int64_t *per_block, int64_t *per_cu) {
-  static int cached[64][2];
+// LDS bytes per workgroup (at most) and per CU, and the CU count, of the
+// current device
+static void lds_limits(int64_t *per_block, int64_t *per_cu, int64_t *n_cu = nullptr) {
+  static int cached[64][3];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
   if (cached[dev][0] == 0) {
-    int blk = 0, cu = 0;
+    int blk = 0, cu = 0, ncu = 0;
     if (hipDeviceGetAttribute(&blk, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
         blk <= 0)
       blk = 65536;
@@ -2027,11 +2028,16 @@ static void lds_limits(int64_t *per_block, int64_t *per_cu) {
             hipSuccess ||
         cu <= 0)
       cu = blk;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        ncu <= 0)
+      ncu = 256;
+    cached[dev][2] = ncu;
     cached[dev][1] = cu;
     cached[dev][0] = blk;
   }
   *per_block = cached[dev][0];
   *per_cu = cached[dev][1];
+  if (n_cu) *n_cu = cached[dev][2];
 }
 
 // LDS pool (words) of a decode workgroup when two are resident per CU next to
@@ -2077,7 +2083,10 @@ static DecShape decode_shape(uint64_t n_words, uint64_t n_tiles) {
   d.pool_words = (uint32_t)(want < lim ? want : lim);
   // the fused kernel's four tiles, within a pool that keeps three of its
   // workgroups resident per CU.  It is used when four tiles of the average
-  // size fit that pool whole.  Measured on the 512^3 sweep (decode +
+  // size fit that pool whole and the field has at least two of its
+  // workgroups per CU (each reconstructs its four tiles one after the
+  // other, which on a small field lengthens the call: 512 x 512 float32,
+  // 32 tiles, took 53 us in it against 35 us in the two kernels).  Measured on the 512^3 sweep (decode +
   // reconstruction with the check): 0.442 -> 0.396, 0.475 -> 0.416 and
   // 0.516 -> 0.457 ms at 40, 60 and 80 dB (1.4-5.6 bits per value); at 100
   // and 120 dB (8.9-12.3 bits) its windows hold a smaller part of each tile
@@ -2086,7 +2095,9 @@ static DecShape decode_shape(uint64_t n_words, uint64_t n_tiles) {
   fw = (fw + 255) & ~255ull;
   const uint64_t flim = fused_pool_limit();
   d.fused_pool_words = (uint32_t)(fw < flim ? fw : flim);
-  d.fused = (uint64_t)kDrWaves * (avg + 2) <= flim;
+  int64_t blk, cu, ncu;
+  lds_limits(&blk, &cu, &ncu);
+  d.fused = (uint64_t)kDrWaves * (avg + 2) <= flim && n_tiles >= (uint64_t)(2 * kDrWaves * ncu);
   return d;
 }
 

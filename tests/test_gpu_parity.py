@@ -136,14 +136,16 @@ def test_parity_outliers_and_patches(ctx, orc):
 
 @pytest.mark.parametrize("case", ["outliers_f32", "patches_f64"])
 def test_parity_tile_fused_exceptions(ctx, orc, case):
-    # TILE-domain blobs whose tiles average at most ~2000 code words are
-    # decoded and reconstructed in one launch (four average tiles fit its
-    # LDS pool); exception records in that path, next to ragged tiles.
+    # TILE-domain blobs whose tiles average at most ~2000 code words, on
+    # fields of at least 2048 tiles (two workgroups of four tiles per CU),
+    # are decoded and reconstructed in one launch; exception records in that
+    # path, next to ragged tiles (z and y) and a last group of one tile
+    # (19 x 17 x 7 = 2261 tiles).
     # outliers: a smooth field of tiny amplitude with sparse spikes of the
     # full range at 120 dB (spike residuals beyond 2^15 bins); patches:
     # float64 values within ulps of bin edges at 60 dB
     import patchfield as pf
-    shape = (33, 48, 96)
+    shape = (289, 257, 224)
     if case == "outliers_f32":
         rng = np.random.default_rng(21)
         x = synth.grf_numpy(shape, -3.0, 21) * 1e-5
