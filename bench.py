@@ -254,10 +254,11 @@ def c1_leg(ctx, dev, domain):
     return r
 
 
-def c5_leg(ctx, dev):
+def c5_leg(ctx, dev, domain):
     """3D float64 1024^3 GRF (k^-3) with 1 % spikes of 1000 sigma at 100 dB:
     device-resident compress and decompress with the fused Eq. 4 check,
-    median of 3 calls each after one warm-up."""
+    median of 3 calls each after one warm-up, in the sweep's Lorenzo domain
+    and in the other."""
     import torch
 
     from paper_1805_07384_amd import fpsz, synth
@@ -267,27 +268,34 @@ def c5_leg(ctx, dev):
     torch.cuda.synchronize()
     n, s = x.numel(), 8
     ws_c = torch.empty(fpsz.compress_workspace_bytes(shape, x.dtype), dtype=torch.uint8, device=dev)
-    blob = torch.empty(n * 4 + (1 << 20), dtype=torch.uint8, device=dev)
-    st, nb, info = ctx.compress_into(x, 100.0, ws_c, blob)
-    if st != fpsz.OK:
-        raise fpsz.FpszError(st, "C5 compress")
-    c = timed_calls(lambda: ctx.compress_into(x, 100.0, ws_c, blob), 3, warm=1)
-    del ws_c
     ws_d = torch.empty(fpsz.decompress_workspace_bytes(shape, x.dtype), dtype=torch.uint8,
                        device=dev)
+    blob = torch.empty(n * 4 + (1 << 20), dtype=torch.uint8, device=dev)
     out = torch.empty_like(x)
-    d = timed_calls(lambda: ctx.decompress_into(blob, nb, ws_d, out), 3, warm=1)
-    dv = timed_calls(lambda: ctx.decompress_verify_into(blob, nb, ws_d, out, x), 3, warm=1)
-    st2, stats = ctx.decompress_verify_into(blob, nb, ws_d, out, x)
+
+    def one(dom):
+        st, nb, info = ctx.compress_into(x, 100.0, ws_c, blob, dom)
+        if st != fpsz.OK:
+            raise fpsz.FpszError(st, "C5 compress")
+        c = timed_calls(lambda: ctx.compress_into(x, 100.0, ws_c, blob, dom), 3, warm=1)
+        d = timed_calls(lambda: ctx.decompress_into(blob, nb, ws_d, out), 3, warm=1)
+        dv = timed_calls(lambda: ctx.decompress_verify_into(blob, nb, ws_d, out, x), 3, warm=1)
+        st2, stats = ctx.decompress_verify_into(blob, nb, ws_d, out, x)
+        return {"domain": "tile" if dom == fpsz.TILE else "global",
+                "compress_ms": round(c[0] * 1e3, 3), "decompress_ms": round(d[0] * 1e3, 3),
+                "decompress_check_ms": round(dv[0] * 1e3, 3),
+                "compress_gbps": round(n * s / c[0] / 1e9, 1),
+                "decompress_gbps": round(n * s / d[0] / 1e9, 1),
+                "bits_per_value": round(info.bits_per_value, 4), "n_outliers": info.n_outliers,
+                "n_patches": info.n_patches, "achieved_psnr": round(stats.psnr, 4),
+                "dpsnr": round(stats.psnr - 100.0, 4), "n_over_eb": stats.n_over_eb,
+                "op_frac": op_fracs(n, s, info.bits_per_value, c[0], d[0], dv[0])}
+
     res = {"workload": "3D float64 1024^3 GRF k^-3 plus 1%% spikes of 1000 sigma, seed 5, 100 dB",
-           "bytes": n * s, "compress_ms": round(c[0] * 1e3, 3), "decompress_ms": round(d[0] * 1e3, 3),
-           "decompress_check_ms": round(dv[0] * 1e3, 3),
-           "compress_gbps": round(n * s / c[0] / 1e9, 1), "decompress_gbps": round(n * s / d[0] / 1e9, 1),
-           "bits_per_value": round(info.bits_per_value, 4), "n_outliers": info.n_outliers,
-           "n_patches": info.n_patches, "achieved_psnr": round(stats.psnr, 4),
-           "dpsnr": round(stats.psnr - 100.0, 4), "n_over_eb": stats.n_over_eb,
-           "op_frac": op_fracs(n, s, info.bits_per_value, c[0], d[0], dv[0])}
-    del x, blob, ws_d, out
+           "bytes": n * s}
+    res.update(one(domain))
+    res["other_domain"] = one(fpsz.GLOBAL if domain == fpsz.TILE else fpsz.TILE)
+    del x, blob, ws_c, ws_d, out
     torch.cuda.empty_cache()
     return res
 
@@ -703,7 +711,7 @@ def main():
         progress("1024^3 float64 leg")
         del x
         torch.cuda.empty_cache()
-        line["c5_1024cube_f64"] = c5_leg(ctx, dev)
+        line["c5_1024cube_f64"] = c5_leg(ctx, dev, domain)
     if not args.no_batched:
         line["batched"] = batched_leg(ctx, dev)
     if not args.no_served:
