@@ -14,7 +14,9 @@
 //           the regions of the field before a tile, split by tile axis);
 //   rec     local 3D prefix sum plus the halo terms, then bin midpoints.
 // Sums are taken modulo 2^32; the true bin indexes fit in 32 bits, so the
-// result is exact.  TILE domain: decode and rec with zero halo.
+// result is exact.  TILE domain: decode and rec with zero halo; for plain
+// blobs of at most ~2000 code words per tile on fields of at least two
+// four-tile workgroups per CU, both in one launch (k_decrec).
 #include <math.h>
 
 #include <initializer_list>
@@ -851,7 +853,7 @@ __global__ __launch_bounds__(kBlock) void k_rec(Plan P, const uint8_t *__restric
   const int tid = threadIdx.x;
   const uint64_t t = xcd_block_tile(P.n_tiles);
   const TileGeo g = tile_geo(P, t);
-  if (g.nt == (uint32_t)kTilePts) return;  // uniform: full tiles in k_rec_full
+  if (g.nt == (uint32_t)kTilePts) return;  // uniform: full tiles in k_rec_full / k_decrec
   const int ez = (int)g.ez, ey = (int)g.ey, ex = (int)g.ex, nt = (int)g.nt;
   const bool full = ez == TZ && ey == TY && ex == TX;
   const uint64_t *teo = reinterpret_cast<const uint64_t *>(blob + P.off_teo);
