@@ -405,6 +405,7 @@ template <> struct PatchTest<double> {
 // global-memory views of the input (the pointers reach the kernels inside
 // job structures, where the compiler cannot see their address space)
 template <typename T> using gptr_t = __attribute__((address_space(1))) const T *;
+typedef unsigned short u16x2_t __attribute__((ext_vector_type(2)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef double f64x2_t __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
@@ -719,13 +720,16 @@ __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restri
       const SegPtrs<NDIM> sp(box, tid);
       int32_t po = sp.o[-1], py = sp.y[-1], pz = sp.z[-1], pzy = sp.zy[-1];
       uint32_t run_sym = 0xffffffffu, run_n = 0;
-      // codes of two steps go out as one 16-byte store (fewer scattered
-      // store instructions: lanes are 64 bytes apart)
-      __attribute__((address_space(1))) u32x4_t *cdst =
-          (__attribute__((address_space(1))) u32x4_t *)(codes + g.start + (uint64_t)i0);
-#pragma unroll 1
+      // The thread's 32 codes are kept (as int16 pairs) until the wave knows
+      // whether all of its codes fit in int8: then they go out as bytes,
+      // each lane's 32 at byte 32 * lane of the wave's 4 KiB slot (half the
+      // traffic for quant's store and the encoder's two reads), else as
+      // int16 at the thread's place in stream order.  Both in 16-byte
+      // pieces.  int8 needs a 16-byte aligned tile start, as the encoder's
+      // fast path does.
+      uint32_t wq[16];
+#pragma unroll
       for (int k2 = 0; k2 < 4; k2++) {
-      uint32_t wq[4];
 #pragma unroll
       for (int kk = 0; kk < 2; kk++) {
         const int k = 2 * k2 + kk;
@@ -777,19 +781,49 @@ __global__ __launch_bounds__(kBlock) void k_quant(CJob one, const CJob *__restri
             run_sym = sy;
           }
         }
-        wq[2 * kk] = c16[0] | (c16[1] << 16);
-        wq[2 * kk + 1] = c16[2] | (c16[3] << 16);
+        wq[4 * k2 + 2 * kk] = c16[0] | (c16[1] << 16);
+        wq[4 * k2 + 2 * kk + 1] = c16[2] | (c16[3] << 16);
+      }
       }
       if (!RECORDS) {
-        u32x4_t w;
-        w.x = wq[0];
-        w.y = wq[1];
-        w.z = wq[2];
-        w.w = wq[3];
-        cdst[k2] = w;
+        atomicAdd(&hist[run_sym], run_n);
+        // int8 when every code of the wave is in -128..127 (an outlier's
+        // 0x8000 is not): code + 128 in 0..255, as packed 16-bit lanes
+        u16x2_t m8 = (u16x2_t)(0);
+#pragma unroll
+        for (int i = 0; i < 16; i++)
+          m8 = __builtin_elementwise_max(m8, __builtin_bit_cast(u16x2_t, wq[i]) + (u16x2_t)(128));
+        const bool w8 = (g.start & 7) == 0 && !__builtin_amdgcn_ballot_w64(m8.x > 255 || m8.y > 255);
+        const int lane = tid & 63, wv = tid >> 6;
+        if (lane == 0) J.W.code_w8[4 * t + wv] = w8 ? 1 : 0;
+        typedef __attribute__((address_space(1))) u32x4_t gq4;
+        if (w8) {
+          uint32_t b[8];
+#pragma unroll
+          for (int m = 0; m < 8; m++) {
+            const uint32_t a = wq[2 * m], c = wq[2 * m + 1];
+            b[m] = (a & 0xffu) | ((a >> 8) & 0xff00u) | ((c & 0xffu) << 16) | ((c << 8) & 0xff000000u);
+          }
+          gq4 *dst = (gq4 *)(reinterpret_cast<uint8_t *>(codes) + 2 * g.start + 4096 * (uint64_t)wv +
+                             32 * (uint64_t)lane);
+          u32x4_t v0, v1;
+          v0.x = b[0]; v0.y = b[1]; v0.z = b[2]; v0.w = b[3];
+          v1.x = b[4]; v1.y = b[5]; v1.z = b[6]; v1.w = b[7];
+          dst[0] = v0;
+          dst[1] = v1;
+        } else {
+          gq4 *dst = (gq4 *)(codes + g.start + (uint64_t)i0);
+#pragma unroll
+          for (int k2 = 0; k2 < 4; k2++) {
+            u32x4_t v;
+            v.x = wq[4 * k2];
+            v.y = wq[4 * k2 + 1];
+            v.z = wq[4 * k2 + 2];
+            v.w = wq[4 * k2 + 3];
+            dst[k2] = v;
+          }
+        }
       }
-      }
-      if (!RECORDS) atomicAdd(&hist[run_sym], run_n);
     } else {
     for (int i = tid; i <= kTilePts / 32; i += kBlock) pmask[i] = 0;
     __syncthreads();
@@ -1765,14 +1799,38 @@ struct EncCodes {
   uint64_t base;
   int cnt;
   bool fast;  // 32 codes, 16-byte aligned (full tiles)
+  bool w8;    // fast, and the wave's codes are stored as int8 (all direct)
+  const uint8_t *bytes;    // the thread's 32 int8 codes
   u32x4_t q0, q1, q2, q3;  // the 32 codes of a fast thread, loaded up front
+                           // (int8: q0, q1 hold them as bytes)
   __device__ void prefetch() {
     if (fast) {
-      gptr_t<u32x4_t> src = (gptr_t<u32x4_t>)(codes + base);
+      gptr_t<u32x4_t> src = w8 ? (gptr_t<u32x4_t>)bytes : (gptr_t<u32x4_t>)(codes + base);
       q0 = src[0];
       q1 = src[1];
-      q2 = src[2];
-      q3 = src[3];
+      if (!w8) {
+        q2 = src[2];
+        q3 = src[3];
+      }
+    }
+  }
+  // fn(code + 512) for the 32 codes in order, all of them direct symbols
+  // (w8, or fast with every code in -511..511)
+  template <class Fn> __device__ void for_direct(Fn fn) const {
+    const uint32_t w[16] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
+                            q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
+    if (w8) {
+#pragma unroll
+      for (int i = 0; i < 8; i++)
+#pragma unroll
+        for (int k = 0; k < 4; k++) fn((((w[i] >> (8 * k)) & 0xffu) ^ 0x80u) + 384u);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 16; i++) {
+        const u16x2_t t = __builtin_bit_cast(u16x2_t, w[i]) + (u16x2_t)(512);
+        fn((uint32_t)t.x & 1023u);
+        fn((uint32_t)t.y & 1023u);
+      }
     }
   }
   __device__ void load8(int v, int32_t c[8]) const {
@@ -1787,13 +1845,16 @@ struct EncCodes {
   }
 };
 
-__device__ inline EncCodes enc_codes(const Plan &P, const int16_t *codes, const TileGeo &g, int tid) {
+__device__ inline EncCodes enc_codes(const CJob &J, const TileGeo &g, uint64_t t, int tid) {
   EncCodes E;
   const int nt = (int)g.nt, i0 = 32 * tid;
-  E.codes = codes;
+  E.codes = J.W.codes;
   E.base = g.start + (uint64_t)i0;
   E.cnt = nt - i0 < 0 ? 0 : (nt - i0 > 32 ? 32 : nt - i0);
   E.fast = nt == kTilePts && (E.base & 7) == 0;  // uniform over the tile
+  E.w8 = E.fast && J.W.code_w8[4 * t + (tid >> 6)] != 0;  // uniform over the wave
+  E.bytes = reinterpret_cast<const uint8_t *>(J.W.codes) + 2 * g.start +
+            4096 * (uint64_t)(tid >> 6) + 32 * (uint64_t)(tid & 63);
   return E;
 }
 
@@ -1801,7 +1862,6 @@ __device__ inline void load_code_table(const CJob &J, uint32_t *sct) {
   for (int s = threadIdx.x; s < kNSym; s += kBlock) sct[s] = (J.W.code[s] << 8) | J.W.code_len[s];
 }
 
-typedef unsigned short u16x2_t __attribute__((ext_vector_type(2)));
 
 // Bits of the 32 codes of a fast thread when every one is a direct symbol
 // (residual + 512 in 1..1023): one byte-table read per code.  *direct
@@ -1843,7 +1903,7 @@ __global__ __launch_bounds__(kBlock) void k_enc_count(CJob one, const CJob *__re
   __syncthreads();
   for (uint64_t t = blockIdx.x; t < P.n_tiles; t += gridDim.x) {
     const TileGeo g = tile_geo(P, t);
-    EncCodes E = enc_codes(P, J.W.codes, g, tid);
+    EncCodes E = enc_codes(J, g, t, tid);
     E.prefetch();
     // the tile's staged exception records to their place in the blob; the
     // tile's bit counts below reuse the same staging bytes, so the records
@@ -1863,7 +1923,12 @@ __global__ __launch_bounds__(kBlock) void k_enc_count(CJob one, const CJob *__re
     }
     uint32_t bits = 0;
     bool direct = false;
-    if (E.fast) bits = direct_bits(E, len8, &direct);
+    if (E.w8) {
+      direct = true;
+      E.for_direct([&](uint32_t t8) { bits += len8[t8]; });
+    } else if (E.fast) {
+      bits = direct_bits(E, len8, &direct);
+    }
     // the general symbol map when some lane of the wave needs it
     if (__builtin_amdgcn_ballot_w64(!direct)) {
       uint32_t gb = 0;
@@ -1946,7 +2011,7 @@ __global__ __launch_bounds__(kBlock) void k_enc_pack(CJob one, const CJob *__res
   const uint64_t off_words = dp->off_words;
   for (uint64_t t = blockIdx.x; t < P.n_tiles; t += gridDim.x) {
     const TileGeo g = tile_geo(P, t);
-    EncCodes E = enc_codes(P, J.W.codes, g, tid);
+    EncCodes E = enc_codes(J, g, t, tid);
     E.prefetch();
     const uint32_t bits = tb[t * kBlock + tid];
     __syncthreads();  // previous tile's words stored; table loaded
@@ -1967,8 +2032,8 @@ __global__ __launch_bounds__(kBlock) void k_enc_pack(CJob one, const CJob *__res
     };
     // direct symbols only (residual + 512 in 1..1023, no extra bits): the
     // table entry is the whole pattern
-    bool direct = false;
-    if (E.fast) {
+    bool direct = E.w8;
+    if (E.fast && !E.w8) {
       u16x2_t mx = (u16x2_t)(0);
       const u32x4_t qs[4] = {E.q0, E.q1, E.q2, E.q3};
 #pragma unroll
@@ -1981,17 +2046,10 @@ __global__ __launch_bounds__(kBlock) void k_enc_pack(CJob one, const CJob *__res
       direct = mx.x < 1023 && mx.y < 1023;
     }
     if (!__builtin_amdgcn_ballot_w64(!direct)) {
-      const u32x4_t qs[4] = {E.q0, E.q1, E.q2, E.q3};
-#pragma unroll
-      for (int v = 0; v < 4; v++)
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-          const uint32_t w = qs[v][i];  // copied out: see direct_bits
-          const u16x2_t t = __builtin_bit_cast(u16x2_t, w) + (u16x2_t)(512);
-          const uint32_t e0 = sct[t.x & 1023], e1 = sct[t.y & 1023];
-          put(e0 >> 8, e0 & 0xffu);
-          put(e1 >> 8, e1 & 0xffu);
-        }
+      E.for_direct([&](uint32_t t8) {
+        const uint32_t e = sct[t8];
+        put(e >> 8, e & 0xffu);
+      });
     } else {
 #pragma unroll 1
       for (int v = 0; v < 4; v++) {

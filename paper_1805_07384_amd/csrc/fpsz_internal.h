@@ -365,6 +365,7 @@ struct CompressWs {
   uint64_t *exc_off;    // per-tile record offsets
   uint32_t *stage;      // staged records, kStage per tile
   uint64_t *word_state;
+  uint8_t *code_w8;     // per tile and wave: its residual codes stored as int8 (1) or int16 (0)
   int16_t *codes;
   uint64_t zero_bytes;  // bytes from P to clear before a call
 };

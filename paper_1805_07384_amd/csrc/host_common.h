@@ -102,7 +102,7 @@ inline fpsz_status make_plan(int ndim, const uint64_t *dims, fpsz_dtype dtype, P
 }
 
 struct CompressLayout {
-  uint64_t off_part, off_hist, off_len, off_code, off_word_state, off_exc_cnt, off_exc_off,
+  uint64_t off_part, off_hist, off_len, off_code, off_word_state, off_w8, off_exc_cnt, off_exc_off,
       off_stage, off_codes, zero, total;
 };
 
@@ -119,6 +119,8 @@ inline CompressLayout compress_layout(const Plan &P) {
   o = align256(o + 4 * (uint64_t)kNSym);
   L.off_word_state = o;
   o = align256(o + 8 * P.n_tiles);
+  L.off_w8 = o;  // one byte per wave of a tile (4 per tile)
+  o = align256(o + 4 * P.n_tiles);
   L.zero = o;  // everything before this is cleared at the start of a call
   L.off_exc_cnt = o;
   o = align256(o + 4 * P.n_tiles);
@@ -263,6 +265,7 @@ inline fpsz_status prepare_compress(fpsz_ctx *ctx, const void *field_dev, int nd
   W.exc_off = (uint64_t *)(ws + L.off_exc_off);
   W.stage = (uint32_t *)(ws + L.off_stage);
   W.word_state = (uint64_t *)(ws + L.off_word_state);
+  W.code_w8 = ws + L.off_w8;
   W.codes = (int16_t *)(ws + L.off_codes);
   W.zero_bytes = L.zero;
   job->P = P;
