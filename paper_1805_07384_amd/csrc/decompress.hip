@@ -2068,9 +2068,10 @@ static uint64_t fused_pool_limit() {
 // Waves per decode workgroup.  The symbol loop is bound by latency, so the
 // number of waves resident matters most: eight per workgroup, two workgroups
 // per CU (four waves per SIMD).  Measured on the 512^3 sweep: fewer waves with
-// whole tiles in LDS (2-4 per workgroup at 100-120 dB) were slower than eight
-// whose large tiles partly read the blob, and ten per workgroup were slower
-// than eight at 40-60 dB.
+// whole tiles in LDS (2-4 per workgroup at 100-120 dB; four per workgroup at
+// two or three workgroups per CU: decode 0.288 -> 0.345 / 0.310 ms at 100 dB)
+// were slower than eight whose large tiles partly read the blob, and ten per
+// workgroup were slower than eight at 40-60 dB.
 static DecShape decode_shape(uint64_t n_words, uint64_t n_tiles) {
   DecShape d;
   d.waves = (uint32_t)kDecWaves;
@@ -2088,7 +2089,8 @@ static DecShape decode_shape(uint64_t n_words, uint64_t n_tiles) {
   // size fit that pool whole and the field has at least two of its
   // workgroups per CU (each reconstructs its four tiles one after the
   // other, which on a small field lengthens the call: 512 x 512 float32,
-  // 32 tiles, took 53 us in it against 35 us in the two kernels).  Measured on the 512^3 sweep (decode +
+  // 32 tiles, took 53 us in it against 35 us in the two kernels).
+  // Measured on the 512^3 sweep (decode +
   // reconstruction with the check): 0.442 -> 0.396, 0.475 -> 0.416 and
   // 0.516 -> 0.457 ms at 40, 60 and 80 dB (1.4-5.6 bits per value); at 100
   // and 120 dB (8.9-12.3 bits) its windows hold a smaller part of each tile
