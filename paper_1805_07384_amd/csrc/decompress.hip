@@ -56,6 +56,10 @@ struct DecodeArgs {
   // in-loop blobs: records per stored point (1 float32, 2 float64); 0 for
   // plain blobs, whose untagged records are the outliers' residuals
   uint32_t il_rw;
+  // one-launch decompression: full tiles' 32-code parts whose codes all lie
+  // in -128..127 go to res8 as bytes, flagged in res8_mask
+  uint8_t *res8;
+  uint64_t *res8_mask;
 };
 
 // Eq. 4 statistics of one tile of the reconstruction against the original,
@@ -420,14 +424,18 @@ __device__ inline uint32_t decode_sym(Reader &R, uint32_t lut_lds, uint32_t sort
 // position after the last symbol: the reader's next 32 bits start
 // 32 (idx - 1) - s bits into the tile (a and b are words idx - 2 and
 // idx - 1, the window's top bit is bit 31 + s of a:b).
+// dst8 (FULL only, may be null): a part of 32 codes that all lie in
+// -128..127 goes there as bytes instead (bit `part` of *parts8 set).
 template <bool FULL, class Reader>
 __device__ inline uint32_t decode_run(Reader &R, int cnt, uint32_t lut_lds, uint32_t sorted_lds,
                                       const LongTabs &LT, int16_t *dst, uint32_t *end,
-                                      bool *bad) {
+                                      bool *bad, uint8_t *dst8 = nullptr,
+                                      uint32_t *parts8 = nullptr) {
   uint32_t nout = 0;
   bool badv = false;
   if (FULL) {
     typedef __attribute__((address_space(1))) du32x4_t gq;
+    uint32_t p8 = 0;
 #pragma unroll 1
     for (int part = 0; part < 4; part++) {
       uint32_t pk[16];
@@ -439,17 +447,42 @@ __device__ inline uint32_t decode_run(Reader &R, int cnt, uint32_t lut_lds, uint
         p2 -= (du16x2_t)(512);
         pk[h >> 1] = __builtin_bit_cast(uint32_t, p2);
       }
-      gq *d = (gq *)(dst + 32 * part);
+      bool fits = false;
+      if (dst8) {
+        du16x2_t m8 = (du16x2_t)(0);
 #pragma unroll
-      for (int k = 0; k < 4; k++) {
-        du32x4_t v;
-        v.x = pk[4 * k];
-        v.y = pk[4 * k + 1];
-        v.z = pk[4 * k + 2];
-        v.w = pk[4 * k + 3];
-        d[k] = v;
+        for (int i = 0; i < 16; i++)
+          m8 = __builtin_elementwise_max(m8, __builtin_bit_cast(du16x2_t, pk[i]) + (du16x2_t)(128));
+        fits = m8.x <= 255 && m8.y <= 255;
+      }
+      if (fits) {
+        uint32_t b8[8];
+#pragma unroll
+        for (int m = 0; m < 8; m++) {
+          const uint32_t a = pk[2 * m], c = pk[2 * m + 1];
+          b8[m] = (a & 0xffu) | ((a >> 8) & 0xff00u) | ((c & 0xffu) << 16) | ((c << 8) & 0xff000000u);
+        }
+        gq *d = (gq *)(dst8 + 32 * part);
+        du32x4_t v0, v1;
+        v0.x = b8[0]; v0.y = b8[1]; v0.z = b8[2]; v0.w = b8[3];
+        v1.x = b8[4]; v1.y = b8[5]; v1.z = b8[6]; v1.w = b8[7];
+        d[0] = v0;
+        d[1] = v1;
+        p8 |= 1u << part;
+      } else {
+        gq *d = (gq *)(dst + 32 * part);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          du32x4_t v;
+          v.x = pk[4 * k];
+          v.y = pk[4 * k + 1];
+          v.z = pk[4 * k + 2];
+          v.w = pk[4 * k + 3];
+          d[k] = v;
+        }
       }
     }
+    if (parts8) *parts8 = p8;
   } else {
     for (int k = 0; k < cnt; k++) {
       const uint32_t a = decode_sym(R, lut_lds, sorted_lds, LT, &nout, badv);
@@ -485,7 +518,7 @@ template <int NDIM>
 __device__ inline void decode_group(const Plan &P, const uint8_t *__restrict__ blob,
                                     const DecodeArgs &A, DevParams *__restrict__ dp,
                                     int16_t *__restrict__ codes, uint32_t pool_words, uint64_t t0,
-                                    const DecLds &L, uint32_t *flag) {
+                                    const DecLds &L, uint32_t *flag, bool allow8 = false) {
   uint16_t *const lut = L.lut;
   uint32_t *const lim = L.lim;
   int32_t *const off = L.off;
@@ -596,6 +629,11 @@ __device__ inline void decode_group(const Plan &P, const uint8_t *__restrict__ b
   int16_t *dst = codes + g.start + k0;
   // full chunks with a 16-byte aligned destination (k0 is a multiple of 128)
   const bool full = cnt == kChunk && (g.start & 7) == 0;
+  // int8 parts: full tiles of the one-launch decompression only (their one
+  // reader checks the masks; ragged tiles keep int16 for the general kernel)
+  const bool use8 = allow8 && nt == kTilePts;
+  uint8_t *dst8 = use8 ? A.res8 + g.start + k0 : nullptr;
+  uint32_t parts8 = 0;
   bool bad = false;
   uint32_t endpos = incl, nout = 0;  // bit position after the chunk
   const bool lds = clw < wn;
@@ -609,7 +647,7 @@ __device__ inline void decode_group(const Plan &P, const uint8_t *__restrict__ b
       R.wlim = wn + 1;
       R.glim = nw - 1;
       R.init(cstart);
-      if (full) nout = decode_run<true>(R, cnt, lut_lds, sorted_lds, LT, dst, &endpos, &bad);
+      if (full) nout = decode_run<true>(R, cnt, lut_lds, sorted_lds, LT, dst, &endpos, &bad, dst8, &parts8);
       else nout = decode_run<false>(R, cnt, lut_lds, sorted_lds, LT, dst, &endpos, &bad);
     }
   } else if (cnt > 0) {
@@ -620,8 +658,15 @@ __device__ inline void decode_group(const Plan &P, const uint8_t *__restrict__ b
     R.wlim = wn + 1;
     R.glim = 0;
     R.init(cstart);
-    if (full) nout = decode_run<true>(R, cnt, lut_lds, sorted_lds, LT, dst, &endpos, &bad);
+    if (full) nout = decode_run<true>(R, cnt, lut_lds, sorted_lds, LT, dst, &endpos, &bad, dst8, &parts8);
     else nout = decode_run<false>(R, cnt, lut_lds, sorted_lds, LT, dst, &endpos, &bad);
+  }
+  if (use8) {  // uniform over the wave (the tile's)
+#pragma unroll
+    for (int p8 = 0; p8 < 4; p8++) {
+      const uint64_t m = __builtin_amdgcn_ballot_w64((parts8 >> p8) & 1u);
+      if (lane == 0) A.res8_mask[4 * t + p8] = m;
+    }
   }
   // every outlier symbol must have its record
   // (in-loop blobs: every outlier symbol is a stored point with A.il_rw
@@ -1006,13 +1051,20 @@ struct SegExc {
 // Residuals of this thread's segment, outliers applied.  lds_m needs 512
 // words; scr 8 words.  Sets *bad (uniform after the final barrier of the
 // caller) on an inconsistent exception list.
+// r8 (may be null): the thread's 32 codes are there as bytes instead.
 template <int NDIM, int RW>
 __device__ inline SegExc load_segment(const TileGeo &g, const int16_t *codes, const uint32_t *exc,
                                       uint64_t e0, uint64_t e1, uint32_t r[32], uint32_t *lds_m,
-                                      uint32_t *scr, uint32_t *s_bad) {
+                                      uint32_t *scr, uint32_t *s_bad, const uint8_t *r8 = nullptr) {
   const int tid = threadIdx.x;
   SegExc X;
-  {
+  if (r8) {
+    dgptr_t<du32x4_t> src = (dgptr_t<du32x4_t>)r8;
+    const du32x4_t q0 = src[0], q1 = src[1];
+    const uint32_t w[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+    for (int k = 0; k < 32; k++) r[k] = (uint32_t)(int32_t)(int8_t)(uint8_t)(w[k >> 2] >> (8 * (k & 3)));
+  } else {
     dgptr_t<du32x4_t> src = (dgptr_t<du32x4_t>)(codes + g.start + 32 * (uint64_t)tid);
     const du32x4_t q0 = src[0], q1 = src[1], q2 = src[2], q3 = src[3];
     const du32x4_t qq[4] = {q0, q1, q2, q3};
@@ -1339,7 +1391,11 @@ __device__ inline bool rec_full_tile(const Plan &P, const uint8_t *__restrict__ 
   if (tid == 0) s_bad = 0;
   __syncthreads();
   uint32_t r[32];
-  const SegExc X = load_segment<NDIM, RW>(g, codes, exc, e0, e1, r, lds_m, scr, &s_bad);
+  // the one-launch decompression's int8 parts: bit tid / 4 of mask tid % 4
+  const uint8_t *r8 = nullptr;
+  if (STREAM && A.res8 && ((A.res8_mask[4 * t + (tid & 3)] >> (tid >> 2)) & 1u))
+    r8 = A.res8 + g.start + 32 * (uint64_t)tid;
+  const SegExc X = load_segment<NDIM, RW>(g, codes, exc, e0, e1, r, lds_m, scr, &s_bad, r8);
   if (fslot >= 0) *reinterpret_cast<du32x4_t *>(s_face + fslot) = fa;
   tile_prefix<NDIM>(r, lds_t);  // its barrier also publishes s_face
   if (GLOBAL) {
@@ -1541,7 +1597,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_decrec(Plan P, const uint8_t *__r
                     reinterpret_cast<int32_t *>(dr_lds + kDrOff),
                     reinterpret_cast<uint16_t *>(dr_lds + kDrSorted), dr_lds + kDrWords,
                     dr_lds + kDrPool};
-  decode_group<NDIM>(P, blob, A, dp, codes, pool_words, t0, D, &s_flag);
+  decode_group<NDIM>(P, blob, A, dp, codes, pool_words, t0, D, &s_flag, true);
   // the group's residuals are visible to the whole workgroup and the
   // decoder's LDS is free
   __syncthreads();
@@ -2136,6 +2192,8 @@ hipError_t launch_decompress_args(const Plan &P, const uint8_t *blob, const Deco
   A.ref = ref;
   A.eb = eb;
   A.vpart = W.vpart;
+  A.res8 = W.res8;
+  A.res8_mask = W.res8_mask;
   A.il_rw = P.variant == kVarInloop ? (P.dtype == FPSZ_F32 ? 1u : 2u) : 0u;
   const DecShape ds = decode_shape(n_words, P.n_tiles);
   if (P.dtype == FPSZ_F32) {

@@ -379,6 +379,8 @@ struct DecompressWs {
   uint32_t *gx, *gy, *gz, *tt;  // per-tile edge vectors and totals
   uint32_t *tmp;           // segment sums of the scans
   int16_t *codes;          // decoded residual codes, stream order
+  uint8_t *res8;           // one-launch decompression: 32-code parts stored as int8, stream order
+  uint64_t *res8_mask;     // per tile, mask p: bit L set when part 4 L + p is in res8
   double *vpart;           // check against the original: per-tile (sse, max |e|, count > eb)
   uint64_t zero_bytes;
 };

@@ -136,7 +136,7 @@ inline CompressLayout compress_layout(const Plan &P) {
 
 struct DecompressLayout {
   uint64_t off_lut, off_ltab, off_sorted, off_fz, off_fy, off_fx, off_gx, off_gy, off_gz, off_tt,
-      off_tmp, off_vpart, off_codes, total;
+      off_tmp, off_vpart, off_codes, off_res8, off_res8m, total;
 };
 
 inline DecompressLayout decompress_layout(const Plan &P) {
@@ -179,6 +179,10 @@ inline DecompressLayout decompress_layout(const Plan &P) {
   o = align256(o + 3 * 8 * (T > (uint64_t)kVerifyBlocks ? T : (uint64_t)kVerifyBlocks));
   L.off_codes = o;
   o = align256(o + 2 * P.n);
+  L.off_res8 = o;  // int8 residual parts (one byte per point)
+  o = align256(o + P.n);
+  L.off_res8m = o;  // four 64-bit part masks per tile
+  o = align256(o + 32 * T);
   L.total = o;
   return L;
 }
@@ -418,6 +422,8 @@ inline fpsz_status prepare_decompress(fpsz_ctx *ctx, const uint8_t *h, const voi
   W.tt = (uint32_t *)(ws + L.off_tt);
   W.tmp = (uint32_t *)(ws + L.off_tmp);
   W.codes = (int16_t *)(ws + L.off_codes);
+  W.res8 = ws + L.off_res8;
+  W.res8_mask = (uint64_t *)(ws + L.off_res8m);
   W.vpart = (double *)(ws + L.off_vpart);
   W.zero_bytes = align256(sizeof(DevParams));
   return FPSZ_OK;
