@@ -1863,13 +1863,11 @@ __device__ inline void load_code_table(const CJob &J, uint32_t *sct) {
 }
 
 
-// Bits of the 32 codes of a fast thread when every one is a direct symbol
-// (residual + 512 in 1..1023): one byte-table read per code.  *direct
-// tells whether that holds; the sum is meaningless otherwise.
-__device__ inline uint32_t direct_bits(const EncCodes &E, const uint8_t *len8, bool *direct) {
+// Whether every one of the 32 int16 codes of a fast thread is a direct
+// symbol (residual + 512 in 1..1023).
+__device__ inline bool all_direct16(const EncCodes &E) {
   const u32x4_t qs[4] = {E.q0, E.q1, E.q2, E.q3};
   u16x2_t mx = (u16x2_t)(0);
-  uint32_t bits = 0;
 #pragma unroll
   for (int v = 0; v < 4; v++)
 #pragma unroll
@@ -1877,13 +1875,10 @@ __device__ inline uint32_t direct_bits(const EncCodes &E, const uint8_t *len8, b
       // (the element is copied out first: a bit cast of a vector element
       // subscript read element 0 whatever the subscript)
       const uint32_t w = qs[v][i];
-      const u16x2_t t = __builtin_bit_cast(u16x2_t, w) + (u16x2_t)(512);
-      // direct: t - 1 in 0..1022 for both halves (packed 16-bit, wrapping)
-      mx = __builtin_elementwise_max(mx, t - (u16x2_t)(1));
-      bits += (uint32_t)len8[t.x & 1023] + (uint32_t)len8[t.y & 1023];
+      // direct: code + 511 in 0..1022 for both halves (packed 16-bit, wrapping)
+      mx = __builtin_elementwise_max(mx, __builtin_bit_cast(u16x2_t, w) + (u16x2_t)(511));
     }
-  *direct = mx.x < 1023 && mx.y < 1023;
-  return bits;
+  return mx.x < 1023 && mx.y < 1023;
 }
 
 __global__ __launch_bounds__(kBlock) void k_enc_count(CJob one, const CJob *__restrict__ jobs) {
@@ -1923,12 +1918,11 @@ __global__ __launch_bounds__(kBlock) void k_enc_count(CJob one, const CJob *__re
     }
     uint32_t bits = 0;
     bool direct = false;
-    if (E.w8) {
-      direct = true;
-      E.for_direct([&](uint32_t t8) { bits += len8[t8]; });
-    } else if (E.fast) {
-      bits = direct_bits(E, len8, &direct);
-    }
+    // the bits of direct symbols by one byte-table read each, when the whole
+    // wave's codes are direct (the sum is not taken for a wave that needs
+    // the general map below)
+    if (E.fast) direct = E.w8 || all_direct16(E);
+    if (!__builtin_amdgcn_ballot_w64(!direct)) E.for_direct([&](uint32_t t8) { bits += len8[t8]; });
     // the general symbol map when some lane of the wave needs it
     if (__builtin_amdgcn_ballot_w64(!direct)) {
       uint32_t gb = 0;
@@ -1944,7 +1938,7 @@ __global__ __launch_bounds__(kBlock) void k_enc_count(CJob one, const CJob *__re
 #pragma unroll
         for (int h = 0; h < 8; h++) gb += 8 * v + h < E.cnt ? (e[h] & 0xffu) + ne[h] : 0u;
       }
-      bits = direct ? bits : gb;
+      bits = gb;  // every lane of the wave, direct or not
     }
     tb[t * kBlock + tid] = (uint16_t)bits;
     // chunk = 4 consecutive threads (128 symbols)
@@ -2040,7 +2034,7 @@ __global__ __launch_bounds__(kBlock) void k_enc_pack(CJob one, const CJob *__res
       for (int v = 0; v < 4; v++)
 #pragma unroll
         for (int i = 0; i < 4; i++) {
-          const uint32_t w = qs[v][i];  // copied out: see direct_bits
+          const uint32_t w = qs[v][i];  // copied out: see all_direct16
           mx = __builtin_elementwise_max(mx, __builtin_bit_cast(u16x2_t, w) + (u16x2_t)(511));
         }
       direct = mx.x < 1023 && mx.y < 1023;
